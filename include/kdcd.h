@@ -1,0 +1,207 @@
+/*
+ * kdcd.h -- C-ABI of the MI355X (gfx950) library for s-step dual coordinate
+ * descent on kernel methods:
+ *
+ *   s-step DCD for kernel SVM (paper: "Scalable Dual Coordinate Descent for
+ *   Kernel Methods", Sec. 3.1-3.2, Algorithms 1-2), and
+ *   s-step block DCD for kernel ridge regression (Sec. 3.3-3.4,
+ *   Algorithms 3-4, Eq. (3)).
+ *
+ * Every outer iteration k of both solvers runs on the device:
+ *   1. the index block S_k: s*b entries of the caller's sequence idx;
+ *   2. the kernel-block product P = A A_S^T (m x sb), dense (MFMA) or CSR;
+ *   3. the kernel map of Table 1 (RBF from precomputed row norms, or
+ *      polynomial), fused into the product's epilogue;
+ *   4. the right-hand side r = U^T beta (U = K(A, A_S) is never stored);
+ *   5. the sampled Gram W = K(A_S, A_S) (sb x sb, FP64);
+ *   6. the s inner coordinate (K-SVM) or b x b block (K-RR) updates;
+ *   7. the scatter alpha_{S_t} += theta_t (or Delta alpha_t), in t order.
+ *
+ * Conventions shared by every entry point
+ *  - Pointers marked "device" are HIP device pointers owned by the caller;
+ *    the library never frees them.  Pointers marked "host" are host memory.
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream).
+ *    Solver entry points synchronise `stream` before returning so that they
+ *    can report errors found on the device.
+ *  - No exception crosses this boundary.  On any error the contents of
+ *    output arrays (alpha, r, W, trace, snapshots) are unspecified.
+ *  - All floating-point inputs and outputs are FP64.  Indices are int32,
+ *    0-based.  Dense A is row-major with leading dimension ld >= n.
+ *  - Calls are reentrant; they share no hidden state across calls.
+ */
+#ifndef KDCD_H
+#define KDCD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+struct ihipStream_t;
+typedef struct ihipStream_t *kdcd_stream; /* identical to hipStream_t */
+
+typedef enum {
+    KDCD_OK = 0,
+    KDCD_ERR_INVALID_ARG = -1,     /* a host-checkable argument is out of its domain       */
+    KDCD_ERR_UNSUPPORTED = -2,     /* valid but not implemented (e.g. b > 32, sb > 1024)   */
+    KDCD_ERR_INDEX_RANGE = -3,     /* some idx entry is outside [0, m)                      */
+    KDCD_ERR_INDEX_DUPLICATE = -4, /* a K-RR block repeats a coordinate (Alg. 3/4 draw a   */
+                                   /* block without replacement)                            */
+    KDCD_ERR_NOT_SPD = -5,         /* a K-RR block matrix G = W_jj/lambda + m I failed its */
+                                   /* factorisation (non-positive or non-finite pivot)      */
+    KDCD_ERR_NONFINITE = -6,       /* NaN/Inf in y, alpha_0, or produced by an update       */
+    KDCD_ERR_HIP = -7,             /* a HIP runtime call failed                             */
+    KDCD_ERR_ALLOC = -8,           /* device workspace allocation failed                   */
+    KDCD_ERR_WORKSPACE = -9        /* caller workspace smaller than kdcd_workspace_bytes    */
+} kdcd_status;
+
+/* Kernel functions of Table 1:
+ *   LINEAR  K(x, z) = x . z
+ *   POLY    K(x, z) = (c + x . z)^degree,  c >= 0, integer degree >= 1
+ *   RBF     K(x, z) = exp(-sigma ||x - z||^2),  sigma > 0                     */
+typedef enum { KDCD_KERNEL_LINEAR = 0, KDCD_KERNEL_POLY = 1, KDCD_KERNEL_RBF = 2 } kdcd_kernel_kind;
+
+typedef struct {
+    int32_t kind;   /* kdcd_kernel_kind */
+    int32_t degree; /* POLY only */
+    double sigma;   /* RBF only */
+    double c;       /* POLY only */
+} kdcd_kernel;
+
+typedef enum { KDCD_DENSE = 0, KDCD_CSR = 1 } kdcd_format;
+
+/* Precision of the kernel-block product P = A A_S^T only.  The Gram W, the
+ * right-hand side r, the recurrence and alpha are always FP64.  F32/BF16/F16
+ * use MFMA with FP32 accumulation; BF16X3 splits A = hi + lo in bf16 and sums
+ * hi*hi + hi*lo + lo*hi.  Low-precision copies of A are library workspace.  */
+typedef enum { KDCD_F64 = 0, KDCD_F32 = 1, KDCD_BF16 = 2, KDCD_F16 = 3, KDCD_BF16X3 = 4 } kdcd_compute;
+
+typedef struct {
+    int32_t format; /* kdcd_format */
+    int32_t reserved;
+    int64_t m, n;   /* rows (samples) and columns (features) */
+    int64_t ld;     /* DENSE: leading dimension (>= n), in elements */
+    int64_t nnz;    /* CSR: number of stored entries */
+    const double *values;    /* device. DENSE: m x ld row-major. CSR: nnz values      */
+    const int64_t *row_ptr;  /* device. CSR: m+1 offsets, row_ptr[0] = 0              */
+    const int32_t *col_idx;  /* device. CSR: nnz columns, strictly increasing per row */
+} kdcd_matrix;
+
+/* Optional per-call stage timings, measured with HIP events recorded on the
+ * call's stream around every launch of the named stage. */
+typedef struct {
+    double kblock_ms;        /* kernel-block product + map + r partials + Gram    */
+    int64_t kblock_launches;
+    double finish_ms;        /* partial reduction of r, K-RR block inverses        */
+    int64_t finish_launches;
+    double recur_ms;         /* s-step recurrence + scatter                         */
+    int64_t recur_launches;
+    double total_ms;         /* first to last event of the solve                   */
+} kdcd_profile;
+
+enum {
+    KDCD_FLAG_GRAPH = 1      /* replay the outer iterations from a captured hipGraph */
+};
+
+typedef struct {
+    int32_t compute;         /* kdcd_compute; default KDCD_F64                               */
+    int32_t loss;            /* K-SVM: 1 = hinge (K-SVM-L1, default), 2 = squared hinge (L2) */
+    int32_t snapshot_every;  /* > 0: copy alpha after every this many outer iterations       */
+    int32_t flags;           /* KDCD_FLAG_*                                                  */
+    double *snapshots;       /* device, (ceil(ceil(H/s)/snapshot_every)) x m, row-major       */
+    double *trace;           /* device, H*b: theta (K-SVM) / Delta alpha (K-RR) per update    */
+    void *workspace;         /* device; NULL = allocated on `stream` and freed before return  */
+    size_t workspace_bytes;
+    kdcd_profile *profile;   /* host; NULL = no timing                                      */
+} kdcd_options;
+
+/*
+ * kdcd_ksvm_solve -- s-step DCD for K-SVM-L1/L2 (Algorithm 2; s = 1 is
+ * Algorithm 1).  The dual Hessian is Q_pq = y_p y_q K(a_p, a_q) (Sec. 3.1).
+ *   A       device matrix (dense or CSR), m x n
+ *   y       device, m labels, each exactly +1 or -1
+ *   kernel  host, kernel function
+ *   C       > 0; hinge: box [0, C]; squared hinge: nu = inf, omega = 1/(2C)
+ *   b       must be 1 (DCD updates one coordinate per inner step)
+ *   s       >= 1 inner steps per outer iteration (s*b <= 1024)
+ *   H       >= 1 inner steps in total; the last outer iteration holds
+ *           H - s*floor(H/s) of them
+ *   idx     device, H coordinates in [0, m); duplicates allowed anywhere
+ *   alpha   device, m: alpha_0 on entry (0 <= alpha_0 <= nu), alpha_H on exit
+ *   opt     host, may be NULL (defaults)
+ * Errors: INVALID_ARG (host checks), UNSUPPORTED, INDEX_RANGE, NONFINITE
+ * (y not +-1 or non-finite, alpha_0 outside the box, or a non-finite update),
+ * HIP, ALLOC, WORKSPACE.
+ */
+kdcd_status kdcd_ksvm_solve(const kdcd_matrix *A, const double *y, const kdcd_kernel *kernel,
+                            double C, int32_t b, int32_t s, int64_t H, const int32_t *idx,
+                            double *alpha, const kdcd_options *opt, kdcd_stream stream);
+
+/*
+ * kdcd_krr_solve -- s-step BDCD for K-RR (Algorithm 4 / Eq. (3); s = 1 is
+ * Algorithm 3).  Minimises 1/2 a^T (K/lambda + m I) a - y^T a, so the fixed
+ * point is alpha* = (K/lambda + m I)^{-1} y = lambda (K + m lambda I)^{-1} y.
+ *   A, kernel as above; y device, m finite targets
+ *   lambda  > 0 (the paper's lambda)
+ *   b       1 <= b <= 32 coordinates per block, b <= m
+ *   s       >= 1 blocks per outer iteration (s*b <= 1024)
+ *   H       >= 1 block updates in total
+ *   idx     device, H*b coordinates, block-major; every block holds b distinct
+ *           coordinates, different blocks may overlap
+ *   alpha   device, m: alpha_0 on entry, alpha_H on exit
+ * Errors: INVALID_ARG, UNSUPPORTED, INDEX_RANGE, INDEX_DUPLICATE, NOT_SPD,
+ * NONFINITE, HIP, ALLOC, WORKSPACE.
+ */
+kdcd_status kdcd_krr_solve(const kdcd_matrix *A, const double *y, const kdcd_kernel *kernel,
+                           double lambda, int32_t b, int32_t s, int64_t H, const int32_t *idx,
+                           double *alpha, const kdcd_options *opt, kdcd_stream stream);
+
+/*
+ * kdcd_kernel_rhs -- one kernel-block pass on its own (steps 2-5 above):
+ *   r[j] = sum_p K(a_p, a_{S_j}) * beta[p] * (beta_scale ? beta_scale[p] : 1)
+ *   W[t*sb + j] = K(a_{S_t}, a_{S_j})              (only if W != NULL)
+ * This is the quantity U_k^T alpha (K-RR) / U_k^T (y o alpha) (K-SVM) of
+ * Algorithms 2 and 4 together with V_k^T U_k.
+ *   S        device, sb indices in [0, m); 1 <= sb <= 1024
+ *   beta     device, m;  beta_scale device, m or NULL
+ *   r        device, sb outputs;  W device, sb*sb outputs or NULL
+ *   compute  kdcd_compute of the product (DENSE only for non-F64)
+ * Synchronises `stream`.  Errors: INVALID_ARG, UNSUPPORTED, INDEX_RANGE, HIP, ALLOC.
+ */
+kdcd_status kdcd_kernel_rhs(const kdcd_matrix *A, const kdcd_kernel *kernel, const int32_t *S,
+                            int32_t sb, const double *beta, const double *beta_scale, double *r,
+                            double *W, int32_t compute, kdcd_stream stream);
+
+/*
+ * kdcd_ksvm_eval / kdcd_krr_eval -- matrix-free FP64 evaluation on the
+ * device (measurement only; m^2 kernel evaluations).
+ *   ksvm: out[0] = f(alpha) = 1/2 a^T Q a - 1^T a (+ ||a||^2/(4C) for loss 2)
+ *         out[1] = primal P(alpha) = 1/2 a^T Q a + C sum max(0, 1-(Qa)_i) (squared for loss 2)
+ *         out[2] = duality gap P + f;  out[3] = max |projected gradient|
+ *   krr:  out[0] = f(alpha) = 1/2 a^T (K/lambda + m I) a - y^T a
+ *         out[1] = ||y - (K/lambda + m I) alpha||_2
+ *   out is host memory (4 resp. 2 doubles).  Synchronises `stream`.
+ */
+kdcd_status kdcd_ksvm_eval(const kdcd_matrix *A, const double *y, const kdcd_kernel *kernel,
+                           double C, int32_t loss, const double *alpha, double *out,
+                           kdcd_stream stream);
+kdcd_status kdcd_krr_eval(const kdcd_matrix *A, const double *y, const kdcd_kernel *kernel,
+                          double lambda, const double *alpha, double *out, kdcd_stream stream);
+
+/* Device workspace a solve needs (problem: 0 = K-SVM, 1 = K-RR). */
+size_t kdcd_workspace_bytes(int32_t problem, const kdcd_matrix *A, const kdcd_kernel *kernel,
+                            int32_t b, int32_t s, int32_t compute);
+
+/* Static, human-readable text for a status code. */
+const char *kdcd_status_string(kdcd_status status);
+
+/* Library version string, e.g. "kdcd 0.1.0 gfx950". */
+const char *kdcd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KDCD_H */

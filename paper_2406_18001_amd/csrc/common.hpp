@@ -1,0 +1,139 @@
+// Internal declarations shared by the kdcd HIP sources (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+#include "kdcd.h"
+
+namespace kdcd {
+
+constexpr int kMaxSB = 1024;   // s*b limit: one recurrence workgroup holds a whole S_k
+constexpr int kMaxB = 32;      // K-RR block size limit (block inverses live in LDS)
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// Kernel parameters as the device sees them.
+struct KParams {
+    int32_t kind;
+    int32_t degree;
+    double sigma;
+    double c;
+};
+
+// Device status word: the first error code written wins.
+__device__ inline void set_status(int32_t *status, int32_t code)
+{
+    if (status) atomicCAS(status, 0, code);
+}
+
+// Table 1 map applied to one inner product P = a_p . a_q.
+//   na, nb: ||a_p||^2 and ||a_q||^2 (RBF only); same: p and q are the same
+//   row, so the distance is exactly zero.
+template <int KIND>
+__device__ __forceinline__ double kernel_map(double P, double na, double nb, bool same,
+                                             const KParams &kp)
+{
+    if constexpr (KIND == KDCD_KERNEL_LINEAR) {
+        return P;
+    } else if constexpr (KIND == KDCD_KERNEL_POLY) {
+        double base = kp.c + P, r = base;
+        for (int t = 1; t < kp.degree; ++t) r *= base;
+        return r;
+    } else {
+        double d2 = same ? 0.0 : fmax(na + nb - 2.0 * P, 0.0);
+        return exp(-kp.sigma * d2);
+    }
+}
+
+template <int KIND>
+__device__ __forceinline__ float kernel_map_f32(float P, float na, float nb, bool same,
+                                                const KParams &kp)
+{
+    if constexpr (KIND == KDCD_KERNEL_LINEAR) {
+        return P;
+    } else if constexpr (KIND == KDCD_KERNEL_POLY) {
+        float base = (float)kp.c + P, r = base;
+        for (int t = 1; t < kp.degree; ++t) r *= base;
+        return r;
+    } else {
+        float d2 = same ? 0.0f : fmaxf(na + nb - 2.0f * P, 0.0f);
+        return expf(-(float)kp.sigma * d2);
+    }
+}
+
+// Workgroup barrier that orders LDS only: outstanding global loads stay in
+// flight across it (a plain __syncthreads() also waits for every global load).
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Orders LDS accesses of one wave (its lanes exchange values through LDS).
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
+__device__ __forceinline__ double wave_sum_xor16_32(double v)
+{
+    v += __shfl_xor(v, 16);
+    v += __shfl_xor(v, 32);
+    return v;
+}
+
+// ------------------------------------------------------------------ host side
+
+#define KDCD_HIP_TRY(expr)                                   \
+    do {                                                     \
+        hipError_t e_ = (expr);                              \
+        if (e_ != hipSuccess) return KDCD_ERR_HIP;           \
+    } while (0)
+
+// Arguments of one kernel-block launch (dense or CSR, any compute type).
+struct KBlockArgs {
+    const kdcd_matrix *A;
+    const void *Alow;        // low-precision copy of A (F32/BF16/F16), or hi part (BF16X3)
+    const void *Alow2;       // lo part (BF16X3)
+    int64_t ldlow;           // leading dimension of the low-precision copies
+    const float *normlow;    // row norms of the rounded data (mixed RBF)
+    const int32_t *S;        // sb sampled rows
+    int32_t sb;
+    const double *norms;     // m row norms ||a_p||^2 (RBF), FP64
+    KParams kp;
+    const double *beta;      // m
+    const double *beta_scale;// m or nullptr
+    double *partial;         // [n_row_groups][sb]
+    double *W;               // sb x sb or nullptr
+    int32_t *status;
+    int32_t compute;
+};
+
+// Launchers (return hipError_t of the launch).
+int64_t kblock_f64_row_groups(int64_t m, int32_t sb);
+hipError_t launch_kblock_f64(const KBlockArgs &a, hipStream_t st);
+hipError_t launch_norms(const kdcd_matrix *A, double *norms, hipStream_t st);
+hipError_t launch_finish(const double *partial, int64_t groups, int32_t sb, double *r,
+                         const double *W, int32_t b, int32_t s_blocks, double inv_lambda,
+                         double mdbl, double *Dinv, int32_t *status, hipStream_t st);
+hipError_t launch_ksvm_recur(const double *r, const double *W, const int32_t *S, int32_t sb,
+                             int64_t m, const double *y, double *alpha, double nu, double omega,
+                             double *trace, int32_t *status, hipStream_t st);
+hipError_t launch_krr_recur(const double *r, const double *W, const double *Dinv,
+                            const int32_t *S, int32_t b, int32_t sk, int64_t m, const double *y,
+                            double *alpha, double lambda, double mdbl, double *trace,
+                            int32_t *status, hipStream_t st);
+hipError_t launch_validate(const int32_t *idx, int64_t count, int64_t m, const double *y,
+                           const double *alpha, int64_t mrows, int32_t problem, double nu,
+                           int32_t *status, hipStream_t st);
+hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t count, hipStream_t st);
+hipError_t launch_iota_i32(int32_t *p, int64_t count, hipStream_t st);
+
+}  // namespace kdcd

@@ -1,0 +1,184 @@
+// Support kernels around the kernel-block product:
+//   - row norms ||a_p||^2 (once per solve, RBF only);
+//   - input validation (index range, labels, box feasibility, finiteness);
+//   - the finish pass of every outer iteration: the deterministic reduction
+//     of the per-row-group partials into r, and, for K-RR, the inverses of
+//     the s diagonal block matrices G_j = W_jj / lambda + m I of Algorithm 4.
+#include "common.hpp"
+
+namespace kdcd {
+namespace {
+
+// One wave per row; lanes stride over the row (dense) or its stored entries (CSR).
+__global__ __launch_bounds__(256) void norms_kernel(const double *__restrict__ vals,
+                                                    const int64_t *__restrict__ row_ptr,
+                                                    int64_t m, int64_t n, int64_t ld,
+                                                    double *__restrict__ norms)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= m) return;
+    double s = 0.0;
+    if (row_ptr) {
+        for (int64_t e = row_ptr[row] + lane; e < row_ptr[row + 1]; e += 64) s += vals[e] * vals[e];
+    } else {
+        const double *x = vals + row * ld;
+        for (int64_t k = lane; k < n; k += 64) s += x[k] * x[k];
+    }
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (lane == 0) norms[row] = s;
+}
+
+// problem 0 (K-SVM): y in {-1,+1}, 0 <= alpha <= nu; problem 1 (K-RR): finite y, alpha.
+__global__ __launch_bounds__(256) void validate_kernel(const int32_t *__restrict__ idx,
+                                                       int64_t count, int64_t m,
+                                                       const double *__restrict__ y,
+                                                       const double *__restrict__ alpha,
+                                                       int64_t mrows, int32_t problem, double nu,
+                                                       int32_t *status)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = i; t < count; t += stride) {
+        const int32_t v = idx[t];
+        if (v < 0 || v >= m) set_status(status, KDCD_ERR_INDEX_RANGE);
+    }
+    for (int64_t p = i; p < mrows; p += stride) {
+        const double yv = y[p], av = alpha[p];
+        if (!isfinite(yv) || !isfinite(av)) set_status(status, KDCD_ERR_NONFINITE);
+        if (problem == 0) {
+            if (yv != 1.0 && yv != -1.0) set_status(status, KDCD_ERR_INVALID_ARG);
+            if (!(av >= 0.0 && av <= nu)) set_status(status, KDCD_ERR_INVALID_ARG);
+        }
+    }
+}
+
+__global__ void fill_i32_kernel(int32_t *p, int32_t v, int64_t count)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = v;
+}
+
+__global__ void iota_i32_kernel(int32_t *p, int64_t count)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = (int32_t)i;
+}
+
+constexpr int FIN_COLS = 16;    // columns per reduction workgroup
+constexpr int FIN_PARTS = 16;   // row-group partitions per column
+
+// Blocks [0, ceil(sb/16)) reduce r; blocks after that invert one K-RR diagonal
+// block each (Gauss-Jordan without pivoting, valid for SPD matrices).
+__global__ __launch_bounds__(256) void finish_kernel(const double *__restrict__ partial,
+                                                     int64_t groups, int32_t sb,
+                                                     double *__restrict__ r,
+                                                     const double *__restrict__ W, int32_t b,
+                                                     int32_t s_blocks, double inv_lambda,
+                                                     double mdbl, double *__restrict__ Dinv,
+                                                     int32_t *status)
+{
+    __shared__ double sh[kMaxB * kMaxB];
+    const int tid = threadIdx.x;
+    const int n_red = (sb + FIN_COLS - 1) / FIN_COLS;
+    if ((int)blockIdx.x < n_red) {
+        const int c = tid % FIN_COLS, part = tid / FIN_COLS;
+        const int64_t col = (int64_t)blockIdx.x * FIN_COLS + c;
+        double s = 0.0;
+        if (col < sb)
+            for (int64_t g = part; g < groups; g += FIN_PARTS) s += partial[g * sb + col];
+        sh[part * FIN_COLS + c] = s;
+        __syncthreads();
+        if (part == 0 && col < sb) {
+            double t = 0.0;
+            for (int p = 0; p < FIN_PARTS; ++p) t += sh[p * FIN_COLS + c];
+            r[col] = t;
+        }
+        return;
+    }
+    const int j = (int)blockIdx.x - n_red;
+    if (j >= s_blocks) return;
+    const int bb = b * b;
+    const int64_t base = (int64_t)j * b;
+    for (int e = tid; e < bb; e += blockDim.x) {
+        const int l = e / b, q = e % b;
+        sh[e] = W[(base + l) * sb + base + q] * inv_lambda + (l == q ? mdbl : 0.0);
+    }
+    __syncthreads();
+    bool bad = false;
+    for (int k = 0; k < b; ++k) {
+        const double piv = sh[k * b + k];
+        if (!(piv > 0.0) || !isfinite(piv)) bad = true;
+        const double pinv = 1.0 / piv;
+        // every thread reads what it needs of row k and column k before anyone writes
+        double rowk[kMaxB * kMaxB / 256 + 1], colk[kMaxB * kMaxB / 256 + 1];
+        int cnt = 0;
+        for (int e = tid; e < bb; e += blockDim.x, ++cnt) {
+            const int l = e / b, q = e % b;
+            rowk[cnt] = (q == k) ? 1.0 : sh[k * b + q];
+            colk[cnt] = sh[l * b + k];
+        }
+        __syncthreads();
+        cnt = 0;
+        for (int e = tid; e < bb; e += blockDim.x, ++cnt) {
+            const int l = e / b, q = e % b;
+            const double nk = rowk[cnt] * pinv;           // new row-k entry in column q
+            if (l == k) sh[e] = nk;
+            else sh[e] = ((q == k) ? 0.0 : sh[e]) - nk * colk[cnt];
+        }
+        __syncthreads();
+    }
+    if (bad && tid == 0) set_status(status, KDCD_ERR_NOT_SPD);
+    for (int e = tid; e < bb; e += blockDim.x) Dinv[(int64_t)j * bb + e] = sh[e];
+}
+
+}  // namespace
+
+hipError_t launch_norms(const kdcd_matrix *A, double *norms, hipStream_t st)
+{
+    const unsigned blocks = (unsigned)((A->m + 3) / 4);
+    const bool csr = A->format == KDCD_CSR;
+    hipLaunchKernelGGL(norms_kernel, dim3(blocks), dim3(256), 0, st, A->values,
+                       csr ? A->row_ptr : nullptr, A->m, A->n, A->ld, norms);
+    return hipGetLastError();
+}
+
+hipError_t launch_validate(const int32_t *idx, int64_t count, int64_t m, const double *y,
+                           const double *alpha, int64_t mrows, int32_t problem, double nu,
+                           int32_t *status, hipStream_t st)
+{
+    const int64_t work = count > mrows ? count : mrows;
+    int64_t blocks = (work + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(validate_kernel, dim3((unsigned)blocks), dim3(256), 0, st, idx, count, m,
+                       y, alpha, mrows, problem, nu, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t count, hipStream_t st)
+{
+    hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st,
+                       p, v, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_iota_i32(int32_t *p, int64_t count, hipStream_t st)
+{
+    hipLaunchKernelGGL(iota_i32_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, p,
+                       count);
+    return hipGetLastError();
+}
+
+hipError_t launch_finish(const double *partial, int64_t groups, int32_t sb, double *r,
+                         const double *W, int32_t b, int32_t s_blocks, double inv_lambda,
+                         double mdbl, double *Dinv, int32_t *status, hipStream_t st)
+{
+    const int n_red = (sb + FIN_COLS - 1) / FIN_COLS;
+    const int n_inv = Dinv ? s_blocks : 0;
+    hipLaunchKernelGGL(finish_kernel, dim3(n_red + n_inv), dim3(256), 0, st, partial, groups, sb,
+                       r, W, b, n_inv, inv_lambda, mdbl, Dinv, status);
+    return hipGetLastError();
+}
+
+}  // namespace kdcd

@@ -1,0 +1,315 @@
+// Dense FP64 kernel block on gfx950 MFMA (v_mfma_f64_16x16x4f64).
+//
+// One launch computes, for the index block S (sb sampled rows):
+//   U-tiles:  P = A A_S^T (m x sb), the Table 1 map K = map(P) in the
+//             epilogue, and the column sums partial[g][j] = sum_{p in group g}
+//             K(a_p, a_{S_j}) beta_p -- the right-hand side U^T beta of
+//             Algorithms 2 and 4 -- without ever writing U;
+//   W-tiles:  W = K(A_S, A_S) (sb x sb), the sampled Gram V^T U.
+// Both read the sampled rows straight from A through S (no gather pass).
+//
+// Tiling: a workgroup of WM x WN waves owns a BM x BN tile; each wave owns
+// TM x TN MFMA blocks of 16 x 16.  K is walked in chunks of 16 doubles that
+// are staged through LDS in "fragment-major" order, so every MFMA operand
+// fetch is one contiguous 512-byte ds_read_b64 per wave.  Inside a chunk,
+// MFMA step ks uses k = 4*(lane/16) + ks for both operands; any bijection of
+// k works as long as A and B agree, and this one makes a thread's 4 doubles
+// of a row contiguous in global memory.
+#include "common.hpp"
+
+namespace kdcd {
+namespace {
+
+constexpr int BK = 16;
+
+__device__ __forceinline__ int64_t clampi(int64_t v, int64_t lo, int64_t hi)
+{
+    return v < lo ? lo : (v > hi ? hi : v);
+}
+
+// Logical tile id from the hardware block id: consecutive logical ids land
+// on the same XCD (workgroups are dealt round-robin over the 8 XCDs), so the
+// column tiles that share one row group of A share that XCD's L2.
+__device__ __forceinline__ int xcd_remap(int bid, int total)
+{
+    const int per = total / 8, rem = total % 8;
+    const int x = bid % 8, w = bid / 8;
+    return x < rem ? x * (per + 1) + w : rem * (per + 1) + (x - rem) * per + w;
+}
+
+template <int WM, int WN, int TM, int TN, int KIND>
+__global__ __launch_bounds__(64 * WM * WN) void kblock_f64_kernel(
+    const double *__restrict__ A, int64_t lda, int64_t m, int64_t n,
+    const int32_t *__restrict__ S, int32_t sb, const double *__restrict__ norms, KParams kp,
+    const double *__restrict__ beta, const double *__restrict__ bscale,
+    double *__restrict__ partial, double *__restrict__ W, int32_t n_u_tiles,
+    int32_t n_row_groups, int32_t n_w_tiles, int32_t n_tiles_n, int32_t aligned)
+{
+    constexpr int NT = 64 * WM * WN;
+    constexpr int BM = 16 * TM * WM;
+    constexpr int BN = 16 * TN * WN;
+    constexpr int SEGA = (BM * 4 + NT - 1) / NT;
+    constexpr int SEGB = (BN * 4 + NT - 1) / NT;
+
+    __shared__ double As[2][BM * BK];
+    __shared__ double Bs[2][BN * BK];
+    __shared__ double red[WM][BN];
+
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int wm = wid / WN, wn = wid % WN;
+    const int total = n_tiles_n * (n_row_groups + n_w_tiles);
+    const int L = xcd_remap(blockIdx.x, total);
+    const int cn = L % n_tiles_n;
+    const int rg = L / n_tiles_n;
+    const bool is_w = rg >= n_row_groups;
+    if (is_w && W == nullptr) return;
+    const int col0 = cn * BN;
+
+    // sampled rows feeding the B operand (clamped so that every load is in bounds)
+    const double *bptr[SEGB];
+#pragma unroll
+    for (int i = 0; i < SEGB; ++i) {
+        const int seg = tid + i * NT;
+        const int r = (seg < BN * 4) ? (seg >> 2) : 0;
+        const int c = seg & 3;
+        const int64_t j = clampi(col0 + r, 0, sb - 1);
+        const int64_t row = clampi(S[j], 0, m - 1);
+        bptr[i] = A + row * lda + 4 * c;
+    }
+    // per-lane output columns of this wave
+    int64_t Sc[TN];
+    double nb[TN];
+    bool colok[TN];
+#pragma unroll
+    for (int tn = 0; tn < TN; ++tn) {
+        const int64_t gcol = col0 + (wn * TN + tn) * 16 + (lane & 15);
+        colok[tn] = gcol < sb;
+        Sc[tn] = clampi(S[clampi(gcol, 0, sb - 1)], 0, m - 1);
+        nb[tn] = (KIND == KDCD_KERNEL_RBF) ? norms[Sc[tn]] : 0.0;
+    }
+
+    double colsum[TN];
+#pragma unroll
+    for (int tn = 0; tn < TN; ++tn) colsum[tn] = 0.0;
+
+    const int rt_first = is_w ? rg - n_row_groups : rg;
+    const int rt_end = is_w ? rt_first + 1 : n_u_tiles;
+    const int rt_step = is_w ? 1 : n_row_groups;
+    const int64_t nK = (n + BK - 1) / BK;
+
+    for (int rt = rt_first; rt < rt_end; rt += rt_step) {
+        const int64_t row0 = (int64_t)rt * BM;
+        const double *aptr[SEGA];
+#pragma unroll
+        for (int i = 0; i < SEGA; ++i) {
+            const int seg = tid + i * NT;
+            const int r = (seg < BM * 4) ? (seg >> 2) : 0;
+            const int c = seg & 3;
+            int64_t row;
+            if (is_w) row = clampi(S[clampi(row0 + r, 0, sb - 1)], 0, m - 1);
+            else row = clampi(row0 + r, 0, m - 1);
+            aptr[i] = A + row * lda + 4 * c;
+        }
+
+        d4 acc[TM][TN];
+#pragma unroll
+        for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+            for (int tn = 0; tn < TN; ++tn) acc[tm][tn] = d4{0.0, 0.0, 0.0, 0.0};
+
+        // Two register stages: while chunk kc is multiplied out of one LDS buffer,
+        // chunk kc+1 waits in registers for its turn to be stored into the other
+        // buffer and chunk kc+2 is already in flight from memory.
+        double ra0[SEGA][4], rb0[SEGB][4], ra1[SEGA][4], rb1[SEGB][4];
+        auto load = [&](int64_t kc, double (&ra)[SEGA][4], double (&rb)[SEGB][4]) {
+            const int64_t k0 = kc * BK;
+#pragma unroll
+            for (int i = 0; i < SEGA; ++i) {
+                const int seg = tid + i * NT;
+                const int64_t kk = k0 + 4 * (seg & 3);
+                if (aligned && kk + 4 <= n) {
+                    const d2 *p = reinterpret_cast<const d2 *>(aptr[i] + k0);
+                    d2 x = p[0], y = p[1];
+                    ra[i][0] = x[0]; ra[i][1] = x[1]; ra[i][2] = y[0]; ra[i][3] = y[1];
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) ra[i][e] = (kk + e < n) ? aptr[i][k0 + e] : 0.0;
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < SEGB; ++i) {
+                const int seg = tid + i * NT;
+                const int64_t kk = k0 + 4 * (seg & 3);
+                if (aligned && kk + 4 <= n) {
+                    const d2 *p = reinterpret_cast<const d2 *>(bptr[i] + k0);
+                    d2 x = p[0], y = p[1];
+                    rb[i][0] = x[0]; rb[i][1] = x[1]; rb[i][2] = y[0]; rb[i][3] = y[1];
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) rb[i][e] = (kk + e < n) ? bptr[i][k0 + e] : 0.0;
+                }
+            }
+        };
+        auto store = [&](int buf, const double (&ra)[SEGA][4], const double (&rb)[SEGB][4]) {
+#pragma unroll
+            for (int i = 0; i < SEGA; ++i) {
+                const int seg = tid + i * NT;
+                if (seg < BM * 4) {
+                    const int r = seg >> 2, c = seg & 3;
+                    double *dst = &As[buf][((r >> 4) * 16 + c) * 16 + (r & 15)];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) dst[e * 64] = ra[i][e];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < SEGB; ++i) {
+                const int seg = tid + i * NT;
+                if (seg < BN * 4) {
+                    const int r = seg >> 2, c = seg & 3;
+                    double *dst = &Bs[buf][((r >> 4) * 16 + c) * 16 + (r & 15)];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) dst[e * 64] = rb[i][e];
+                }
+            }
+        };
+        auto compute = [&](int buf) {
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) {
+                double a[TM], b[TN];
+#pragma unroll
+                for (int tm = 0; tm < TM; ++tm) a[tm] = As[buf][((wm * TM + tm) * 4 + ks) * 64 + lane];
+#pragma unroll
+                for (int tn = 0; tn < TN; ++tn) b[tn] = Bs[buf][((wn * TN + tn) * 4 + ks) * 64 + lane];
+#pragma unroll
+                for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+                    for (int tn = 0; tn < TN; ++tn)
+                        acc[tm][tn] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[tm], b[tn], acc[tm][tn], 0, 0, 0);
+            }
+        };
+
+        load(0, ra0, rb0);
+        if (nK > 1) load(1, ra1, rb1);
+        store(0, ra0, rb0);
+        lds_barrier();
+        for (int64_t kc = 0; kc < nK; kc += 2) {
+            if (kc + 2 < nK) load(kc + 2, ra0, rb0);
+            compute(0);
+            if (kc + 1 < nK) store(1, ra1, rb1);
+            lds_barrier();
+            if (kc + 1 >= nK) break;
+            if (kc + 3 < nK) load(kc + 3, ra1, rb1);
+            compute(1);
+            if (kc + 2 < nK) store(0, ra0, rb0);
+            lds_barrier();
+        }
+
+        // epilogue: item v of MFMA output lane l is row (l/16) + 4v, column l%16 of its block
+#pragma unroll
+        for (int tm = 0; tm < TM; ++tm) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t lrow = (wm * TM + tm) * 16 + (lane >> 4) + 4 * v;
+                const int64_t grow = row0 + lrow;
+                if (!is_w) {
+                    if (grow < m) {
+                        double bval = beta[grow];
+                        if (bscale) bval *= bscale[grow];
+                        const double na = (KIND == KDCD_KERNEL_RBF) ? norms[grow] : 0.0;
+#pragma unroll
+                        for (int tn = 0; tn < TN; ++tn)
+                            if (colok[tn])
+                                colsum[tn] += bval * kernel_map<KIND>(acc[tm][tn][v], na, nb[tn],
+                                                                      grow == Sc[tn], kp);
+                    }
+                } else if (grow < sb) {
+                    const int64_t St = clampi(S[grow], 0, m - 1);
+                    const double na = (KIND == KDCD_KERNEL_RBF) ? norms[St] : 0.0;
+#pragma unroll
+                    for (int tn = 0; tn < TN; ++tn) {
+                        const int64_t gcol = col0 + (wn * TN + tn) * 16 + (lane & 15);
+                        if (colok[tn])
+                            W[grow * sb + gcol] = kernel_map<KIND>(acc[tm][tn][v], na, nb[tn],
+                                                                   St == Sc[tn], kp);
+                    }
+                }
+            }
+        }
+    }
+    if (is_w) return;
+
+    // deterministic column reduction: lanes -> waves -> one partial row per group
+#pragma unroll
+    for (int tn = 0; tn < TN; ++tn) {
+        const double v = wave_sum_xor16_32(colsum[tn]);
+        if (lane < 16) red[wm][(wn * TN + tn) * 16 + lane] = v;
+    }
+    __syncthreads();
+    for (int c = tid; c < BN; c += NT) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < WM; ++w) s += red[w][c];
+        if (col0 + c < sb) partial[(int64_t)rg * sb + col0 + c] = s;
+    }
+}
+
+struct Cfg {
+    int bm, bn;
+};
+
+// Tile shape per width of the index block.
+Cfg pick_cfg(int32_t sb)
+{
+    if (sb <= 16) return {128, 16};
+    if (sb <= 32) return {128, 32};
+    if (sb <= 64) return {64, 64};
+    return {64, 128};
+}
+
+constexpr int64_t kMaxRowGroups = 1024;
+
+template <int WM, int WN, int TM, int TN>
+hipError_t launch_cfg(const KBlockArgs &a, hipStream_t st)
+{
+    constexpr int BM = 16 * TM * WM, BN = 16 * TN * WN;
+    const kdcd_matrix *A = a.A;
+    const int64_t n_u = (A->m + BM - 1) / BM;
+    const int64_t groups = n_u < kMaxRowGroups ? n_u : kMaxRowGroups;
+    const int64_t n_w = a.W ? (a.sb + BM - 1) / BM : 0;
+    const int64_t n_n = (a.sb + BN - 1) / BN;
+    const int64_t blocks = n_n * (groups + n_w);
+    const int aligned = (A->ld % 2 == 0) && ((reinterpret_cast<uintptr_t>(A->values) & 15) == 0);
+    dim3 grid((unsigned)blocks), block(64 * WM * WN);
+#define KDCD_LAUNCH(KIND)                                                                      \
+    hipLaunchKernelGGL((kblock_f64_kernel<WM, WN, TM, TN, KIND>), grid, block, 0, st,          \
+                       A->values, A->ld, A->m, A->n, a.S, a.sb, a.norms, a.kp, a.beta,          \
+                       a.beta_scale, a.partial, a.W, (int32_t)n_u, (int32_t)groups,            \
+                       (int32_t)n_w, (int32_t)n_n, aligned)
+    switch (a.kp.kind) {
+    case KDCD_KERNEL_LINEAR: KDCD_LAUNCH(KDCD_KERNEL_LINEAR); break;
+    case KDCD_KERNEL_POLY: KDCD_LAUNCH(KDCD_KERNEL_POLY); break;
+    default: KDCD_LAUNCH(KDCD_KERNEL_RBF); break;
+    }
+#undef KDCD_LAUNCH
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int64_t kblock_f64_row_groups(int64_t m, int32_t sb)
+{
+    const Cfg c = pick_cfg(sb);
+    const int64_t n_u = (m + c.bm - 1) / c.bm;
+    return n_u < kMaxRowGroups ? n_u : kMaxRowGroups;
+}
+
+hipError_t launch_kblock_f64(const KBlockArgs &a, hipStream_t st)
+{
+    const Cfg c = pick_cfg(a.sb);
+    if (c.bn == 16) return launch_cfg<4, 1, 2, 1>(a, st);
+    if (c.bn == 32) return launch_cfg<4, 1, 2, 2>(a, st);
+    if (c.bn == 64) return launch_cfg<2, 2, 2, 2>(a, st);
+    return launch_cfg<2, 2, 2, 4>(a, st);
+}
+
+}  // namespace kdcd

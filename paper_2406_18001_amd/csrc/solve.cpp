@@ -1,0 +1,562 @@
+// Host driver of the kdcd C-ABI: argument validation, workspace, the outer
+// loop of Algorithms 2 and 4 (kernel block -> finish -> recurrence per outer
+// iteration), status reporting and optional stage timing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "common.hpp"
+
+using namespace kdcd;
+
+namespace kdcd {
+hipError_t launch_kblock_mixed(const KBlockArgs &a, hipStream_t st);
+int64_t kblock_mixed_row_groups(int64_t m, int32_t sb);
+hipError_t launch_kblock_csr(const KBlockArgs &a, hipStream_t st);
+int64_t kblock_csr_row_groups(int64_t m, int32_t sb);
+hipError_t launch_convert_lowp(const kdcd_matrix *A, int32_t compute, void *hi, void *lo,
+                               int64_t ldlow, float *normlow, hipStream_t st);
+int krr_recur_threads(int32_t b, int32_t sk);
+}  // namespace kdcd
+
+namespace {
+
+constexpr int64_t kMaxGroups = 1024;   // upper bound on row groups of any kernel-block launch
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+kdcd_status check_matrix(const kdcd_matrix *A)
+{
+    if (!A || !A->values || A->m < 1 || A->n < 1) return KDCD_ERR_INVALID_ARG;
+    if (A->m > INT32_MAX) return KDCD_ERR_UNSUPPORTED;
+    if (A->format == KDCD_DENSE) {
+        if (A->ld < A->n) return KDCD_ERR_INVALID_ARG;
+    } else if (A->format == KDCD_CSR) {
+        if (!A->row_ptr || !A->col_idx || A->nnz < 0 || A->n > INT32_MAX) return KDCD_ERR_INVALID_ARG;
+    } else {
+        return KDCD_ERR_INVALID_ARG;
+    }
+    return KDCD_OK;
+}
+
+kdcd_status check_kernel(const kdcd_kernel *k)
+{
+    if (!k) return KDCD_ERR_INVALID_ARG;
+    switch (k->kind) {
+    case KDCD_KERNEL_LINEAR: return KDCD_OK;
+    case KDCD_KERNEL_POLY:
+        return (std::isfinite(k->c) && k->c >= 0.0 && k->degree >= 1 && k->degree <= 64)
+                   ? KDCD_OK : KDCD_ERR_INVALID_ARG;
+    case KDCD_KERNEL_RBF: return finite_pos(k->sigma) ? KDCD_OK : KDCD_ERR_INVALID_ARG;
+    default: return KDCD_ERR_INVALID_ARG;
+    }
+}
+
+kdcd_status check_compute(const kdcd_matrix *A, int32_t compute)
+{
+    if (compute < KDCD_F64 || compute > KDCD_BF16X3) return KDCD_ERR_INVALID_ARG;
+    if (compute != KDCD_F64 && A->format != KDCD_DENSE) return KDCD_ERR_UNSUPPORTED;
+    return KDCD_OK;
+}
+
+int64_t row_groups(const kdcd_matrix *A, int32_t sb, int32_t compute)
+{
+    if (A->format == KDCD_CSR) return kblock_csr_row_groups(A->m, sb);
+    if (compute == KDCD_F64) return kblock_f64_row_groups(A->m, sb);
+    return kblock_mixed_row_groups(A->m, sb);
+}
+
+hipError_t launch_kblock(const KBlockArgs &a, hipStream_t st)
+{
+    if (a.A->format == KDCD_CSR) return launch_kblock_csr(a, st);
+    if (a.compute == KDCD_F64) return launch_kblock_f64(a, st);
+    return launch_kblock_mixed(a, st);
+}
+
+size_t lowp_elem_bytes(int32_t compute) { return compute == KDCD_F32 ? 4 : 2; }
+
+// Workspace regions of one solve.
+struct Layout {
+    size_t status, norms, partial, r, W, Dinv, iota, hi, lo, normlow, total;
+    int64_t ldlow;
+};
+
+Layout make_layout(int32_t problem, const kdcd_matrix *A, const kdcd_kernel *kernel, int32_t b,
+                   int32_t s, int32_t compute)
+{
+    Layout L{};
+    const int64_t sb = (int64_t)s * b;
+    size_t off = 0;
+    L.status = off; off += 256;
+    L.norms = off; off += align256(sizeof(double) * (size_t)A->m);
+    L.partial = off; off += align256(sizeof(double) * (size_t)(kMaxGroups * sb));
+    L.r = off; off += align256(sizeof(double) * (size_t)sb);
+    L.W = off; off += align256(sizeof(double) * (size_t)(sb * sb));
+    L.Dinv = off; off += (problem == 1) ? align256(sizeof(double) * (size_t)(sb * b)) : 0;
+    L.iota = off; off += (problem == 2) ? align256(sizeof(int32_t) * (size_t)A->m) : 0;
+    L.ldlow = 0;
+    L.hi = L.lo = L.normlow = off;
+    if (compute != KDCD_F64) {
+        L.ldlow = (A->n + 31) / 32 * 32;   // pad K to whole MFMA chunks
+        const size_t bytes = align256(lowp_elem_bytes(compute) * (size_t)(A->m * L.ldlow));
+        L.hi = off; off += bytes;
+        L.lo = off; off += (compute == KDCD_BF16X3) ? bytes : 0;
+        L.normlow = off; off += align256(sizeof(float) * (size_t)A->m);
+    }
+    (void)kernel;
+    L.total = off;
+    return L;
+}
+
+// Device workspace: caller-provided or allocated on the stream.
+struct Workspace {
+    char *base = nullptr;
+    bool owned = false;
+    hipStream_t st = nullptr;
+    ~Workspace()
+    {
+        if (owned && base) {
+            (void)hipFreeAsync(base, st);
+            (void)hipStreamSynchronize(st);
+        }
+    }
+    template <class T> T *at(size_t off) const { return reinterpret_cast<T *>(base + off); }
+};
+
+kdcd_status acquire(Workspace &ws, const Layout &L, const kdcd_options *opt, hipStream_t st)
+{
+    ws.st = st;
+    if (opt && opt->workspace) {
+        if (opt->workspace_bytes < L.total) return KDCD_ERR_WORKSPACE;
+        if (reinterpret_cast<uintptr_t>(opt->workspace) & 255) return KDCD_ERR_INVALID_ARG;
+        ws.base = static_cast<char *>(opt->workspace);
+        return KDCD_OK;
+    }
+    void *p = nullptr;
+    if (hipMallocAsync(&p, L.total, st) != hipSuccess || !p) return KDCD_ERR_ALLOC;
+    ws.base = static_cast<char *>(p);
+    ws.owned = true;
+    return KDCD_OK;
+}
+
+// Event pairs around launches of one stage.
+struct StageTimer {
+    bool on = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[3];
+    hipEvent_t first = nullptr;   // alias of the first recorded event (owned by ev)
+    ~StageTimer()
+    {
+        for (auto &v : ev)
+            for (auto &p : v) { (void)hipEventDestroy(p.first); (void)hipEventDestroy(p.second); }
+    }
+    hipEvent_t mk()
+    {
+        hipEvent_t e = nullptr;
+        (void)hipEventCreate(&e);
+        return e;
+    }
+    void begin(int stage, hipStream_t st)
+    {
+        if (!on) return;
+        ev[stage].push_back({mk(), mk()});
+        (void)hipEventRecord(ev[stage].back().first, st);
+        if (!first) { first = ev[stage].back().first; }
+    }
+    void end(int stage, hipStream_t st)
+    {
+        if (!on) return;
+        (void)hipEventRecord(ev[stage].back().second, st);
+    }
+    void report(kdcd_profile *p)
+    {
+        if (!on || !p) return;
+        double ms[3] = {0, 0, 0};
+        for (int s = 0; s < 3; ++s)
+            for (auto &e : ev[s]) {
+                float t = 0.f;
+                (void)hipEventElapsedTime(&t, e.first, e.second);
+                ms[s] += t;
+            }
+        p->kblock_ms = ms[0]; p->kblock_launches = (int64_t)ev[0].size();
+        p->finish_ms = ms[1]; p->finish_launches = (int64_t)ev[1].size();
+        p->recur_ms = ms[2]; p->recur_launches = (int64_t)ev[2].size();
+        p->total_ms = 0.0;
+        hipEvent_t lastev = nullptr;
+        for (int s = 2; s >= 0 && !lastev; --s)
+            if (!ev[s].empty()) lastev = ev[s].back().second;
+        if (first && lastev) {
+            float t = 0.f;
+            (void)hipEventElapsedTime(&t, first, lastev);
+            p->total_ms = t;
+        }
+    }
+};
+
+kdcd_status read_status(int32_t *dstatus, hipStream_t st)
+{
+    int32_t hs = 0;
+    if (hipMemcpyAsync(&hs, dstatus, sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess)
+        return KDCD_ERR_HIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return KDCD_ERR_HIP;
+    return (kdcd_status)hs;
+}
+
+KParams to_params(const kdcd_kernel *k) { return KParams{k->kind, k->degree, k->sigma, k->c}; }
+
+struct SolveArgs {
+    int32_t problem;   // 0 = K-SVM, 1 = K-RR
+    const kdcd_matrix *A;
+    const double *y;
+    const kdcd_kernel *kernel;
+    double C, lambda;
+    int32_t b, s;
+    int64_t H;
+    const int32_t *idx;
+    double *alpha;
+    kdcd_options opt;
+    hipStream_t st;
+};
+
+kdcd_status prepare_lowp(const KBlockArgs &base, const Layout &L, Workspace &ws, hipStream_t st,
+                         KBlockArgs &a)
+{
+    a = base;
+    if (base.compute == KDCD_F64 || base.A->format != KDCD_DENSE) return KDCD_OK;
+    a.Alow = ws.at<void>(L.hi);
+    a.Alow2 = ws.at<void>(L.lo);
+    a.ldlow = L.ldlow;
+    a.normlow = ws.at<float>(L.normlow);
+    KDCD_HIP_TRY(launch_convert_lowp(base.A, base.compute, ws.at<void>(L.hi), ws.at<void>(L.lo),
+                                     L.ldlow, ws.at<float>(L.normlow), st));
+    return KDCD_OK;
+}
+
+kdcd_status run_solve(const SolveArgs &sa)
+{
+    const kdcd_matrix *A = sa.A;
+    const hipStream_t st = sa.st;
+    const Layout L = make_layout(sa.problem, A, sa.kernel, sa.b, sa.s, sa.opt.compute);
+    Workspace ws;
+    kdcd_status rc = acquire(ws, L, &sa.opt, st);
+    if (rc != KDCD_OK) return rc;
+    int32_t *status = ws.at<int32_t>(L.status);
+    double *norms = ws.at<double>(L.norms);
+    double *partial = ws.at<double>(L.partial);
+    double *r = ws.at<double>(L.r);
+    double *W = ws.at<double>(L.W);
+    double *Dinv = sa.problem == 1 ? ws.at<double>(L.Dinv) : nullptr;
+
+    const bool svm = sa.problem == 0;
+    const double nu = svm ? (sa.opt.loss == 2 ? INFINITY : sa.C) : 0.0;
+    const double omega = (svm && sa.opt.loss == 2) ? 1.0 / (2.0 * sa.C) : 0.0;
+
+    KDCD_HIP_TRY(launch_fill_i32(status, 0, 1, st));
+    KDCD_HIP_TRY(launch_validate(sa.idx, sa.H * sa.b, A->m, sa.y, sa.alpha, A->m, sa.problem, nu,
+                                 status, st));
+    if (sa.kernel->kind == KDCD_KERNEL_RBF) KDCD_HIP_TRY(launch_norms(A, norms, st));
+
+    KBlockArgs base{};
+    base.A = A;
+    base.norms = norms;
+    base.kp = to_params(sa.kernel);
+    base.beta = sa.alpha;
+    base.beta_scale = svm ? sa.y : nullptr;
+    base.partial = partial;
+    base.W = W;
+    base.status = status;
+    base.compute = sa.opt.compute;
+    KBlockArgs kb;
+    rc = prepare_lowp(base, L, ws, st, kb);
+    if (rc != KDCD_OK) return rc;
+
+    StageTimer timer;
+    timer.on = sa.opt.profile != nullptr;
+    const int64_t n_outer = (sa.H + sa.s - 1) / sa.s;
+    int64_t snap = 0;
+    for (int64_t k = 0; k < n_outer; ++k) {
+        const int64_t done = k * sa.s;
+        const int32_t sk = (int32_t)std::min<int64_t>(sa.s, sa.H - done);
+        const int32_t sb = sk * sa.b;
+        const int32_t *S = sa.idx + done * sa.b;
+        kb.S = S;
+        kb.sb = sb;
+        timer.begin(0, st);
+        KDCD_HIP_TRY(launch_kblock(kb, st));
+        timer.end(0, st);
+        timer.begin(1, st);
+        KDCD_HIP_TRY(launch_finish(partial, row_groups(A, sb, sa.opt.compute), sb, r, W, sa.b, sk,
+                                   svm ? 0.0 : 1.0 / sa.lambda, (double)A->m, Dinv, status, st));
+        timer.end(1, st);
+        timer.begin(2, st);
+        double *tr = sa.opt.trace ? sa.opt.trace + done * sa.b : nullptr;
+        if (svm)
+            KDCD_HIP_TRY(launch_ksvm_recur(r, W, S, sb, A->m, sa.y, sa.alpha, nu, omega, tr,
+                                           status, st));
+        else
+            KDCD_HIP_TRY(launch_krr_recur(r, W, Dinv, S, sa.b, sk, A->m, sa.y, sa.alpha,
+                                          sa.lambda, (double)A->m, tr, status, st));
+        timer.end(2, st);
+        if (sa.opt.snapshot_every > 0 && sa.opt.snapshots &&
+            ((k + 1) % sa.opt.snapshot_every == 0 || k + 1 == n_outer)) {
+            KDCD_HIP_TRY(hipMemcpyAsync(sa.opt.snapshots + snap * A->m, sa.alpha,
+                                        sizeof(double) * (size_t)A->m, hipMemcpyDeviceToDevice,
+                                        st));
+            ++snap;
+        }
+    }
+    rc = read_status(status, st);
+    timer.report(sa.opt.profile);
+    return rc;
+}
+
+kdcd_status common_checks(const kdcd_matrix *A, const double *y, const kdcd_kernel *kernel,
+                          int32_t b, int32_t s, int64_t H, const int32_t *idx, double *alpha,
+                          const kdcd_options *opt)
+{
+    kdcd_status rc = check_matrix(A);
+    if (rc != KDCD_OK) return rc;
+    if ((rc = check_kernel(kernel)) != KDCD_OK) return rc;
+    if (!y || !idx || !alpha) return KDCD_ERR_INVALID_ARG;
+    if (b < 1 || s < 1 || H < 1) return KDCD_ERR_INVALID_ARG;
+    if (b > A->m) return KDCD_ERR_INVALID_ARG;
+    if (opt) {
+        if ((rc = check_compute(A, opt->compute)) != KDCD_OK) return rc;
+        if (opt->snapshot_every < 0) return KDCD_ERR_INVALID_ARG;
+        if (opt->snapshot_every > 0 && !opt->snapshots) return KDCD_ERR_INVALID_ARG;
+    }
+    if ((int64_t)s * b > kMaxSB) return KDCD_ERR_UNSUPPORTED;
+    return KDCD_OK;
+}
+
+kdcd_options defaults(const kdcd_options *opt)
+{
+    kdcd_options o{};
+    if (opt) o = *opt;
+    if (o.loss == 0) o.loss = 1;
+    return o;
+}
+
+}  // namespace
+
+extern "C" {
+
+kdcd_status kdcd_ksvm_solve(const kdcd_matrix *A, const double *y, const kdcd_kernel *kernel,
+                            double C, int32_t b, int32_t s, int64_t H, const int32_t *idx,
+                            double *alpha, const kdcd_options *opt, kdcd_stream stream)
+{
+    kdcd_status rc = common_checks(A, y, kernel, b, s, H, idx, alpha, opt);
+    if (rc != KDCD_OK) return rc;
+    if (!finite_pos(C)) return KDCD_ERR_INVALID_ARG;
+    if (b != 1) return KDCD_ERR_INVALID_ARG;
+    kdcd_options o = defaults(opt);
+    if (o.loss != 1 && o.loss != 2) return KDCD_ERR_INVALID_ARG;
+    SolveArgs sa{0, A, y, kernel, C, 0.0, b, s, H, idx, alpha, o, (hipStream_t)stream};
+    return run_solve(sa);
+}
+
+kdcd_status kdcd_krr_solve(const kdcd_matrix *A, const double *y, const kdcd_kernel *kernel,
+                           double lambda, int32_t b, int32_t s, int64_t H, const int32_t *idx,
+                           double *alpha, const kdcd_options *opt, kdcd_stream stream)
+{
+    kdcd_status rc = common_checks(A, y, kernel, b, s, H, idx, alpha, opt);
+    if (rc != KDCD_OK) return rc;
+    if (!finite_pos(lambda)) return KDCD_ERR_INVALID_ARG;
+    if (b > kMaxB) return KDCD_ERR_UNSUPPORTED;
+    // one recurrence wave per panel of floor(64/b)*b elements; wide blocks keep <= 512 threads
+    const int nt = krr_recur_threads(b, s);
+    if (nt > 1024 || (b > 16 && nt > 512)) return KDCD_ERR_UNSUPPORTED;
+    kdcd_options o = defaults(opt);
+    SolveArgs sa{1, A, y, kernel, 0.0, lambda, b, s, H, idx, alpha, o, (hipStream_t)stream};
+    return run_solve(sa);
+}
+
+kdcd_status kdcd_kernel_rhs(const kdcd_matrix *A, const kdcd_kernel *kernel, const int32_t *S,
+                            int32_t sb, const double *beta, const double *beta_scale, double *r,
+                            double *W, int32_t compute, kdcd_stream stream)
+{
+    kdcd_status rc = check_matrix(A);
+    if (rc != KDCD_OK) return rc;
+    if ((rc = check_kernel(kernel)) != KDCD_OK) return rc;
+    if ((rc = check_compute(A, compute)) != KDCD_OK) return rc;
+    if (!S || !beta || !r || sb < 1) return KDCD_ERR_INVALID_ARG;
+    if (sb > kMaxSB) return KDCD_ERR_UNSUPPORTED;
+    const hipStream_t st = (hipStream_t)stream;
+    const Layout L = make_layout(0, A, kernel, 1, sb, compute);
+    Workspace ws;
+    if ((rc = acquire(ws, L, nullptr, st)) != KDCD_OK) return rc;
+    int32_t *status = ws.at<int32_t>(L.status);
+    double *norms = ws.at<double>(L.norms);
+    double *partial = ws.at<double>(L.partial);
+    KDCD_HIP_TRY(launch_fill_i32(status, 0, 1, st));
+    KDCD_HIP_TRY(launch_validate(S, sb, A->m, nullptr, nullptr, 0, 0, 0.0, status, st));
+    if (kernel->kind == KDCD_KERNEL_RBF) KDCD_HIP_TRY(launch_norms(A, norms, st));
+    KBlockArgs base{};
+    base.A = A;
+    base.S = S;
+    base.sb = sb;
+    base.norms = norms;
+    base.kp = to_params(kernel);
+    base.beta = beta;
+    base.beta_scale = beta_scale;
+    base.partial = partial;
+    base.W = W;
+    base.status = status;
+    base.compute = compute;
+    KBlockArgs kb;
+    if ((rc = prepare_lowp(base, L, ws, st, kb)) != KDCD_OK) return rc;
+    KDCD_HIP_TRY(launch_kblock(kb, st));
+    KDCD_HIP_TRY(launch_finish(partial, row_groups(A, sb, compute), sb, r, nullptr, 1, 0, 0.0, 0.0,
+                               nullptr, status, st));
+    return read_status(status, st);
+}
+
+// (K beta) for all rows, FP64, in column chunks of kMaxSB through the kernel-block path.
+static kdcd_status kernel_matvec(const kdcd_matrix *A, const kdcd_kernel *kernel,
+                                 const double *beta, std::vector<double> &out, hipStream_t st)
+{
+    const int64_t m = A->m;
+    const int32_t chunk = kMaxSB;
+    const Layout L = make_layout(2, A, kernel, 1, chunk, KDCD_F64);
+    Workspace ws;
+    kdcd_status rc = acquire(ws, L, nullptr, st);
+    if (rc != KDCD_OK) return rc;
+    int32_t *status = ws.at<int32_t>(L.status);
+    double *norms = ws.at<double>(L.norms);
+    double *partial = ws.at<double>(L.partial);
+    double *r = ws.at<double>(L.r);
+    int32_t *iota = ws.at<int32_t>(L.iota);
+    KDCD_HIP_TRY(launch_fill_i32(status, 0, 1, st));
+    KDCD_HIP_TRY(launch_iota_i32(iota, m, st));
+    if (kernel->kind == KDCD_KERNEL_RBF) KDCD_HIP_TRY(launch_norms(A, norms, st));
+    out.assign((size_t)m, 0.0);
+    for (int64_t c0 = 0; c0 < m; c0 += chunk) {
+        const int32_t sb = (int32_t)std::min<int64_t>(chunk, m - c0);
+        KBlockArgs a{};
+        a.A = A;
+        a.S = iota + c0;
+        a.sb = sb;
+        a.norms = norms;
+        a.kp = to_params(kernel);
+        a.beta = beta;
+        a.partial = partial;
+        a.W = nullptr;
+        a.status = status;
+        a.compute = KDCD_F64;
+        KDCD_HIP_TRY(launch_kblock(a, st));
+        KDCD_HIP_TRY(launch_finish(partial, row_groups(A, sb, KDCD_F64), sb, r, nullptr, 1, 0, 0.0,
+                                   0.0, nullptr, status, st));
+        KDCD_HIP_TRY(hipMemcpyAsync(out.data() + c0, r, sizeof(double) * (size_t)sb,
+                                    hipMemcpyDeviceToHost, st));
+    }
+    return read_status(status, st);
+}
+
+static void copy_to_host(std::vector<double> &h, const double *d, int64_t m, hipStream_t st)
+{
+    h.assign((size_t)m, 0.0);
+    (void)hipMemcpyAsync(h.data(), d, sizeof(double) * (size_t)m, hipMemcpyDeviceToHost, st);
+    (void)hipStreamSynchronize(st);
+}
+
+kdcd_status kdcd_ksvm_eval(const kdcd_matrix *A, const double *y, const kdcd_kernel *kernel,
+                           double C, int32_t loss, const double *alpha, double *out,
+                           kdcd_stream stream)
+{
+    kdcd_status rc = check_matrix(A);
+    if (rc != KDCD_OK) return rc;
+    if ((rc = check_kernel(kernel)) != KDCD_OK) return rc;
+    if (!y || !alpha || !out || !finite_pos(C) || (loss != 1 && loss != 2)) return KDCD_ERR_INVALID_ARG;
+    const hipStream_t st = (hipStream_t)stream;
+    std::vector<double> hy, ha;
+    copy_to_host(hy, y, A->m, st);
+    copy_to_host(ha, alpha, A->m, st);
+    std::vector<double> beta((size_t)A->m);
+    for (int64_t p = 0; p < A->m; ++p) beta[p] = hy[p] * ha[p];
+    double *dbeta = nullptr;
+    if (hipMalloc(&dbeta, sizeof(double) * (size_t)A->m) != hipSuccess) return KDCD_ERR_ALLOC;
+    (void)hipMemcpy(dbeta, beta.data(), sizeof(double) * (size_t)A->m, hipMemcpyHostToDevice);
+    std::vector<double> Kb;
+    rc = kernel_matvec(A, kernel, dbeta, Kb, st);
+    (void)hipFree(dbeta);
+    if (rc != KDCD_OK) return rc;
+    const double nu = loss == 2 ? INFINITY : C, omega = loss == 2 ? 1.0 / (2.0 * C) : 0.0;
+    long double aQa = 0, sa = 0, sa2 = 0, hinge = 0;
+    double kkt = 0.0;
+    for (int64_t p = 0; p < A->m; ++p) {
+        const double Qa = hy[p] * Kb[p];
+        aQa += (long double)ha[p] * Qa;
+        sa += ha[p];
+        sa2 += (long double)ha[p] * ha[p];
+        const double xi = std::max(0.0, 1.0 - Qa);
+        hinge += loss == 2 ? (long double)xi * xi : xi;
+        const double g = Qa - 1.0 + omega * ha[p];
+        const double pg = ha[p] <= 0.0 ? std::min(0.0, g) : (ha[p] >= nu ? std::max(0.0, g) : g);
+        kkt = std::max(kkt, std::fabs(pg));
+    }
+    const double f = (double)(0.5L * aQa - sa + (loss == 2 ? sa2 / (4.0L * C) : 0.0L));
+    const double P = (double)(0.5L * aQa + (long double)C * hinge);
+    out[0] = f;
+    out[1] = P;
+    out[2] = P + f;
+    out[3] = kkt;
+    return KDCD_OK;
+}
+
+kdcd_status kdcd_krr_eval(const kdcd_matrix *A, const double *y, const kdcd_kernel *kernel,
+                          double lambda, const double *alpha, double *out, kdcd_stream stream)
+{
+    kdcd_status rc = check_matrix(A);
+    if (rc != KDCD_OK) return rc;
+    if ((rc = check_kernel(kernel)) != KDCD_OK) return rc;
+    if (!y || !alpha || !out || !finite_pos(lambda)) return KDCD_ERR_INVALID_ARG;
+    const hipStream_t st = (hipStream_t)stream;
+    std::vector<double> Ka, hy, ha;
+    if ((rc = kernel_matvec(A, kernel, alpha, Ka, st)) != KDCD_OK) return rc;
+    copy_to_host(hy, y, A->m, st);
+    copy_to_host(ha, alpha, A->m, st);
+    long double aMa = 0, ya = 0, rr = 0;
+    const double m = (double)A->m;
+    for (int64_t p = 0; p < A->m; ++p) {
+        const double Ma = Ka[p] / lambda + m * ha[p];
+        aMa += (long double)ha[p] * Ma;
+        ya += (long double)hy[p] * ha[p];
+        const double res = hy[p] - Ma;
+        rr += (long double)res * res;
+    }
+    out[0] = (double)(0.5L * aMa - ya);
+    out[1] = std::sqrt((double)rr);
+    return KDCD_OK;
+}
+
+size_t kdcd_workspace_bytes(int32_t problem, const kdcd_matrix *A, const kdcd_kernel *kernel,
+                            int32_t b, int32_t s, int32_t compute)
+{
+    if (!A || b < 1 || s < 1 || (problem != 0 && problem != 1)) return 0;
+    return make_layout(problem, A, kernel, b, s, compute).total;
+}
+
+const char *kdcd_status_string(kdcd_status st)
+{
+    switch (st) {
+    case KDCD_OK: return "ok";
+    case KDCD_ERR_INVALID_ARG: return "invalid argument";
+    case KDCD_ERR_UNSUPPORTED: return "unsupported configuration";
+    case KDCD_ERR_INDEX_RANGE: return "coordinate index out of range";
+    case KDCD_ERR_INDEX_DUPLICATE: return "duplicate coordinate inside a K-RR block";
+    case KDCD_ERR_NOT_SPD: return "block matrix not symmetric positive definite";
+    case KDCD_ERR_NONFINITE: return "non-finite value";
+    case KDCD_ERR_HIP: return "HIP runtime error";
+    case KDCD_ERR_ALLOC: return "device allocation failed";
+    case KDCD_ERR_WORKSPACE: return "workspace too small";
+    }
+    return "unknown status";
+}
+
+const char *kdcd_version(void) { return "kdcd 0.1.0 gfx950"; }
+
+}  // extern "C"

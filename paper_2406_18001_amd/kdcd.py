@@ -1,0 +1,277 @@
+"""Python binding of the kdcd C-ABI (include/kdcd.h).
+
+Argument marshalling only: torch tensors provide device memory and the
+current HIP stream; every step of the solvers runs in the HIP library
+``libkdcd.so`` built in this package directory.  Importing this module on a
+machine without the built library raises immediately -- there is no CPU
+fallback.
+
+The binding checks what the C-ABI cannot see through plain pointers
+(device, dtype, contiguity and lengths of every buffer), so that a wrong
+tensor becomes a Python error rather than an out-of-bounds device access.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import NamedTuple, Optional
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkdcd.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"kdcd HIP library not built: {LIB_PATH} is missing "
+                      "(run __graft_entry__.build())")
+_lib = ctypes.CDLL(LIB_PATH)
+
+KERNEL_LINEAR, KERNEL_POLY, KERNEL_RBF = 0, 1, 2
+DENSE, CSR_FORMAT = 0, 1
+COMPUTE = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3, "bf16x3": 4}
+FLAG_GRAPH = 1
+
+STATUS = {0: "KDCD_OK", -1: "KDCD_ERR_INVALID_ARG", -2: "KDCD_ERR_UNSUPPORTED",
+          -3: "KDCD_ERR_INDEX_RANGE", -4: "KDCD_ERR_INDEX_DUPLICATE", -5: "KDCD_ERR_NOT_SPD",
+          -6: "KDCD_ERR_NONFINITE", -7: "KDCD_ERR_HIP", -8: "KDCD_ERR_ALLOC",
+          -9: "KDCD_ERR_WORKSPACE"}
+
+
+class Kernel(NamedTuple):
+    """Table 1 kernel: kind 0 linear, 1 polynomial (c + x.z)^degree, 2 RBF exp(-sigma |x-z|^2)."""
+    kind: int
+    sigma: float = 0.0
+    c: float = 0.0
+    degree: int = 1
+
+
+class CSR(NamedTuple):
+    """CSR matrix on the device: row_ptr int64 (m+1), col_idx int32 (nnz), values float64 (nnz)."""
+    row_ptr: torch.Tensor
+    col_idx: torch.Tensor
+    values: torch.Tensor
+    m: int
+    n: int
+
+
+class KdcdError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {STATUS.get(status, status)} ({kdcd_status_string(status)})")
+
+
+class _Matrix(ctypes.Structure):
+    _fields_ = [("format", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("m", ctypes.c_int64), ("n", ctypes.c_int64), ("ld", ctypes.c_int64),
+                ("nnz", ctypes.c_int64), ("values", ctypes.c_void_p),
+                ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p)]
+
+
+class _Kernel(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("degree", ctypes.c_int32),
+                ("sigma", ctypes.c_double), ("c", ctypes.c_double)]
+
+
+class _Profile(ctypes.Structure):
+    _fields_ = [("kblock_ms", ctypes.c_double), ("kblock_launches", ctypes.c_int64),
+                ("finish_ms", ctypes.c_double), ("finish_launches", ctypes.c_int64),
+                ("recur_ms", ctypes.c_double), ("recur_launches", ctypes.c_int64),
+                ("total_ms", ctypes.c_double)]
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("compute", ctypes.c_int32), ("loss", ctypes.c_int32),
+                ("snapshot_every", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("snapshots", ctypes.c_void_p), ("trace", ctypes.c_void_p),
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
+                ("profile", ctypes.c_void_p)]
+
+
+_P = ctypes.c_void_p
+_lib.kdcd_ksvm_solve.restype = ctypes.c_int
+_lib.kdcd_ksvm_solve.argtypes = [_P, _P, _P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
+                                 ctypes.c_int64, _P, _P, _P, _P]
+_lib.kdcd_krr_solve.restype = ctypes.c_int
+_lib.kdcd_krr_solve.argtypes = _lib.kdcd_ksvm_solve.argtypes
+_lib.kdcd_kernel_rhs.restype = ctypes.c_int
+_lib.kdcd_kernel_rhs.argtypes = [_P, _P, _P, ctypes.c_int32, _P, _P, _P, _P, ctypes.c_int32, _P]
+_lib.kdcd_ksvm_eval.restype = ctypes.c_int
+_lib.kdcd_ksvm_eval.argtypes = [_P, _P, _P, ctypes.c_double, ctypes.c_int32, _P, _P, _P]
+_lib.kdcd_krr_eval.restype = ctypes.c_int
+_lib.kdcd_krr_eval.argtypes = [_P, _P, _P, ctypes.c_double, _P, _P, _P]
+_lib.kdcd_workspace_bytes.restype = ctypes.c_size_t
+_lib.kdcd_workspace_bytes.argtypes = [ctypes.c_int32, _P, _P, ctypes.c_int32, ctypes.c_int32,
+                                      ctypes.c_int32]
+_lib.kdcd_status_string.restype = ctypes.c_char_p
+_lib.kdcd_status_string.argtypes = [ctypes.c_int]
+_lib.kdcd_version.restype = ctypes.c_char_p
+_lib.kdcd_version.argtypes = []
+
+
+def kdcd_status_string(status: int) -> str:
+    return _lib.kdcd_status_string(int(status)).decode()
+
+
+def kdcd_version() -> str:
+    return _lib.kdcd_version().decode()
+
+
+# ------------------------------------------------------------- marshalling
+
+def _dev(t: torch.Tensor, dtype: torch.dtype, n: Optional[int], name: str) -> int:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must live on the GPU")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if n is not None and t.numel() < n:
+        raise ValueError(f"{name} holds {t.numel()} elements, needs {n}")
+    return t.data_ptr()
+
+
+def _matrix(A) -> tuple[_Matrix, int, int]:
+    mat = _Matrix()
+    if isinstance(A, CSR):
+        m, n = int(A.m), int(A.n)
+        _dev(A.row_ptr, torch.int64, m + 1, "A.row_ptr")
+        nnz = int(A.values.numel())
+        mat.format, mat.m, mat.n, mat.ld, mat.nnz = CSR_FORMAT, m, n, n, nnz
+        mat.values = _dev(A.values, torch.float64, nnz, "A.values")
+        mat.row_ptr = A.row_ptr.data_ptr()
+        mat.col_idx = _dev(A.col_idx, torch.int32, nnz, "A.col_idx")
+    else:
+        if A.dim() != 2:
+            raise ValueError("dense A must be 2-D (m x n)")
+        m, n = A.shape
+        if A.stride(1) != 1:
+            raise ValueError("dense A must be row-major with unit column stride")
+        mat.format, mat.m, mat.n, mat.ld, mat.nnz = DENSE, m, n, A.stride(0), 0
+        if A.device.type != "cuda" or A.dtype != torch.float64:
+            raise TypeError("dense A must be a float64 GPU tensor")
+        mat.values = A.data_ptr()
+        mat.row_ptr = mat.col_idx = None
+    return mat, int(mat.m), int(mat.n)
+
+
+def _kernel(k) -> _Kernel:
+    k = k if isinstance(k, Kernel) else Kernel(*k)
+    return _Kernel(int(k.kind), int(k.degree), float(k.sigma), float(k.c))
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _options(compute, loss, snapshot_every, snapshots, trace, workspace, profile, flags,
+             m, n_outer, n_updates):
+    o = _Options()
+    o.compute = COMPUTE[compute] if isinstance(compute, str) else int(compute)
+    o.loss = int(loss)
+    o.snapshot_every = int(snapshot_every)
+    o.flags = int(flags)
+    if snapshot_every:
+        rows = -(-n_outer // int(snapshot_every))
+        o.snapshots = _dev(snapshots, torch.float64, rows * m, "snapshots")
+    if trace is not None:
+        o.trace = _dev(trace, torch.float64, n_updates, "trace")
+    if workspace is not None:
+        o.workspace = _dev(workspace, torch.uint8, None, "workspace")
+        o.workspace_bytes = workspace.numel()
+    prof = None
+    if profile:
+        prof = _Profile()
+        o.profile = ctypes.cast(ctypes.pointer(prof), ctypes.c_void_p)
+    return o, prof
+
+
+def _solve(fn, name, A, y, kernel, param, b, s, H, idx, alpha, compute, loss, snapshot_every,
+           snapshots, trace, workspace, profile, flags, stream):
+    mat, m, _ = _matrix(A)
+    _dev(y, torch.float64, m, "y")
+    _dev(alpha, torch.float64, m, "alpha")
+    _dev(idx, torch.int32, int(H) * int(b), "idx")
+    n_outer = -(-int(H) // max(int(s), 1))
+    opt, prof = _options(compute, loss, snapshot_every, snapshots, trace, workspace, profile,
+                         flags, m, n_outer, int(H) * int(b))
+    kern = _kernel(kernel)
+    st = fn(ctypes.byref(mat), y.data_ptr(), ctypes.byref(kern), float(param), int(b), int(s),
+            int(H), idx.data_ptr(), alpha.data_ptr(), ctypes.byref(opt), _stream(stream))
+    if st != 0:
+        raise KdcdError(st, name)
+    if prof is not None:
+        return {f: getattr(prof, f) for f, _ in _Profile._fields_}
+    return None
+
+
+def kdcd_ksvm_solve(A, y, kernel, C, b, s, H, idx, alpha, *, compute="f64", loss=1,
+                    snapshot_every=0, snapshots=None, trace=None, workspace=None, profile=False,
+                    flags=0, stream=None):
+    """s-step DCD for K-SVM (Algorithm 2); alpha is updated in place.
+    Returns the stage timings (dict) when profile=True, else None."""
+    return _solve(_lib.kdcd_ksvm_solve, "kdcd_ksvm_solve", A, y, kernel, C, b, s, H, idx, alpha,
+                  compute, loss, snapshot_every, snapshots, trace, workspace, profile, flags,
+                  stream)
+
+
+def kdcd_krr_solve(A, y, kernel, lam, b, s, H, idx, alpha, *, compute="f64", snapshot_every=0,
+                   snapshots=None, trace=None, workspace=None, profile=False, flags=0,
+                   stream=None):
+    """s-step BDCD for K-RR (Algorithm 4); alpha is updated in place."""
+    return _solve(_lib.kdcd_krr_solve, "kdcd_krr_solve", A, y, kernel, lam, b, s, H, idx, alpha,
+                  compute, 1, snapshot_every, snapshots, trace, workspace, profile, flags, stream)
+
+
+def kdcd_kernel_rhs(A, kernel, S, beta, beta_scale=None, *, want_W=False, compute="f64",
+                    stream=None):
+    """r[j] = sum_p K(a_p, a_{S_j}) beta_p (beta_scale_p); W = K(A_S, A_S) if want_W."""
+    mat, m, _ = _matrix(A)
+    sb = int(S.numel())
+    _dev(S, torch.int32, sb, "S")
+    _dev(beta, torch.float64, m, "beta")
+    bs = _dev(beta_scale, torch.float64, m, "beta_scale") if beta_scale is not None else None
+    r = torch.empty(sb, dtype=torch.float64, device=beta.device)
+    W = torch.empty(sb * sb, dtype=torch.float64, device=beta.device) if want_W else None
+    kern = _kernel(kernel)
+    cmp = COMPUTE[compute] if isinstance(compute, str) else int(compute)
+    st = _lib.kdcd_kernel_rhs(ctypes.byref(mat), ctypes.byref(kern), S.data_ptr(), sb,
+                              beta.data_ptr(), bs, r.data_ptr(),
+                              W.data_ptr() if W is not None else None, cmp, _stream(stream))
+    if st != 0:
+        raise KdcdError(st, "kdcd_kernel_rhs")
+    return (r, W.view(sb, sb)) if want_W else r
+
+
+def kdcd_ksvm_eval(A, y, kernel, C, alpha, loss=1, stream=None) -> dict:
+    mat, m, _ = _matrix(A)
+    _dev(y, torch.float64, m, "y")
+    _dev(alpha, torch.float64, m, "alpha")
+    out = (ctypes.c_double * 4)()
+    st = _lib.kdcd_ksvm_eval(ctypes.byref(mat), y.data_ptr(), ctypes.byref(_kernel(kernel)),
+                             float(C), int(loss), alpha.data_ptr(), out, _stream(stream))
+    if st != 0:
+        raise KdcdError(st, "kdcd_ksvm_eval")
+    return {"dual": out[0], "primal": out[1], "gap": out[2], "kkt": out[3]}
+
+
+def kdcd_krr_eval(A, y, kernel, lam, alpha, stream=None) -> dict:
+    mat, m, _ = _matrix(A)
+    _dev(y, torch.float64, m, "y")
+    _dev(alpha, torch.float64, m, "alpha")
+    out = (ctypes.c_double * 2)()
+    st = _lib.kdcd_krr_eval(ctypes.byref(mat), y.data_ptr(), ctypes.byref(_kernel(kernel)),
+                            float(lam), alpha.data_ptr(), out, _stream(stream))
+    if st != 0:
+        raise KdcdError(st, "kdcd_krr_eval")
+    return {"objective": out[0], "residual_norm": out[1]}
+
+
+def kdcd_workspace_bytes(problem, A, kernel, b, s, compute="f64") -> int:
+    mat, _, _ = _matrix(A)
+    cmp = COMPUTE[compute] if isinstance(compute, str) else int(compute)
+    return int(_lib.kdcd_workspace_bytes(int(problem), ctypes.byref(mat),
+                                         ctypes.byref(_kernel(kernel)), int(b), int(s), cmp))

@@ -1,0 +1,76 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports
+every entry point include/kdcd.h declares, and reports status strings."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "kdcd.h")
+LIB = os.path.join(ROOT, "paper_2406_18001_amd", "libkdcd.so")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(kdcd_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_entry_points():
+    syms = declared_symbols()
+    for s in ("kdcd_ksvm_solve", "kdcd_krr_solve", "kdcd_kernel_rhs", "kdcd_status_string",
+              "kdcd_workspace_bytes"):
+        assert s in syms
+
+
+def test_library_exports_every_declared_symbol():
+    assert os.path.exists(LIB), "build the library first (__graft_entry__.build())"
+    lib = ctypes.CDLL(LIB)
+    missing = [s for s in declared_symbols() if not hasattr(lib, s)]
+    assert not missing, f"undefined entry points: {missing}"
+
+
+def test_status_strings_and_version():
+    lib = ctypes.CDLL(LIB)
+    lib.kdcd_status_string.restype = ctypes.c_char_p
+    lib.kdcd_version.restype = ctypes.c_char_p
+    for code in range(-9, 1):
+        assert lib.kdcd_status_string(code).decode() not in ("", "unknown status")
+    assert lib.kdcd_status_string(-100).decode() == "unknown status"
+    assert b"gfx950" in lib.kdcd_version()
+
+
+def test_host_argument_checks_need_no_device():
+    """Arguments rejected on the host never touch the device."""
+    from paper_2406_18001_amd import kdcd as K
+    mat = K._Matrix()
+    mat.format, mat.m, mat.n, mat.ld = 0, 10, 4, 4
+    mat.values = None                      # null values pointer
+    kern = K._Kernel(2, 1, 1.0, 0.0)
+    rc = K._lib.kdcd_ksvm_solve(ctypes.byref(mat), None, ctypes.byref(kern), 1.0, 1, 1, 1,
+                                None, None, None, None)
+    assert rc == -1
+    mat.values = 16                        # any non-null value: rejected before use
+    for kind, sigma, deg, c in ((2, 0.0, 1, 0.0), (2, -1.0, 1, 0.0), (1, 0.0, 0, 1.0),
+                                (1, 0.0, 3, -1.0), (7, 1.0, 1, 0.0)):
+        bad = K._Kernel(kind, deg, sigma, c)
+        rc = K._lib.kdcd_krr_solve(ctypes.byref(mat), 16, ctypes.byref(bad), 1.0, 1, 1, 1,
+                                   16, 16, None, None)
+        assert rc == -1, (kind, sigma, deg, c)
+    good = K._Kernel(2, 1, 1.0, 0.0)
+    cases = [  # (C or lambda, b, s, H) -> expected status
+        ((0.0, 1, 1, 1), -1), ((1.0, 0, 1, 1), -1), ((1.0, 1, 0, 1), -1), ((1.0, 1, 1, 0), -1),
+        ((1.0, 11, 1, 1), -1), ((float("nan"), 1, 1, 1), -1)]
+    for (p, b, s, H), want in cases:
+        rc = K._lib.kdcd_krr_solve(ctypes.byref(mat), 16, ctypes.byref(good), p, b, s, H,
+                                   16, 16, None, None)
+        assert rc == want, ((p, b, s, H), rc)
+    # K-SVM requires b = 1; K-RR caps b at 32 and s*b at 1024
+    assert K._lib.kdcd_ksvm_solve(ctypes.byref(mat), 16, ctypes.byref(good), 1.0, 2, 1, 1,
+                                  16, 16, None, None) == -1
+    mat.m = 5000
+    assert K._lib.kdcd_krr_solve(ctypes.byref(mat), 16, ctypes.byref(good), 1.0, 33, 1, 1,
+                                 16, 16, None, None) == -2
+    assert K._lib.kdcd_krr_solve(ctypes.byref(mat), 16, ctypes.byref(good), 1.0, 8, 129, 1,
+                                 16, 16, None, None) == -2
