@@ -48,6 +48,33 @@ __device__ __forceinline__ double dcd_theta(double rho, double g, double inv_eta
     return (gt != 0.0 && inv_eta > 0.0) ? th : 0.0;
 }
 
+// Last-occurrence table of the index block: an open-addressing hash in LDS
+// (2 * kMaxSB slots for at most kMaxSB keys, so every probe sequence ends at
+// an empty slot).  Each element inserts its coordinate and keeps the largest
+// element index per coordinate; after a barrier an element is the last
+// occurrence of its coordinate iff the slot holds its own index.
+constexpr int kHashSlots = 2 * kMaxSB;
+
+__device__ __forceinline__ void lastocc_clear(int32_t *keys, int32_t *idxs, int tid, int nt)
+{
+    for (int x = tid; x < kHashSlots; x += nt) {
+        keys[x] = -1;
+        idxs[x] = -1;
+    }
+}
+
+__device__ __forceinline__ int lastocc_insert(int32_t *keys, int32_t *idxs, int32_t key, int e)
+{
+    uint32_t h = ((uint32_t)key * 2654435761u) & (kHashSlots - 1);
+    for (;;) {
+        const int32_t old = atomicCAS(&keys[h], -1, key);
+        if (old == -1 || old == key) break;
+        h = (h + 1) & (kHashSlots - 1);
+    }
+    atomicMax(&idxs[h], e);
+    return (int)h;
+}
+
 // Stage the 64 x 64 diagonal block of panel q of W into dst (zero outside
 // the sb x sb matrix), using threads rank in [0, count): loads are issued in
 // batches of 8 before the matching LDS stores.
@@ -83,9 +110,10 @@ __global__ __launch_bounds__(NT) void ksvm_recur_kernel(
 {
     constexpr int PF = NT <= 512 ? 64 : 32;
     __shared__ double Wd[2][64 * 64];
-    __shared__ double th_l[kMaxSB];
-    __shared__ double y_l[kMaxSB];
-    __shared__ int32_t S_l[kMaxSB];
+    __shared__ double th_l[kMaxSB + 64];       // padded: entries >= sb hold 0 / -1
+    __shared__ double y_l[kMaxSB + 64];
+    __shared__ __align__(16) int32_t S_l[kMaxSB + 64];
+    __shared__ int32_t hkeys[kHashSlots], hidx[kHashSlots];
     const int j = threadIdx.x, lane = j & 63, wid = j >> 6;
     const bool act = j < sb;
     const int64_t Sj = act ? clampi(S[j], 0, m - 1) : -1;
@@ -97,8 +125,12 @@ __global__ __launch_bounds__(NT) void ksvm_recur_kernel(
     double gacc = 0.0, theta = 0.0;
     S_l[j] = (int32_t)Sj;
     y_l[j] = yj;
+    th_l[j] = 0.0;
+    if (j < 64) { S_l[NT + j] = -1; y_l[NT + j] = 0.0; th_l[NT + j] = 0.0; }
+    lastocc_clear(hkeys, hidx, j, NT);
     stage_diag(W, sb, 0, Wd[0], j, NT);
     lds_barrier();
+    const int hslot = act ? lastocc_insert(hkeys, hidx, (int32_t)Sj, j) : 0;
 
     const int npanels = (sb + 63) / 64;
     for (int p = 0; p < npanels; ++p) {
@@ -133,13 +165,12 @@ __global__ __launch_bounds__(NT) void ksvm_recur_kernel(
         }
         lds_barrier();
         if (later) {
+            // branch-free: wpre[t] and th_l[P0 + t] are 0 past the end of S_k
 #pragma unroll
             for (int t = 0; t < PF; ++t) {
-                if (t < plen) {
-                    const double tt = th_l[P0 + t];
-                    gacc += y_l[P0 + t] * yj * wpre[t] * tt;
-                    if (S_l[P0 + t] == (int32_t)Sj) rho += tt;
-                }
+                const double tt = th_l[P0 + t];
+                gacc += y_l[P0 + t] * yj * wpre[t] * tt;
+                rho += (S_l[P0 + t] == (int32_t)Sj) ? tt : 0.0;
             }
             for (int t = PF; t < plen; ++t) {
                 const double tt = th_l[P0 + t];
@@ -148,10 +179,8 @@ __global__ __launch_bounds__(NT) void ksvm_recur_kernel(
             }
         }
     }
+    const bool last = act && hidx[hslot] == j;
     if (act) {
-        bool last = true;
-        for (int q = j + 1; q < sb; ++q)
-            if (S_l[q] == (int32_t)Sj) { last = false; break; }
         const double nv = rho + theta;
         if (!isfinite(nv)) set_status(status, KDCD_ERR_NONFINITE);
         if (last) alpha[Sj] = nv;
@@ -161,21 +190,25 @@ __global__ __launch_bounds__(NT) void ksvm_recur_kernel(
 
 // K-RR recurrence.  Elements are grouped in panels of PE = floor(64/b)*b
 // (whole blocks); panel q lives on lanes [0, PE) of wave q.  Inside a panel
-// the wave runs its blocks one after the other (LDS exchange, no workgroup
-// barrier); then one barrier and every later element folds in the panel's
-// Delta values.  BMAX bounds b, NT the thread count.
-template <int BMAX, int NT>
+// the wave runs its blocks one after the other (values exchanged between
+// lanes with readlane, no workgroup barrier); then one barrier and every
+// later element folds in the panel's Delta values.  BMAX bounds b, NT the
+// thread count; BX > 0 fixes b = BX at compile time (fully unrolled block
+// loops), BX = 0 handles any b <= BMAX.
+template <int BMAX, int NT, int BX>
 __global__ __launch_bounds__(NT) void krr_recur_kernel(
     const double *__restrict__ r, const double *__restrict__ W, const double *__restrict__ Dinv,
     const int32_t *__restrict__ S, int32_t b, int32_t sk, int64_t m,
     const double *__restrict__ y, double *__restrict__ alpha, double lambda, double mdbl,
     double *__restrict__ trace, int32_t *status)
 {
-    constexpr int PF = NT <= 512 ? 64 : 16;
+    constexpr int PF = NT > 512 ? 16 : ((BMAX >= 32 || BX == 0) ? 32 : 64);
     __shared__ double Wd[2][64 * 64];
-    __shared__ double c_l[kMaxSB];
-    __shared__ double d_l[kMaxSB];
-    __shared__ int32_t S_l[kMaxSB];
+    __shared__ double c_l[kMaxSB + 64];        // padded: entries past the last panel hold 0 / -1
+    __shared__ double d_l[kMaxSB + 64];
+    __shared__ __align__(16) int32_t S_l[kMaxSB + 64];
+    __shared__ int32_t hkeys[kHashSlots], hidx[kHashSlots];
+    if (BX > 0) b = BX;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int sb = sk * b;
     const int PE = (64 / b) * b;
@@ -189,6 +222,12 @@ __global__ __launch_bounds__(NT) void krr_recur_kernel(
     const int myblk = act ? e / b : sk;
     const int ll = act ? e % b : 0;
     const int lblk = lane / b;                        // block index inside the panel
+    for (int x = tid; x < kMaxSB + 64; x += NT) {   // every slot without an owner: S = -1, d = 0
+        S_l[x] = -1;
+        d_l[x] = 0.0;
+    }
+    lastocc_clear(hkeys, hidx, tid, NT);
+    lds_barrier();
     if (act) {
         S_l[e] = (int32_t)Sp;
         c_l[e] = c;
@@ -219,13 +258,14 @@ __global__ __launch_bounds__(NT) void krr_recur_kernel(
     };
     stage(0, Wd[0], tid, NT);
     lds_barrier();
+    const int hslot = act ? lastocc_insert(hkeys, hidx, (int32_t)Sp, e) : 0;
     if (act) {
         const int q0 = myblk * b;
         for (int q = q0; q < q0 + b; ++q)
             if (q != e && S_l[q] == (int32_t)Sp) set_status(status, KDCD_ERR_INDEX_DUPLICATE);
     }
 
-    double delta = 0.0;
+    double delta = 0.0, dsum = 0.0;   // dsum: updates of earlier repeats of this coordinate, in order
     for (int p = 0; p < npanels; ++p) {
         const int P0 = p * PE;
         const int plen = (sb - P0) < PE ? (sb - P0) : PE;
@@ -240,56 +280,71 @@ __global__ __launch_bounds__(NT) void krr_recur_kernel(
         if (wid == p) {
             const double *wd = Wd[buf];
             const int nbl = plen / b;
+            constexpr int QN = BX > 0 ? BX : BMAX;
             for (int bl = 0; bl < nbl; ++bl) {
                 const int l0 = bl * b;                 // first lane of block bl
+                // coefficients of the fold-in, independent of the chain: fetched first
+                double coef[QN];
+#pragma unroll
+                for (int q = 0; q < QN; ++q) {
+                    if (BX > 0 || q < b) {
+                        const int32_t Sq = __builtin_amdgcn_readlane((int)Sp, l0 + q);
+                        coef[q] = (Sq == (int32_t)Sp ? mdbl : 0.0) + wd[(l0 + q) * 64 + lane] * inv_lambda;
+                    }
+                }
                 // Delta for block bl: lanes of the block combine the block's c values
                 double dl = 0.0;
 #pragma unroll
-                for (int q = 0; q < BMAX; ++q)
-                    if (q < b) dl += dv[q] * readlane_d(c, l0 + q);
+                for (int q = 0; q < QN; ++q)
+                    if (BX > 0 || q < b) dl += dv[q] * readlane_d(c, l0 + q);
                 if (lblk == bl) delta = dl;
                 // every later lane of the panel subtracts (m [S_e = S_q] + W_qe / lambda) Delta_q
-                double acc = 0.0;
+                double acc = 0.0, dup_acc = 0.0;
+                bool any_dup = false;
 #pragma unroll
-                for (int q = 0; q < BMAX; ++q) {
-                    if (q < b) {
+                for (int q = 0; q < QN; ++q) {
+                    if (BX > 0 || q < b) {
                         const double dq = readlane_d(dl, l0 + q);
-                        const int32_t Sq = __builtin_amdgcn_readlane((int)Sp, l0 + q);
-                        const double coef = (Sq == (int32_t)Sp ? mdbl : 0.0) + wd[(l0 + q) * 64 + lane] * inv_lambda;
-                        acc += coef * dq;
+                        const bool dup = __builtin_amdgcn_readlane((int)Sp, l0 + q) == (int32_t)Sp;
+                        acc += coef[q] * dq;
+                        dup_acc += dup ? dq : 0.0;
+                        any_dup |= dup;
                     }
                 }
-                if (act && lblk > bl) c -= acc;
+                if (act && lblk > bl) {
+                    c -= acc;
+                    if (any_dup) dsum += dup_acc;
+                }
             }
             if (act) d_l[e] = delta;
         }
         lds_barrier();
         if (later) {
+            // branch-free: wpre[t] and d_l[P0 + t] are 0 past the end of the panel
             double acc = 0.0;
 #pragma unroll
             for (int t = 0; t < PF; ++t) {
-                if (t < plen) {
-                    const double coef = (S_l[P0 + t] == (int32_t)Sp ? mdbl : 0.0) + wpre[t] * inv_lambda;
-                    acc += coef * d_l[P0 + t];
-                }
+                const bool dup = S_l[P0 + t] == (int32_t)Sp;
+                const double dt = d_l[P0 + t];
+                acc += ((dup ? mdbl : 0.0) + wpre[t] * inv_lambda) * dt;
+                dsum += dup ? dt : 0.0;
             }
             for (int t = PF; t < plen; ++t) {
-                const double coef = (S_l[P0 + t] == (int32_t)Sp ? mdbl : 0.0) +
-                                    W[(int64_t)(P0 + t) * sb + e] * inv_lambda;
-                acc += coef * d_l[P0 + t];
+                const bool dup = S_l[P0 + t] == (int32_t)Sp;
+                const double dt = d_l[P0 + t];
+                acc += ((dup ? mdbl : 0.0) + W[(int64_t)(P0 + t) * sb + e] * inv_lambda) * dt;
+                if (dup) dsum += dt;
             }
             c -= acc;
             c_l[e] = c;
         }
     }
+    // scatter: the last occurrence of a coordinate writes alpha_0 plus all of
+    // its updates (earlier repeats were folded into dsum in order)
+    const bool last = act && hidx[hslot] == e;
+    const double v = a0 + (dsum + delta);
     if (act) {
-        bool last = true;
-        for (int q = e + 1; q < sb; ++q)
-            if (S_l[q] == (int32_t)Sp) { last = false; break; }
         if (last) {
-            double v = a0;
-            for (int q = 0; q <= e; ++q)
-                if (S_l[q] == (int32_t)Sp) v += d_l[q];
             if (!isfinite(v)) set_status(status, KDCD_ERR_NONFINITE);
             alpha[Sp] = v;
         }
@@ -327,17 +382,34 @@ hipError_t launch_krr_recur(const double *r, const double *W, const double *Dinv
 {
     const int nt = krr_recur_threads(b, sk);
     if (nt > 1024 || b > kMaxB) return hipErrorInvalidValue;
-#define KDCD_KRR(BM_, NT_)                                                                    \
-    hipLaunchKernelGGL((krr_recur_kernel<BM_, NT_>), dim3(1), dim3(NT_), 0, st, r, W, Dinv, S, b, \
-                       sk, m, y, alpha, lambda, mdbl, trace, status)
+#define KDCD_KRR(BM_, NT_, BX_)                                                               \
+    hipLaunchKernelGGL((krr_recur_kernel<BM_, NT_, BX_>), dim3(1), dim3(NT_), 0, st, r, W, Dinv, S, \
+                       b, sk, m, y, alpha, lambda, mdbl, trace, status)
     if (nt <= 512) {
-        if (b <= 8) KDCD_KRR(8, 512);
-        else if (b <= 16) KDCD_KRR(16, 512);
-        else KDCD_KRR(32, 512);
+        switch (b) {
+        case 1: KDCD_KRR(1, 512, 1); break;
+        case 2: KDCD_KRR(2, 512, 2); break;
+        case 4: KDCD_KRR(4, 512, 4); break;
+        case 8: KDCD_KRR(8, 512, 8); break;
+        case 16: KDCD_KRR(16, 512, 16); break;
+        case 32: KDCD_KRR(32, 512, 32); break;
+        default:
+            if (b <= 8) KDCD_KRR(8, 512, 0);
+            else if (b <= 16) KDCD_KRR(16, 512, 0);
+            else KDCD_KRR(32, 512, 0);
+        }
     } else {
-        if (b <= 8) KDCD_KRR(8, 1024);
-        else if (b <= 16) KDCD_KRR(16, 1024);
-        else return hipErrorInvalidValue;
+        switch (b) {
+        case 1: KDCD_KRR(1, 1024, 1); break;
+        case 2: KDCD_KRR(2, 1024, 2); break;
+        case 4: KDCD_KRR(4, 1024, 4); break;
+        case 8: KDCD_KRR(8, 1024, 8); break;
+        case 16: KDCD_KRR(16, 1024, 16); break;
+        default:
+            if (b <= 8) KDCD_KRR(8, 1024, 0);
+            else if (b <= 16) KDCD_KRR(16, 1024, 0);
+            else return hipErrorInvalidValue;
+        }
     }
 #undef KDCD_KRR
     return hipGetLastError();
