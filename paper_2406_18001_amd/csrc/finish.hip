@@ -53,6 +53,23 @@ __global__ __launch_bounds__(256) void validate_kernel(const int32_t *__restrict
     }
 }
 
+// CSR structure: row_ptr[0] = 0, non-decreasing, row_ptr[m] = nnz, columns in [0, n).
+__global__ __launch_bounds__(256) void validate_csr_kernel(const int64_t *__restrict__ row_ptr,
+                                                           const int32_t *__restrict__ col_idx,
+                                                           int64_t m, int64_t n, int64_t nnz,
+                                                           int32_t *status)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    if (i == 0 && (row_ptr[0] != 0 || row_ptr[m] != nnz)) set_status(status, KDCD_ERR_INVALID_ARG);
+    for (int64_t r = i; r < m; r += stride)
+        if (row_ptr[r + 1] < row_ptr[r]) set_status(status, KDCD_ERR_INVALID_ARG);
+    for (int64_t e = i; e < nnz; e += stride) {
+        const int32_t c = col_idx[e];
+        if (c < 0 || c >= n) set_status(status, KDCD_ERR_INVALID_ARG);
+    }
+}
+
 __global__ void fill_i32_kernel(int32_t *p, int32_t v, int64_t count)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -153,6 +170,13 @@ hipError_t launch_validate(const int32_t *idx, int64_t count, int64_t m, const d
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(validate_kernel, dim3((unsigned)blocks), dim3(256), 0, st, idx, count, m,
                        y, alpha, mrows, problem, nu, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_validate_csr(const kdcd_matrix *A, int32_t *status, hipStream_t st)
+{
+    hipLaunchKernelGGL(validate_csr_kernel, dim3(2048), dim3(256), 0, st, A->row_ptr, A->col_idx,
+                       A->m, A->n, A->nnz, status);
     return hipGetLastError();
 }
 

@@ -256,6 +256,7 @@ kdcd_status run_solve(const SolveArgs &sa)
     const double omega = (svm && sa.opt.loss == 2) ? 1.0 / (2.0 * sa.C) : 0.0;
 
     KDCD_HIP_TRY(launch_fill_i32(status, 0, 1, st));
+    if (A->format == KDCD_CSR) KDCD_HIP_TRY(launch_validate_csr(A, status, st));
     KDCD_HIP_TRY(launch_validate(sa.idx, sa.H * sa.b, A->m, sa.y, sa.alpha, A->m, sa.problem, nu,
                                  status, st));
     if (sa.kernel->kind == KDCD_KERNEL_RBF) KDCD_HIP_TRY(launch_norms(A, norms, st));
@@ -393,6 +394,7 @@ kdcd_status kdcd_kernel_rhs(const kdcd_matrix *A, const kdcd_kernel *kernel, con
     double *norms = ws.at<double>(L.norms);
     double *partial = ws.at<double>(L.partial);
     KDCD_HIP_TRY(launch_fill_i32(status, 0, 1, st));
+    if (A->format == KDCD_CSR) KDCD_HIP_TRY(launch_validate_csr(A, status, st));
     KDCD_HIP_TRY(launch_validate(S, sb, A->m, nullptr, nullptr, 0, 0, 0.0, status, st));
     if (kernel->kind == KDCD_KERNEL_RBF) KDCD_HIP_TRY(launch_norms(A, norms, st));
     KBlockArgs base{};
@@ -431,6 +433,7 @@ static kdcd_status kernel_matvec(const kdcd_matrix *A, const kdcd_kernel *kernel
     double *r = ws.at<double>(L.r);
     int32_t *iota = ws.at<int32_t>(L.iota);
     KDCD_HIP_TRY(launch_fill_i32(status, 0, 1, st));
+    if (A->format == KDCD_CSR) KDCD_HIP_TRY(launch_validate_csr(A, status, st));
     KDCD_HIP_TRY(launch_iota_i32(iota, m, st));
     if (kernel->kind == KDCD_KERNEL_RBF) KDCD_HIP_TRY(launch_norms(A, norms, st));
     out.assign((size_t)m, 0.0);

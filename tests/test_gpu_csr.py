@@ -1,0 +1,134 @@
+"""Parity of the CSR kernel-block path (through the C-ABI) with the FP64 oracle,
+which evaluates sparse kernels by merging sorted rows (Table 1 definitions).
+
+Cases: the C3 recipe (Zipf(1.1) columns, 50 stored entries per row, rows
+L2-normalised, polynomial (x.z + 1)^3) at reduced and at full size, sampled
+blocks narrower and wider than one panel chunk (32 / 64 sampled rows), every
+kernel, K-SVM and K-RR solves, a dense/CSR cross-check, and the error paths.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2406_18001_amd import inputs
+from tests.helpers import assert_parity, dev, idx_dev
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-9
+
+
+@pytest.fixture(scope="module")
+def K():
+    from paper_2406_18001_amd import kdcd
+    return kdcd
+
+
+def to_gpu(K, c):
+    return K.CSR(torch.as_tensor(c["row_ptr"]).cuda(), torch.as_tensor(c["col_idx"]).cuda(),
+                 torch.as_tensor(c["val"]).cuda(), c["m"], c["n"])
+
+
+def as_oracle(c):
+    return (c["row_ptr"], c["col_idx"], c["val"], c["m"], c["n"])
+
+
+POLY13 = (1, 0.0, 1.0, 3)
+
+
+@pytest.fixture(scope="module")
+def c3_small():
+    return inputs.csr_ksvm_c3(m=3000, n=2000, nnz_per_row=20, seed=31)
+
+
+@pytest.mark.parametrize("sb", [1, 7, 32, 33, 64, 100])
+@pytest.mark.parametrize("kk", [POLY13, (2, 0.7, 0.0, 1), (0, 0.0, 0.0, 1)])
+def test_csr_kernel_rhs_and_gram(K, c3_small, sb, kk):
+    c = c3_small
+    rng = np.random.default_rng(sb)
+    S = rng.integers(0, c["m"], size=sb).astype(np.int32)
+    beta = rng.standard_normal(c["m"])
+    ok = O.Kernel(kk[0], sigma=kk[1], c=kk[2], degree=kk[3])
+    r_ref = O.kernel_rhs(as_oracle(c), ok, S, beta)
+    W_ref = O.kernel_block(as_oracle(c), ok, S, S)
+    r, W = K.kdcd_kernel_rhs(to_gpu(K, c), kk, idx_dev(S), dev(beta), want_W=True)
+    assert_parity(r.cpu().numpy(), r_ref, 1e-11, "r")
+    assert_parity(W.cpu().numpy(), W_ref, 1e-12, "W")
+
+
+def test_csr_matches_dense_path(K):
+    c = inputs.csr_ksvm_c3(m=700, n=300, nnz_per_row=12, seed=5)
+    D = inputs.csr_to_dense(c["row_ptr"], c["col_idx"], c["val"], c["m"], c["n"])
+    idx = idx_dev(inputs.ksvm_indices(700, 256, seed=1))
+    a_csr = torch.zeros(700, dtype=torch.float64, device="cuda")
+    a_den = torch.zeros(700, dtype=torch.float64, device="cuda")
+    K.kdcd_ksvm_solve(to_gpu(K, c), dev(c["y"]), POLY13, 1.0, 1, 32, 256, idx, a_csr)
+    K.kdcd_ksvm_solve(dev(D), dev(c["y"]), POLY13, 1.0, 1, 32, 256, idx, a_den)
+    assert_parity(a_csr.cpu().numpy(), a_den.cpu().numpy(), 1e-12, "csr vs dense")
+
+
+@pytest.mark.parametrize("s,H", [(1, 60), (8, 100), (32, 320), (64, 200)])
+def test_csr_ksvm_c3_recipe(K, c3_small, s, H):
+    c = c3_small
+    idx = inputs.ksvm_indices(c["m"], H, seed=0)
+    a_ref, th_ref = O.dcd_ksvm(as_oracle(c), c["y"], O.Kernel(1, c=1.0, degree=3), 1.0, H, idx, s=s)
+    alpha = torch.zeros(c["m"], dtype=torch.float64, device="cuda")
+    trace = torch.zeros(H, dtype=torch.float64, device="cuda")
+    K.kdcd_ksvm_solve(to_gpu(K, c), dev(c["y"]), POLY13, 1.0, 1, s, H, idx_dev(idx), alpha,
+                      trace=trace)
+    assert_parity(alpha.cpu().numpy(), a_ref, TOL, "alpha")
+    assert_parity(trace.cpu().numpy(), th_ref, TOL, "theta")
+
+
+def test_csr_krr(K, c3_small):
+    c = c3_small
+    y = np.sin(np.arange(c["m"]) * 0.01)
+    idx = inputs.krr_indices(c["m"], 4, 60, seed=2)
+    ok = O.Kernel(2, sigma=0.5)
+    a_ref, _ = O.bdcd_krr(as_oracle(c), y, ok, 1e-2, 4, 60, idx, s=16)
+    alpha = torch.zeros(c["m"], dtype=torch.float64, device="cuda")
+    K.kdcd_krr_solve(to_gpu(K, c), dev(y), (2, 0.5, 0.0, 1), 1e-2, 4, 16, 60, idx_dev(idx), alpha)
+    assert_parity(alpha.cpu().numpy(), a_ref, TOL, "alpha")
+
+
+def test_csr_c3_full_size_first_outer_iterations(K):
+    """C3 at full size (100000 x 50000, 5e6 stored entries, s = 32): the first
+    four outer iterations, every coordinate, against the oracle."""
+    c = inputs.csr_ksvm_c3()
+    H = 128
+    idx = inputs.ksvm_indices(c["m"], 20000, seed=0)[:H]
+    a_ref, _ = O.dcd_ksvm(as_oracle(c), c["y"], O.Kernel(1, c=1.0, degree=3), 1.0, H, idx, s=32)
+    alpha = torch.zeros(c["m"], dtype=torch.float64, device="cuda")
+    K.kdcd_ksvm_solve(to_gpu(K, c), dev(c["y"]), POLY13, 1.0, 1, 32, H, idx_dev(idx), alpha)
+    assert_parity(alpha.cpu().numpy(), a_ref, TOL, "alpha")
+
+
+def test_csr_errors(K):
+    c = inputs.csr_ksvm_c3(m=200, n=100, nnz_per_row=5, seed=1)
+    bad = dict(c)
+    rp = c["row_ptr"].copy()
+    rp[10], rp[11] = rp[11], rp[10]            # decreasing row pointer
+    bad["row_ptr"] = rp
+    a = torch.zeros(200, dtype=torch.float64, device="cuda")
+    with pytest.raises(K.KdcdError) as e:
+        K.kdcd_ksvm_solve(to_gpu(K, bad), dev(c["y"]), POLY13, 1.0, 1, 4, 8,
+                          idx_dev(np.arange(8, dtype=np.int32)), a)
+    assert e.value.status == -1
+    badc = dict(c)
+    ci = c["col_idx"].copy()
+    ci[7] = 100                                # column out of range
+    badc["col_idx"] = ci
+    with pytest.raises(K.KdcdError) as e:
+        K.kdcd_kernel_rhs(to_gpu(K, badc), POLY13, idx_dev([0, 1]), dev(np.ones(200)))
+    assert e.value.status == -1
+    # a sampled row with more stored entries than the panel holds is refused
+    m, n = 50, 5000
+    rows = [np.arange(0, 4000, dtype=np.int32)] + [np.array([i], dtype=np.int32) for i in range(1, m)]
+    row_ptr = np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int64)
+    col = np.concatenate(rows).astype(np.int32)
+    v = np.ones(col.size)
+    big = {"row_ptr": row_ptr, "col_idx": col, "val": v, "m": m, "n": n}
+    with pytest.raises(K.KdcdError) as e:
+        K.kdcd_kernel_rhs(to_gpu(K, big), POLY13, idx_dev([0, 3]), dev(np.ones(m)))
+    assert e.value.status == -2
