@@ -114,6 +114,7 @@ struct KBlockArgs {
     double *W;               // sb x sb or nullptr
     int32_t *status;
     int32_t compute;
+    int32_t w_only;          // FP64 kernel: compute the Gram tiles only (no U-part)
 };
 
 // Launchers (return hipError_t of the launch).

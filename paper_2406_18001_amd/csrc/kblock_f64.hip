@@ -273,9 +273,10 @@ hipError_t launch_cfg(const KBlockArgs &a, hipStream_t st)
 {
     constexpr int BM = 16 * TM * WM, BN = 16 * TN * WN;
     const kdcd_matrix *A = a.A;
-    const int64_t n_u = (A->m + BM - 1) / BM;
+    const int64_t n_u = a.w_only ? 0 : (A->m + BM - 1) / BM;
     const int64_t groups = n_u < kMaxRowGroups ? n_u : kMaxRowGroups;
     const int64_t n_w = a.W ? (a.sb + BM - 1) / BM : 0;
+    if (groups + n_w == 0) return hipSuccess;
     const int64_t n_n = (a.sb + BN - 1) / BN;
     const int64_t blocks = n_n * (groups + n_w);
     const int aligned = (A->ld % 2 == 0) && ((reinterpret_cast<uintptr_t>(A->values) & 15) == 0);

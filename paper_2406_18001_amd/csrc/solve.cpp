@@ -71,11 +71,18 @@ int64_t row_groups(const kdcd_matrix *A, int32_t sb, int32_t compute)
     return kblock_mixed_row_groups(A->m, sb);
 }
 
+// One kernel-block pass.  Mixed precisions produce the U-part only; their
+// Gram W comes from the FP64 kernel run on the Gram tiles alone.
 hipError_t launch_kblock(const KBlockArgs &a, hipStream_t st)
 {
     if (a.A->format == KDCD_CSR) return launch_kblock_csr(a, st);
     if (a.compute == KDCD_F64) return launch_kblock_f64(a, st);
-    return launch_kblock_mixed(a, st);
+    hipError_t e = launch_kblock_mixed(a, st);
+    if (e != hipSuccess || !a.W) return e;
+    KBlockArgs w = a;
+    w.compute = KDCD_F64;
+    w.w_only = 1;
+    return launch_kblock_f64(w, st);
 }
 
 size_t lowp_elem_bytes(int32_t compute) { return compute == KDCD_F32 ? 4 : 2; }
