@@ -158,6 +158,43 @@ kdcd_status kdcd_krr_solve(const kdcd_matrix *A, const double *y, const kdcd_ker
                            double lambda, int32_t b, int32_t s, int64_t H, const int32_t *idx,
                            double *alpha, const kdcd_options *opt, kdcd_stream stream);
 
+/* One problem of a batched solve. */
+typedef struct {
+    int32_t problem;      /* 0 = K-SVM, 1 = K-RR                                        */
+    int32_t loss;         /* K-SVM: 1 = hinge, 2 = squared hinge (0 means 1)             */
+    double param;         /* C (K-SVM, > 0) or lambda (K-RR, > 0)                        */
+    double sigma;         /* RBF sigma of this problem (> 0); ignored for other kernels  */
+    const double *y;      /* device, m: labels (+-1) or targets                          */
+    double *alpha;        /* device, m: alpha_0 on entry, alpha_H on exit                */
+    double *trace;        /* device or NULL: per-update theta / Delta alpha, H*b entries */
+} kdcd_batch_problem;
+
+/*
+ * kdcd_batch_solve -- several problems over one matrix and one index
+ * sequence, sharing every kernel-block product (the batching of
+ * a (lambda, sigma) K-RR sweep and one-vs-rest K-SVMs; the paper's Alg. 2
+ * and 4 per problem).  Per outer iteration one launch forms P = A A_S^T once,
+ * maps it once per distinct sigma and reduces it against every problem's
+ * alpha; one launch forms every sigma's Gram; the recurrences of all problems
+ * run in one launch per problem kind.
+ * Each problem's result equals its single solve:
+ *   K-RR  problem p == kdcd_krr_solve(A, y_p, kernel(sigma_p), lambda_p, b, s, H, idx, alpha_p)
+ *   K-SVM problem q == kdcd_ksvm_solve(A, y_q, kernel(sigma_q), C_q, 1, s*b, H*b, idx, alpha_q)
+ * (the K-SVM problems take the same s*b indices of each outer iteration as
+ * s*b scalar steps), up to the summation order of the shared reduction.
+ *   kernel     host: kind, c and degree shared; sigma comes from each problem
+ *   b, s, H    as in kdcd_krr_solve (b = 1 allowed); s*b <= 1024; every
+ *              b-block of idx distinct when any K-RR problem is present
+ *   problems   host array of n_problems (1..32) descriptors; at most 8
+ *              distinct sigma values
+ *   opt        compute, snapshot-free; workspace / profile as elsewhere
+ * Errors: as kdcd_krr_solve / kdcd_ksvm_solve; UNSUPPORTED beyond the limits.
+ */
+kdcd_status kdcd_batch_solve(const kdcd_matrix *A, const kdcd_kernel *kernel, int32_t b,
+                             int32_t s, int64_t H, const int32_t *idx,
+                             const kdcd_batch_problem *problems, int32_t n_problems,
+                             const kdcd_options *opt, kdcd_stream stream);
+
 /*
  * kdcd_kernel_rhs -- one kernel-block pass on its own (steps 2-5 above):
  *   r[j] = sum_p K(a_p, a_{S_j}) * beta[p] * (beta_scale ? beta_scale[p] : 1)

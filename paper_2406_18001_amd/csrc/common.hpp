@@ -97,6 +97,22 @@ __device__ __forceinline__ double wave_sum_xor16_32(double v)
         if (e_ != hipSuccess) return KDCD_ERR_HIP;           \
     } while (0)
 
+constexpr int kMaxProblems = 32;   // problems of one batched solve
+constexpr int kMaxSigmas = 8;      // distinct RBF widths of one batched solve
+
+// Problems sharing one kernel block (passed by value to the kernel-block
+// launch).  Problem p reduces K_{group[p]} against beta[p] (* bscale[p]);
+// group g maps P with sigma[g].  partial is laid out [p][row group][sb], the
+// Gram W [g][sb][sb].
+struct BatchDesc {
+    int32_t nprob;
+    int32_t ngroups;
+    double sigma[kMaxSigmas];
+    const double *beta[kMaxProblems];
+    const double *bscale[kMaxProblems];
+    int32_t group[kMaxProblems];
+};
+
 // Arguments of one kernel-block launch (dense or CSR, any compute type).
 struct KBlockArgs {
     const kdcd_matrix *A;
@@ -115,22 +131,53 @@ struct KBlockArgs {
     int32_t *status;
     int32_t compute;
     int32_t w_only;          // FP64 kernel: compute the Gram tiles only (no U-part)
+    const BatchDesc *batch;  // non-null: batched epilogue (dense F64 and mixed kernels)
 };
 
 // Launchers (return hipError_t of the launch).
-int64_t kblock_f64_row_groups(int64_t m, int32_t sb);
+int64_t kblock_f64_row_groups(int64_t m, int32_t sb, bool batch = false);
+int64_t kblock_mixed_row_groups(int64_t m, int32_t sb, bool batch = false);
 hipError_t launch_kblock_f64(const KBlockArgs &a, hipStream_t st);
 hipError_t launch_norms(const kdcd_matrix *A, double *norms, hipStream_t st);
-hipError_t launch_finish(const double *partial, int64_t groups, int32_t sb, double *r,
-                         const double *W, int32_t b, int32_t s_blocks, double inv_lambda,
-                         double mdbl, double *Dinv, int32_t *status, hipStream_t st);
-hipError_t launch_ksvm_recur(const double *r, const double *W, const int32_t *S, int32_t sb,
-                             int64_t m, const double *y, double *alpha, double nu, double omega,
-                             double *trace, int32_t *status, hipStream_t st);
-hipError_t launch_krr_recur(const double *r, const double *W, const double *Dinv,
-                            const int32_t *S, int32_t b, int32_t sk, int64_t m, const double *y,
-                            double *alpha, double lambda, double mdbl, double *trace,
-                            int32_t *status, hipStream_t st);
+// Per-problem arguments of the finish pass and of the recurrences; one entry
+// per workgroup-problem (blockIdx.x), passed by value.
+struct FinishDesc {
+    int32_t nprob;          // problems whose r is reduced
+    int32_t nkrr;           // K-RR problems whose diagonal blocks are inverted
+    int32_t groups;         // row groups of the partial sums
+    const double *partial[kMaxProblems];   // [groups][sb] each
+    double *r[kMaxProblems];               // [sb] each
+    const double *W[kMaxProblems];         // Gram of K-RR problem k, [sb][sb]
+    double *Dinv[kMaxProblems];            // inverses of K-RR problem k, [sk][b][b]
+    double inv_lambda[kMaxProblems];
+};
+
+struct KsvmRecurDesc {
+    const double *r[kMaxProblems];
+    const double *W[kMaxProblems];
+    const double *y[kMaxProblems];
+    double *alpha[kMaxProblems];
+    double *trace[kMaxProblems];
+    double nu[kMaxProblems];
+    double omega[kMaxProblems];
+};
+
+struct KrrRecurDesc {
+    const double *r[kMaxProblems];
+    const double *W[kMaxProblems];
+    const double *Dinv[kMaxProblems];
+    const double *y[kMaxProblems];
+    double *alpha[kMaxProblems];
+    double *trace[kMaxProblems];
+    double lambda[kMaxProblems];
+};
+
+hipError_t launch_finish(const FinishDesc &d, int32_t sb, int32_t b, int32_t sk, double mdbl,
+                         int32_t *status, hipStream_t st);
+hipError_t launch_ksvm_recur(const KsvmRecurDesc &d, int32_t nprob, const int32_t *S, int32_t sb,
+                             int64_t m, int32_t *status, hipStream_t st);
+hipError_t launch_krr_recur(const KrrRecurDesc &d, int32_t nprob, const int32_t *S, int32_t b,
+                            int32_t sk, int64_t m, double mdbl, int32_t *status, hipStream_t st);
 hipError_t launch_validate(const int32_t *idx, int64_t count, int64_t m, const double *y,
                            const double *alpha, int64_t mrows, int32_t problem, double nu,
                            int32_t *status, hipStream_t st);

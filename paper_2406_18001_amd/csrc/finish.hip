@@ -85,36 +85,38 @@ __global__ void iota_i32_kernel(int32_t *p, int64_t count)
 constexpr int FIN_COLS = 16;    // columns per reduction workgroup
 constexpr int FIN_PARTS = 16;   // row-group partitions per column
 
-// Blocks [0, ceil(sb/16)) reduce r; blocks after that invert one K-RR diagonal
-// block each (Gauss-Jordan without pivoting, valid for SPD matrices).
-__global__ __launch_bounds__(256) void finish_kernel(const double *__restrict__ partial,
-                                                     int64_t groups, int32_t sb,
-                                                     double *__restrict__ r,
-                                                     const double *__restrict__ W, int32_t b,
-                                                     int32_t s_blocks, double inv_lambda,
-                                                     double mdbl, double *__restrict__ Dinv,
-                                                     int32_t *status)
+// Blocks [0, nprob * ceil(sb/16)) reduce r of every problem; the blocks after
+// that invert one diagonal block of one K-RR problem each (Gauss-Jordan
+// without pivoting, valid for SPD matrices).
+__global__ __launch_bounds__(256) void finish_kernel(const FinishDesc d, int32_t sb, int32_t b,
+                                                     int32_t sk, double mdbl, int32_t *status)
 {
     __shared__ double sh[kMaxB * kMaxB];
     const int tid = threadIdx.x;
-    const int n_red = (sb + FIN_COLS - 1) / FIN_COLS;
+    const int per = (sb + FIN_COLS - 1) / FIN_COLS;
+    const int n_red = per * d.nprob;
     if ((int)blockIdx.x < n_red) {
+        const int p = (int)blockIdx.x / per;
         const int c = tid % FIN_COLS, part = tid / FIN_COLS;
-        const int64_t col = (int64_t)blockIdx.x * FIN_COLS + c;
+        const int64_t col = (int64_t)((int)blockIdx.x % per) * FIN_COLS + c;
+        const double *partial = d.partial[p];
         double s = 0.0;
         if (col < sb)
-            for (int64_t g = part; g < groups; g += FIN_PARTS) s += partial[g * sb + col];
+            for (int64_t g = part; g < d.groups; g += FIN_PARTS) s += partial[g * sb + col];
         sh[part * FIN_COLS + c] = s;
         __syncthreads();
         if (part == 0 && col < sb) {
             double t = 0.0;
-            for (int p = 0; p < FIN_PARTS; ++p) t += sh[p * FIN_COLS + c];
-            r[col] = t;
+            for (int q = 0; q < FIN_PARTS; ++q) t += sh[q * FIN_COLS + c];
+            d.r[p][col] = t;
         }
         return;
     }
-    const int j = (int)blockIdx.x - n_red;
-    if (j >= s_blocks) return;
+    const int x = (int)blockIdx.x - n_red;
+    const int k = x / sk, j = x % sk;
+    if (k >= d.nkrr) return;
+    const double *W = d.W[k];
+    const double inv_lambda = d.inv_lambda[k];
     const int bb = b * b;
     const int64_t base = (int64_t)j * b;
     for (int e = tid; e < bb; e += blockDim.x) {
@@ -123,29 +125,30 @@ __global__ __launch_bounds__(256) void finish_kernel(const double *__restrict__ 
     }
     __syncthreads();
     bool bad = false;
-    for (int k = 0; k < b; ++k) {
-        const double piv = sh[k * b + k];
+    for (int kk = 0; kk < b; ++kk) {
+        const double piv = sh[kk * b + kk];
         if (!(piv > 0.0) || !isfinite(piv)) bad = true;
         const double pinv = 1.0 / piv;
-        // every thread reads what it needs of row k and column k before anyone writes
+        // every thread reads what it needs of row kk and column kk before anyone writes
         double rowk[kMaxB * kMaxB / 256 + 1], colk[kMaxB * kMaxB / 256 + 1];
         int cnt = 0;
         for (int e = tid; e < bb; e += blockDim.x, ++cnt) {
             const int l = e / b, q = e % b;
-            rowk[cnt] = (q == k) ? 1.0 : sh[k * b + q];
-            colk[cnt] = sh[l * b + k];
+            rowk[cnt] = (q == kk) ? 1.0 : sh[kk * b + q];
+            colk[cnt] = sh[l * b + kk];
         }
         __syncthreads();
         cnt = 0;
         for (int e = tid; e < bb; e += blockDim.x, ++cnt) {
             const int l = e / b, q = e % b;
-            const double nk = rowk[cnt] * pinv;           // new row-k entry in column q
-            if (l == k) sh[e] = nk;
-            else sh[e] = ((q == k) ? 0.0 : sh[e]) - nk * colk[cnt];
+            const double nk = rowk[cnt] * pinv;           // new row-kk entry in column q
+            if (l == kk) sh[e] = nk;
+            else sh[e] = ((q == kk) ? 0.0 : sh[e]) - nk * colk[cnt];
         }
         __syncthreads();
     }
     if (bad && tid == 0) set_status(status, KDCD_ERR_NOT_SPD);
+    double *Dinv = d.Dinv[k];
     for (int e = tid; e < bb; e += blockDim.x) Dinv[(int64_t)j * bb + e] = sh[e];
 }
 
@@ -194,14 +197,12 @@ hipError_t launch_iota_i32(int32_t *p, int64_t count, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_finish(const double *partial, int64_t groups, int32_t sb, double *r,
-                         const double *W, int32_t b, int32_t s_blocks, double inv_lambda,
-                         double mdbl, double *Dinv, int32_t *status, hipStream_t st)
+hipError_t launch_finish(const FinishDesc &d, int32_t sb, int32_t b, int32_t sk, double mdbl,
+                         int32_t *status, hipStream_t st)
 {
-    const int n_red = (sb + FIN_COLS - 1) / FIN_COLS;
-    const int n_inv = Dinv ? s_blocks : 0;
-    hipLaunchKernelGGL(finish_kernel, dim3(n_red + n_inv), dim3(256), 0, st, partial, groups, sb,
-                       r, W, b, n_inv, inv_lambda, mdbl, Dinv, status);
+    const int per = (sb + FIN_COLS - 1) / FIN_COLS;
+    const int blocks = per * d.nprob + d.nkrr * sk;
+    hipLaunchKernelGGL(finish_kernel, dim3(blocks), dim3(256), 0, st, d, sb, b, sk, mdbl, status);
     return hipGetLastError();
 }
 

@@ -37,13 +37,18 @@ __device__ __forceinline__ int xcd_remap(int bid, int total)
     return x < rem ? x * (per + 1) + w : rem * (per + 1) + (x - rem) * per + w;
 }
 
-template <int WM, int WN, int TM, int TN, int KIND>
+// BATCH: several problems share the product (descriptor bd in device memory):
+// the map runs once per sigma group, every problem reduces its own beta, and
+// the Gram tiles are written once per group.  partial is then [p][group][sb]
+// and W is [g][sb][sb].
+template <int WM, int WN, int TM, int TN, int KIND, bool BATCH>
 __global__ __launch_bounds__(64 * WM * WN) void kblock_f64_kernel(
     const double *__restrict__ A, int64_t lda, int64_t m, int64_t n,
     const int32_t *__restrict__ S, int32_t sb, const double *__restrict__ norms, KParams kp,
     const double *__restrict__ beta, const double *__restrict__ bscale,
     double *__restrict__ partial, double *__restrict__ W, int32_t n_u_tiles,
-    int32_t n_row_groups, int32_t n_w_tiles, int32_t n_tiles_n, int32_t aligned)
+    int32_t n_row_groups, int32_t n_w_tiles, int32_t n_tiles_n, int32_t aligned,
+    const BatchDesc *__restrict__ bd)
 {
     constexpr int NT = 64 * WM * WN;
     constexpr int BM = 16 * TM * WM;
@@ -54,6 +59,7 @@ __global__ __launch_bounds__(64 * WM * WN) void kblock_f64_kernel(
     __shared__ double As[2][BM * BK];
     __shared__ double Bs[2][BN * BK];
     __shared__ double red[WM][BN];
+    __shared__ double redb[BATCH ? kMaxProblems : 1][WM][BN];   // batched column sums
 
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int wm = wid / WN, wn = wid % WN;
@@ -91,6 +97,10 @@ __global__ __launch_bounds__(64 * WM * WN) void kblock_f64_kernel(
     double colsum[TN];
 #pragma unroll
     for (int tn = 0; tn < TN; ++tn) colsum[tn] = 0.0;
+    if constexpr (BATCH) {
+        for (int x = tid; x < kMaxProblems * WM * BN; x += NT) (&redb[0][0][0])[x] = 0.0;
+        __syncthreads();
+    }
 
     const int rt_first = is_w ? rg - n_row_groups : rg;
     const int rt_end = is_w ? rt_first + 1 : n_u_tiles;
@@ -205,32 +215,108 @@ __global__ __launch_bounds__(64 * WM * WN) void kblock_f64_kernel(
         }
 
         // epilogue: item v of MFMA output lane l is row (l/16) + 4v, column l%16 of its block
+        if constexpr (BATCH) {
+            const int ng = bd->ngroups, np = bd->nprob;
+            double na[TM][4];
 #pragma unroll
-        for (int tm = 0; tm < TM; ++tm) {
+            for (int tm = 0; tm < TM; ++tm)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int64_t lrow = (wm * TM + tm) * 16 + (lane >> 4) + 4 * v;
-                const int64_t grow = row0 + lrow;
-                if (!is_w) {
-                    if (grow < m) {
-                        double bval = beta[grow];
-                        if (bscale) bval *= bscale[grow];
-                        const double na = (KIND == KDCD_KERNEL_RBF) ? norms[grow] : 0.0;
+                for (int v = 0; v < 4; ++v) {
+                    const int64_t grow = row0 + (wm * TM + tm) * 16 + (lane >> 4) + 4 * v;
+                    const int64_t rr = is_w ? clampi(S[clampi(grow, 0, sb - 1)], 0, m - 1)
+                                            : clampi(grow, 0, m - 1);
+                    na[tm][v] = (KIND == KDCD_KERNEL_RBF) ? norms[rr] : 0.0;
+                }
+            for (int g = 0; g < ng; ++g) {
+                KParams kg = kp;
+                kg.sigma = bd->sigma[g];
+                double kv[TM][4][TN];
+#pragma unroll
+                for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int64_t grow = row0 + (wm * TM + tm) * 16 + (lane >> 4) + 4 * v;
+                        const int64_t rr = is_w ? clampi(S[clampi(grow, 0, sb - 1)], 0, m - 1) : grow;
+                        const bool rok = is_w ? grow < sb : grow < m;
 #pragma unroll
                         for (int tn = 0; tn < TN; ++tn)
-                            if (colok[tn])
-                                colsum[tn] += bval * kernel_map<KIND>(acc[tm][tn][v], na, nb[tn],
-                                                                      grow == Sc[tn], kp);
+                            kv[tm][v][tn] = (rok && colok[tn])
+                                                ? kernel_map<KIND>(acc[tm][tn][v], na[tm][v], nb[tn],
+                                                                   rr == Sc[tn], kg)
+                                                : 0.0;
                     }
-                } else if (grow < sb) {
-                    const int64_t St = clampi(S[grow], 0, m - 1);
-                    const double na = (KIND == KDCD_KERNEL_RBF) ? norms[St] : 0.0;
+                if (is_w) {
+#pragma unroll
+                    for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int64_t grow = row0 + (wm * TM + tm) * 16 + (lane >> 4) + 4 * v;
+#pragma unroll
+                            for (int tn = 0; tn < TN; ++tn) {
+                                const int64_t gcol = col0 + (wn * TN + tn) * 16 + (lane & 15);
+                                if (grow < sb && colok[tn])
+                                    W[((int64_t)g * sb + grow) * sb + gcol] = kv[tm][v][tn];
+                            }
+                        }
+                    continue;
+                }
+                for (int p = 0; p < np; ++p) {
+                    if (bd->group[p] != g) continue;
+                    const double *bp = bd->beta[p];
+                    const double *sp = bd->bscale[p];
+                    double bv[TM][4];
+#pragma unroll
+                    for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int64_t grow = row0 + (wm * TM + tm) * 16 + (lane >> 4) + 4 * v;
+                            double x = 0.0;
+                            if (grow < m) {
+                                x = bp[grow];
+                                if (sp) x *= sp[grow];
+                            }
+                            bv[tm][v] = x;
+                        }
 #pragma unroll
                     for (int tn = 0; tn < TN; ++tn) {
-                        const int64_t gcol = col0 + (wn * TN + tn) * 16 + (lane & 15);
-                        if (colok[tn])
-                            W[grow * sb + gcol] = kernel_map<KIND>(acc[tm][tn][v], na, nb[tn],
-                                                                   St == Sc[tn], kp);
+                        double acc_p = 0.0;
+#pragma unroll
+                        for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) acc_p += bv[tm][v] * kv[tm][v][tn];
+                        acc_p = wave_sum_xor16_32(acc_p);
+                        if (lane < 16) redb[p][wm][(wn * TN + tn) * 16 + lane] += acc_p;
+                    }
+                }
+            }
+        } else {
+#pragma unroll
+            for (int tm = 0; tm < TM; ++tm) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int64_t lrow = (wm * TM + tm) * 16 + (lane >> 4) + 4 * v;
+                    const int64_t grow = row0 + lrow;
+                    if (!is_w) {
+                        if (grow < m) {
+                            double bval = beta[grow];
+                            if (bscale) bval *= bscale[grow];
+                            const double na = (KIND == KDCD_KERNEL_RBF) ? norms[grow] : 0.0;
+#pragma unroll
+                            for (int tn = 0; tn < TN; ++tn)
+                                if (colok[tn])
+                                    colsum[tn] += bval * kernel_map<KIND>(acc[tm][tn][v], na, nb[tn],
+                                                                          grow == Sc[tn], kp);
+                        }
+                    } else if (grow < sb) {
+                        const int64_t St = clampi(S[grow], 0, m - 1);
+                        const double na = (KIND == KDCD_KERNEL_RBF) ? norms[St] : 0.0;
+#pragma unroll
+                        for (int tn = 0; tn < TN; ++tn) {
+                            const int64_t gcol = col0 + (wn * TN + tn) * 16 + (lane & 15);
+                            if (colok[tn])
+                                W[grow * sb + gcol] = kernel_map<KIND>(acc[tm][tn][v], na, nb[tn],
+                                                                       St == Sc[tn], kp);
+                        }
                     }
                 }
             }
@@ -238,6 +324,18 @@ __global__ __launch_bounds__(64 * WM * WN) void kblock_f64_kernel(
     }
     if (is_w) return;
 
+    if constexpr (BATCH) {   // every problem: waves -> one partial row per group
+        __syncthreads();
+        const int np = bd->nprob;
+        for (int x = tid; x < np * BN; x += NT) {
+            const int p = x / BN, c = x % BN;
+            double s = 0.0;
+#pragma unroll
+            for (int w = 0; w < WM; ++w) s += redb[p][w][c];
+            if (col0 + c < sb) partial[((int64_t)p * n_row_groups + rg) * sb + col0 + c] = s;
+        }
+        return;
+    }
     // deterministic column reduction: lanes -> waves -> one partial row per group
 #pragma unroll
     for (int tn = 0; tn < TN; ++tn) {
@@ -268,7 +366,7 @@ Cfg pick_cfg(int32_t sb)
 
 constexpr int64_t kMaxRowGroups = 1024;
 
-template <int WM, int WN, int TM, int TN>
+template <int WM, int WN, int TM, int TN, bool BATCH>
 hipError_t launch_cfg(const KBlockArgs &a, hipStream_t st)
 {
     constexpr int BM = 16 * TM * WM, BN = 16 * TN * WN;
@@ -282,10 +380,10 @@ hipError_t launch_cfg(const KBlockArgs &a, hipStream_t st)
     const int aligned = (A->ld % 2 == 0) && ((reinterpret_cast<uintptr_t>(A->values) & 15) == 0);
     dim3 grid((unsigned)blocks), block(64 * WM * WN);
 #define KDCD_LAUNCH(KIND)                                                                      \
-    hipLaunchKernelGGL((kblock_f64_kernel<WM, WN, TM, TN, KIND>), grid, block, 0, st,          \
+    hipLaunchKernelGGL((kblock_f64_kernel<WM, WN, TM, TN, KIND, BATCH>), grid, block, 0, st,   \
                        A->values, A->ld, A->m, A->n, a.S, a.sb, a.norms, a.kp, a.beta,          \
                        a.beta_scale, a.partial, a.W, (int32_t)n_u, (int32_t)groups,            \
-                       (int32_t)n_w, (int32_t)n_n, aligned)
+                       (int32_t)n_w, (int32_t)n_n, aligned, a.batch)
     switch (a.kp.kind) {
     case KDCD_KERNEL_LINEAR: KDCD_LAUNCH(KDCD_KERNEL_LINEAR); break;
     case KDCD_KERNEL_POLY: KDCD_LAUNCH(KDCD_KERNEL_POLY); break;
@@ -297,20 +395,35 @@ hipError_t launch_cfg(const KBlockArgs &a, hipStream_t st)
 
 }  // namespace
 
-int64_t kblock_f64_row_groups(int64_t m, int32_t sb)
+// Batched launches use a 64 x 64 tile: the mapped values of every sigma group
+// stay in registers while the problems of the group are reduced.
+Cfg pick_cfg_batch(int32_t sb)
 {
-    const Cfg c = pick_cfg(sb);
+    if (sb <= 16) return {128, 16};
+    if (sb <= 32) return {128, 32};
+    return {64, 64};
+}
+
+int64_t kblock_f64_row_groups(int64_t m, int32_t sb, bool batch)
+{
+    const Cfg c = batch ? pick_cfg_batch(sb) : pick_cfg(sb);
     const int64_t n_u = (m + c.bm - 1) / c.bm;
     return n_u < kMaxRowGroups ? n_u : kMaxRowGroups;
 }
 
 hipError_t launch_kblock_f64(const KBlockArgs &a, hipStream_t st)
 {
+    if (a.batch) {
+        const Cfg c = pick_cfg_batch(a.sb);
+        if (c.bn == 16) return launch_cfg<4, 1, 2, 1, true>(a, st);
+        if (c.bn == 32) return launch_cfg<4, 1, 2, 2, true>(a, st);
+        return launch_cfg<2, 2, 2, 2, true>(a, st);
+    }
     const Cfg c = pick_cfg(a.sb);
-    if (c.bn == 16) return launch_cfg<4, 1, 2, 1>(a, st);
-    if (c.bn == 32) return launch_cfg<4, 1, 2, 2>(a, st);
-    if (c.bn == 64) return launch_cfg<2, 2, 2, 2>(a, st);
-    return launch_cfg<2, 2, 2, 4>(a, st);
+    if (c.bn == 16) return launch_cfg<4, 1, 2, 1, false>(a, st);
+    if (c.bn == 32) return launch_cfg<4, 1, 2, 2, false>(a, st);
+    if (c.bn == 64) return launch_cfg<2, 2, 2, 2, false>(a, st);
+    return launch_cfg<2, 2, 2, 4, false>(a, st);
 }
 
 }  // namespace kdcd

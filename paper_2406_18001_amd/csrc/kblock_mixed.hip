@@ -62,12 +62,16 @@ __device__ __forceinline__ f4 mfma_seg(u4 a, u4 b, f4 acc)
 // Elements per 16-byte segment.
 template <int CMP> constexpr int seg_elems() { return CMP == KDCD_F32 ? 4 : 8; }
 
-template <int CMP, int WM, int WN, int TM, int TN, int KIND>
+// BATCH: several problems share the product (see the FP64 kernel): the map
+// runs once per sigma group and every problem reduces its own beta;
+// partial is then [p][row group][sb].
+template <int CMP, int WM, int WN, int TM, int TN, int KIND, bool BATCH>
 __global__ __launch_bounds__(64 * WM * WN) void kblock_mixed_kernel(
     const u4 *__restrict__ Ahi, const u4 *__restrict__ Alo, int64_t ldseg, int64_t m,
     int64_t nseg, const float *__restrict__ normlow, const int32_t *__restrict__ S, int32_t sb,
     KParams kp, const double *__restrict__ beta, const double *__restrict__ bscale,
-    double *__restrict__ partial, int32_t n_u_tiles, int32_t n_row_groups, int32_t n_tiles_n)
+    double *__restrict__ partial, int32_t n_u_tiles, int32_t n_row_groups, int32_t n_tiles_n,
+    const BatchDesc *__restrict__ bd)
 {
     constexpr bool X3 = CMP == KDCD_BF16X3;
     constexpr int NT = 64 * WM * WN;
@@ -80,6 +84,7 @@ __global__ __launch_bounds__(64 * WM * WN) void kblock_mixed_kernel(
     __shared__ u4 As[2][NL][BM * 4];
     __shared__ u4 Bs[2][NL][BN * 4];
     __shared__ double red[WM][BN];
+    __shared__ double redb[BATCH ? kMaxProblems : 1][WM][BN];
 
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int wm = wid / WN, wn = wid % WN;
@@ -110,6 +115,10 @@ __global__ __launch_bounds__(64 * WM * WN) void kblock_mixed_kernel(
     double colsum[TN];
 #pragma unroll
     for (int tn = 0; tn < TN; ++tn) colsum[tn] = 0.0;
+    if constexpr (BATCH) {
+        for (int x = tid; x < kMaxProblems * WM * BN; x += NT) (&redb[0][0][0])[x] = 0.0;
+        __syncthreads();
+    }
 
     const int64_t nK = (nseg + 3) / 4;            // chunks of 4 segments per row
     for (int rt = rg; rt < n_u_tiles; rt += n_row_groups) {
@@ -204,6 +213,55 @@ __global__ __launch_bounds__(64 * WM * WN) void kblock_mixed_kernel(
         }
 
         // epilogue: item v of lane l is row 4 (l/16) + v, column l%16 of its block
+        if constexpr (BATCH) {
+            const int ng = bd->ngroups, np = bd->nprob;
+            for (int g = 0; g < ng; ++g) {
+                KParams kg = kp;
+                kg.sigma = bd->sigma[g];
+                float kv[TM][4][TN];
+#pragma unroll
+                for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int64_t grow = row0 + (wm * TM + tm) * 16 + 4 * (lane >> 4) + v;
+                        const float na = (KIND == KDCD_KERNEL_RBF) ? normlow[clampi(grow, 0, m - 1)] : 0.0f;
+#pragma unroll
+                        for (int tn = 0; tn < TN; ++tn)
+                            kv[tm][v][tn] = (grow < m && colok[tn])
+                                                ? kernel_map_f32<KIND>(acc[tm][tn][v], na, nb[tn],
+                                                                       grow == Sc[tn], kg)
+                                                : 0.0f;
+                    }
+                for (int p = 0; p < np; ++p) {
+                    if (bd->group[p] != g) continue;
+                    const double *bp = bd->beta[p];
+                    const double *sp = bd->bscale[p];
+                    double bv[TM][4];
+#pragma unroll
+                    for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int64_t grow = row0 + (wm * TM + tm) * 16 + 4 * (lane >> 4) + v;
+                            double x = 0.0;
+                            if (grow < m) {
+                                x = bp[grow];
+                                if (sp) x *= sp[grow];
+                            }
+                            bv[tm][v] = x;
+                        }
+#pragma unroll
+                    for (int tn = 0; tn < TN; ++tn) {
+                        double acc_p = 0.0;
+#pragma unroll
+                        for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) acc_p += bv[tm][v] * (double)kv[tm][v][tn];
+                        acc_p = wave_sum_xor16_32(acc_p);
+                        if (lane < 16) redb[p][wm][(wn * TN + tn) * 16 + lane] += acc_p;
+                    }
+                }
+            }
+        } else {
 #pragma unroll
         for (int tm = 0; tm < TM; ++tm) {
 #pragma unroll
@@ -221,8 +279,21 @@ __global__ __launch_bounds__(64 * WM * WN) void kblock_mixed_kernel(
                 }
             }
         }
+        }
     }
 
+    if constexpr (BATCH) {
+        __syncthreads();
+        const int np = bd->nprob;
+        for (int x = tid; x < np * BN; x += NT) {
+            const int p = x / BN, c = x % BN;
+            double s = 0.0;
+#pragma unroll
+            for (int w = 0; w < WM; ++w) s += redb[p][w][c];
+            if (col0 + c < sb) partial[((int64_t)p * n_row_groups + rg) * sb + col0 + c] = s;
+        }
+        return;
+    }
 #pragma unroll
     for (int tn = 0; tn < TN; ++tn) {
         const double v = wave_sum_xor16_32(colsum[tn]);
@@ -291,7 +362,7 @@ Cfg pick_cfg(int32_t sb)
     return {128, 128};
 }
 
-template <int CMP, int WM, int WN, int TM, int TN>
+template <int CMP, int WM, int WN, int TM, int TN, bool BATCH>
 hipError_t launch_cfg(const KBlockArgs &a, hipStream_t st)
 {
     constexpr int BM = 16 * TM * WM, BN = 16 * TN * WN;
@@ -304,10 +375,10 @@ hipError_t launch_cfg(const KBlockArgs &a, hipStream_t st)
     const int64_t nseg = (A->n * esz + 15) / 16;
     dim3 grid((unsigned)(n_n * groups)), block(64 * WM * WN);
 #define KDCD_LAUNCH(KIND)                                                                       \
-    hipLaunchKernelGGL((kblock_mixed_kernel<CMP, WM, WN, TM, TN, KIND>), grid, block, 0, st,    \
+    hipLaunchKernelGGL((kblock_mixed_kernel<CMP, WM, WN, TM, TN, KIND, BATCH>), grid, block, 0, st, \
                        static_cast<const u4 *>(a.Alow), static_cast<const u4 *>(a.Alow2), ldseg, \
                        A->m, nseg, a.normlow, a.S, a.sb, a.kp, a.beta, a.beta_scale, a.partial, \
-                       (int32_t)n_u, (int32_t)groups, (int32_t)n_n)
+                       (int32_t)n_u, (int32_t)groups, (int32_t)n_n, a.batch)
     switch (a.kp.kind) {
     case KDCD_KERNEL_LINEAR: KDCD_LAUNCH(KDCD_KERNEL_LINEAR); break;
     case KDCD_KERNEL_POLY: KDCD_LAUNCH(KDCD_KERNEL_POLY); break;
@@ -317,21 +388,36 @@ hipError_t launch_cfg(const KBlockArgs &a, hipStream_t st)
     return hipGetLastError();
 }
 
+// Batched launches use at most a 128 x 64 tile (mapped values of a sigma group
+// stay in registers while its problems are reduced).
+Cfg pick_cfg_batch(int32_t sb)
+{
+    if (sb <= 16) return {128, 16};
+    if (sb <= 32) return {128, 32};
+    return {128, 64};
+}
+
 template <int CMP>
 hipError_t launch_for(const KBlockArgs &a, hipStream_t st)
 {
+    if (a.batch) {
+        const Cfg c = pick_cfg_batch(a.sb);
+        if (c.bn == 16) return launch_cfg<CMP, 4, 1, 2, 1, true>(a, st);
+        if (c.bn == 32) return launch_cfg<CMP, 4, 1, 2, 2, true>(a, st);
+        return launch_cfg<CMP, 2, 2, 4, 2, true>(a, st);
+    }
     const Cfg c = pick_cfg(a.sb);
-    if (c.bn == 16) return launch_cfg<CMP, 4, 1, 2, 1>(a, st);
-    if (c.bn == 32) return launch_cfg<CMP, 4, 1, 2, 2>(a, st);
-    if (c.bn == 64) return launch_cfg<CMP, 2, 2, 4, 2>(a, st);
-    return launch_cfg<CMP, 2, 2, 4, 4>(a, st);
+    if (c.bn == 16) return launch_cfg<CMP, 4, 1, 2, 1, false>(a, st);
+    if (c.bn == 32) return launch_cfg<CMP, 4, 1, 2, 2, false>(a, st);
+    if (c.bn == 64) return launch_cfg<CMP, 2, 2, 4, 2, false>(a, st);
+    return launch_cfg<CMP, 2, 2, 4, 4, false>(a, st);
 }
 
 }  // namespace
 
-int64_t kblock_mixed_row_groups(int64_t m, int32_t sb)
+int64_t kblock_mixed_row_groups(int64_t m, int32_t sb, bool batch)
 {
-    const Cfg c = pick_cfg(sb);
+    const Cfg c = batch ? pick_cfg_batch(sb) : pick_cfg(sb);
     const int64_t n_u = (m + c.bm - 1) / c.bm;
     return n_u < kMaxRowGroups ? n_u : kMaxRowGroups;
 }

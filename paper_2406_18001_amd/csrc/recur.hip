@@ -103,11 +103,18 @@ __device__ __forceinline__ void stage_diag(const double *__restrict__ W, int32_t
 // K-SVM recurrence.  NT threads (512 covers sb <= 512, 1024 covers sb <= 1024);
 // PF = W values of the next fold-in phase prefetched into registers.
 template <int NT>
-__global__ __launch_bounds__(NT) void ksvm_recur_kernel(
-    const double *__restrict__ r, const double *__restrict__ W, const int32_t *__restrict__ S,
-    int32_t sb, int64_t m, const double *__restrict__ y, double *__restrict__ alpha, double nu,
-    double omega, double *__restrict__ trace, int32_t *status)
+__global__ __launch_bounds__(NT) void ksvm_recur_kernel(const KsvmRecurDesc D,
+                                                        const int32_t *__restrict__ S, int32_t sb,
+                                                        int64_t m, int32_t *status)
 {
+    // problem of this workgroup (one workgroup per problem of a batch)
+    const int pb = blockIdx.x;
+    const double *__restrict__ r = D.r[pb];
+    const double *__restrict__ W = D.W[pb];
+    const double *__restrict__ y = D.y[pb];
+    double *__restrict__ alpha = D.alpha[pb];
+    double *__restrict__ trace = D.trace[pb];
+    const double nu = D.nu[pb], omega = D.omega[pb];
     constexpr int PF = NT <= 512 ? 64 : 32;
     __shared__ double Wd[2][64 * 64];
     __shared__ double th_l[kMaxSB + 64];       // padded: entries >= sb hold 0 / -1
@@ -196,12 +203,20 @@ __global__ __launch_bounds__(NT) void ksvm_recur_kernel(
 // thread count; BX > 0 fixes b = BX at compile time (fully unrolled block
 // loops), BX = 0 handles any b <= BMAX.
 template <int BMAX, int NT, int BX>
-__global__ __launch_bounds__(NT) void krr_recur_kernel(
-    const double *__restrict__ r, const double *__restrict__ W, const double *__restrict__ Dinv,
-    const int32_t *__restrict__ S, int32_t b, int32_t sk, int64_t m,
-    const double *__restrict__ y, double *__restrict__ alpha, double lambda, double mdbl,
-    double *__restrict__ trace, int32_t *status)
+__global__ __launch_bounds__(NT) void krr_recur_kernel(const KrrRecurDesc D,
+                                                       const int32_t *__restrict__ S, int32_t b,
+                                                       int32_t sk, int64_t m, double mdbl,
+                                                       int32_t *status)
 {
+    // problem of this workgroup (one workgroup per problem of a batch)
+    const int pb = blockIdx.x;
+    const double *__restrict__ r = D.r[pb];
+    const double *__restrict__ W = D.W[pb];
+    const double *__restrict__ Dinv = D.Dinv[pb];
+    const double *__restrict__ y = D.y[pb];
+    double *__restrict__ alpha = D.alpha[pb];
+    double *__restrict__ trace = D.trace[pb];
+    const double lambda = D.lambda[pb];
     constexpr int PF = NT > 512 ? 16 : ((BMAX >= 32 || BX == 0) ? 32 : 64);
     __shared__ double Wd[2][64 * 64];
     __shared__ double c_l[kMaxSB + 64];        // padded: entries past the last panel hold 0 / -1
@@ -362,29 +377,26 @@ int krr_recur_threads(int32_t b, int32_t sk)
     return waves * 64;
 }
 
-hipError_t launch_ksvm_recur(const double *r, const double *W, const int32_t *S, int32_t sb,
-                             int64_t m, const double *y, double *alpha, double nu, double omega,
-                             double *trace, int32_t *status, hipStream_t st)
+hipError_t launch_ksvm_recur(const KsvmRecurDesc &d, int32_t nprob, const int32_t *S, int32_t sb,
+                             int64_t m, int32_t *status, hipStream_t st)
 {
     if (sb <= 512)
-        hipLaunchKernelGGL((ksvm_recur_kernel<512>), dim3(1), dim3(512), 0, st, r, W, S, sb, m, y,
-                           alpha, nu, omega, trace, status);
+        hipLaunchKernelGGL((ksvm_recur_kernel<512>), dim3(nprob), dim3(512), 0, st, d, S, sb, m,
+                           status);
     else
-        hipLaunchKernelGGL((ksvm_recur_kernel<1024>), dim3(1), dim3(1024), 0, st, r, W, S, sb, m,
-                           y, alpha, nu, omega, trace, status);
+        hipLaunchKernelGGL((ksvm_recur_kernel<1024>), dim3(nprob), dim3(1024), 0, st, d, S, sb, m,
+                           status);
     return hipGetLastError();
 }
 
-hipError_t launch_krr_recur(const double *r, const double *W, const double *Dinv,
-                            const int32_t *S, int32_t b, int32_t sk, int64_t m, const double *y,
-                            double *alpha, double lambda, double mdbl, double *trace,
-                            int32_t *status, hipStream_t st)
+hipError_t launch_krr_recur(const KrrRecurDesc &d, int32_t nprob, const int32_t *S, int32_t b,
+                            int32_t sk, int64_t m, double mdbl, int32_t *status, hipStream_t st)
 {
     const int nt = krr_recur_threads(b, sk);
     if (nt > 1024 || b > kMaxB) return hipErrorInvalidValue;
-#define KDCD_KRR(BM_, NT_, BX_)                                                               \
-    hipLaunchKernelGGL((krr_recur_kernel<BM_, NT_, BX_>), dim3(1), dim3(NT_), 0, st, r, W, Dinv, S, \
-                       b, sk, m, y, alpha, lambda, mdbl, trace, status)
+#define KDCD_KRR(BM_, NT_, BX_)                                                                 \
+    hipLaunchKernelGGL((krr_recur_kernel<BM_, NT_, BX_>), dim3(nprob), dim3(NT_), 0, st, d, S, b, \
+                       sk, m, mdbl, status)
     if (nt <= 512) {
         switch (b) {
         case 1: KDCD_KRR(1, 512, 1); break;

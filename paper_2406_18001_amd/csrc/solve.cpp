@@ -14,7 +14,6 @@ using namespace kdcd;
 
 namespace kdcd {
 hipError_t launch_kblock_mixed(const KBlockArgs &a, hipStream_t st);
-int64_t kblock_mixed_row_groups(int64_t m, int32_t sb);
 hipError_t launch_kblock_csr(const KBlockArgs &a, hipStream_t st);
 int64_t kblock_csr_row_groups(int64_t m, int32_t sb);
 hipError_t launch_convert_lowp(const kdcd_matrix *A, int32_t compute, void *hi, void *lo,
@@ -64,11 +63,11 @@ kdcd_status check_compute(const kdcd_matrix *A, int32_t compute)
     return KDCD_OK;
 }
 
-int64_t row_groups(const kdcd_matrix *A, int32_t sb, int32_t compute)
+int64_t row_groups(const kdcd_matrix *A, int32_t sb, int32_t compute, bool batch = false)
 {
     if (A->format == KDCD_CSR) return kblock_csr_row_groups(A->m, sb);
-    if (compute == KDCD_F64) return kblock_f64_row_groups(A->m, sb);
-    return kblock_mixed_row_groups(A->m, sb);
+    if (compute == KDCD_F64) return kblock_f64_row_groups(A->m, sb, batch);
+    return kblock_mixed_row_groups(A->m, sb, batch);
 }
 
 // One kernel-block pass.  Mixed precisions produce the U-part only; their
@@ -297,17 +296,40 @@ kdcd_status run_solve(const SolveArgs &sa)
         KDCD_HIP_TRY(launch_kblock(kb, st));
         timer.end(0, st);
         timer.begin(1, st);
-        KDCD_HIP_TRY(launch_finish(partial, row_groups(A, sb, sa.opt.compute), sb, r, W, sa.b, sk,
-                                   svm ? 0.0 : 1.0 / sa.lambda, (double)A->m, Dinv, status, st));
+        FinishDesc fd{};
+        fd.nprob = 1;
+        fd.nkrr = svm ? 0 : 1;
+        fd.groups = (int32_t)row_groups(A, sb, sa.opt.compute);
+        fd.partial[0] = partial;
+        fd.r[0] = r;
+        fd.W[0] = W;
+        fd.Dinv[0] = Dinv;
+        fd.inv_lambda[0] = svm ? 0.0 : 1.0 / sa.lambda;
+        KDCD_HIP_TRY(launch_finish(fd, sb, sa.b, sk, (double)A->m, status, st));
         timer.end(1, st);
         timer.begin(2, st);
         double *tr = sa.opt.trace ? sa.opt.trace + done * sa.b : nullptr;
-        if (svm)
-            KDCD_HIP_TRY(launch_ksvm_recur(r, W, S, sb, A->m, sa.y, sa.alpha, nu, omega, tr,
-                                           status, st));
-        else
-            KDCD_HIP_TRY(launch_krr_recur(r, W, Dinv, S, sa.b, sk, A->m, sa.y, sa.alpha,
-                                          sa.lambda, (double)A->m, tr, status, st));
+        if (svm) {
+            KsvmRecurDesc kd{};
+            kd.r[0] = r;
+            kd.W[0] = W;
+            kd.y[0] = sa.y;
+            kd.alpha[0] = sa.alpha;
+            kd.trace[0] = tr;
+            kd.nu[0] = nu;
+            kd.omega[0] = omega;
+            KDCD_HIP_TRY(launch_ksvm_recur(kd, 1, S, sb, A->m, status, st));
+        } else {
+            KrrRecurDesc rd{};
+            rd.r[0] = r;
+            rd.W[0] = W;
+            rd.Dinv[0] = Dinv;
+            rd.y[0] = sa.y;
+            rd.alpha[0] = sa.alpha;
+            rd.trace[0] = tr;
+            rd.lambda[0] = sa.lambda;
+            KDCD_HIP_TRY(launch_krr_recur(rd, 1, S, sa.b, sk, A->m, (double)A->m, status, st));
+        }
         timer.end(2, st);
         if (sa.opt.snapshot_every > 0 && sa.opt.snapshots &&
             ((k + 1) % sa.opt.snapshot_every == 0 || k + 1 == n_outer)) {
@@ -383,6 +405,181 @@ kdcd_status kdcd_krr_solve(const kdcd_matrix *A, const double *y, const kdcd_ker
     return run_solve(sa);
 }
 
+kdcd_status kdcd_batch_solve(const kdcd_matrix *A, const kdcd_kernel *kernel, int32_t b,
+                             int32_t s, int64_t H, const int32_t *idx,
+                             const kdcd_batch_problem *problems, int32_t n_problems,
+                             const kdcd_options *opt, kdcd_stream stream)
+{
+    kdcd_status rc = check_matrix(A);
+    if (rc != KDCD_OK) return rc;
+    if (!kernel || kernel->kind < KDCD_KERNEL_LINEAR || kernel->kind > KDCD_KERNEL_RBF)
+        return KDCD_ERR_INVALID_ARG;
+    if (!idx || !problems || n_problems < 1 || b < 1 || s < 1 || H < 1 || b > A->m)
+        return KDCD_ERR_INVALID_ARG;
+    if (n_problems > kMaxProblems || (int64_t)s * b > kMaxSB) return KDCD_ERR_UNSUPPORTED;
+    kdcd_options o = defaults(opt);
+    if ((rc = check_compute(A, o.compute)) != KDCD_OK) return rc;
+    if (A->format != KDCD_DENSE) return KDCD_ERR_UNSUPPORTED;
+    if (o.snapshot_every != 0 || o.trace) return KDCD_ERR_INVALID_ARG;   // per problem instead
+    const bool rbf = kernel->kind == KDCD_KERNEL_RBF;
+
+    // sigma groups and problem lists
+    BatchDesc bd{};
+    bd.nprob = n_problems;
+    std::vector<int> krr, svm;
+    for (int p = 0; p < n_problems; ++p) {
+        const kdcd_batch_problem &q = problems[p];
+        kdcd_kernel kp = *kernel;
+        kp.sigma = q.sigma;
+        if ((rc = check_kernel(&kp)) != KDCD_OK) return rc;
+        if (!q.y || !q.alpha || !finite_pos(q.param)) return KDCD_ERR_INVALID_ARG;
+        if (q.problem == 1) {
+            krr.push_back(p);
+        } else if (q.problem == 0) {
+            if (q.loss != 0 && q.loss != 1 && q.loss != 2) return KDCD_ERR_INVALID_ARG;
+            svm.push_back(p);
+        } else {
+            return KDCD_ERR_INVALID_ARG;
+        }
+        int g = 0;
+        if (rbf) {
+            while (g < bd.ngroups && bd.sigma[g] != q.sigma) ++g;
+            if (g == bd.ngroups) {
+                if (bd.ngroups == kMaxSigmas) return KDCD_ERR_UNSUPPORTED;
+                bd.sigma[bd.ngroups++] = q.sigma;
+            }
+        } else {
+            bd.ngroups = 1;
+            bd.sigma[0] = kernel->sigma;
+        }
+        bd.group[p] = g;
+        bd.beta[p] = q.alpha;
+        bd.bscale[p] = q.problem == 0 ? q.y : nullptr;
+    }
+    if (!krr.empty()) {
+        if (b > kMaxB) return KDCD_ERR_UNSUPPORTED;
+        const int nt = krr_recur_threads(b, s);
+        if (nt > 1024 || (b > 16 && nt > 512)) return KDCD_ERR_UNSUPPORTED;
+    }
+
+    // workspace: single-problem layout plus the per-problem / per-sigma buffers
+    const hipStream_t st = (hipStream_t)stream;
+    const int64_t sbmax = (int64_t)s * b;
+    Layout L = make_layout(0, A, kernel, b, s, o.compute);
+    size_t off = L.total;
+    const size_t o_bd = off; off += align256(sizeof(BatchDesc));
+    // every dense tile is at least 64 rows tall, so no launch has more row groups
+    const int64_t max_groups = std::min<int64_t>(kMaxGroups, (A->m + 63) / 64);
+    const size_t o_part = off; off += align256(sizeof(double) * (size_t)(n_problems * max_groups * sbmax));
+    const size_t o_r = off; off += align256(sizeof(double) * (size_t)(n_problems * sbmax));
+    const size_t o_W = off; off += align256(sizeof(double) * (size_t)(bd.ngroups * sbmax * sbmax));
+    const size_t o_D = off; off += align256(sizeof(double) * (size_t)(krr.size() * sbmax * b + 1));
+    L.total = off;
+    Workspace ws;
+    if ((rc = acquire(ws, L, &o, st)) != KDCD_OK) return rc;
+    int32_t *status = ws.at<int32_t>(L.status);
+    double *norms = ws.at<double>(L.norms);
+    BatchDesc *dbd = ws.at<BatchDesc>(o_bd);
+    double *partial = ws.at<double>(o_part);
+    double *r = ws.at<double>(o_r);
+    double *W = ws.at<double>(o_W);
+    double *Dinv = ws.at<double>(o_D);
+
+    KDCD_HIP_TRY(hipMemcpyAsync(dbd, &bd, sizeof(BatchDesc), hipMemcpyHostToDevice, st));
+    KDCD_HIP_TRY(launch_fill_i32(status, 0, 1, st));
+    KDCD_HIP_TRY(launch_validate(idx, H * b, A->m, nullptr, nullptr, 0, 0, 0.0, status, st));
+    for (int p = 0; p < n_problems; ++p) {
+        const kdcd_batch_problem &q = problems[p];
+        const double nu = q.problem == 0 ? (q.loss == 2 ? INFINITY : q.param) : 0.0;
+        KDCD_HIP_TRY(launch_validate(idx, 0, A->m, q.y, q.alpha, A->m, q.problem == 0 ? 0 : 1, nu,
+                                     status, st));
+    }
+    if (rbf) KDCD_HIP_TRY(launch_norms(A, norms, st));
+
+    KBlockArgs base{};
+    base.A = A;
+    base.norms = norms;
+    base.kp = to_params(kernel);
+    base.beta = problems[0].alpha;
+    base.partial = partial;
+    base.W = W;
+    base.status = status;
+    base.compute = o.compute;
+    base.batch = dbd;
+    KBlockArgs kb;
+    if ((rc = prepare_lowp(base, L, ws, st, kb)) != KDCD_OK) return rc;
+
+    StageTimer timer;
+    timer.on = o.profile != nullptr;
+    const int64_t n_outer = (H + s - 1) / s;
+    for (int64_t k = 0; k < n_outer; ++k) {
+        const int64_t done = k * s;
+        const int32_t sk = (int32_t)std::min<int64_t>(s, H - done);
+        const int32_t sb = sk * b;
+        const int32_t *S = idx + done * b;
+        const int32_t groups = (int32_t)row_groups(A, sb, o.compute, true);
+        kb.S = S;
+        kb.sb = sb;
+        timer.begin(0, st);
+        KDCD_HIP_TRY(launch_kblock(kb, st));
+        timer.end(0, st);
+
+        timer.begin(1, st);
+        FinishDesc fd{};
+        fd.nprob = n_problems;
+        fd.nkrr = (int32_t)krr.size();
+        fd.groups = groups;
+        for (int p = 0; p < n_problems; ++p) {
+            fd.partial[p] = partial + (int64_t)p * groups * sb;
+            fd.r[p] = r + (int64_t)p * sb;
+        }
+        for (size_t kk = 0; kk < krr.size(); ++kk) {
+            const int p = krr[kk];
+            fd.W[kk] = W + (int64_t)bd.group[p] * sb * sb;
+            fd.Dinv[kk] = Dinv + (int64_t)kk * sb * b;
+            fd.inv_lambda[kk] = 1.0 / problems[p].param;
+        }
+        KDCD_HIP_TRY(launch_finish(fd, sb, b, sk, (double)A->m, status, st));
+        timer.end(1, st);
+
+        timer.begin(2, st);
+        if (!krr.empty()) {
+            KrrRecurDesc rd{};
+            for (size_t kk = 0; kk < krr.size(); ++kk) {
+                const int p = krr[kk];
+                rd.r[kk] = r + (int64_t)p * sb;
+                rd.W[kk] = W + (int64_t)bd.group[p] * sb * sb;
+                rd.Dinv[kk] = Dinv + (int64_t)kk * sb * b;
+                rd.y[kk] = problems[p].y;
+                rd.alpha[kk] = problems[p].alpha;
+                rd.trace[kk] = problems[p].trace ? problems[p].trace + done * b : nullptr;
+                rd.lambda[kk] = problems[p].param;
+            }
+            KDCD_HIP_TRY(launch_krr_recur(rd, (int32_t)krr.size(), S, b, sk, A->m, (double)A->m,
+                                          status, st));
+        }
+        if (!svm.empty()) {
+            KsvmRecurDesc kd{};
+            for (size_t qq = 0; qq < svm.size(); ++qq) {
+                const int p = svm[qq];
+                const kdcd_batch_problem &q = problems[p];
+                kd.r[qq] = r + (int64_t)p * sb;
+                kd.W[qq] = W + (int64_t)bd.group[p] * sb * sb;
+                kd.y[qq] = q.y;
+                kd.alpha[qq] = q.alpha;
+                kd.trace[qq] = q.trace ? q.trace + done * b : nullptr;
+                kd.nu[qq] = q.loss == 2 ? INFINITY : q.param;
+                kd.omega[qq] = q.loss == 2 ? 1.0 / (2.0 * q.param) : 0.0;
+            }
+            KDCD_HIP_TRY(launch_ksvm_recur(kd, (int32_t)svm.size(), S, sb, A->m, status, st));
+        }
+        timer.end(2, st);
+    }
+    rc = read_status(status, st);
+    timer.report(o.profile);
+    return rc;
+}
+
 kdcd_status kdcd_kernel_rhs(const kdcd_matrix *A, const kdcd_kernel *kernel, const int32_t *S,
                             int32_t sb, const double *beta, const double *beta_scale, double *r,
                             double *W, int32_t compute, kdcd_stream stream)
@@ -419,8 +616,12 @@ kdcd_status kdcd_kernel_rhs(const kdcd_matrix *A, const kdcd_kernel *kernel, con
     KBlockArgs kb;
     if ((rc = prepare_lowp(base, L, ws, st, kb)) != KDCD_OK) return rc;
     KDCD_HIP_TRY(launch_kblock(kb, st));
-    KDCD_HIP_TRY(launch_finish(partial, row_groups(A, sb, compute), sb, r, nullptr, 1, 0, 0.0, 0.0,
-                               nullptr, status, st));
+    FinishDesc fd{};
+    fd.nprob = 1;
+    fd.groups = (int32_t)row_groups(A, sb, compute);
+    fd.partial[0] = partial;
+    fd.r[0] = r;
+    KDCD_HIP_TRY(launch_finish(fd, sb, 1, 0, 0.0, status, st));
     return read_status(status, st);
 }
 
@@ -458,8 +659,12 @@ static kdcd_status kernel_matvec(const kdcd_matrix *A, const kdcd_kernel *kernel
         a.status = status;
         a.compute = KDCD_F64;
         KDCD_HIP_TRY(launch_kblock(a, st));
-        KDCD_HIP_TRY(launch_finish(partial, row_groups(A, sb, KDCD_F64), sb, r, nullptr, 1, 0, 0.0,
-                                   0.0, nullptr, status, st));
+        FinishDesc fd{};
+        fd.nprob = 1;
+        fd.groups = (int32_t)row_groups(A, sb, KDCD_F64);
+        fd.partial[0] = partial;
+        fd.r[0] = r;
+        KDCD_HIP_TRY(launch_finish(fd, sb, 1, 0, 0.0, status, st));
         KDCD_HIP_TRY(hipMemcpyAsync(out.data() + c0, r, sizeof(double) * (size_t)sb,
                                     hipMemcpyDeviceToHost, st));
     }

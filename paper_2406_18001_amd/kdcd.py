@@ -79,6 +79,12 @@ class _Profile(ctypes.Structure):
                 ("total_ms", ctypes.c_double)]
 
 
+class _BatchProblem(ctypes.Structure):
+    _fields_ = [("problem", ctypes.c_int32), ("loss", ctypes.c_int32),
+                ("param", ctypes.c_double), ("sigma", ctypes.c_double),
+                ("y", ctypes.c_void_p), ("alpha", ctypes.c_void_p), ("trace", ctypes.c_void_p)]
+
+
 class _Options(ctypes.Structure):
     _fields_ = [("compute", ctypes.c_int32), ("loss", ctypes.c_int32),
                 ("snapshot_every", ctypes.c_int32), ("flags", ctypes.c_int32),
@@ -93,6 +99,9 @@ _lib.kdcd_ksvm_solve.argtypes = [_P, _P, _P, ctypes.c_double, ctypes.c_int32, ct
                                  ctypes.c_int64, _P, _P, _P, _P]
 _lib.kdcd_krr_solve.restype = ctypes.c_int
 _lib.kdcd_krr_solve.argtypes = _lib.kdcd_ksvm_solve.argtypes
+_lib.kdcd_batch_solve.restype = ctypes.c_int
+_lib.kdcd_batch_solve.argtypes = [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, _P, _P,
+                                  ctypes.c_int32, _P, _P]
 _lib.kdcd_kernel_rhs.restype = ctypes.c_int
 _lib.kdcd_kernel_rhs.argtypes = [_P, _P, _P, ctypes.c_int32, _P, _P, _P, _P, ctypes.c_int32, _P]
 _lib.kdcd_ksvm_eval.restype = ctypes.c_int
@@ -224,6 +233,52 @@ def kdcd_krr_solve(A, y, kernel, lam, b, s, H, idx, alpha, *, compute="f64", sna
     """s-step BDCD for K-RR (Algorithm 4); alpha is updated in place."""
     return _solve(_lib.kdcd_krr_solve, "kdcd_krr_solve", A, y, kernel, lam, b, s, H, idx, alpha,
                   compute, 1, snapshot_every, snapshots, trace, workspace, profile, flags, stream)
+
+
+class BatchProblem(NamedTuple):
+    """One problem of kdcd_batch_solve.  problem: "ksvm" or "krr"; param: C or
+    lambda; sigma: the RBF width of this problem (ignored by other kernels);
+    y, alpha (updated in place) and the optional trace (H*b entries) are
+    float64 GPU tensors."""
+    problem: str
+    param: float
+    sigma: float
+    y: torch.Tensor
+    alpha: torch.Tensor
+    loss: int = 1
+    trace: Optional[torch.Tensor] = None
+
+
+def kdcd_batch_solve(A, kernel, b, s, H, idx, problems, *, compute="f64", workspace=None,
+                     profile=False, flags=0, stream=None):
+    """Batched s-step solves sharing every kernel-block product: K-RR problem p
+    equals kdcd_krr_solve(..., b, s, H, ...) and K-SVM problem q equals
+    kdcd_ksvm_solve(..., 1, s*b, H*b, ...) over the same idx."""
+    mat, m, _ = _matrix(A)
+    _dev(idx, torch.int32, int(H) * int(b), "idx")
+    arr = (_BatchProblem * max(len(problems), 1))()
+    for i, q in enumerate(problems):
+        q = q if isinstance(q, BatchProblem) else BatchProblem(**q)
+        if q.problem not in ("ksvm", "krr"):
+            raise ValueError(f"problem {i}: kind must be 'ksvm' or 'krr'")
+        arr[i].problem = 0 if q.problem == "ksvm" else 1
+        arr[i].loss = int(q.loss)
+        arr[i].param = float(q.param)
+        arr[i].sigma = float(q.sigma)
+        arr[i].y = _dev(q.y, torch.float64, m, f"problems[{i}].y")
+        arr[i].alpha = _dev(q.alpha, torch.float64, m, f"problems[{i}].alpha")
+        arr[i].trace = (None if q.trace is None else
+                        _dev(q.trace, torch.float64, int(H) * int(b), f"problems[{i}].trace"))
+    opt, prof = _options(compute, 1, 0, None, None, workspace, profile, flags, m, 0, 0)
+    kern = _kernel(kernel)
+    st = _lib.kdcd_batch_solve(ctypes.byref(mat), ctypes.byref(kern), int(b), int(s), int(H),
+                               idx.data_ptr(), arr, len(problems), ctypes.byref(opt),
+                               _stream(stream))
+    if st != 0:
+        raise KdcdError(st, "kdcd_batch_solve")
+    if prof is not None:
+        return {f: getattr(prof, f) for f, _ in _Profile._fields_}
+    return None
 
 
 def kdcd_kernel_rhs(A, kernel, S, beta, beta_scale=None, *, want_W=False, compute="f64",
