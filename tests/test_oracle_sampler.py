@@ -1,0 +1,150 @@
+"""Pins of the learned-sampler oracle (oracle/sampler.py) against values and
+properties fixed outside it: Philox's published known-answer vectors, the
+Gumbel-max property (the argmax of score/tau + Gumbel noise is distributed as
+softmax(score/tau)), brute-force ranking, hand-evaluated networks, central
+finite differences of the loss, and Adam's closed forms under constant
+gradients."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import sampler as S
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "philox_kat.json")
+
+
+def test_philox_known_answers():
+    cases = json.load(open(GOLD))["cases"]
+    for c in cases:
+        ctr = [int(x, 16) for x in c["ctr"]]
+        key = [int(x, 16) for x in c["key"]]
+        out = S.philox4x32_10([ctr], key)[0]
+        assert [int(v) for v in out] == [int(x, 16) for x in c["out"]]
+
+
+def test_philox_counters_are_independent_streams():
+    x = S.philox4x32_10([[i, 7, 0, 0] for i in range(20000)], S.seed_key(3))
+    u = S.to_unit(x[:, 0])
+    assert np.all((u > 0) & (u < 1))
+    assert abs(u.mean() - 0.5) < 0.01 and abs(u.var() - 1 / 12) < 0.005
+    assert len(np.unique(x[:, 0])) == 20000
+    y = S.philox4x32_10([[i, 8, 0, 0] for i in range(20000)], S.seed_key(3))
+    assert np.corrcoef(S.to_unit(y[:, 0]), u)[0, 1] < 0.03
+
+
+def test_gumbel_max_samples_softmax():
+    scores = np.array([0.0, 1.0, -0.5, 2.0, 0.3], dtype=np.float32)
+    tau = 0.7
+    trials = 20000
+    counts = np.zeros(5)
+    for k in range(trials):
+        counts[np.argmax(S.gumbel_keys(scores, tau, k, seed=11))] += 1
+    p = np.exp(scores / tau)
+    p /= p.sum()
+    assert np.max(np.abs(counts / trials - p)) < 0.012, (counts / trials, p)
+
+
+def test_select_top_keys_ties_and_uniform_slots():
+    rng = np.random.default_rng(0)
+    keys = rng.standard_normal(300).astype(np.float32)
+    keys[[10, 20, 30]] = 5.0                     # a tie at the top: smaller index first
+    top = S.select(keys, 12, 0.0, k=0, seed=1)
+    ranked = sorted(range(300), key=lambda i: (-float(keys[i]), i))
+    assert list(top) == ranked[:12]
+    assert list(top[:3]) == [10, 20, 30]
+    uni = np.concatenate([S.select(keys, 64, 1.0, k=k, seed=2) for k in range(200)])
+    assert uni.min() >= 0 and uni.max() < 300
+    hist = np.bincount(uni, minlength=300)
+    assert hist.min() > 10 and hist.max() < 80      # 42.7 expected per coordinate
+    mix = S.select(keys, 64, 0.25, k=3, seed=4)
+    ctr = [[j, 3, S.TAG_SLOT, 0] for j in range(64)]
+    x = S.philox4x32_10(ctr, S.seed_key(4))
+    is_uni = S.to_unit(x[:, 0]) < 0.25
+    assert 5 <= is_uni.sum() <= 30
+    assert list(mix[~is_uni]) == ranked[:int((~is_uni).sum())]
+
+
+def test_forward_of_hand_built_network():
+    p = np.zeros(S.NPARAMS)
+    w = S.unpack(np.arange(S.NPARAMS, dtype=np.float64))   # offsets of each block
+    o_W1, o_W2, o_w3, o_b3 = int(w["W1"][0, 0]), int(w["W2"][0, 0]), int(w["w3"][0]), int(w["b3"])
+    p[o_W1 + 0] = 1.0          # h1_0 = tanh(x_0)
+    p[o_W1 + 4 + 3] = -2.0     # h1_1 = tanh(-2 x_3)
+    p[o_W2 + 0] = 1.0          # h2_0 = tanh(h1_0)
+    p[o_W2 + 64 + 1] = 0.5     # h2_1 = tanh(0.5 h1_1)
+    p[o_w3 + 0] = 2.0
+    p[o_w3 + 1] = -1.0
+    p[o_b3] = 0.25
+    X = np.array([[0.3, 9.0, -4.0, 1.0], [-1.2, 0.0, 0.0, -0.5]])
+    f, _, _ = S.forward(p, X)
+    for r in range(2):
+        x0, x3 = X[r, 0], X[r, 3]
+        ref = 2.0 * math.tanh(math.tanh(x0)) - math.tanh(0.5 * math.tanh(-2.0 * x3)) + 0.25
+        assert abs(f[r] - ref) < 1e-15
+
+
+def test_gradient_matches_central_differences():
+    rng = np.random.default_rng(5)
+    p = S.init_params(9).astype(np.float64) + 0.05 * rng.standard_normal(S.NPARAMS)
+    X = rng.standard_normal((37, 4))
+    t = rng.standard_normal(37)
+    L, g = S.loss_and_grad(p, X, t)
+    h = 1e-6
+    picks = np.concatenate([rng.choice(S.NPARAMS, 200, replace=False), [S.NPARAMS - 1, 0, 300]])
+    for q in picks:
+        e = np.zeros(S.NPARAMS)
+        e[q] = h
+        fd = (S.loss_and_grad(p + e, X, t)[0] - S.loss_and_grad(p - e, X, t)[0]) / (2 * h)
+        assert abs(fd - g[q]) <= 1e-7 * max(1.0, abs(g[q])) + 1e-9, (q, fd, g[q])
+    assert abs(L - 0.5 * np.mean((S.forward(p, X)[0] - t) ** 2)) < 1e-15
+
+
+def test_gradient_of_constant_network():
+    p = np.zeros(S.NPARAMS)
+    p[-1] = 0.75                                   # f(x) = b3 for every x
+    X = np.random.default_rng(1).standard_normal((10, 4))
+    t = np.linspace(-1, 1, 10)
+    L, g = S.loss_and_grad(p, X, t)
+    assert abs(L - 0.5 * np.mean((0.75 - t) ** 2)) < 1e-15
+    assert abs(g[-1] - np.mean(0.75 - t)) < 1e-15
+    assert np.all(g[:-1] == 0.0)
+
+
+def test_adam_closed_forms():
+    p = np.array([1.0, -2.0, 0.5])
+    g = np.array([0.3, -1e-3, 4.0])
+    m = v = np.zeros(3)
+    for step in range(1, 6):                       # constant gradient: bias correction is exact
+        p_new, m, v = S.adam_step(p, g, m, v, step, lr=0.01)
+        np.testing.assert_allclose(p_new - p, -0.01 * g / (np.abs(g) + 1e-8), rtol=1e-9)
+        p = p_new
+    p2, _, _ = S.adam_step(p, np.zeros(3), np.zeros(3), np.zeros(3), 1, lr=0.1)
+    assert np.all(p2 == p)
+
+
+def test_init_is_glorot_and_seeded():
+    a = S.init_params(1)
+    b = S.init_params(1)
+    c = S.init_params(2)
+    assert a.dtype == np.float32 and np.array_equal(a, b) and not np.array_equal(a, c)
+    w = S.unpack(a.astype(np.float64))
+    for name, bound in (("W1", math.sqrt(6 / 68)), ("W2", math.sqrt(6 / 128)), ("w3", math.sqrt(6 / 65))):
+        x = np.abs(w[name])
+        assert x.max() <= bound * (1 + 1e-7) and x.max() > 0.8 * bound
+    assert np.all(w["b1"] == 0) and np.all(w["b2"] == 0) and w["b3"] == 0
+
+
+def test_train_reduces_loss_and_single_batch_is_one_adam_step():
+    rng = np.random.default_rng(2)
+    X = rng.uniform(-1, 1, (400, 4))
+    t = np.abs(X[:, 0] - X[:, 1]) + 0.5 * X[:, 3]
+    p0 = S.init_params(3)
+    p, losses = S.train(p0, X, t, batch=64, epochs=30, lr=3e-3)
+    assert losses[-1] < 0.25 * losses[0]
+    p1, _ = S.train(p0, X, t, batch=400, epochs=1, lr=1e-3)
+    _, g = S.loss_and_grad(p0, X, t)
+    ref, _, _ = S.adam_step(p0.astype(np.float64), g, 0, 0, 1, 1e-3)
+    np.testing.assert_allclose(p1, ref, rtol=0, atol=1e-15)
