@@ -227,6 +227,94 @@ kdcd_status kdcd_ksvm_eval(const kdcd_matrix *A, const double *y, const kdcd_ker
 kdcd_status kdcd_krr_eval(const kdcd_matrix *A, const double *y, const kdcd_kernel *kernel,
                           double lambda, const double *alpha, double *out, kdcd_stream stream);
 
+/* ---------------------------------------------------------------------------
+ * Learned coordinate sampler.  Algorithms 1-4 take their coordinate sequence
+ * as an input and the paper draws it uniformly (Section 3); here a small MLP
+ * (4 -> 64 -> 64 -> 1, tanh hidden units, FP32) scores every coordinate of a
+ * K-SVM from its state x_i = (alpha_i / C, g_i, K_ii, y_i), where
+ * g = Q alpha - 1 + omega alpha is the full dual gradient, and the s
+ * coordinates of an outer iteration are drawn by Gumbel-top-k over
+ * score / tau, a share epsilon of the slots being drawn uniformly.
+ *
+ * Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC 2011) with
+ * key (seed mod 2^32, seed >> 32); a 32-bit output x gives u = (x + 0.5)/2^32.
+ *   coordinate noise of outer iteration k: counter (i, k, 0, 0), Gumbel
+ *     G_i = -log(-log u(x0)); key_i = float(score_i / tau + G_i)
+ *   slot j of outer iteration k: counter (j, k, 1, 0); the slot is uniform
+ *     when u(x0) < epsilon and then takes coordinate floor(x1 * m / 2^32),
+ *     otherwise it takes the next best key (keys ranked by value, ties by the
+ *     smaller index)
+ *   initial weight p: counter (p, 0, 2, 0); Glorot-uniform weights with bound
+ *     sqrt(6 / (fan_in + fan_out)), zero biases
+ * Parameter layout (KDCD_SAMPLER_NPARAMS floats): W1[64][4], b1[64],
+ * W2[64][64], b2[64], w3[64], b3.  Training minimises
+ * 1/(2n) sum_i (f(x_i) - t_i)^2 with Adam (Kingma and Ba, 2015; beta1 0.9,
+ * beta2 0.999, eps 1e-8), one step per minibatch, minibatches in data order.
+ * A model lives on the device that was current at creation; all calls on it
+ * must use that device.  Calls on one model must not overlap.
+ * ------------------------------------------------------------------------- */
+#define KDCD_SAMPLER_NPARAMS 4545
+typedef struct kdcd_sampler kdcd_sampler;
+
+/* Allocate a model on the current device with Glorot-uniform weights. */
+kdcd_status kdcd_sampler_create(kdcd_sampler **out, uint64_t seed);
+void kdcd_sampler_destroy(kdcd_sampler *model);
+/* Copy the parameters to / from device memory (KDCD_SAMPLER_NPARAMS floats);
+ * set_params also clears the Adam state.  Both synchronise `stream`. */
+kdcd_status kdcd_sampler_get_params(const kdcd_sampler *model, float *params, kdcd_stream stream);
+kdcd_status kdcd_sampler_set_params(kdcd_sampler *model, const float *params, kdcd_stream stream);
+/* out[i] = f(x_i); x device n x 4 row-major, out device n.  Asynchronous. */
+kdcd_status kdcd_sampler_forward(const kdcd_sampler *model, const float *x, int64_t n, float *out,
+                                 kdcd_stream stream);
+/* Loss and its gradient over n samples (1 <= n <= 65536): grad device
+ * KDCD_SAMPLER_NPARAMS floats, loss device 1 float.  Asynchronous. */
+kdcd_status kdcd_sampler_grad(const kdcd_sampler *model, const float *x, const float *t,
+                              int64_t n, float *grad, float *loss, kdcd_stream stream);
+/* `epochs` passes over (x, t) in minibatches of `batch` (<= 65536), one Adam
+ * step of rate lr each; epoch_loss (device, epochs floats, or NULL) receives
+ * each epoch's size-weighted mean minibatch loss.  Synchronises `stream`. */
+kdcd_status kdcd_sampler_train(kdcd_sampler *model, const float *x, const float *t, int64_t n,
+                               int32_t batch, int32_t epochs, float lr, float *epoch_loss,
+                               kdcd_stream stream);
+/* keys[i] = float(f(x_i) / tau + G_i) with the noise of outer iteration
+ * `outer` (n < 2^31).  Asynchronous. */
+kdcd_status kdcd_sampler_keys(const kdcd_sampler *model, const float *x, int64_t n, double tau,
+                              uint64_t seed, int64_t outer, float *keys, kdcd_stream stream);
+/* The s slots of outer iteration `outer` from caller-given finite keys
+ * (device, m): S device, s outputs; 1 <= s <= min(m, 1024).  Errors:
+ * NONFINITE (a key), UNSUPPORTED (more than 2048 keys tied at the threshold).
+ * Synchronises `stream`. */
+kdcd_status kdcd_sampler_select(const float *keys, int64_t m, int32_t s, double epsilon,
+                                uint64_t seed, int64_t outer, int32_t *S, kdcd_stream stream);
+
+/* Sampling options of kdcd_ksvm_solve_sampled. */
+typedef struct {
+    const kdcd_sampler *model; /* NULL: every slot uniform (the paper's draw)        */
+    double epsilon;            /* [0, 1]: share of uniform slots (model != NULL)      */
+    double tau;                /* > 0: temperature of the Gumbel keys                 */
+    uint64_t seed;             /* Philox key                                          */
+    int32_t *idx_out;          /* device, H: the realised coordinates (required)      */
+    float *features_out;       /* device or NULL: H x 4, x_i of every drawn coordinate
+                                  at the start of its outer iteration                 */
+    double *grad_out;          /* device or NULL: m, the maintained g on exit         */
+} kdcd_sampling;
+
+/*
+ * kdcd_ksvm_solve_sampled -- Algorithm 2 (b = 1) whose s coordinates per
+ * outer iteration are drawn on the device, before the kernel block, by the
+ * sampler above; the full gradient g is kept current by
+ * g += diag(y) U_k diag(y_S) theta + omega * (scatter of theta), with U_k
+ * stored by the kernel-block pass.  The result equals kdcd_ksvm_solve with
+ * b = 1 on idx_out.  Dense FP64 only; H < 2^31 * s; when model != NULL,
+ * s <= m.  Other arguments as kdcd_ksvm_solve (opt->trace receives theta).
+ * Errors: as kdcd_ksvm_solve; UNSUPPORTED for CSR, low precision or a tie
+ * group beyond 2048 keys; NONFINITE for a non-finite score.
+ */
+kdcd_status kdcd_ksvm_solve_sampled(const kdcd_matrix *A, const double *y,
+                                    const kdcd_kernel *kernel, double C, int32_t s, int64_t H,
+                                    const kdcd_sampling *sampling, double *alpha,
+                                    const kdcd_options *opt, kdcd_stream stream);
+
 /* Device workspace a solve needs (problem: 0 = K-SVM, 1 = K-RR). */
 size_t kdcd_workspace_bytes(int32_t problem, const kdcd_matrix *A, const kdcd_kernel *kernel,
                             int32_t b, int32_t s, int32_t compute);

@@ -132,6 +132,7 @@ struct KBlockArgs {
     int32_t compute;
     int32_t w_only;          // FP64 kernel: compute the Gram tiles only (no U-part)
     const BatchDesc *batch;  // non-null: batched epilogue (dense F64 and mixed kernels)
+    double *U;               // dense F64 only: non-null stores K(a_p, a_{S_j}) at U[j*m + p]
 };
 
 // Launchers (return hipError_t of the launch).

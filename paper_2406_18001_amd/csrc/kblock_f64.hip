@@ -48,7 +48,7 @@ __global__ __launch_bounds__(64 * WM * WN) void kblock_f64_kernel(
     const double *__restrict__ beta, const double *__restrict__ bscale,
     double *__restrict__ partial, double *__restrict__ W, int32_t n_u_tiles,
     int32_t n_row_groups, int32_t n_w_tiles, int32_t n_tiles_n, int32_t aligned,
-    const BatchDesc *__restrict__ bd)
+    const BatchDesc *__restrict__ bd, double *__restrict__ U)
 {
     constexpr int NT = 64 * WM * WN;
     constexpr int BM = 16 * TM * WM;
@@ -303,9 +303,15 @@ __global__ __launch_bounds__(64 * WM * WN) void kblock_f64_kernel(
                             const double na = (KIND == KDCD_KERNEL_RBF) ? norms[grow] : 0.0;
 #pragma unroll
                             for (int tn = 0; tn < TN; ++tn)
-                                if (colok[tn])
-                                    colsum[tn] += bval * kernel_map<KIND>(acc[tm][tn][v], na, nb[tn],
-                                                                          grow == Sc[tn], kp);
+                                if (colok[tn]) {
+                                    const double kv = kernel_map<KIND>(acc[tm][tn][v], na, nb[tn],
+                                                                       grow == Sc[tn], kp);
+                                    colsum[tn] += bval * kv;
+                                    if (U) {
+                                        const int64_t gcol = col0 + (wn * TN + tn) * 16 + (lane & 15);
+                                        U[gcol * m + grow] = kv;
+                                    }
+                                }
                         }
                     } else if (grow < sb) {
                         const int64_t St = clampi(S[grow], 0, m - 1);
@@ -383,7 +389,7 @@ hipError_t launch_cfg(const KBlockArgs &a, hipStream_t st)
     hipLaunchKernelGGL((kblock_f64_kernel<WM, WN, TM, TN, KIND, BATCH>), grid, block, 0, st,   \
                        A->values, A->ld, A->m, A->n, a.S, a.sb, a.norms, a.kp, a.beta,          \
                        a.beta_scale, a.partial, a.W, (int32_t)n_u, (int32_t)groups,            \
-                       (int32_t)n_w, (int32_t)n_n, aligned, a.batch)
+                       (int32_t)n_w, (int32_t)n_n, aligned, a.batch, BATCH ? nullptr : a.U)
     switch (a.kp.kind) {
     case KDCD_KERNEL_LINEAR: KDCD_LAUNCH(KDCD_KERNEL_LINEAR); break;
     case KDCD_KERNEL_POLY: KDCD_LAUNCH(KDCD_KERNEL_POLY); break;

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "sampler.hpp"
 
 using namespace kdcd;
 
@@ -580,6 +581,169 @@ kdcd_status kdcd_batch_solve(const kdcd_matrix *A, const kdcd_kernel *kernel, in
     return rc;
 }
 
+}  // extern "C"
+
+static kdcd_status kernel_matvec(const kdcd_matrix *A, const kdcd_kernel *kernel,
+                                 const double *beta, std::vector<double> *host, double *dev,
+                                 hipStream_t st);
+
+extern "C" {
+
+kdcd_status kdcd_ksvm_solve_sampled(const kdcd_matrix *A, const double *y,
+                                    const kdcd_kernel *kernel, double C, int32_t s, int64_t H,
+                                    const kdcd_sampling *smp, double *alpha,
+                                    const kdcd_options *opt, kdcd_stream stream)
+{
+    kdcd_status rc = check_matrix(A);
+    if (rc != KDCD_OK) return rc;
+    if ((rc = check_kernel(kernel)) != KDCD_OK) return rc;
+    if (!y || !alpha || !smp || !smp->idx_out || !finite_pos(C) || s < 1 || H < 1)
+        return KDCD_ERR_INVALID_ARG;
+    kdcd_options o = defaults(opt);
+    if (o.loss != 1 && o.loss != 2) return KDCD_ERR_INVALID_ARG;
+    if (o.snapshot_every < 0 || (o.snapshot_every > 0 && !o.snapshots)) return KDCD_ERR_INVALID_ARG;
+    if ((rc = check_compute(A, o.compute)) != KDCD_OK) return rc;
+    if (A->format != KDCD_DENSE || o.compute != KDCD_F64) return KDCD_ERR_UNSUPPORTED;
+    if (s > kMaxSB || A->m >= ((int64_t)1 << 31)) return KDCD_ERR_UNSUPPORTED;
+    const int64_t m = A->m;
+    const int64_t n_outer = (H + s - 1) / s;
+    if (n_outer > (int64_t)0xFFFFFFFF) return KDCD_ERR_UNSUPPORTED;
+    const bool learned = smp->model != nullptr;
+    if (learned) {
+        if (s > m || !(smp->tau > 0.0) || !std::isfinite(smp->tau) ||
+            !(smp->epsilon >= 0.0 && smp->epsilon <= 1.0))
+            return KDCD_ERR_INVALID_ARG;
+        int dev = -1;
+        if (hipGetDevice(&dev) != hipSuccess || dev != smp->model->device)
+            return KDCD_ERR_INVALID_ARG;
+    }
+    const hipStream_t st = (hipStream_t)stream;
+    const double nu = o.loss == 2 ? INFINITY : C;
+    const double omega = o.loss == 2 ? 1.0 / (2.0 * C) : 0.0;
+
+    Layout L = make_layout(0, A, kernel, 1, s, KDCD_F64);
+    size_t off = L.total;
+    const size_t o_g = off; off += align256(sizeof(double) * (size_t)m);
+    const size_t o_U = off; off += align256(sizeof(double) * (size_t)(s * m));
+    const size_t o_th = off; off += align256(sizeof(double) * (size_t)s);
+    const size_t o_tmp = off; off += align256(sizeof(double) * (size_t)m);
+    const size_t o_flag = off; off += 256;
+    const size_t o_sel = off; off += align256(select_workspace_bytes(m));
+    L.total = off;
+    Workspace ws;
+    if ((rc = acquire(ws, L, &o, st)) != KDCD_OK) return rc;
+    int32_t *status = ws.at<int32_t>(L.status);
+    double *norms = ws.at<double>(L.norms);
+    double *partial = ws.at<double>(L.partial);
+    double *r = ws.at<double>(L.r);
+    double *W = ws.at<double>(L.W);
+    double *g = smp->grad_out ? smp->grad_out : ws.at<double>(o_g);
+    double *U = ws.at<double>(o_U);
+    double *theta = ws.at<double>(o_th);
+    double *tmp = ws.at<double>(o_tmp);
+    int32_t *flag = ws.at<int32_t>(o_flag);
+    const SelectWs sel = select_workspace(ws.at<char>(o_sel), m);
+    const KParams kp = to_params(kernel);
+
+    KDCD_HIP_TRY(launch_fill_i32(status, 0, 1, st));
+    KDCD_HIP_TRY(launch_fill_i32(flag, 0, 1, st));
+    KDCD_HIP_TRY(launch_validate(nullptr, 0, m, y, alpha, m, 0, nu, status, st));
+    KDCD_HIP_TRY(launch_norms(A, norms, st));
+    // g = Q alpha_0 - 1 + omega alpha_0; the kernel product only for a nonzero alpha_0
+    KDCD_HIP_TRY(launch_product(y, alpha, m, tmp, flag, st));
+    int32_t nonzero = 0;
+    KDCD_HIP_TRY(hipMemcpyAsync(&nonzero, flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    KDCD_HIP_TRY(hipStreamSynchronize(st));
+    if (nonzero) {
+        if ((rc = kernel_matvec(A, kernel, tmp, nullptr, g, st)) != KDCD_OK) return rc;
+        KDCD_HIP_TRY(launch_grad_init(g, y, alpha, omega, m, g, st));
+    } else {
+        KDCD_HIP_TRY(launch_grad_init(nullptr, y, alpha, omega, m, g, st));
+    }
+    KDCD_HIP_TRY(launch_select_reset(sel, st));
+
+    KBlockArgs kb{};
+    kb.A = A;
+    kb.norms = norms;
+    kb.kp = kp;
+    kb.beta = alpha;
+    kb.beta_scale = y;
+    kb.partial = partial;
+    kb.W = W;
+    kb.status = status;
+    kb.compute = KDCD_F64;
+    kb.U = U;
+
+    StageTimer timer;
+    timer.on = o.profile != nullptr;
+    int64_t snap = 0;
+    for (int64_t k = 0; k < n_outer; ++k) {
+        const int64_t done = k * s;
+        const int32_t sk = (int32_t)std::min<int64_t>(s, H - done);
+        int32_t *S = smp->idx_out + done;
+        timer.begin(2, st);
+        SelectArgs a{};
+        a.ws = sel;
+        a.m = m;
+        a.ns = sk;
+        a.topk = learned;
+        a.epsilon = smp->epsilon;
+        a.tau = smp->tau;
+        a.seed = smp->seed;
+        a.outer = (uint32_t)k;
+        a.params = learned ? smp->model->params : nullptr;
+        a.alpha = alpha;
+        a.g = g;
+        a.norms = norms;
+        a.y = y;
+        a.kp = kp;
+        a.invC = 1.0 / C;
+        a.S = S;
+        a.status = status;
+        KDCD_HIP_TRY(launch_select(a, st));
+        if (smp->features_out)
+            KDCD_HIP_TRY(launch_features(S, sk, alpha, g, norms, y, kp, 1.0 / C,
+                                         smp->features_out + 4 * done, st));
+        timer.end(2, st);
+        kb.S = S;
+        kb.sb = sk;
+        timer.begin(0, st);
+        KDCD_HIP_TRY(launch_kblock(kb, st));
+        timer.end(0, st);
+        timer.begin(1, st);
+        FinishDesc fd{};
+        fd.nprob = 1;
+        fd.groups = (int32_t)row_groups(A, sk, KDCD_F64);
+        fd.partial[0] = partial;
+        fd.r[0] = r;
+        KDCD_HIP_TRY(launch_finish(fd, sk, 1, sk, (double)m, status, st));
+        timer.end(1, st);
+        timer.begin(2, st);
+        KsvmRecurDesc kd{};
+        kd.r[0] = r;
+        kd.W[0] = W;
+        kd.y[0] = y;
+        kd.alpha[0] = alpha;
+        kd.trace[0] = theta;
+        kd.nu[0] = nu;
+        kd.omega[0] = omega;
+        KDCD_HIP_TRY(launch_ksvm_recur(kd, 1, S, sk, m, status, st));
+        KDCD_HIP_TRY(launch_grad_update(U, m, sk, S, theta, y, omega, g, st));
+        timer.end(2, st);
+        if (o.trace)
+            KDCD_HIP_TRY(hipMemcpyAsync(o.trace + done, theta, sizeof(double) * (size_t)sk,
+                                        hipMemcpyDeviceToDevice, st));
+        if (o.snapshot_every > 0 && ((k + 1) % o.snapshot_every == 0 || k + 1 == n_outer)) {
+            KDCD_HIP_TRY(hipMemcpyAsync(o.snapshots + snap * m, alpha, sizeof(double) * (size_t)m,
+                                        hipMemcpyDeviceToDevice, st));
+            ++snap;
+        }
+    }
+    rc = read_status(status, st);
+    timer.report(o.profile);
+    return rc;
+}
+
 kdcd_status kdcd_kernel_rhs(const kdcd_matrix *A, const kdcd_kernel *kernel, const int32_t *S,
                             int32_t sb, const double *beta, const double *beta_scale, double *r,
                             double *W, int32_t compute, kdcd_stream stream)
@@ -626,8 +790,10 @@ kdcd_status kdcd_kernel_rhs(const kdcd_matrix *A, const kdcd_kernel *kernel, con
 }
 
 // (K beta) for all rows, FP64, in column chunks of kMaxSB through the kernel-block path.
+// The result goes to host memory (host != nullptr) or to device memory (dev).
 static kdcd_status kernel_matvec(const kdcd_matrix *A, const kdcd_kernel *kernel,
-                                 const double *beta, std::vector<double> &out, hipStream_t st)
+                                 const double *beta, std::vector<double> *host, double *dev,
+                                 hipStream_t st)
 {
     const int64_t m = A->m;
     const int32_t chunk = kMaxSB;
@@ -644,7 +810,7 @@ static kdcd_status kernel_matvec(const kdcd_matrix *A, const kdcd_kernel *kernel
     if (A->format == KDCD_CSR) KDCD_HIP_TRY(launch_validate_csr(A, status, st));
     KDCD_HIP_TRY(launch_iota_i32(iota, m, st));
     if (kernel->kind == KDCD_KERNEL_RBF) KDCD_HIP_TRY(launch_norms(A, norms, st));
-    out.assign((size_t)m, 0.0);
+    if (host) host->assign((size_t)m, 0.0);
     for (int64_t c0 = 0; c0 < m; c0 += chunk) {
         const int32_t sb = (int32_t)std::min<int64_t>(chunk, m - c0);
         KBlockArgs a{};
@@ -665,8 +831,12 @@ static kdcd_status kernel_matvec(const kdcd_matrix *A, const kdcd_kernel *kernel
         fd.partial[0] = partial;
         fd.r[0] = r;
         KDCD_HIP_TRY(launch_finish(fd, sb, 1, 0, 0.0, status, st));
-        KDCD_HIP_TRY(hipMemcpyAsync(out.data() + c0, r, sizeof(double) * (size_t)sb,
-                                    hipMemcpyDeviceToHost, st));
+        if (host)
+            KDCD_HIP_TRY(hipMemcpyAsync(host->data() + c0, r, sizeof(double) * (size_t)sb,
+                                        hipMemcpyDeviceToHost, st));
+        else
+            KDCD_HIP_TRY(hipMemcpyAsync(dev + c0, r, sizeof(double) * (size_t)sb,
+                                        hipMemcpyDeviceToDevice, st));
     }
     return read_status(status, st);
 }
@@ -696,7 +866,7 @@ kdcd_status kdcd_ksvm_eval(const kdcd_matrix *A, const double *y, const kdcd_ker
     if (hipMalloc(&dbeta, sizeof(double) * (size_t)A->m) != hipSuccess) return KDCD_ERR_ALLOC;
     (void)hipMemcpy(dbeta, beta.data(), sizeof(double) * (size_t)A->m, hipMemcpyHostToDevice);
     std::vector<double> Kb;
-    rc = kernel_matvec(A, kernel, dbeta, Kb, st);
+    rc = kernel_matvec(A, kernel, dbeta, &Kb, nullptr, st);
     (void)hipFree(dbeta);
     if (rc != KDCD_OK) return rc;
     const double nu = loss == 2 ? INFINITY : C, omega = loss == 2 ? 1.0 / (2.0 * C) : 0.0;
@@ -731,7 +901,7 @@ kdcd_status kdcd_krr_eval(const kdcd_matrix *A, const double *y, const kdcd_kern
     if (!y || !alpha || !out || !finite_pos(lambda)) return KDCD_ERR_INVALID_ARG;
     const hipStream_t st = (hipStream_t)stream;
     std::vector<double> Ka, hy, ha;
-    if ((rc = kernel_matvec(A, kernel, alpha, Ka, st)) != KDCD_OK) return rc;
+    if ((rc = kernel_matvec(A, kernel, alpha, &Ka, nullptr, st)) != KDCD_OK) return rc;
     copy_to_host(hy, y, A->m, st);
     copy_to_host(ha, alpha, A->m, st);
     long double aMa = 0, ya = 0, rr = 0;

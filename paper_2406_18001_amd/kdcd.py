@@ -85,6 +85,13 @@ class _BatchProblem(ctypes.Structure):
                 ("y", ctypes.c_void_p), ("alpha", ctypes.c_void_p), ("trace", ctypes.c_void_p)]
 
 
+class _Sampling(ctypes.Structure):
+    _fields_ = [("model", ctypes.c_void_p), ("epsilon", ctypes.c_double),
+                ("tau", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("idx_out", ctypes.c_void_p), ("features_out", ctypes.c_void_p),
+                ("grad_out", ctypes.c_void_p)]
+
+
 class _Options(ctypes.Structure):
     _fields_ = [("compute", ctypes.c_int32), ("loss", ctypes.c_int32),
                 ("snapshot_every", ctypes.c_int32), ("flags", ctypes.c_int32),
@@ -102,6 +109,30 @@ _lib.kdcd_krr_solve.argtypes = _lib.kdcd_ksvm_solve.argtypes
 _lib.kdcd_batch_solve.restype = ctypes.c_int
 _lib.kdcd_batch_solve.argtypes = [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, _P, _P,
                                   ctypes.c_int32, _P, _P]
+_lib.kdcd_sampler_create.restype = ctypes.c_int
+_lib.kdcd_sampler_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint64]
+_lib.kdcd_sampler_destroy.restype = None
+_lib.kdcd_sampler_destroy.argtypes = [_P]
+_lib.kdcd_sampler_get_params.restype = ctypes.c_int
+_lib.kdcd_sampler_get_params.argtypes = [_P, _P, _P]
+_lib.kdcd_sampler_set_params.restype = ctypes.c_int
+_lib.kdcd_sampler_set_params.argtypes = [_P, _P, _P]
+_lib.kdcd_sampler_forward.restype = ctypes.c_int
+_lib.kdcd_sampler_forward.argtypes = [_P, _P, ctypes.c_int64, _P, _P]
+_lib.kdcd_sampler_grad.restype = ctypes.c_int
+_lib.kdcd_sampler_grad.argtypes = [_P, _P, _P, ctypes.c_int64, _P, _P, _P]
+_lib.kdcd_sampler_train.restype = ctypes.c_int
+_lib.kdcd_sampler_train.argtypes = [_P, _P, _P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.c_float, _P, _P]
+_lib.kdcd_sampler_keys.restype = ctypes.c_int
+_lib.kdcd_sampler_keys.argtypes = [_P, _P, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64,
+                                   ctypes.c_int64, _P, _P]
+_lib.kdcd_sampler_select.restype = ctypes.c_int
+_lib.kdcd_sampler_select.argtypes = [_P, ctypes.c_int64, ctypes.c_int32, ctypes.c_double,
+                                     ctypes.c_uint64, ctypes.c_int64, _P, _P]
+_lib.kdcd_ksvm_solve_sampled.restype = ctypes.c_int
+_lib.kdcd_ksvm_solve_sampled.argtypes = [_P, _P, _P, ctypes.c_double, ctypes.c_int32,
+                                         ctypes.c_int64, _P, _P, _P, _P]
 _lib.kdcd_kernel_rhs.restype = ctypes.c_int
 _lib.kdcd_kernel_rhs.argtypes = [_P, _P, _P, ctypes.c_int32, _P, _P, _P, _P, ctypes.c_int32, _P]
 _lib.kdcd_ksvm_eval.restype = ctypes.c_int
@@ -330,3 +361,130 @@ def kdcd_workspace_bytes(problem, A, kernel, b, s, compute="f64") -> int:
     cmp = COMPUTE[compute] if isinstance(compute, str) else int(compute)
     return int(_lib.kdcd_workspace_bytes(int(problem), ctypes.byref(mat),
                                          ctypes.byref(_kernel(kernel)), int(b), int(s), cmp))
+
+
+# ------------------------------------------------------------ learned sampler
+
+SAMPLER_NPARAMS = 4545
+
+
+def _check(st, name):
+    if st != 0:
+        raise KdcdError(st, name)
+
+
+class Sampler:
+    """A learned coordinate sampler (MLP 4 -> 64 -> 64 -> 1) living on the
+    current GPU: thin owner of the kdcd_sampler handle."""
+
+    def __init__(self, seed: int = 0):
+        h = ctypes.c_void_p()
+        _check(_lib.kdcd_sampler_create(ctypes.byref(h), int(seed)), "kdcd_sampler_create")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.kdcd_sampler_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self, stream=None) -> torch.Tensor:
+        out = torch.empty(SAMPLER_NPARAMS, dtype=torch.float32, device="cuda")
+        _check(_lib.kdcd_sampler_get_params(self.handle, out.data_ptr(), _stream(stream)),
+               "kdcd_sampler_get_params")
+        return out
+
+    def set_params(self, params: torch.Tensor, stream=None):
+        _dev(params, torch.float32, SAMPLER_NPARAMS, "params")
+        _check(_lib.kdcd_sampler_set_params(self.handle, params.data_ptr(), _stream(stream)),
+               "kdcd_sampler_set_params")
+
+    def forward(self, x: torch.Tensor, stream=None) -> torch.Tensor:
+        n = x.shape[0]
+        _dev(x, torch.float32, 4 * n, "x")
+        out = torch.empty(n, dtype=torch.float32, device="cuda")
+        _check(_lib.kdcd_sampler_forward(self.handle, x.data_ptr(), n, out.data_ptr(),
+                                         _stream(stream)), "kdcd_sampler_forward")
+        return out
+
+    def grad(self, x: torch.Tensor, t: torch.Tensor, stream=None):
+        n = x.shape[0]
+        _dev(x, torch.float32, 4 * n, "x")
+        _dev(t, torch.float32, n, "t")
+        g = torch.empty(SAMPLER_NPARAMS, dtype=torch.float32, device="cuda")
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        _check(_lib.kdcd_sampler_grad(self.handle, x.data_ptr(), t.data_ptr(), n, g.data_ptr(),
+                                      loss.data_ptr(), _stream(stream)), "kdcd_sampler_grad")
+        return g, loss
+
+    def train(self, x: torch.Tensor, t: torch.Tensor, batch: int, epochs: int, lr: float,
+              stream=None) -> torch.Tensor:
+        n = x.shape[0]
+        _dev(x, torch.float32, 4 * n, "x")
+        _dev(t, torch.float32, n, "t")
+        losses = torch.zeros(max(int(epochs), 1), dtype=torch.float32, device="cuda")
+        _check(_lib.kdcd_sampler_train(self.handle, x.data_ptr(), t.data_ptr(), n, int(batch),
+                                       int(epochs), float(lr), losses.data_ptr(),
+                                       _stream(stream)), "kdcd_sampler_train")
+        return losses[:int(epochs)]
+
+    def keys(self, x: torch.Tensor, tau: float, seed: int, outer: int, stream=None):
+        n = x.shape[0]
+        _dev(x, torch.float32, 4 * n, "x")
+        out = torch.empty(n, dtype=torch.float32, device="cuda")
+        _check(_lib.kdcd_sampler_keys(self.handle, x.data_ptr(), n, float(tau), int(seed),
+                                      int(outer), out.data_ptr(), _stream(stream)),
+               "kdcd_sampler_keys")
+        return out
+
+
+def kdcd_sampler_select(keys: torch.Tensor, s: int, epsilon: float, seed: int, outer: int,
+                        stream=None) -> torch.Tensor:
+    """The s coordinates of outer iteration `outer` from float32 keys."""
+    m = keys.numel()
+    _dev(keys, torch.float32, m, "keys")
+    S = torch.empty(int(s), dtype=torch.int32, device="cuda")
+    _check(_lib.kdcd_sampler_select(keys.data_ptr(), m, int(s), float(epsilon), int(seed),
+                                    int(outer), S.data_ptr(), _stream(stream)),
+           "kdcd_sampler_select")
+    return S
+
+
+def kdcd_ksvm_solve_sampled(A, y, kernel, C, s, H, alpha, *, model=None, epsilon=0.0, tau=1.0,
+                            seed=0, idx_out=None, features_out=None, grad_out=None, loss=1,
+                            trace=None, snapshot_every=0, snapshots=None, workspace=None,
+                            profile=False, stream=None):
+    """Algorithm 2 (b = 1) with the coordinates drawn on the device by
+    `model` (a Sampler; None draws uniformly).  Returns (idx_out, profile or
+    None); alpha is updated in place."""
+    mat, m, _ = _matrix(A)
+    _dev(y, torch.float64, m, "y")
+    _dev(alpha, torch.float64, m, "alpha")
+    H = int(H)
+    if idx_out is None:
+        idx_out = torch.empty(H, dtype=torch.int32, device="cuda")
+    smp = _Sampling()
+    smp.model = model.handle if model is not None else None
+    smp.epsilon = float(epsilon)
+    smp.tau = float(tau)
+    smp.seed = int(seed)
+    smp.idx_out = _dev(idx_out, torch.int32, H, "idx_out")
+    if features_out is not None:
+        smp.features_out = _dev(features_out, torch.float32, 4 * H, "features_out")
+    if grad_out is not None:
+        smp.grad_out = _dev(grad_out, torch.float64, m, "grad_out")
+    n_outer = -(-H // max(int(s), 1))
+    opt, prof = _options("f64", loss, snapshot_every, snapshots, trace, workspace, profile, 0,
+                         m, n_outer, H)
+    kern = _kernel(kernel)
+    st = _lib.kdcd_ksvm_solve_sampled(ctypes.byref(mat), y.data_ptr(), ctypes.byref(kern),
+                                      float(C), int(s), H, ctypes.byref(smp), alpha.data_ptr(),
+                                      ctypes.byref(opt), _stream(stream))
+    _check(st, "kdcd_ksvm_solve_sampled")
+    p = {f: getattr(prof, f) for f, _ in _Profile._fields_} if prof is not None else None
+    return idx_out, p
