@@ -297,6 +297,11 @@ typedef struct {
     float *features_out;       /* device or NULL: H x 4, x_i of every drawn coordinate
                                   at the start of its outer iteration                 */
     double *grad_out;          /* device or NULL: m, the maintained g on exit         */
+    int32_t pool;              /* 0: score every coordinate; s <= pool <= 2048: score
+                                  only `pool` candidates per outer iteration, drawn
+                                  uniformly from counters (j, k, 3, 0) as
+                                  floor(x0 * m / 2^32) and ranked by key, ties by
+                                  pool position (duplicates possible)               */
 } kdcd_sampling;
 
 /*
@@ -305,8 +310,9 @@ typedef struct {
  * sampler above; the full gradient g is kept current by
  * g += diag(y) U_k diag(y_S) theta + omega * (scatter of theta), with U_k
  * stored by the kernel-block pass.  The result equals kdcd_ksvm_solve with
- * b = 1 on idx_out.  Dense FP64 only; H < 2^31 * s; when model != NULL,
- * s <= m.  Other arguments as kdcd_ksvm_solve (opt->trace receives theta).
+ * b = 1 on idx_out.  Dense FP64 only; H < 2^32 * s; when model != NULL,
+ * s <= m (pool == 0) or s <= pool.  Other arguments as kdcd_ksvm_solve
+ * (opt->trace receives theta).
  * Errors: as kdcd_ksvm_solve; UNSUPPORTED for CSR, low precision or a tie
  * group beyond 2048 keys; NONFINITE for a non-finite score.
  */

@@ -23,13 +23,18 @@ needs is defined here:
   value, ties by the smaller index.
 * Slot j is uniform when u(x0) < epsilon, and then takes coordinate
   floor(x1 * m / 2^32); otherwise it takes the next best key.
+* Pool variant: only P candidates floor(x0 * m / 2^32), counters (j, k, 3, 0),
+  are scored; each keeps the noise of its coordinate and they are ranked by
+  key, ties by pool position.
 * MLP 4 -> 64 -> 64 -> 1 with tanh hidden units; flat parameter layout
   W1[64][4], b1[64], W2[64][64], b2[64], w3[64], b3 (4545 floats);
   Glorot-uniform weights (bound sqrt(6/(fan_in+fan_out))), zero biases.
 * Loss 1/(2n) sum (f(x_i) - t_i)^2; Adam (Kingma and Ba, ICLR 2015,
   Algorithm 1) with beta1 = 0.9, beta2 = 0.999, eps = 1e-8.
-* K-SVM features of coordinate i: (alpha_i / C, g_i, K_ii, y_i) with the full
-  dual gradient g = Q alpha - 1 + omega alpha, Q = diag(y) K diag(y).
+* K-SVM features of coordinate i: (alpha_i / C, slog(g_i), K_ii, y_i) with the
+  full dual gradient g = Q alpha - 1 + omega alpha, Q = diag(y) K diag(y), and
+  slog the signed pseudo-logarithm below (float32 throughout: alpha_i / C is
+  the float32 rounding of alpha_i * (1/C)).
 """
 from __future__ import annotations
 
@@ -43,7 +48,7 @@ NIN, NH = 4, 64
 SIZES = [("W1", NH * NIN), ("b1", NH), ("W2", NH * NH), ("b2", NH), ("w3", NH), ("b3", 1)]
 NPARAMS = sum(n for _, n in SIZES)
 
-TAG_NOISE, TAG_SLOT, TAG_INIT = 0, 1, 2
+TAG_NOISE, TAG_SLOT, TAG_INIT, TAG_POOL = 0, 1, 2, 3
 
 
 # ------------------------------------------------------------------ Philox
@@ -107,6 +112,35 @@ def select(keys, s: int, epsilon: float, k: int, seed: int) -> np.ndarray:
             out[t] = int((int(x[t, 1]) * m) >> 32)
         else:
             out[t] = order[nxt]
+            nxt += 1
+    return out
+
+
+def pool_candidates(m: int, P: int, k: int, seed: int) -> np.ndarray:
+    """The P candidates of outer iteration k: floor(x0 m / 2^32) from counters
+    (j, k, 3, 0); drawn with replacement."""
+    j = np.arange(P, dtype=np.uint64)
+    ctr = np.stack([j, np.full(P, k), np.full(P, TAG_POOL), np.zeros(P)], axis=1)
+    x = philox4x32_10(ctr, seed_key(seed))[:, 0]
+    return ((x * np.uint64(m)) >> np.uint64(32)).astype(np.int32)
+
+
+def select_pool(keys_pool, cand, m: int, s: int, epsilon: float, k: int, seed: int) -> np.ndarray:
+    """Slots of outer iteration k when only the pool `cand` is scored: the pool
+    is ranked by key (ties by pool position); uniform slots as in select."""
+    keys_pool = np.asarray(keys_pool, dtype=np.float32)
+    P = keys_pool.shape[0]
+    order = np.lexsort((np.arange(P), -keys_pool.astype(np.float64)))
+    j = np.arange(s, dtype=np.uint64)
+    ctr = np.stack([j, np.full(s, k), np.full(s, TAG_SLOT), np.zeros(s)], axis=1)
+    x = philox4x32_10(ctr, seed_key(seed))
+    out = np.empty(s, dtype=np.int32)
+    nxt = 0
+    for t in range(s):
+        if to_unit(x[t, 0]) < epsilon:
+            out[t] = int((int(x[t, 1]) * m) >> 32)
+        else:
+            out[t] = cand[order[nxt]]
             nxt += 1
     return out
 
@@ -204,5 +238,22 @@ def train(p, X, t, batch: int, epochs: int, lr: float):
 
 # ------------------------------------------------------------ K-SVM state
 
+def slog(g) -> np.ndarray:
+    """Signed pseudo-logarithm of g in float32: v = float32(|g| 2^20); for
+    v < 1 the value is v, otherwise 1 + (e - 1) + (2 mant - 1) with
+    v = mant 2^e, mant in [0.5, 1) (a piecewise-linear log2 that is exact
+    at powers of two); the sign of g is restored and the result divided by 8."""
+    g = np.asarray(g, dtype=np.float64)
+    v = (np.abs(g) * 1048576.0).astype(np.float32)
+    mant, e = np.frexp(v)
+    frac = (np.float32(2.0) * mant.astype(np.float32)) - np.float32(1.0)
+    big = np.float32(1.0) + ((e - 1).astype(np.float32) + frac)
+    L = np.where(v < np.float32(1.0), v, big).astype(np.float32)
+    return (np.sign(g).astype(np.float32) * L * np.float32(0.125)).astype(np.float32)
+
+
 def ksvm_features(alpha, g, kdiag, y, C) -> np.ndarray:
-    return np.stack([np.asarray(alpha) / C, g, kdiag, y], axis=1)
+    """float32 features (n x 4) of the coordinates given by the arrays."""
+    a = (np.asarray(alpha, dtype=np.float64) * (1.0 / C)).astype(np.float32)
+    return np.stack([a, slog(g), np.asarray(kdiag, dtype=np.float32),
+                     np.asarray(y, dtype=np.float32)], axis=1)

@@ -58,32 +58,64 @@ namespace {
 
 // ---------------------------------------------------------------- the MLP
 
+// Parameters as staged in LDS: W2 rows padded to 65 floats so that the four
+// lanes of a quad (rows o = q + 4j) read distinct banks.
+constexpr int LW2 = SMP_NH + 1;
+constexpr int LP_W1 = 0, LP_B1 = LP_W1 + SMP_NH * SMP_NIN, LP_W2 = LP_B1 + SMP_NH,
+              LP_B2 = LP_W2 + SMP_NH * LW2, LP_W3 = LP_B2 + SMP_NH, LP_B3 = LP_W3 + SMP_NH,
+              LP_N = LP_B3 + 1;
+
+__device__ __forceinline__ void load_params_padded(float *sp, const float *__restrict__ params)
+{
+    for (int q = threadIdx.x; q < SMP_NP; q += blockDim.x) {
+        int d;
+        if (q < SMP_W2) d = q;                                   // W1, b1
+        else if (q < SMP_B2) d = LP_W2 + ((q - SMP_W2) / SMP_NH) * LW2 + (q - SMP_W2) % SMP_NH;
+        else d = LP_B2 + (q - SMP_B2);                           // b2, w3, b3
+        sp[d] = params[q];
+    }
+    __syncthreads();
+}
+
 __device__ __forceinline__ void load_params(float *sp, const float *__restrict__ params)
 {
     for (int q = threadIdx.x; q < SMP_NP; q += blockDim.x) sp[q] = params[q];
     __syncthreads();
 }
 
-// f(x) for one coordinate; sp holds the parameters in LDS (every lane reads
-// the same address at a time, so the reads are broadcasts).
-__device__ __forceinline__ float mlp_eval(const float *sp, const float x[4])
+// The scoring MLP f(x), evaluated by a quad of lanes (q = lane & 3) that
+// holds the same x.  Lane q owns hidden units o = q + 4j, j = 0..15:
+//   h1_o = tanh(b1_o + sum_i W1[o][i] x_i)            (fma chain, i ascending)
+//   h2_o = tanh(b2_o + sum_i W2[o][i] h1_i)           (fma chain, i ascending)
+//   C_q  = sum_j w3_o h2_o                             (fma chain from 0, j ascending)
+//   f    = ((C_0 + C_1) + (C_2 + C_3)) + b3
+// Every inference path uses this routine, so a coordinate's score has the
+// same bits wherever it is computed.  h1row: this quad's 64-float LDS row.
+__device__ __forceinline__ float quad_mlp_eval(const float *sp, const float x[4], float *h1row)
 {
-    float h1[SMP_NH];
+    const int q = threadIdx.x & 3;
 #pragma unroll
-    for (int o = 0; o < SMP_NH; ++o) {
-        float z = sp[SMP_B1 + o];
+    for (int j = 0; j < SMP_NH / 4; ++j) {
+        const int o = q + 4 * j;
+        float z = sp[LP_B1 + o];
 #pragma unroll
-        for (int i = 0; i < SMP_NIN; ++i) z = fmaf(sp[SMP_W1 + o * SMP_NIN + i], x[i], z);
-        h1[o] = tanhf(z);
+        for (int i = 0; i < SMP_NIN; ++i) z = fmaf(sp[LP_W1 + o * SMP_NIN + i], x[i], z);
+        h1row[o] = tanhf(z);
     }
-    float f = sp[SMP_B3];
-    for (int o = 0; o < SMP_NH; ++o) {
-        float z = sp[SMP_B2 + o];
+    wave_lds_sync();
+    float c = 0.0f;
+    for (int j = 0; j < SMP_NH / 4; ++j) {
+        const int o = q + 4 * j;
+        const float *w2 = sp + LP_W2 + o * LW2;
+        float z = sp[LP_B2 + o];
 #pragma unroll
-        for (int i = 0; i < SMP_NH; ++i) z = fmaf(sp[SMP_W2 + o * SMP_NH + i], h1[i], z);
-        f = fmaf(sp[SMP_W3 + o], tanhf(z), f);
+        for (int i = 0; i < SMP_NH; ++i) z = fmaf(w2[i], h1row[i], z);
+        c = fmaf(sp[LP_W3 + o], tanhf(z), c);
     }
-    return f;
+    wave_lds_sync();   // h1row may be reused by the next candidate
+    const float s01 = c + __shfl_xor(c, 1);
+    const float s = s01 + __shfl_xor(s01, 2);
+    return s + sp[LP_B3];
 }
 
 // Gumbel key of coordinate i in outer iteration k: float(score / tau + G).
@@ -112,27 +144,52 @@ __device__ __forceinline__ float kdiag_of(double nrm, const KParams &kp)
     return (float)r;
 }
 
+// Signed pseudo-logarithm of the gradient: v = float(|g| 2^20); v below 1
+// is kept, above it the exponent plus the mantissa's fraction (a piecewise-
+// linear log2) is used, 1 + e + (m - 1) for v = m 2^e, m in [1, 2); the sign
+// of g is restored and the result scaled by 1/8.  Every step is an exact or
+// correctly rounded float operation, so the host reproduces it bit for bit.
+__device__ __forceinline__ float slog_feature(double g)
+{
+    const float v = (float)(fabs(g) * 1048576.0);
+    float L = v;
+    if (v >= 1.0f) {
+        int e = 0;
+        const float mant = frexpf(v, &e);    // v = mant 2^e, mant in [0.5, 1)
+        const float frac = 2.0f * mant - 1.0f;
+        L = 1.0f + ((float)(e - 1) + frac);
+    }
+    return copysignf(L, (float)g) * 0.125f;
+}
+
 __device__ __forceinline__ void state_features(int64_t i, const double *alpha, const double *g,
                                                const double *norms, const double *y,
                                                const KParams &kp, double invC, float x[4])
 {
     x[0] = (float)(alpha[i] * invC);
-    x[1] = (float)g[i];
+    x[1] = slog_feature(g[i]);
     x[2] = kdiag_of(norms[i], kp);
     x[3] = (float)y[i];
 }
+
+// 256 threads = 64 quads = 64 coordinates per workgroup.
+constexpr int QB = 64;
+constexpr int QB_LD = SMP_NH + 1;   // padded h1 rows: the 16 quads of a wave hit distinct banks
 
 __global__ __launch_bounds__(256) void forward_kernel(const float *__restrict__ params,
                                                       const float *__restrict__ x, int64_t n,
                                                       float *__restrict__ out)
 {
-    __shared__ float sp[SMP_NP];
-    load_params(sp, params);
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        float xi[4] = {x[4 * i], x[4 * i + 1], x[4 * i + 2], x[4 * i + 3]};
-        out[i] = mlp_eval(sp, xi);
-    }
+    __shared__ float sp[LP_N];
+    __shared__ float h1s[QB * QB_LD];
+    load_params_padded(sp, params);
+    const int cq = threadIdx.x >> 2;
+    const int64_t i = (int64_t)blockIdx.x * QB + cq;
+    float xi[4] = {0.f, 0.f, 0.f, 0.f};
+    if (i < n)
+        for (int e = 0; e < 4; ++e) xi[e] = x[4 * i + e];
+    const float f = quad_mlp_eval(sp, xi, h1s + cq * QB_LD);
+    if (i < n && (threadIdx.x & 3) == 0) out[i] = f;
 }
 
 __global__ __launch_bounds__(256) void keys_kernel(const float *__restrict__ params,
@@ -140,13 +197,16 @@ __global__ __launch_bounds__(256) void keys_kernel(const float *__restrict__ par
                                                    double tau, uint32_t k, uint32_t k0,
                                                    uint32_t k1, float *__restrict__ keys)
 {
-    __shared__ float sp[SMP_NP];
-    load_params(sp, params);
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        float xi[4] = {x[4 * i], x[4 * i + 1], x[4 * i + 2], x[4 * i + 3]};
-        keys[i] = gumbel_key(mlp_eval(sp, xi), tau, (uint32_t)i, k, k0, k1);
-    }
+    __shared__ float sp[LP_N];
+    __shared__ float h1s[QB * QB_LD];
+    load_params_padded(sp, params);
+    const int cq = threadIdx.x >> 2;
+    const int64_t i = (int64_t)blockIdx.x * QB + cq;
+    float xi[4] = {0.f, 0.f, 0.f, 0.f};
+    if (i < n)
+        for (int e = 0; e < 4; ++e) xi[e] = x[4 * i + e];
+    const float f = quad_mlp_eval(sp, xi, h1s + cq * QB_LD);
+    if (i < n && (threadIdx.x & 3) == 0) keys[i] = gumbel_key(f, tau, (uint32_t)i, k, k0, k1);
 }
 
 // ----------------------------------------------------- radix top-k select
@@ -158,6 +218,8 @@ __global__ __launch_bounds__(256) void keys_kernel(const float *__restrict__ par
 constexpr int SEL_BINS = 2048;
 constexpr int SEL_CEQ = 2048;      // capacity for keys tied with T
 constexpr int SEL_CAND = 4096;     // power of two >= kMaxSB + SEL_CEQ
+constexpr int TK_CH = 2048;        // the one-chunk path ranks up to this many coordinates
+constexpr int POOL_MAX = 2048;     // candidate-pool size limit
 
 __device__ __forceinline__ int pass_shift(int pass) { return pass == 0 ? 21 : (pass == 1 ? 10 : 0); }
 __device__ __forceinline__ uint32_t pass_dmask(int pass) { return pass == 2 ? 0x3FFu : 0x7FFu; }
@@ -179,28 +241,57 @@ __device__ __forceinline__ void hist_clear(uint32_t *lh)
     __syncthreads();
 }
 
-// Pass 0 fused with the keys of the solve's state.
+__device__ __forceinline__ uint64_t composite(uint32_t code, uint32_t i)
+{
+    return ((uint64_t)code << 32) | (uint64_t)(0xFFFFFFFFu - i);   // value desc, index asc
+}
+
+// Bitonic sort of key[0, N) (N a power of two) into descending order.
+__device__ __forceinline__ void bitonic_desc(uint64_t *key, int N)
+{
+    for (int size = 2; size <= N; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int e = threadIdx.x; e < N; e += blockDim.x) {
+                const int p = e ^ stride;
+                if (p > e) {
+                    const bool desc = (e & size) == 0;
+                    const uint64_t a = key[e], b = key[p];
+                    if (desc ? (a < b) : (a > b)) {
+                        key[e] = b;
+                        key[p] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Pass 0 fused with the keys of the solve's state (hist may be null: codes only).
 __global__ __launch_bounds__(256) void state_keys_kernel(
     const float *__restrict__ params, const double *__restrict__ alpha,
     const double *__restrict__ g, const double *__restrict__ norms, const double *__restrict__ y,
     KParams kp, double invC, int64_t m, double tau, uint32_t k, uint32_t k0, uint32_t k1,
     uint32_t *__restrict__ codes, uint32_t *__restrict__ hist, int32_t *status)
 {
-    __shared__ float sp[SMP_NP];
+    __shared__ float sp[LP_N];
+    __shared__ float h1s[QB * QB_LD];
     __shared__ uint32_t lh[SEL_BINS];
-    hist_clear(lh);
-    load_params(sp, params);
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        float x[4];
-        state_features(i, alpha, g, norms, y, kp, invC, x);
-        const float key = gumbel_key(mlp_eval(sp, x), tau, (uint32_t)i, k, k0, k1);
+    if (hist) hist_clear(lh);
+    load_params_padded(sp, params);
+    const int cq = threadIdx.x >> 2;
+    const int64_t i = (int64_t)blockIdx.x * QB + cq;
+    float x[4] = {0.f, 0.f, 0.f, 0.f};
+    if (i < m) state_features(i, alpha, g, norms, y, kp, invC, x);
+    const float f = quad_mlp_eval(sp, x, h1s + cq * QB_LD);
+    if (i < m && (threadIdx.x & 3) == 0) {
+        const float key = gumbel_key(f, tau, (uint32_t)i, k, k0, k1);
         if (!isfinite(key)) set_status(status, KDCD_ERR_NONFINITE);
         const uint32_t c = order_code(key);
         codes[i] = c;
-        atomicAdd(&lh[c >> 21], 1u);
+        if (hist) atomicAdd(&lh[c >> 21], 1u);
     }
-    hist_flush(lh, hist);
+    if (hist) hist_flush(lh, hist);
 }
 
 // Pass 0 over caller-given float keys.
@@ -216,10 +307,12 @@ __global__ __launch_bounds__(256) void codes_kernel(const float *__restrict__ ke
         if (!isfinite(key)) set_status(status, KDCD_ERR_NONFINITE);
         const uint32_t c = order_code(key);
         codes[i] = c;
-        atomicAdd(&lh[c >> 21], 1u);
+        if (hist) atomicAdd(&lh[c >> 21], 1u);
     }
-    hist_flush(lh, hist);
+    if (hist) hist_flush(lh, hist);
 }
+
+
 
 // Passes 1 and 2: histogram of the next digit among codes matching the prefix.
 __global__ __launch_bounds__(256) void hist_kernel(const uint32_t *__restrict__ codes, int64_t m,
@@ -295,53 +388,86 @@ __global__ __launch_bounds__(256) void collect_kernel(const uint32_t *__restrict
 // Sort the candidates, fill the slots.  Slot j: uniform when u(x0) < epsilon
 // (coordinate floor(x1 * m / 2^32)), else the next best key.  With topk == 0
 // every slot is uniform and no candidates are read.
+// Candidate pool: P candidates c_j = floor(x0 m / 2^32) from counters
+// (j, k, 3, 0), scored from the state and keyed with the noise of their
+// coordinate, (i, k, 0, 0); pkey[j] = composite(code, j), pcid[j] = c_j.
+__global__ __launch_bounds__(256) void pool_score_kernel(
+    const float *__restrict__ params, const double *__restrict__ alpha,
+    const double *__restrict__ g, const double *__restrict__ norms, const double *__restrict__ y,
+    KParams kp, double invC, int64_t m, int32_t P, double tau, uint32_t k, uint32_t k0,
+    uint32_t k1, uint64_t *__restrict__ pkey, int32_t *__restrict__ pcid, int32_t *status)
+{
+    __shared__ float sp[LP_N];
+    __shared__ float h1s[QB * QB_LD];
+    load_params_padded(sp, params);
+    const int cq = threadIdx.x >> 2;
+    const int j = blockIdx.x * QB + cq;
+    int32_t i = 0;
+    float x[4] = {0.f, 0.f, 0.f, 0.f};
+    if (j < P) {
+        uint32_t c[4] = {(uint32_t)j, k, 3u, 0u};
+        philox4x32_10(c, k0, k1);
+        i = (int32_t)(((uint64_t)c[0] * (uint64_t)m) >> 32);
+        state_features(i, alpha, g, norms, y, kp, invC, x);
+    }
+    const float f = quad_mlp_eval(sp, x, h1s + cq * QB_LD);
+    if (j < P && (threadIdx.x & 3) == 0) {
+        const float kv = gumbel_key(f, tau, (uint32_t)i, k, k0, k1);
+        if (!isfinite(kv)) set_status(status, KDCD_ERR_NONFINITE);
+        pkey[j] = composite(order_code(kv), (uint32_t)j);
+        pcid[j] = i;
+    }
+}
+
+// mode 0: every slot uniform; mode 1: candidates of the radix select
+// (cand_gt / cand_eq with their codes); mode 2: all ncand = m <= TK_CH codes;
+// mode 3: the ncand pool keys pkey, coordinates pcid.
 __global__ __launch_bounds__(1024) void slots_kernel(const uint32_t *__restrict__ codes,
                                                      int64_t m, SelState *__restrict__ st,
                                                      const int32_t *__restrict__ cand_gt,
                                                      const int32_t *__restrict__ cand_eq,
-                                                     int32_t ns, double epsilon, uint32_t k,
-                                                     uint32_t k0, uint32_t k1, int topk,
-                                                     int32_t *__restrict__ S, int32_t *status)
+                                                     const uint64_t *__restrict__ pkey,
+                                                     const int32_t *__restrict__ pcid,
+                                                     int32_t ncand, int32_t ns, double epsilon,
+                                                     uint32_t k, uint32_t k0, uint32_t k1,
+                                                     int mode, int32_t *__restrict__ S,
+                                                     int32_t *status)
 {
     __shared__ uint64_t key[SEL_CAND];
     __shared__ int32_t rank[1024];
     const int t = threadIdx.x;
-    int N = 0;
-    if (topk) {
+    const bool topk = mode != 0;
+    if (mode == 1) {
         const uint32_t ngt = st->n_gt, neq = st->n_eq, krem = st->krem;
         if (neq > (uint32_t)SEL_CEQ && krem < neq) {
             if (t == 0) set_status(status, KDCD_ERR_UNSUPPORTED);
         }
         const int cg = (int)min(ngt, (uint32_t)kMaxSB), ce = (int)min(neq, (uint32_t)SEL_CEQ);
         const int cnt = cg + ce;
-        N = 1;
+        int N = 1;
         while (N < cnt) N <<= 1;
         for (int e = t; e < N; e += 1024) {
             uint64_t v = 0;
             if (e < cnt) {
                 const int32_t i = e < cg ? cand_gt[e] : cand_eq[e - cg];
-                v = ((uint64_t)codes[i] << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)i);
+                v = composite(codes[i], (uint32_t)i);
             }
             key[e] = v;
         }
         __syncthreads();
-        // bitonic sort, descending
-        for (int size = 2; size <= N; size <<= 1) {
-            for (int stride = size >> 1; stride > 0; stride >>= 1) {
-                for (int e = t; e < N; e += 1024) {
-                    const int p = e ^ stride;
-                    if (p > e) {
-                        const bool desc = (e & size) == 0;
-                        const uint64_t a = key[e], b = key[p];
-                        if (desc ? (a < b) : (a > b)) {
-                            key[e] = b;
-                            key[p] = a;
-                        }
-                    }
-                }
-                __syncthreads();
-            }
-        }
+        bitonic_desc(key, N);
+    } else if (mode == 3) {
+        int N = 1;
+        while (N < ncand) N <<= 1;
+        for (int e = t; e < N; e += 1024) key[e] = e < ncand ? pkey[e] : 0ull;
+        __syncthreads();
+        bitonic_desc(key, N);
+    } else if (mode == 2) {     // ncand = m <= TK_CH: rank every coordinate
+        int N = 1;
+        while (N < ncand) N <<= 1;
+        for (int e = t; e < N; e += 1024) key[e] = e < ncand ? composite(codes[e], (uint32_t)e) : 0ull;
+        __syncthreads();
+        bitonic_desc(key, N);
     }
     // slot kinds and the rank of every top-k slot
     bool uni = true;
@@ -369,10 +495,11 @@ __global__ __launch_bounds__(1024) void slots_kernel(const uint32_t *__restrict_
         } else {
             const int r = v - 1;   // exclusive rank among top-k slots
             idx = (int32_t)(0xFFFFFFFFu - (uint32_t)(key[r] & 0xFFFFFFFFu));
+            if (mode == 3) idx = pcid[idx];
         }
         S[t] = idx;
     }
-    if (t == 0) {
+    if (t == 0 && mode == 1) {
         st->n_gt = 0u;
         st->n_eq = 0u;
         st->prefix = 0u;
@@ -610,43 +737,65 @@ unsigned grid_for(int64_t n, int64_t cap = 2048)
 hipError_t launch_mlp_forward(const float *params, const float *x, int64_t n, float *out,
                               hipStream_t st)
 {
-    hipLaunchKernelGGL(forward_kernel, dim3(grid_for(n)), dim3(256), 0, st, params, x, n, out);
+    hipLaunchKernelGGL(forward_kernel, dim3((unsigned)((n + QB - 1) / QB)), dim3(256), 0, st, params,
+                       x, n, out);
     return hipGetLastError();
 }
 
 hipError_t launch_mlp_keys(const float *params, const float *x, int64_t n, double tau,
                            uint32_t k, uint64_t seed, float *keys, hipStream_t st)
 {
-    hipLaunchKernelGGL(keys_kernel, dim3(grid_for(n)), dim3(256), 0, st, params, x, n, tau, k,
+    hipLaunchKernelGGL(keys_kernel, dim3((unsigned)((n + QB - 1) / QB)), dim3(256), 0, st, params,
+                       x, n, tau, k,
                        (uint32_t)seed, (uint32_t)(seed >> 32), keys);
     return hipGetLastError();
 }
+
 
 hipError_t launch_select(const SelectArgs &a, hipStream_t st)
 {
     const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
     const unsigned grid = grid_for(a.m, 1024);
-    if (a.topk) {
+    const unsigned qgrid = (unsigned)((a.m + QB - 1) / QB);
+    int mode = 0;
+    int32_t ncand = 0;
+    if (a.topk && a.pool > 0) {
+        mode = 3;
+        ncand = a.pool;
+        hipLaunchKernelGGL(pool_score_kernel, dim3((unsigned)((a.pool + QB - 1) / QB)), dim3(256), 0,
+                           st, a.params, a.alpha, a.g, a.norms, a.y, a.kp, a.invC, a.m, a.pool,
+                           a.tau, a.outer, k0, k1, a.ws.pkey, a.ws.pcid, a.status);
+    } else if (a.topk) {
+        // small problems: every coordinate is a candidate of one sort
+        const int64_t nc = a.m <= TK_CH ? a.m : 0;
+        uint32_t *hist = nc ? nullptr : a.ws.hist;
         if (a.params)
-            hipLaunchKernelGGL(state_keys_kernel, dim3(grid), dim3(256), 0, st, a.params, a.alpha,
+            hipLaunchKernelGGL(state_keys_kernel, dim3(qgrid), dim3(256), 0, st, a.params, a.alpha,
                                a.g, a.norms, a.y, a.kp, a.invC, a.m, a.tau, a.outer, k0, k1,
-                               a.ws.codes, a.ws.hist, a.status);
+                               a.ws.codes, hist, a.status);
         else
             hipLaunchKernelGGL(codes_kernel, dim3(grid), dim3(256), 0, st, a.keys, a.m, a.ws.codes,
-                               a.ws.hist, a.status);
-        for (int pass = 0; pass < 3; ++pass) {
-            if (pass > 0)
-                hipLaunchKernelGGL(hist_kernel, dim3(grid), dim3(256), 0, st, a.ws.codes, a.m,
-                                   a.ws.state, pass, a.ws.hist);
-            hipLaunchKernelGGL(pick_kernel, dim3(1), dim3(1024), 0, st, a.ws.hist, a.ws.state,
-                               pass, a.ns);
+                               hist, a.status);
+        if (nc) {
+            mode = 2;
+            ncand = (int32_t)nc;
+        } else {
+            mode = 1;
+            for (int pass = 0; pass < 3; ++pass) {
+                if (pass > 0)
+                    hipLaunchKernelGGL(hist_kernel, dim3(grid), dim3(256), 0, st, a.ws.codes, a.m,
+                                       a.ws.state, pass, a.ws.hist);
+                hipLaunchKernelGGL(pick_kernel, dim3(1), dim3(1024), 0, st, a.ws.hist, a.ws.state,
+                                   pass, a.ns);
+            }
+            hipLaunchKernelGGL(collect_kernel, dim3(grid), dim3(256), 0, st, a.ws.codes, a.m,
+                               a.ws.state, a.ws.cand_gt, a.ws.cand_eq);
         }
-        hipLaunchKernelGGL(collect_kernel, dim3(grid), dim3(256), 0, st, a.ws.codes, a.m,
-                           a.ws.state, a.ws.cand_gt, a.ws.cand_eq);
     }
     hipLaunchKernelGGL(slots_kernel, dim3(1), dim3(1024), 0, st, a.ws.codes, a.m, a.ws.state,
-                       a.ws.cand_gt, a.ws.cand_eq, a.ns, a.epsilon, a.outer, k0, k1, a.topk ? 1 : 0,
-                       a.S, a.status);
+                       a.ws.cand_gt, a.ws.cand_eq, a.ws.pkey, a.ws.pcid, ncand, a.ns, a.epsilon,
+                       a.outer,
+                       k0, k1, mode, a.S, a.status);
     return hipGetLastError();
 }
 
@@ -654,7 +803,8 @@ size_t select_workspace_bytes(int64_t m)
 {
     auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
     return al(sizeof(uint32_t) * (size_t)m) + al(sizeof(uint32_t) * SEL_BINS) + al(sizeof(SelState)) +
-           al(sizeof(int32_t) * kMaxSB) + al(sizeof(int32_t) * SEL_CEQ);
+           al(sizeof(int32_t) * kMaxSB) + al(sizeof(int32_t) * SEL_CEQ) +
+           al(sizeof(uint64_t) * POOL_MAX) + al(sizeof(int32_t) * POOL_MAX);
 }
 
 SelectWs select_workspace(void *base, int64_t m)
@@ -671,6 +821,10 @@ SelectWs select_workspace(void *base, int64_t m)
     w.cand_gt = reinterpret_cast<int32_t *>(p);
     p += al(sizeof(int32_t) * kMaxSB);
     w.cand_eq = reinterpret_cast<int32_t *>(p);
+    p += al(sizeof(int32_t) * SEL_CEQ);
+    w.pkey = reinterpret_cast<uint64_t *>(p);
+    p += al(sizeof(uint64_t) * POOL_MAX);
+    w.pcid = reinterpret_cast<int32_t *>(p);
     return w;
 }
 

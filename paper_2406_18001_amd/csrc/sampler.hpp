@@ -19,6 +19,7 @@ constexpr int SMP_NP = SMP_B3 + 1;
 static_assert(SMP_NP == KDCD_SAMPLER_NPARAMS, "parameter count");
 
 constexpr int SMP_MAX_BATCH = 65536;   // training minibatch limit
+constexpr int SMP_MAX_POOL = 2048;     // candidate-pool size limit
 
 // Radix-select state (device).
 struct SelState {
@@ -31,6 +32,8 @@ struct SelectWs {
     SelState *state;
     int32_t *cand_gt;   // kMaxSB candidates above the threshold
     int32_t *cand_eq;   // candidates tied with it
+    uint64_t *pkey;     // pool keys (composite with the pool position)
+    int32_t *pcid;      // pool coordinates
 };
 
 struct SelectArgs {
@@ -38,6 +41,7 @@ struct SelectArgs {
     int64_t m;
     int32_t ns;            // slots to fill (<= kMaxSB, <= m when topk)
     bool topk;             // false: every slot uniform
+    int32_t pool;          // > 0: score only this many random candidates (<= 2048)
     double epsilon, tau;
     uint64_t seed;
     uint32_t outer;        // outer-iteration counter k

@@ -610,8 +610,10 @@ kdcd_status kdcd_ksvm_solve_sampled(const kdcd_matrix *A, const double *y,
     if (n_outer > (int64_t)0xFFFFFFFF) return KDCD_ERR_UNSUPPORTED;
     const bool learned = smp->model != nullptr;
     if (learned) {
-        if (s > m || !(smp->tau > 0.0) || !std::isfinite(smp->tau) ||
+        if (!(smp->tau > 0.0) || !std::isfinite(smp->tau) ||
             !(smp->epsilon >= 0.0 && smp->epsilon <= 1.0))
+            return KDCD_ERR_INVALID_ARG;
+        if (smp->pool == 0 ? s > m : (smp->pool < s || smp->pool > SMP_MAX_POOL))
             return KDCD_ERR_INVALID_ARG;
         int dev = -1;
         if (hipGetDevice(&dev) != hipSuccess || dev != smp->model->device)
@@ -687,6 +689,7 @@ kdcd_status kdcd_ksvm_solve_sampled(const kdcd_matrix *A, const double *y,
         a.m = m;
         a.ns = sk;
         a.topk = learned;
+        a.pool = learned ? smp->pool : 0;
         a.epsilon = smp->epsilon;
         a.tau = smp->tau;
         a.seed = smp->seed;

@@ -89,7 +89,7 @@ class _Sampling(ctypes.Structure):
     _fields_ = [("model", ctypes.c_void_p), ("epsilon", ctypes.c_double),
                 ("tau", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("idx_out", ctypes.c_void_p), ("features_out", ctypes.c_void_p),
-                ("grad_out", ctypes.c_void_p)]
+                ("grad_out", ctypes.c_void_p), ("pool", ctypes.c_int32)]
 
 
 class _Options(ctypes.Structure):
@@ -456,7 +456,7 @@ def kdcd_sampler_select(keys: torch.Tensor, s: int, epsilon: float, seed: int, o
 
 
 def kdcd_ksvm_solve_sampled(A, y, kernel, C, s, H, alpha, *, model=None, epsilon=0.0, tau=1.0,
-                            seed=0, idx_out=None, features_out=None, grad_out=None, loss=1,
+                            seed=0, pool=0, idx_out=None, features_out=None, grad_out=None, loss=1,
                             trace=None, snapshot_every=0, snapshots=None, workspace=None,
                             profile=False, stream=None):
     """Algorithm 2 (b = 1) with the coordinates drawn on the device by
@@ -473,6 +473,7 @@ def kdcd_ksvm_solve_sampled(A, y, kernel, C, s, H, alpha, *, model=None, epsilon
     smp.epsilon = float(epsilon)
     smp.tau = float(tau)
     smp.seed = int(seed)
+    smp.pool = int(pool)
     smp.idx_out = _dev(idx_out, torch.int32, H, "idx_out")
     if features_out is not None:
         smp.features_out = _dev(features_out, torch.float32, 4 * H, "features_out")

@@ -98,7 +98,8 @@ def test_keys_and_selection_match_oracle(K):
     rng = np.random.default_rng(2)
     for m, s, eps, tau, k in [(1024, 1, 0.0, 1.0, 0), (5000, 7, 0.3, 0.5, 3),
                               (70000, 64, 0.1, 0.2, 11), (3000, 1024, 0.0, 2.0, 5),
-                              (1000, 1000, 0.5, 1.0, 2), (20000, 512, 1.0, 1.0, 9)]:
+                              (1000, 1000, 0.5, 1.0, 2), (20000, 512, 1.0, 1.0, 9),
+                              (100000, 1024, 0.2, 1.0, 4), (300000, 64, 0.0, 0.7, 1)]:
         X = rng.standard_normal((m, 4)).astype(np.float32)
         keys = smp.keys(f32(X), tau, seed=77, outer=k)
         kk = keys.cpu().numpy()
@@ -111,7 +112,8 @@ def test_keys_and_selection_match_oracle(K):
 
 def test_selection_with_heavy_ties(K):
     rng = np.random.default_rng(3)
-    for m, s in [(5000, 100), (3000, 1024), (50000, 33)]:
+    # chunked path (few candidates) and radix path (chunks x s above 8192)
+    for m, s in [(5000, 100), (3000, 1024), (50000, 33), (100000, 700), (100000, 1024)]:
         keys = (np.round(rng.standard_normal(m) * 8) / 8).astype(np.float32)
         keys[:7] = keys.max()
         S = K.kdcd_sampler_select(f32(keys), s, 0.0, seed=1, outer=0).cpu().numpy()
@@ -119,10 +121,14 @@ def test_selection_with_heavy_ties(K):
 
 
 def test_selection_errors(K):
-    keys = f32(np.zeros(5000))           # 5000 keys tied at the threshold
-    with pytest.raises(K.KdcdError) as e:
-        K.kdcd_sampler_select(keys, 10, 0.0, seed=0, outer=0)
-    assert e.value.status == -2
+    # up to 2048 coordinates are ranked by one sort (any number of ties); above
+    # that the radix path holds at most 2048 keys tied at the threshold
+    S = K.kdcd_sampler_select(f32(np.zeros(2000)), 10, 0.0, seed=0, outer=0).cpu().numpy()
+    np.testing.assert_array_equal(S, np.arange(10))
+    for m in (5000, 100000):
+        with pytest.raises(K.KdcdError) as e:
+            K.kdcd_sampler_select(f32(np.zeros(m)), 10, 0.0, seed=0, outer=0)
+        assert e.value.status == -2
     bad = np.zeros(100, dtype=np.float32)
     bad[3] = np.nan
     with pytest.raises(K.KdcdError) as e:
@@ -196,12 +202,11 @@ def test_learned_sampled_solve_replays_and_selects_exactly(K):
     assert_parity(a_gpu, a_ref, 1e-9, "alpha")
     # outer iteration kk from the device's own state after kk iterations
     _, ak, gk = runs[kk * s]
-    X = np.stack([(ak * (1.0 / C)).astype(np.float32), gk.astype(np.float32),
-                  np.ones(m, np.float32), y.astype(np.float32)], axis=1)
+    X = SO.ksvm_features(ak, gk, np.ones(m), y, C)       # the device's float32 features
     keys = smp.keys(f32(X), tau, seed, kk).cpu().numpy()
     np.testing.assert_array_equal(idx[kk * s:(kk + 1) * s], SO.select(keys, s, eps, kk, seed))
     # the first outer iteration from alpha = 0: features are exact in float32
-    X0 = np.stack([np.zeros(m), -np.ones(m), np.ones(m), y], axis=1).astype(np.float32)
+    X0 = SO.ksvm_features(np.zeros(m), -np.ones(m), np.ones(m), y, C)
     keys0 = smp.keys(f32(X0), tau, seed, 0).cpu().numpy()
     np.testing.assert_array_equal(idx[:s], SO.select(keys0, s, eps, 0, seed))
 
@@ -221,16 +226,62 @@ def test_trained_sampler_beats_uniform(K):
     K.kdcd_ksvm_solve_sampled(A, y, kern, C, s, H, alpha, seed=100, features_out=feats,
                               trace=trace)
     x = feats.view(H, 4)
-    t = torch.log(1e-4 + trace.abs() / C).float()
+    t = torch.log(1e-7 + trace.abs() / C).float()
     smp = K.Sampler(1)
     losses = smp.train(x.contiguous(), t.contiguous(), batch=512, epochs=15, lr=3e-3)
-    assert losses[-1].item() < 0.5 * losses[0].item()
+    assert losses[-1].item() < 0.7 * losses[0].item()
     results = {}
-    for name, model in (("uniform", None), ("learned", smp)):
+    for name, model, eps, tau, pool in (("uniform", None, 1.0, 1.0, 0),
+                                        ("learned", smp, 0.3, 1.0, 0),
+                                        ("pool", smp, 0.5, 1.0, 256)):
         a = torch.zeros(m, dtype=torch.float64, device="cuda")
-        K.kdcd_ksvm_solve_sampled(A, y, kern, C, s, m, a, model=model, epsilon=0.1, tau=0.3,
-                                  seed=200)
+        K.kdcd_ksvm_solve_sampled(A, y, kern, C, s, m, a, model=model, epsilon=eps, tau=tau,
+                                  pool=pool, seed=200)
         results[name] = K.kdcd_ksvm_eval(A, y, kern, C, a)
     print({k: (v["dual"], v["gap"]) for k, v in results.items()})
-    assert results["learned"]["dual"] < results["uniform"]["dual"]
-    assert results["learned"]["gap"] < 0.7 * results["uniform"]["gap"]
+    for name in ("learned", "pool"):
+        assert results[name]["dual"] < results["uniform"]["dual"]
+        assert results[name]["gap"] < 0.7 * results["uniform"]["gap"]
+
+
+@pytest.mark.parametrize("pool,s", [(256, 32), (64, 64), (2048, 100)])
+def test_pool_sampled_solve_replays_and_selects_exactly(K, pool, s):
+    d = inputs.dense_ksvm_c5(m=3000, n=32, seed=24)
+    A, y = d["A"], d["y"]
+    m, C = 3000, 5.0
+    sig = 2.0 / 32
+    smp = K.Sampler(10)
+    eps, tau, seed = 0.25, 0.7, 17
+    kk = 4
+    H = (kk + 1) * s + 3
+    runs = {}
+    for HH in (kk * s, H):
+        alpha = torch.zeros(m, dtype=torch.float64, device="cuda")
+        g = torch.zeros(m, dtype=torch.float64, device="cuda")
+        idx, _ = K.kdcd_ksvm_solve_sampled(dev(A), dev(y), (2, sig, 0.0, 1), C, s, HH, alpha,
+                                           model=smp, epsilon=eps, tau=tau, seed=seed, pool=pool,
+                                           grad_out=g)
+        runs[HH] = (idx.cpu().numpy(), alpha.cpu().numpy(), g.cpu().numpy())
+    idx, a_gpu, g_gpu = runs[H]
+    np.testing.assert_array_equal(idx[:kk * s], runs[kk * s][0])
+    a_ref, _ = O.dcd_ksvm(A, y, O.Kernel(O.RBF, sigma=sig), C, H, idx, s=s)
+    assert_parity(a_gpu, a_ref, 1e-9, "alpha")
+    assert_parity(g_gpu, oracle_grad(A, y, O.Kernel(O.RBF, sigma=sig), C, a_ref, 1), 1e-9, "g")
+    for k, (ak, gk) in ((0, (np.zeros(m), -np.ones(m))), (kk, runs[kk * s][1:])):
+        X = SO.ksvm_features(ak, gk, np.ones(m), y, C)
+        keys = smp.keys(f32(X), tau, seed, k).cpu().numpy()      # noise of coordinate i
+        cand = SO.pool_candidates(m, pool, k, seed)
+        ref = SO.select_pool(keys[cand], cand, m, s, eps, k, seed)
+        np.testing.assert_array_equal(idx[k * s:(k + 1) * s], ref)
+
+
+def test_pool_argument_errors(K):
+    m = 500
+    A = torch.randn(m, 8, dtype=torch.float64, device="cuda")
+    y = torch.ones(m, dtype=torch.float64, device="cuda")
+    a = torch.zeros(m, dtype=torch.float64, device="cuda")
+    smp = K.Sampler(0)
+    for pool, s in ((16, 32), (4096, 32)):
+        with pytest.raises(K.KdcdError) as e:
+            K.kdcd_ksvm_solve_sampled(A, y, (2, 1.0, 0.0, 1), 1.0, s, 64, a, model=smp, pool=pool)
+        assert e.value.status == -1

@@ -148,3 +148,28 @@ def test_train_reduces_loss_and_single_batch_is_one_adam_step():
     _, g = S.loss_and_grad(p0, X, t)
     ref, _, _ = S.adam_step(p0.astype(np.float64), g, 0, 0, 1, 1e-3)
     np.testing.assert_allclose(p1, ref, rtol=0, atol=1e-15)
+
+
+def test_slog_feature_values():
+    g = np.array([0.0, 1.0, -1.0, 2.0 ** -20, -(2.0 ** -21), 3.0 * 2 ** -20, 0.75, 1e6, -5e-7])
+    x = S.slog(g)
+    # |g| 2^20 = v: v < 1 kept, else 1 + log2 at powers of two, linear between them
+    expect = np.array([0.0, 21.0, -21.0, 1.0, -0.5, 1 + 1 + 0.5, 1 + 19 + 0.5,
+                       1 + 39 + (1e6 * 2 ** 20 / 2 ** 39 - 1), -(5e-7 * 2 ** 20)]) / 8
+    np.testing.assert_allclose(x, expect, rtol=1e-6, atol=0)
+    gg = np.sort(np.random.default_rng(0).standard_normal(10000) * 10.0 ** np.random.default_rng(1).uniform(-8, 2, 10000))
+    xs = S.slog(gg)
+    assert np.all(np.diff(xs) >= 0)                          # monotone
+    assert np.all(np.sign(xs) == np.sign(gg))
+
+
+def test_pool_candidates_and_pool_selection():
+    c = np.concatenate([S.pool_candidates(50, 512, k, seed=3) for k in range(100)])
+    assert c.min() >= 0 and c.max() < 50
+    h = np.bincount(c, minlength=50)
+    assert h.min() > 850 and h.max() < 1200          # 1024 expected per coordinate
+    cand = S.pool_candidates(1000, 64, 7, seed=2)
+    keys = np.random.default_rng(0).standard_normal(64).astype(np.float32)
+    out = S.select_pool(keys, cand, 1000, 16, 0.0, 7, 2)
+    ranked = sorted(range(64), key=lambda j: (-float(keys[j]), j))
+    assert list(out) == [int(cand[j]) for j in ranked[:16]]
