@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--compute", default="f64", help="kernel-block precision (f64, f32, bf16, f16, bf16x3)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-convergence", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the built-in tile rule instead of timing the configurations")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the oracle sample")
     ap.add_argument("--workload", default="c2", choices=["c2", "c4-sweep", "c5s-sampler"],
                     help="c2: the headline line; c4-sweep: batched (lambda, sigma) sweep and "
@@ -465,6 +467,14 @@ def main():
     alpha = torch.zeros(M, dtype=torch.float64, device=dev)
     kern = K.Kernel(K.KERNEL_RBF, sigma=SIGMA)
 
+    tuned = {}
+    if args.compute == "f64" and not args.no_autotune:
+        # the library's autotuner picks the tile of every block width the solve uses
+        for sb in sorted({s * B, (H % s) * B} - {0}):
+            cid, us = K.kdcd_autotune(A, kern, sb, reps=10)
+            tuned[sb] = {"config": cid, "tile": list(K.kdcd_tune_configs("f64")[cid]),
+                         "us": round(us, 2)}
+        log(f"autotune: {tuned}")
     for _ in range(args.warmup):
         alpha.zero_()
         K.kdcd_krr_solve(A, y, kern, LAM, B, s, H, I, alpha, compute=args.compute)
@@ -510,7 +520,8 @@ def main():
         "roofline": {"bound": "mfma", "achieved": round(achieved, 4), "peak": PEAK_F64,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_F64, 4), "traffic": traffic,
                      "kernel": "kblock_f64_kernel", "launches": kb_launches,
-                     "avg_launch_us": round(kb_ms / kb_launches * 1e3, 2)},
+                     "avg_launch_us": round(kb_ms / kb_launches * 1e3, 2),
+                     "tiles": tuned or "built-in rule"},
         "stages_ms_per_step": {"kblock": round(kb_ms / args.steps, 4),
                                "finish": round(fin_ms / args.steps, 4),
                                "recurrence": round(rec_ms / args.steps, 4)},

@@ -321,6 +321,32 @@ kdcd_status kdcd_ksvm_solve_sampled(const kdcd_matrix *A, const double *y,
                                     const kdcd_sampling *sampling, double *alpha,
                                     const kdcd_options *opt, kdcd_stream stream);
 
+/* ---------------------------------------------------------------------------
+ * Tuning of the kernel-block product.  The tile configuration of the FP64
+ * product is chosen per (compute, n, sb) from a process-wide table, else by a
+ * built-in rule.  Entries come from kdcd_autotune (which times every
+ * configuration on the caller's matrix) or kdcd_tune_set, and can be saved to
+ * and loaded from a text file.  Table updates must not overlap solves.
+ * ------------------------------------------------------------------------- */
+/* Number of configurations for `compute` (0 if not tunable); fills up to
+ * `max` entries of bm, bn (tile rows x columns) and waves per workgroup
+ * (each array may be NULL). */
+int32_t kdcd_tune_configs(int32_t compute, int32_t *bm, int32_t *bn, int32_t *waves, int32_t max);
+/* Pin configuration `id` for (compute, n, sb); id < 0 removes the entry. */
+kdcd_status kdcd_tune_set(int32_t compute, int64_t n, int32_t sb, int32_t id);
+/* The configuration a launch with (compute, n, sb) uses now (-1: invalid). */
+int32_t kdcd_tune_get(int32_t compute, int64_t n, int32_t sb);
+/* Time every configuration on A with sb sampled rows (evenly strided),
+ * three rounds of `reps` launches each (a configuration counts with its
+ * fastest round), record the fastest for (compute, A->n, sb).
+ * best_id / best_us (host, may be NULL) receive the winner and its mean
+ * launch time.  Dense A only.  Synchronises `stream`. */
+kdcd_status kdcd_autotune(const kdcd_matrix *A, const kdcd_kernel *kernel, int32_t sb,
+                          int32_t compute, int32_t reps, int32_t *best_id, double *best_us,
+                          kdcd_stream stream);
+kdcd_status kdcd_tune_save(const char *path);
+kdcd_status kdcd_tune_load(const char *path);
+
 /* Device workspace a solve needs (problem: 0 = K-SVM, 1 = K-RR). */
 size_t kdcd_workspace_bytes(int32_t problem, const kdcd_matrix *A, const kdcd_kernel *kernel,
                             int32_t b, int32_t s, int32_t compute);

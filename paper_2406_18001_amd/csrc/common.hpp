@@ -136,7 +136,13 @@ struct KBlockArgs {
 };
 
 // Launchers (return hipError_t of the launch).
-int64_t kblock_f64_row_groups(int64_t m, int32_t sb, bool batch = false);
+int64_t kblock_f64_row_groups(int64_t m, int64_t n, int32_t sb, bool batch = false);
+// Tile configurations of the FP64 product and the process-wide tuning table.
+int f64_config_count();
+void f64_config_shape(int id, int *bm, int *bn, int *waves);
+int f64_config_id(int64_t n, int32_t sb);
+int tune_lookup(int32_t compute, int64_t n, int32_t sb);   // -1: no entry
+void tune_store(int32_t compute, int64_t n, int32_t sb, int id);   // id < 0 removes
 int64_t kblock_mixed_row_groups(int64_t m, int32_t sb, bool batch = false);
 hipError_t launch_kblock_f64(const KBlockArgs &a, hipStream_t st);
 hipError_t launch_norms(const kdcd_matrix *A, double *norms, hipStream_t st);

@@ -361,15 +361,6 @@ struct Cfg {
     int bm, bn;
 };
 
-// Tile shape per width of the index block.
-Cfg pick_cfg(int32_t sb)
-{
-    if (sb <= 16) return {128, 16};
-    if (sb <= 32) return {128, 32};
-    if (sb <= 64) return {64, 64};
-    return {64, 128};
-}
-
 constexpr int64_t kMaxRowGroups = 1024;
 
 template <int WM, int WN, int TM, int TN, bool BATCH>
@@ -410,10 +401,56 @@ Cfg pick_cfg_batch(int32_t sb)
     return {64, 64};
 }
 
-int64_t kblock_f64_row_groups(int64_t m, int32_t sb, bool batch)
+// Configurations of the single-problem launch: (WM, WN, TM, TN).  The 8-wave
+// shapes keep the 64 x 128 / 128 x 64 tile at two waves per SIMD.
+struct F64Cfg {
+    int wm, wn, tm, tn;
+};
+constexpr F64Cfg kF64Cfgs[] = {
+    {4, 1, 2, 1},   // 0: 128 x 16, 4 waves
+    {4, 1, 2, 2},   // 1: 128 x 32, 4 waves
+    {2, 2, 2, 2},   // 2: 64 x 64, 4 waves
+    {2, 2, 2, 4},   // 3: 64 x 128, 4 waves
+    {2, 4, 2, 2},   // 4: 64 x 128, 8 waves
+    {4, 2, 2, 2},   // 5: 128 x 64, 8 waves
+};
+constexpr int kF64NumCfgs = sizeof(kF64Cfgs) / sizeof(kF64Cfgs[0]);
+
+int f64_config_count() { return kF64NumCfgs; }
+
+void f64_config_shape(int id, int *bm, int *bn, int *waves)
 {
-    const Cfg c = batch ? pick_cfg_batch(sb) : pick_cfg(sb);
-    const int64_t n_u = (m + c.bm - 1) / c.bm;
+    const F64Cfg &c = kF64Cfgs[id];
+    *bm = 16 * c.tm * c.wm;
+    *bn = 16 * c.tn * c.wn;
+    *waves = c.wm * c.wn;
+}
+
+// Built-in rule, used when the tuning table has no entry for (n, sb).
+static int f64_default_id(int32_t sb)
+{
+    if (sb <= 16) return 0;
+    if (sb <= 32) return 1;
+    if (sb <= 64) return 2;
+    return 3;
+}
+
+int f64_config_id(int64_t n, int32_t sb)
+{
+    const int id = tune_lookup(KDCD_F64, n, sb);
+    return (id >= 0 && id < kF64NumCfgs) ? id : f64_default_id(sb);
+}
+
+int64_t kblock_f64_row_groups(int64_t m, int64_t n, int32_t sb, bool batch)
+{
+    int bm;
+    if (batch) {
+        bm = pick_cfg_batch(sb).bm;
+    } else {
+        int bn, w;
+        f64_config_shape(f64_config_id(n, sb), &bm, &bn, &w);
+    }
+    const int64_t n_u = (m + bm - 1) / bm;
     return n_u < kMaxRowGroups ? n_u : kMaxRowGroups;
 }
 
@@ -425,11 +462,14 @@ hipError_t launch_kblock_f64(const KBlockArgs &a, hipStream_t st)
         if (c.bn == 32) return launch_cfg<4, 1, 2, 2, true>(a, st);
         return launch_cfg<2, 2, 2, 2, true>(a, st);
     }
-    const Cfg c = pick_cfg(a.sb);
-    if (c.bn == 16) return launch_cfg<4, 1, 2, 1, false>(a, st);
-    if (c.bn == 32) return launch_cfg<4, 1, 2, 2, false>(a, st);
-    if (c.bn == 64) return launch_cfg<2, 2, 2, 2, false>(a, st);
-    return launch_cfg<2, 2, 2, 4, false>(a, st);
+    switch (f64_config_id(a.A->n, a.sb)) {
+    case 0: return launch_cfg<4, 1, 2, 1, false>(a, st);
+    case 1: return launch_cfg<4, 1, 2, 2, false>(a, st);
+    case 2: return launch_cfg<2, 2, 2, 2, false>(a, st);
+    case 3: return launch_cfg<2, 2, 2, 4, false>(a, st);
+    case 4: return launch_cfg<2, 4, 2, 2, false>(a, st);
+    default: return launch_cfg<4, 2, 2, 2, false>(a, st);
+    }
 }
 
 }  // namespace kdcd

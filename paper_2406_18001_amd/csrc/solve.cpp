@@ -67,7 +67,7 @@ kdcd_status check_compute(const kdcd_matrix *A, int32_t compute)
 int64_t row_groups(const kdcd_matrix *A, int32_t sb, int32_t compute, bool batch = false)
 {
     if (A->format == KDCD_CSR) return kblock_csr_row_groups(A->m, sb);
-    if (compute == KDCD_F64) return kblock_f64_row_groups(A->m, sb, batch);
+    if (compute == KDCD_F64) return kblock_f64_row_groups(A->m, A->n, sb, batch);
     return kblock_mixed_row_groups(A->m, sb, batch);
 }
 
@@ -745,6 +745,83 @@ kdcd_status kdcd_ksvm_solve_sampled(const kdcd_matrix *A, const double *y,
     rc = read_status(status, st);
     timer.report(o.profile);
     return rc;
+}
+
+kdcd_status kdcd_autotune(const kdcd_matrix *A, const kdcd_kernel *kernel, int32_t sb,
+                          int32_t compute, int32_t reps, int32_t *best_id, double *best_us,
+                          kdcd_stream stream)
+{
+    kdcd_status rc = check_matrix(A);
+    if (rc != KDCD_OK) return rc;
+    if ((rc = check_kernel(kernel)) != KDCD_OK) return rc;
+    if (compute != KDCD_F64 || A->format != KDCD_DENSE) return KDCD_ERR_UNSUPPORTED;
+    if (sb < 1 || sb > kMaxSB || sb > A->m || reps < 1) return KDCD_ERR_INVALID_ARG;
+    const hipStream_t st = (hipStream_t)stream;
+    Layout L = make_layout(0, A, kernel, 1, sb, KDCD_F64);
+    const size_t o_S = L.total;
+    L.total += align256(sizeof(int32_t) * (size_t)sb);
+    Workspace ws;
+    if ((rc = acquire(ws, L, nullptr, st)) != KDCD_OK) return rc;
+    int32_t *S = ws.at<int32_t>(o_S);
+    std::vector<int32_t> hS((size_t)sb);
+    for (int32_t j = 0; j < sb; ++j) hS[(size_t)j] = (int32_t)(((int64_t)j * A->m) / sb);
+    KDCD_HIP_TRY(hipMemcpyAsync(S, hS.data(), sizeof(int32_t) * (size_t)sb, hipMemcpyHostToDevice, st));
+    double *norms = ws.at<double>(L.norms);
+    KDCD_HIP_TRY(launch_fill_i32(ws.at<int32_t>(L.status), 0, 1, st));
+    KDCD_HIP_TRY(launch_norms(A, norms, st));
+    KBlockArgs kb{};
+    kb.A = A;
+    kb.S = S;
+    kb.sb = sb;
+    kb.norms = norms;
+    kb.kp = to_params(kernel);
+    kb.beta = norms;                 // any finite m-vector
+    kb.partial = ws.at<double>(L.partial);
+    kb.W = ws.at<double>(L.W);
+    kb.status = ws.at<int32_t>(L.status);
+    kb.compute = KDCD_F64;
+    const int prev = tune_lookup(compute, A->n, sb);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return KDCD_ERR_HIP;
+    // three interleaved rounds; a configuration's time is its fastest round
+    const int ncfg = f64_config_count();
+    std::vector<double> tmin((size_t)ncfg, 0.0);
+    rc = KDCD_OK;
+    for (int round = 0; round < 3 && rc == KDCD_OK; ++round) {
+        for (int id = 0; id < ncfg && rc == KDCD_OK; ++id) {
+            tune_store(compute, A->n, sb, id);
+            float ms = 0.f;
+            if (launch_kblock(kb, st) != hipSuccess || hipEventRecord(e0, st) != hipSuccess) {
+                rc = KDCD_ERR_HIP;
+                break;
+            }
+            for (int r = 0; r < reps && rc == KDCD_OK; ++r)
+                if (launch_kblock(kb, st) != hipSuccess) rc = KDCD_ERR_HIP;
+            if (rc != KDCD_OK || hipEventRecord(e1, st) != hipSuccess ||
+                hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                rc = KDCD_ERR_HIP;
+                break;
+            }
+            const double t = 1e3 * (double)ms / reps;
+            if (round == 0 || t < tmin[(size_t)id]) tmin[(size_t)id] = t;
+        }
+    }
+    int best = -1;
+    double best_t = 0.0;
+    for (int id = 0; id < ncfg; ++id)
+        if (best < 0 || tmin[(size_t)id] < best_t) {
+            best = id;
+            best_t = tmin[(size_t)id];
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    tune_store(compute, A->n, sb, rc == KDCD_OK ? best : prev);
+    if (rc != KDCD_OK) return rc;
+    if ((rc = read_status(ws.at<int32_t>(L.status), st)) != KDCD_OK) return rc;
+    if (best_id) *best_id = best;
+    if (best_us) *best_us = best_t;
+    return KDCD_OK;
 }
 
 kdcd_status kdcd_kernel_rhs(const kdcd_matrix *A, const kdcd_kernel *kernel, const int32_t *S,

@@ -1,0 +1,115 @@
+// Process-wide tuning table of the kernel-block product: the tile
+// configuration chosen per (compute, n, sb), filled by kdcd_autotune or
+// kdcd_tune_set, saved to and loaded from a plain text file
+// ("compute n sb id" per line).
+#include <cstdio>
+#include <map>
+#include <mutex>
+#include <tuple>
+
+#include "common.hpp"
+
+namespace kdcd {
+namespace {
+
+using Key = std::tuple<int32_t, int64_t, int32_t>;
+
+std::mutex &table_mutex()
+{
+    static std::mutex mu;
+    return mu;
+}
+
+std::map<Key, int> &table()
+{
+    static std::map<Key, int> t;
+    return t;
+}
+
+}  // namespace
+
+int tune_lookup(int32_t compute, int64_t n, int32_t sb)
+{
+    std::lock_guard<std::mutex> lk(table_mutex());
+    const auto it = table().find(Key(compute, n, sb));
+    return it == table().end() ? -1 : it->second;
+}
+
+void tune_store(int32_t compute, int64_t n, int32_t sb, int id)
+{
+    std::lock_guard<std::mutex> lk(table_mutex());
+    if (id < 0) table().erase(Key(compute, n, sb));
+    else table()[Key(compute, n, sb)] = id;
+}
+
+}  // namespace kdcd
+
+using namespace kdcd;
+
+extern "C" {
+
+int32_t kdcd_tune_configs(int32_t compute, int32_t *bm, int32_t *bn, int32_t *waves, int32_t max)
+{
+    if (compute != KDCD_F64) return 0;
+    const int n = f64_config_count();
+    for (int i = 0; i < n && i < max; ++i) {
+        int a, b, w;
+        f64_config_shape(i, &a, &b, &w);
+        if (bm) bm[i] = a;
+        if (bn) bn[i] = b;
+        if (waves) waves[i] = w;
+    }
+    return n;
+}
+
+kdcd_status kdcd_tune_set(int32_t compute, int64_t n, int32_t sb, int32_t id)
+{
+    if (compute != KDCD_F64) return KDCD_ERR_UNSUPPORTED;
+    if (n < 1 || sb < 1 || sb > kMaxSB || id >= f64_config_count()) return KDCD_ERR_INVALID_ARG;
+    tune_store(compute, n, sb, id < 0 ? -1 : id);
+    return KDCD_OK;
+}
+
+int32_t kdcd_tune_get(int32_t compute, int64_t n, int32_t sb)
+{
+    if (compute != KDCD_F64 || n < 1 || sb < 1 || sb > kMaxSB) return -1;
+    return f64_config_id(n, sb);
+}
+
+kdcd_status kdcd_tune_save(const char *path)
+{
+    if (!path) return KDCD_ERR_INVALID_ARG;
+    FILE *f = std::fopen(path, "w");
+    if (!f) return KDCD_ERR_INVALID_ARG;
+    {
+        std::lock_guard<std::mutex> lk(table_mutex());
+        for (const auto &e : table())
+            std::fprintf(f, "%d %lld %d %d\n", (int)std::get<0>(e.first),
+                         (long long)std::get<1>(e.first), (int)std::get<2>(e.first), e.second);
+    }
+    return std::fclose(f) == 0 ? KDCD_OK : KDCD_ERR_INVALID_ARG;
+}
+
+kdcd_status kdcd_tune_load(const char *path)
+{
+    if (!path) return KDCD_ERR_INVALID_ARG;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return KDCD_ERR_INVALID_ARG;
+    int c, sb, id;
+    long long n;
+    kdcd_status rc = KDCD_OK;
+    while (true) {
+        const int got = std::fscanf(f, "%d %lld %d %d", &c, &n, &sb, &id);
+        if (got == EOF) break;
+        if (got != 4 || c != KDCD_F64 || n < 1 || sb < 1 || sb > kMaxSB || id < 0 ||
+            id >= f64_config_count()) {
+            rc = KDCD_ERR_INVALID_ARG;
+            break;
+        }
+        tune_store(c, n, sb, id);
+    }
+    std::fclose(f);
+    return rc;
+}
+
+}  // extern "C"

@@ -133,6 +133,18 @@ _lib.kdcd_sampler_select.argtypes = [_P, ctypes.c_int64, ctypes.c_int32, ctypes.
 _lib.kdcd_ksvm_solve_sampled.restype = ctypes.c_int
 _lib.kdcd_ksvm_solve_sampled.argtypes = [_P, _P, _P, ctypes.c_double, ctypes.c_int32,
                                          ctypes.c_int64, _P, _P, _P, _P]
+_lib.kdcd_tune_configs.restype = ctypes.c_int32
+_lib.kdcd_tune_configs.argtypes = [ctypes.c_int32, _P, _P, _P, ctypes.c_int32]
+_lib.kdcd_tune_set.restype = ctypes.c_int
+_lib.kdcd_tune_set.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32]
+_lib.kdcd_tune_get.restype = ctypes.c_int32
+_lib.kdcd_tune_get.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32]
+_lib.kdcd_autotune.restype = ctypes.c_int
+_lib.kdcd_autotune.argtypes = [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P, _P]
+_lib.kdcd_tune_save.restype = ctypes.c_int
+_lib.kdcd_tune_save.argtypes = [ctypes.c_char_p]
+_lib.kdcd_tune_load.restype = ctypes.c_int
+_lib.kdcd_tune_load.argtypes = [ctypes.c_char_p]
 _lib.kdcd_kernel_rhs.restype = ctypes.c_int
 _lib.kdcd_kernel_rhs.argtypes = [_P, _P, _P, ctypes.c_int32, _P, _P, _P, _P, ctypes.c_int32, _P]
 _lib.kdcd_ksvm_eval.restype = ctypes.c_int
@@ -489,3 +501,46 @@ def kdcd_ksvm_solve_sampled(A, y, kernel, C, s, H, alpha, *, model=None, epsilon
     _check(st, "kdcd_ksvm_solve_sampled")
     p = {f: getattr(prof, f) for f, _ in _Profile._fields_} if prof is not None else None
     return idx_out, p
+
+
+# ------------------------------------------------------------------ tuning
+
+def _compute_id(compute):
+    return COMPUTE[compute] if isinstance(compute, str) else int(compute)
+
+
+def kdcd_tune_configs(compute="f64") -> list:
+    """[(bm, bn, waves)] of the tile configurations, indexed by id."""
+    n = _lib.kdcd_tune_configs(_compute_id(compute), None, None, None, 0)
+    bm, bn, w = (ctypes.c_int32 * max(n, 1))(), (ctypes.c_int32 * max(n, 1))(), (ctypes.c_int32 * max(n, 1))()
+    _lib.kdcd_tune_configs(_compute_id(compute), bm, bn, w, n)
+    return [(bm[i], bn[i], w[i]) for i in range(n)]
+
+
+def kdcd_tune_set(compute, n, sb, config_id):
+    _check(_lib.kdcd_tune_set(_compute_id(compute), int(n), int(sb), int(config_id)),
+           "kdcd_tune_set")
+
+
+def kdcd_tune_get(compute, n, sb) -> int:
+    return int(_lib.kdcd_tune_get(_compute_id(compute), int(n), int(sb)))
+
+
+def kdcd_autotune(A, kernel, sb, compute="f64", reps=10, stream=None):
+    """Time every configuration on A; returns (best id, mean launch us)."""
+    mat, _, _ = _matrix(A)
+    kern = _kernel(kernel)
+    best = ctypes.c_int32(-1)
+    us = ctypes.c_double(0.0)
+    _check(_lib.kdcd_autotune(ctypes.byref(mat), ctypes.byref(kern), int(sb), _compute_id(compute),
+                              int(reps), ctypes.byref(best), ctypes.byref(us), _stream(stream)),
+           "kdcd_autotune")
+    return best.value, us.value
+
+
+def kdcd_tune_save(path):
+    _check(_lib.kdcd_tune_save(str(path).encode()), "kdcd_tune_save")
+
+
+def kdcd_tune_load(path):
+    _check(_lib.kdcd_tune_load(str(path).encode()), "kdcd_tune_load")

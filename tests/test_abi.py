@@ -74,3 +74,39 @@ def test_host_argument_checks_need_no_device():
                                  16, 16, None, None) == -2
     assert K._lib.kdcd_krr_solve(ctypes.byref(mat), 16, ctypes.byref(good), 1.0, 8, 129, 1,
                                  16, 16, None, None) == -2
+
+
+def test_tuning_table_host_side(tmp_path):
+    """The tuning table is host state: set / get / save / load without a GPU."""
+    lib = ctypes.CDLL(LIB)
+    lib.kdcd_tune_configs.restype = ctypes.c_int32
+    lib.kdcd_tune_configs.argtypes = [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_int32]
+    lib.kdcd_tune_set.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32]
+    lib.kdcd_tune_get.restype = ctypes.c_int32
+    lib.kdcd_tune_get.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32]
+    lib.kdcd_tune_save.argtypes = [ctypes.c_char_p]
+    lib.kdcd_tune_load.argtypes = [ctypes.c_char_p]
+    n = lib.kdcd_tune_configs(0, None, None, None, 0)
+    assert n >= 4
+    bm, bn, w = (ctypes.c_int32 * n)(), (ctypes.c_int32 * n)(), (ctypes.c_int32 * n)()
+    assert lib.kdcd_tune_configs(0, bm, bn, w, n) == n
+    assert all(bm[i] % 16 == 0 and bn[i] % 16 == 0 and w[i] in (4, 8) for i in range(n))
+    assert lib.kdcd_tune_configs(2, None, None, None, 0) == 0          # bf16: not tunable
+    default = lib.kdcd_tune_get(0, 777, 96)
+    assert 0 <= default < n
+    other = (default + 1) % n
+    assert lib.kdcd_tune_set(0, 777, 96, other) == 0
+    assert lib.kdcd_tune_get(0, 777, 96) == other
+    path = str(tmp_path / "tune.txt")
+    assert lib.kdcd_tune_save(path.encode()) == 0
+    assert lib.kdcd_tune_set(0, 777, 96, -1) == 0
+    assert lib.kdcd_tune_get(0, 777, 96) == default
+    assert lib.kdcd_tune_load(path.encode()) == 0
+    assert lib.kdcd_tune_get(0, 777, 96) == other
+    assert lib.kdcd_tune_set(0, 777, 96, n) == -1                      # unknown id
+    assert lib.kdcd_tune_set(2, 777, 96, 0) == -2
+    bad = tmp_path / "bad.txt"
+    bad.write_text("0 10 10 99\n")
+    assert lib.kdcd_tune_load(str(bad).encode()) == -1
+    assert lib.kdcd_tune_set(0, 777, 96, -1) == 0

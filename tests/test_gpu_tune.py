@@ -1,0 +1,69 @@
+"""Every tile configuration of the FP64 kernel block, forced through the
+tuning table, against the FP64 oracle; the autotuner's choice is recorded and
+used."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2406_18001_amd import inputs
+from tests.helpers import assert_parity, dev, idx_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def K():
+    from paper_2406_18001_amd import kdcd
+    return kdcd
+
+
+@pytest.mark.parametrize("m,n,sb", [(1000, 100, 7), (777, 64, 33), (2500, 513, 128),
+                                    (300, 40, 300), (1200, 96, 1024)])
+@pytest.mark.parametrize("kk", [(2, 0.9, 0.0, 1), (1, 0.0, 1.0, 3), (0, 0.0, 0.0, 1)])
+def test_every_config_matches_oracle(K, m, n, sb, kk):
+    rng = np.random.default_rng(m + sb)
+    A = rng.standard_normal((m, n)) / np.sqrt(n)
+    S = rng.integers(0, m, size=sb).astype(np.int32)
+    beta = rng.standard_normal(m)
+    ok = O.Kernel(kk[0], sigma=kk[1], c=kk[2], degree=kk[3])
+    r_ref = O.kernel_rhs(A, ok, S, beta)
+    W_ref = O.kernel_block(A, ok, S, S)
+    try:
+        for cid in range(len(K.kdcd_tune_configs("f64"))):
+            K.kdcd_tune_set("f64", n, sb, cid)
+            assert K.kdcd_tune_get("f64", n, sb) == cid
+            r, W = K.kdcd_kernel_rhs(dev(A), kk, idx_dev(S), dev(beta), want_W=True)
+            assert_parity(r.cpu().numpy(), r_ref, 1e-11, f"r config {cid}")
+            assert_parity(W.cpu().numpy(), W_ref, 1e-12, f"W config {cid}")
+    finally:
+        K.kdcd_tune_set("f64", n, sb, -1)
+
+
+def test_solve_with_each_config(K):
+    d = inputs.dense_krr_c2(m=3000, n=128, seed=5)
+    idx = inputs.krr_indices(3000, 8, 200, seed=0)
+    a_ref, _ = O.bdcd_krr(d["A"], d["y"], O.Kernel(O.RBF, sigma=1.0), 1e-3, 8, 200, idx, s=16)
+    try:
+        for cid in range(len(K.kdcd_tune_configs("f64"))):
+            K.kdcd_tune_set("f64", 128, 128, cid)
+            K.kdcd_tune_set("f64", 128, 64, cid)       # the ragged last outer iteration
+            a = torch.zeros(3000, dtype=torch.float64, device="cuda")
+            K.kdcd_krr_solve(dev(d["A"]), dev(d["y"]), (2, 1.0, 0.0, 1), 1e-3, 8, 16, 200,
+                             idx_dev(idx), a)
+            assert_parity(a.cpu().numpy(), a_ref, 1e-9, f"alpha config {cid}")
+    finally:
+        K.kdcd_tune_set("f64", 128, 128, -1)
+        K.kdcd_tune_set("f64", 128, 64, -1)
+
+
+def test_autotune_records_its_choice(K):
+    d = inputs.dense_krr_c2(m=8000, n=256, seed=6)
+    A = dev(d["A"])
+    try:
+        best, us = K.kdcd_autotune(A, (2, 1.0, 0.0, 1), 256, reps=5)
+        assert 0 <= best < len(K.kdcd_tune_configs("f64")) and us > 0
+        assert K.kdcd_tune_get("f64", 256, 256) == best
+        print(f"autotune 8000x256 sb=256: config {best} {K.kdcd_tune_configs('f64')[best]} {us:.1f} us")
+    finally:
+        K.kdcd_tune_set("f64", 256, 256, -1)
