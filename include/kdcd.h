@@ -101,8 +101,20 @@ typedef struct {
     double total_ms;         /* first to last event of the solve                   */
 } kdcd_profile;
 
+/*
+ * KDCD_FLAG_GRAPH (kdcd_ksvm_solve, kdcd_krr_solve, kdcd_batch_solve): the
+ * call's whole launch sequence (validation, norms, every outer iteration,
+ * snapshot copies) is captured once into a hipGraph on a private stream of
+ * the current device and kept in a process-wide cache of 8 entries keyed by
+ * every argument (pointers included, stream excluded); an identical later
+ * call launches the instantiated graph on `stream`, so it re-reads the
+ * current contents of A, y, idx and alpha.  A cache entry keeps its own
+ * workspace (allocated once with hipMalloc) unless opt->workspace is given,
+ * which then must stay valid while the entry lives.  Graph-mode calls are
+ * serialised by one lock.  With a profile, only total_ms is reported.
+ */
 enum {
-    KDCD_FLAG_GRAPH = 1      /* replay the outer iterations from a captured hipGraph */
+    KDCD_FLAG_GRAPH = 1
 };
 
 typedef struct {
@@ -313,8 +325,9 @@ typedef struct {
  * b = 1 on idx_out.  Dense FP64 only; H < 2^32 * s; when model != NULL,
  * s <= m (pool == 0) or s <= pool.  Other arguments as kdcd_ksvm_solve
  * (opt->trace receives theta).
- * Errors: as kdcd_ksvm_solve; UNSUPPORTED for CSR, low precision or a tie
- * group beyond 2048 keys; NONFINITE for a non-finite score.
+ * Errors: as kdcd_ksvm_solve; UNSUPPORTED for CSR, low precision,
+ * KDCD_FLAG_GRAPH or a tie group beyond 2048 keys; NONFINITE for a
+ * non-finite score.
  */
 kdcd_status kdcd_ksvm_solve_sampled(const kdcd_matrix *A, const double *y,
                                     const kdcd_kernel *kernel, double C, int32_t s, int64_t H,
@@ -346,6 +359,10 @@ kdcd_status kdcd_autotune(const kdcd_matrix *A, const kdcd_kernel *kernel, int32
                           kdcd_stream stream);
 kdcd_status kdcd_tune_save(const char *path);
 kdcd_status kdcd_tune_load(const char *path);
+
+/* Destroy every graph cached by KDCD_FLAG_GRAPH calls and free the
+ * workspaces they own (no call may be running). */
+void kdcd_graph_cache_clear(void);
 
 /* Device workspace a solve needs (problem: 0 = K-SVM, 1 = K-RR). */
 size_t kdcd_workspace_bytes(int32_t problem, const kdcd_matrix *A, const kdcd_kernel *kernel,

@@ -6,6 +6,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "common.hpp"
@@ -243,14 +246,15 @@ kdcd_status prepare_lowp(const KBlockArgs &base, const Layout &L, Workspace &ws,
     return KDCD_OK;
 }
 
-kdcd_status run_solve(const SolveArgs &sa)
+// Everything a solve puts on its stream, in the workspace at `base`, without
+// the final status read (the status word is at offset L.status).
+kdcd_status enqueue_solve(const SolveArgs &sa, const Layout &L, char *wsbase, StageTimer &timer)
 {
     const kdcd_matrix *A = sa.A;
     const hipStream_t st = sa.st;
-    const Layout L = make_layout(sa.problem, A, sa.kernel, sa.b, sa.s, sa.opt.compute);
-    Workspace ws;
-    kdcd_status rc = acquire(ws, L, &sa.opt, st);
-    if (rc != KDCD_OK) return rc;
+    Workspace ws;            // a view: not owned, never freed here
+    ws.base = wsbase;
+    kdcd_status rc = KDCD_OK;
     int32_t *status = ws.at<int32_t>(L.status);
     double *norms = ws.at<double>(L.norms);
     double *partial = ws.at<double>(L.partial);
@@ -282,8 +286,6 @@ kdcd_status run_solve(const SolveArgs &sa)
     rc = prepare_lowp(base, L, ws, st, kb);
     if (rc != KDCD_OK) return rc;
 
-    StageTimer timer;
-    timer.on = sa.opt.profile != nullptr;
     const int64_t n_outer = (sa.H + sa.s - 1) / sa.s;
     int64_t snap = 0;
     for (int64_t k = 0; k < n_outer; ++k) {
@@ -340,7 +342,173 @@ kdcd_status run_solve(const SolveArgs &sa)
             ++snap;
         }
     }
-    rc = read_status(status, st);
+    return KDCD_OK;
+}
+
+// ------------------------------------------------------------ graph replay
+// KDCD_FLAG_GRAPH: the whole enqueue sequence of a call is captured once on a
+// private stream of the device into a hipGraph, instantiated and kept in a
+// small process-wide cache keyed by every argument of the call; identical
+// later calls launch the instantiated graph on the caller's stream.  A cache
+// entry owns its workspace unless the caller passed one.  Device memory is
+// cleared by kernels, never by memset nodes.  Calls in graph mode are
+// serialised by one mutex, held until the call's status is read.
+
+struct GraphEntry {
+    std::string key;
+    int device = -1;
+    hipGraphExec_t exec = nullptr;
+    char *ws = nullptr;
+    bool owned = false;
+    uint64_t used = 0;
+};
+
+struct GraphCache {
+    std::mutex mu;
+    std::vector<GraphEntry> entries;
+    hipStream_t capture[64] = {};
+    uint64_t tick = 0;
+};
+
+GraphCache &graph_cache()
+{
+    static GraphCache c;
+    return c;
+}
+
+constexpr size_t kGraphCacheSize = 8;
+
+void drop_entry(GraphEntry &e)
+{
+    if (e.exec) (void)hipGraphExecDestroy(e.exec);
+    if (e.owned && e.ws) (void)hipFree(e.ws);
+    e.exec = nullptr;
+    e.ws = nullptr;
+}
+
+struct KeyBuilder {
+    std::string k;
+    template <class T> void add(const T &v) { k.append(reinterpret_cast<const char *>(&v), sizeof(T)); }
+    void matrix(const kdcd_matrix *A)
+    {
+        add(A->format); add(A->m); add(A->n); add(A->ld); add(A->nnz);
+        add(A->values); add(A->row_ptr); add(A->col_idx);
+    }
+    void kernel(const kdcd_kernel *k) { add(k->kind); add(k->degree); add(k->sigma); add(k->c); }
+    void options(const kdcd_options &o)
+    {
+        add(o.compute); add(o.loss); add(o.snapshot_every); add(o.snapshots); add(o.trace);
+        add(o.workspace); add(o.workspace_bytes);
+    }
+};
+
+// prepare(base): synchronous set-up before the capture (host-to-device copies
+// of data the graph reads); enqueue(base, stream): the work to capture.
+kdcd_status run_graph(const std::string &key, size_t bytes, const kdcd_options &opt,
+                      hipStream_t st, const std::function<kdcd_status(char *)> &prepare,
+                      const std::function<kdcd_status(char *, hipStream_t)> &enqueue)
+{
+    GraphCache &c = graph_cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return KDCD_ERR_HIP;
+    GraphEntry *e = nullptr;
+    for (auto &x : c.entries)
+        if (x.device == dev && x.key == key) e = &x;
+    if (!e) {
+        if (!c.capture[dev] &&
+            hipStreamCreateWithFlags(&c.capture[dev], hipStreamNonBlocking) != hipSuccess)
+            return KDCD_ERR_HIP;
+        GraphEntry ne;
+        ne.key = key;
+        ne.device = dev;
+        if (opt.workspace) {
+            if (opt.workspace_bytes < bytes) return KDCD_ERR_WORKSPACE;
+            if (reinterpret_cast<uintptr_t>(opt.workspace) & 255) return KDCD_ERR_INVALID_ARG;
+            ne.ws = static_cast<char *>(opt.workspace);
+        } else {
+            void *p = nullptr;
+            if (hipMalloc(&p, bytes) != hipSuccess || !p) return KDCD_ERR_ALLOC;
+            ne.ws = static_cast<char *>(p);
+            ne.owned = true;
+        }
+        kdcd_status rc = prepare ? prepare(ne.ws) : KDCD_OK;
+        hipGraph_t g = nullptr;
+        if (rc == KDCD_OK) {
+            if (hipStreamBeginCapture(c.capture[dev], hipStreamCaptureModeThreadLocal) != hipSuccess) {
+                rc = KDCD_ERR_HIP;
+            } else {
+                rc = enqueue(ne.ws, c.capture[dev]);
+                const hipError_t ce = hipStreamEndCapture(c.capture[dev], &g);
+                if (rc == KDCD_OK && ce != hipSuccess) rc = KDCD_ERR_HIP;
+            }
+        }
+        if (rc == KDCD_OK && hipGraphInstantiate(&ne.exec, g, nullptr, nullptr, 0) != hipSuccess)
+            rc = KDCD_ERR_HIP;
+        if (g) (void)hipGraphDestroy(g);
+        if (rc != KDCD_OK) {
+            drop_entry(ne);
+            return rc;
+        }
+        if (c.entries.size() >= kGraphCacheSize) {   // least recently used goes
+            size_t lru = 0;
+            for (size_t i = 1; i < c.entries.size(); ++i)
+                if (c.entries[i].used < c.entries[lru].used) lru = i;
+            drop_entry(c.entries[lru]);
+            c.entries.erase(c.entries.begin() + (std::ptrdiff_t)lru);
+        }
+        c.entries.push_back(ne);
+        e = &c.entries.back();
+    }
+    e->used = ++c.tick;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (opt.profile) {
+        (void)hipEventCreate(&e0);
+        (void)hipEventCreate(&e1);
+        (void)hipEventRecord(e0, st);
+    }
+    if (hipGraphLaunch(e->exec, st) != hipSuccess) return KDCD_ERR_HIP;
+    if (opt.profile) (void)hipEventRecord(e1, st);
+    const kdcd_status rc = read_status(reinterpret_cast<int32_t *>(e->ws), st);
+    if (opt.profile) {
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        *opt.profile = kdcd_profile{};
+        opt.profile->total_ms = ms;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    }
+    return rc;
+}
+
+kdcd_status run_solve(const SolveArgs &sa)
+{
+    const Layout L = make_layout(sa.problem, sa.A, sa.kernel, sa.b, sa.s, sa.opt.compute);
+    if (sa.opt.flags & KDCD_FLAG_GRAPH) {
+        KeyBuilder kb;
+        kb.add('S');
+        kb.add(sa.problem);
+        kb.matrix(sa.A);
+        kb.add(sa.y);
+        kb.kernel(sa.kernel);
+        kb.add(sa.C); kb.add(sa.lambda); kb.add(sa.b); kb.add(sa.s); kb.add(sa.H);
+        kb.add(sa.idx); kb.add(sa.alpha);
+        kb.options(sa.opt);
+        return run_graph(kb.k, L.total, sa.opt, sa.st, nullptr,
+                         [&](char *base, hipStream_t cs) {
+                             SolveArgs g = sa;
+                             g.st = cs;
+                             StageTimer off;
+                             return enqueue_solve(g, L, base, off);
+                         });
+    }
+    Workspace ws;
+    kdcd_status rc = acquire(ws, L, &sa.opt, sa.st);
+    if (rc != KDCD_OK) return rc;
+    StageTimer timer;
+    timer.on = sa.opt.profile != nullptr;
+    if ((rc = enqueue_solve(sa, L, ws.base, timer)) != KDCD_OK) return rc;
+    rc = read_status(ws.at<int32_t>(L.status), sa.st);
     timer.report(sa.opt.profile);
     return rc;
 }
@@ -375,6 +543,14 @@ kdcd_options defaults(const kdcd_options *opt)
 }  // namespace
 
 extern "C" {
+
+void kdcd_graph_cache_clear(void)
+{
+    GraphCache &c = graph_cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    for (auto &e : c.entries) drop_entry(e);
+    c.entries.clear();
+}
 
 kdcd_status kdcd_ksvm_solve(const kdcd_matrix *A, const double *y, const kdcd_kernel *kernel,
                             double C, int32_t b, int32_t s, int64_t H, const int32_t *idx,
@@ -476,8 +652,14 @@ kdcd_status kdcd_batch_solve(const kdcd_matrix *A, const kdcd_kernel *kernel, in
     const size_t o_W = off; off += align256(sizeof(double) * (size_t)(bd.ngroups * sbmax * sbmax));
     const size_t o_D = off; off += align256(sizeof(double) * (size_t)(krr.size() * sbmax * b + 1));
     L.total = off;
-    Workspace ws;
-    if ((rc = acquire(ws, L, &o, st)) != KDCD_OK) return rc;
+
+    // the work of the call on stream cs in the workspace at wsbase; in graph
+    // mode the descriptor was copied before the capture
+    auto enqueue = [&](char *wsbase, hipStream_t cs, bool graph, StageTimer &timer) -> kdcd_status {
+    const hipStream_t st = cs;
+    Workspace ws;            // a view: not owned
+    ws.base = wsbase;
+    kdcd_status rc = KDCD_OK;
     int32_t *status = ws.at<int32_t>(L.status);
     double *norms = ws.at<double>(L.norms);
     BatchDesc *dbd = ws.at<BatchDesc>(o_bd);
@@ -486,7 +668,7 @@ kdcd_status kdcd_batch_solve(const kdcd_matrix *A, const kdcd_kernel *kernel, in
     double *W = ws.at<double>(o_W);
     double *Dinv = ws.at<double>(o_D);
 
-    KDCD_HIP_TRY(hipMemcpyAsync(dbd, &bd, sizeof(BatchDesc), hipMemcpyHostToDevice, st));
+    if (!graph) KDCD_HIP_TRY(hipMemcpyAsync(dbd, &bd, sizeof(BatchDesc), hipMemcpyHostToDevice, st));
     KDCD_HIP_TRY(launch_fill_i32(status, 0, 1, st));
     KDCD_HIP_TRY(launch_validate(idx, H * b, A->m, nullptr, nullptr, 0, 0, 0.0, status, st));
     for (int p = 0; p < n_problems; ++p) {
@@ -510,8 +692,6 @@ kdcd_status kdcd_batch_solve(const kdcd_matrix *A, const kdcd_kernel *kernel, in
     KBlockArgs kb;
     if ((rc = prepare_lowp(base, L, ws, st, kb)) != KDCD_OK) return rc;
 
-    StageTimer timer;
-    timer.on = o.profile != nullptr;
     const int64_t n_outer = (H + s - 1) / s;
     for (int64_t k = 0; k < n_outer; ++k) {
         const int64_t done = k * s;
@@ -576,7 +756,40 @@ kdcd_status kdcd_batch_solve(const kdcd_matrix *A, const kdcd_kernel *kernel, in
         }
         timer.end(2, st);
     }
-    rc = read_status(status, st);
+    return rc;
+    };
+
+    if (o.flags & KDCD_FLAG_GRAPH) {
+        KeyBuilder key;
+        key.add('B');
+        key.matrix(A);
+        key.kernel(kernel);
+        key.add(b); key.add(s); key.add(H); key.add(idx); key.add(n_problems);
+        for (int p = 0; p < n_problems; ++p) {
+            const kdcd_batch_problem &q = problems[p];
+            key.add(q.problem); key.add(q.loss); key.add(q.param); key.add(q.sigma);
+            key.add(q.y); key.add(q.alpha); key.add(q.trace);
+        }
+        key.options(o);
+        return run_graph(
+            key.k, L.total, o, st,
+            [&](char *wsbase) {
+                return hipMemcpy(wsbase + o_bd, &bd, sizeof(BatchDesc), hipMemcpyHostToDevice) ==
+                               hipSuccess
+                           ? KDCD_OK
+                           : KDCD_ERR_HIP;
+            },
+            [&](char *wsbase, hipStream_t cs) {
+                StageTimer off;
+                return enqueue(wsbase, cs, true, off);
+            });
+    }
+    Workspace ws;
+    if ((rc = acquire(ws, L, &o, st)) != KDCD_OK) return rc;
+    StageTimer timer;
+    timer.on = o.profile != nullptr;
+    if ((rc = enqueue(ws.base, st, false, timer)) != KDCD_OK) return rc;
+    rc = read_status(ws.at<int32_t>(L.status), st);
     timer.report(o.profile);
     return rc;
 }
@@ -605,6 +818,7 @@ kdcd_status kdcd_ksvm_solve_sampled(const kdcd_matrix *A, const double *y,
     if ((rc = check_compute(A, o.compute)) != KDCD_OK) return rc;
     if (A->format != KDCD_DENSE || o.compute != KDCD_F64) return KDCD_ERR_UNSUPPORTED;
     if (s > kMaxSB || A->m >= ((int64_t)1 << 31)) return KDCD_ERR_UNSUPPORTED;
+    if (o.flags & KDCD_FLAG_GRAPH) return KDCD_ERR_UNSUPPORTED;   // host-side decisions inside
     const int64_t m = A->m;
     const int64_t n_outer = (H + s - 1) / s;
     if (n_outer > (int64_t)0xFFFFFFFF) return KDCD_ERR_UNSUPPORTED;

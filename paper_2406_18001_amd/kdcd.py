@@ -133,6 +133,8 @@ _lib.kdcd_sampler_select.argtypes = [_P, ctypes.c_int64, ctypes.c_int32, ctypes.
 _lib.kdcd_ksvm_solve_sampled.restype = ctypes.c_int
 _lib.kdcd_ksvm_solve_sampled.argtypes = [_P, _P, _P, ctypes.c_double, ctypes.c_int32,
                                          ctypes.c_int64, _P, _P, _P, _P]
+_lib.kdcd_graph_cache_clear.restype = None
+_lib.kdcd_graph_cache_clear.argtypes = []
 _lib.kdcd_tune_configs.restype = ctypes.c_int32
 _lib.kdcd_tune_configs.argtypes = [ctypes.c_int32, _P, _P, _P, ctypes.c_int32]
 _lib.kdcd_tune_set.restype = ctypes.c_int
@@ -470,7 +472,7 @@ def kdcd_sampler_select(keys: torch.Tensor, s: int, epsilon: float, seed: int, o
 def kdcd_ksvm_solve_sampled(A, y, kernel, C, s, H, alpha, *, model=None, epsilon=0.0, tau=1.0,
                             seed=0, pool=0, idx_out=None, features_out=None, grad_out=None, loss=1,
                             trace=None, snapshot_every=0, snapshots=None, workspace=None,
-                            profile=False, stream=None):
+                            profile=False, flags=0, stream=None):
     """Algorithm 2 (b = 1) with the coordinates drawn on the device by
     `model` (a Sampler; None draws uniformly).  Returns (idx_out, profile or
     None); alpha is updated in place."""
@@ -492,7 +494,7 @@ def kdcd_ksvm_solve_sampled(A, y, kernel, C, s, H, alpha, *, model=None, epsilon
     if grad_out is not None:
         smp.grad_out = _dev(grad_out, torch.float64, m, "grad_out")
     n_outer = -(-H // max(int(s), 1))
-    opt, prof = _options("f64", loss, snapshot_every, snapshots, trace, workspace, profile, 0,
+    opt, prof = _options("f64", loss, snapshot_every, snapshots, trace, workspace, profile, flags,
                          m, n_outer, H)
     kern = _kernel(kernel)
     st = _lib.kdcd_ksvm_solve_sampled(ctypes.byref(mat), y.data_ptr(), ctypes.byref(kern),
@@ -544,3 +546,11 @@ def kdcd_tune_save(path):
 
 def kdcd_tune_load(path):
     _check(_lib.kdcd_tune_load(str(path).encode()), "kdcd_tune_load")
+
+
+FLAG_GRAPH = 1
+
+
+def kdcd_graph_cache_clear():
+    """Destroy the graphs cached by calls with flags=FLAG_GRAPH."""
+    _lib.kdcd_graph_cache_clear()

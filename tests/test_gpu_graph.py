@@ -1,0 +1,149 @@
+"""KDCD_FLAG_GRAPH: the captured launch sequence, replayed, gives the eager
+result bit for bit.  Every replay is checked, with the program's own eager
+work (resets, in-place changes of the inputs, other solves) and
+synchronisations between the replays, so that a replay reading stale or
+wrongly cleared memory shows up."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2406_18001_amd import inputs
+from tests.helpers import assert_parity, dev, idx_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def K():
+    from paper_2406_18001_amd import kdcd
+    yield kdcd
+    kdcd.kdcd_graph_cache_clear()
+
+
+def test_krr_graph_replays_equal_eager(K):
+    d = inputs.dense_krr_c2(m=3000, n=96, seed=3)
+    A, y = dev(d["A"]), dev(d["y"])
+    idx = idx_dev(inputs.krr_indices(3000, 8, 203, seed=1))
+    kern = (2, 1.0, 0.0, 1)
+    eager = torch.zeros(3000, dtype=torch.float64, device="cuda")
+    K.kdcd_krr_solve(A, y, kern, 1e-3, 8, 16, 203, idx, eager)
+    alpha = torch.zeros(3000, dtype=torch.float64, device="cuda")
+    for rep in range(4):
+        alpha.zero_()
+        K.kdcd_krr_solve(A, y, kern, 1e-3, 8, 16, 203, idx, alpha, flags=K.FLAG_GRAPH)
+        torch.cuda.synchronize()
+        assert torch.equal(alpha, eager), f"replay {rep}"
+        tmp = torch.zeros_like(alpha)                 # unrelated eager work in between
+        K.kdcd_krr_solve(A, y, kern, 1e-2, 8, 4, 40, idx, tmp)
+    # the graph reads the current contents of its inputs
+    y.mul_(2.0)
+    eager2 = torch.zeros_like(alpha)
+    K.kdcd_krr_solve(A, y, kern, 1e-3, 8, 16, 203, idx, eager2)
+    alpha.zero_()
+    K.kdcd_krr_solve(A, y, kern, 1e-3, 8, 16, 203, idx, alpha, flags=K.FLAG_GRAPH)
+    assert torch.equal(alpha, eager2)
+    assert_parity(alpha.cpu().numpy(), 2.0 * eager.cpu().numpy(), 1e-12, "linear in y")
+
+
+def test_ksvm_graph_with_trace_snapshots_and_warm_start(K):
+    d = inputs.dense_ksvm_c1(m=1200, n=32, seed=4)
+    A, y = dev(d["A"]), dev(d["y"])
+    H, s = 300, 32
+    idx = inputs.ksvm_indices(1200, H, seed=2)
+    kern = (2, 1.0 / 32, 0.0, 1)
+    a0 = np.random.default_rng(1).uniform(0, 1.0, 1200)
+    rows = -(-(-(-H // s)) // 3)
+    outs = []
+    for flags in (0, K.FLAG_GRAPH, K.FLAG_GRAPH, K.FLAG_GRAPH):
+        a = dev(a0)
+        tr = torch.zeros(H, dtype=torch.float64, device="cuda")
+        sn = torch.zeros(rows * 1200, dtype=torch.float64, device="cuda")
+        K.kdcd_ksvm_solve(A, y, kern, 1.0, 1, s, H, idx_dev(idx), a, loss=2, trace=tr,
+                          snapshot_every=3, snapshots=sn, flags=flags)
+        outs.append((a.cpu(), tr.cpu(), sn.cpu()))
+    for o in outs[1:]:
+        for x, ref in zip(o, outs[0]):
+            assert torch.equal(x, ref)
+    a_ref, _ = O.dcd_ksvm(d["A"], d["y"], O.Kernel(O.RBF, sigma=1 / 32), 1.0, H, idx,
+                          alpha0=a0, loss=2, s=s)
+    assert_parity(outs[1][0].numpy(), a_ref, 1e-9, "alpha")
+
+
+@pytest.mark.parametrize("compute", ["f64", "bf16x3"])
+def test_batch_graph_replays_equal_eager(K, compute):
+    d = inputs.dense_c4(m=2000, n=64, n_classes=3, seed=5)
+    A, y = dev(d["A"]), dev(d["y"])
+    Y = [dev(d["Y_ovr"][c]) for c in range(3)]
+    b, s, H = 4, 8, 50
+    idx = idx_dev(inputs.krr_indices(2000, b, H, seed=0))
+
+    def run(flags):
+        probs = [K.BatchProblem("krr", 1e-3, sg, y, torch.zeros(2000, dtype=torch.float64, device="cuda"))
+                 for sg in (0.5, 1.0)]
+        probs += [K.BatchProblem("ksvm", 1.0, 1.0, yc, torch.zeros(2000, dtype=torch.float64, device="cuda"),
+                                 trace=torch.zeros(H * b, dtype=torch.float64, device="cuda"))
+                  for yc in Y]
+        return probs
+
+    eager = run(0)
+    K.kdcd_batch_solve(A, (2, 1.0, 0.0, 1), b, s, H, idx, eager, compute=compute)
+    g = run(K.FLAG_GRAPH)
+    for rep in range(3):
+        for p in g:
+            p.alpha.zero_()
+            if p.trace is not None:
+                p.trace.fill_(7.0)
+        K.kdcd_batch_solve(A, (2, 1.0, 0.0, 1), b, s, H, idx, g, compute=compute,
+                           flags=K.FLAG_GRAPH)
+        torch.cuda.synchronize()
+        for pe, pg in zip(eager, g):
+            assert torch.equal(pe.alpha, pg.alpha), f"replay {rep}"
+            if pe.trace is not None:
+                assert torch.equal(pe.trace, pg.trace)
+
+
+def test_graph_reports_device_errors_on_every_replay(K):
+    d = inputs.dense_krr_c2(m=500, n=16, seed=1)
+    A, y = dev(d["A"]), dev(d["y"])
+    idx = idx_dev(inputs.krr_indices(500, 4, 20, seed=0))
+    a = torch.zeros(500, dtype=torch.float64, device="cuda")
+    K.kdcd_krr_solve(A, y, (2, 1.0, 0.0, 1), 1e-3, 4, 5, 20, idx, a, flags=K.FLAG_GRAPH)
+    idx[7] = 500                                     # out of range, read at replay time
+    for _ in range(2):
+        with pytest.raises(K.KdcdError) as e:
+            K.kdcd_krr_solve(A, y, (2, 1.0, 0.0, 1), 1e-3, 4, 5, 20, idx, a, flags=K.FLAG_GRAPH)
+        assert e.value.status == -3
+    idx[7] = idx[6]                                  # a duplicate inside one block
+    a.zero_()
+    with pytest.raises(K.KdcdError) as e:
+        K.kdcd_krr_solve(A, y, (2, 1.0, 0.0, 1), 1e-3, 4, 5, 20, idx, a, flags=K.FLAG_GRAPH)
+    assert e.value.status == -4
+
+
+def test_graph_cache_eviction_keeps_results(K):
+    d = inputs.dense_krr_c2(m=800, n=16, seed=2)
+    A, y = dev(d["A"]), dev(d["y"])
+    idx = idx_dev(inputs.krr_indices(800, 2, 60, seed=0))
+    for lam in [10.0 ** (-k) for k in range(1, 12)]:      # 11 keys > 8 cache entries
+        a = torch.zeros(800, dtype=torch.float64, device="cuda")
+        e = torch.zeros(800, dtype=torch.float64, device="cuda")
+        K.kdcd_krr_solve(A, y, (2, 1.0, 0.0, 1), lam, 2, 6, 60, idx, a, flags=K.FLAG_GRAPH)
+        K.kdcd_krr_solve(A, y, (2, 1.0, 0.0, 1), lam, 2, 6, 60, idx, e)
+        assert torch.equal(a, e)
+    K.kdcd_graph_cache_clear()
+    a = torch.zeros(800, dtype=torch.float64, device="cuda")
+    K.kdcd_krr_solve(A, y, (2, 1.0, 0.0, 1), 1e-3, 2, 6, 60, idx, a, flags=K.FLAG_GRAPH)
+    e = torch.zeros(800, dtype=torch.float64, device="cuda")
+    K.kdcd_krr_solve(A, y, (2, 1.0, 0.0, 1), 1e-3, 2, 6, 60, idx, e)
+    assert torch.equal(a, e)
+
+
+def test_sampled_solve_refuses_graph(K):
+    m = 200
+    A = torch.randn(m, 8, dtype=torch.float64, device="cuda")
+    y = torch.ones(m, dtype=torch.float64, device="cuda")
+    a = torch.zeros(m, dtype=torch.float64, device="cuda")
+    with pytest.raises(K.KdcdError) as e:
+        K.kdcd_ksvm_solve_sampled(A, y, (2, 1.0, 0.0, 1), 1.0, 8, 16, a, flags=K.FLAG_GRAPH)
+    assert e.value.status == -2
