@@ -127,7 +127,31 @@ typedef struct {
     void *workspace;         /* device; NULL = allocated on `stream` and freed before return  */
     size_t workspace_bytes;
     kdcd_profile *profile;   /* host; NULL = no timing                                      */
+    int32_t monitor_every;   /* > 0: convergence monitor every this many outer iterations   */
+    int32_t reserved;
+    double tol;              /* monitor: stop once the certified relative error <= tol      */
+    int64_t *outer_done;     /* host or NULL: outer iterations performed                    */
+    double *rel_err;         /* host or NULL: last certified relative objective error       */
 } kdcd_options;
+
+/*
+ * Convergence monitor (monitor_every > 0; kdcd_ksvm_solve / kdcd_krr_solve on
+ * dense A in FP64, and kdcd_ksvm_solve_sampled; not with KDCD_FLAG_GRAPH).
+ * The solve keeps the full dual gradient current on the device (K-SVM:
+ * g = Q alpha - 1 + omega alpha; K-RR: the residual y - M alpha, M =
+ * K/lambda + m I) from the kernel block it already computes, and every
+ * monitor_every outer iterations (and after the last) evaluates in O(m) a
+ * certified bound on the relative objective error (f - f*) / |f*|:
+ *   K-RR: ||y - M alpha||^2 / (2m) / (|f| - that), since lambda_min(M) >= m;
+ *   K-SVM: the duality gap P(alpha) + f(alpha), divided by |f|.
+ * Once the bound is <= tol every later launch of the solve returns at once
+ * (no host round trip); alpha and the snapshots stop changing, trace entries
+ * past that point are unspecified.  The monitor adds about
+ * 8 (m (s b + 2) + s b) bytes + 8 KiB to the workspace (not counted by
+ * kdcd_workspace_bytes).
+ * Costs per outer iteration: m*s*b*8 bytes written and read (the stored
+ * kernel block) plus the O(m) evaluation.
+ */
 
 /*
  * kdcd_ksvm_solve -- s-step DCD for K-SVM-L1/L2 (Algorithm 2; s = 1 is

@@ -133,6 +133,7 @@ struct KBlockArgs {
     int32_t w_only;          // FP64 kernel: compute the Gram tiles only (no U-part)
     const BatchDesc *batch;  // non-null: batched epilogue (dense F64 and mixed kernels)
     double *U;               // dense F64 only: non-null stores K(a_p, a_{S_j}) at U[j*m + p]
+    const int32_t *stop;     // dense F64 only: non-null and set -> the launch does nothing
 };
 
 // Launchers (return hipError_t of the launch).
@@ -157,6 +158,7 @@ struct FinishDesc {
     const double *W[kMaxProblems];         // Gram of K-RR problem k, [sb][sb]
     double *Dinv[kMaxProblems];            // inverses of K-RR problem k, [sk][b][b]
     double inv_lambda[kMaxProblems];
+    const int32_t *stop;    // non-null and set: the solve has converged, do nothing
 };
 
 struct KsvmRecurDesc {
@@ -167,6 +169,7 @@ struct KsvmRecurDesc {
     double *trace[kMaxProblems];
     double nu[kMaxProblems];
     double omega[kMaxProblems];
+    const int32_t *stop;
 };
 
 struct KrrRecurDesc {
@@ -177,7 +180,29 @@ struct KrrRecurDesc {
     double *alpha[kMaxProblems];
     double *trace[kMaxProblems];
     double lambda[kMaxProblems];
+    const int32_t *stop;
 };
+
+// Convergence monitor state (device): stop word first, so that &stop can be
+// handed to kernels as a plain int32 pointer.
+struct MonitorState {
+    int32_t stop;
+    int32_t pad;
+    int64_t outer_done;   // outer iterations done at the last evaluation
+    double rel;           // last certified relative objective error
+    double f;             // last objective value
+};
+
+hipError_t launch_dual_update(const double *U, int64_t m, int32_t sb, const int32_t *S,
+                              const double *theta, const double *vscale, double uscale,
+                              const double *wscale, double diag, double *v, const int32_t *stop,
+                              hipStream_t st);
+size_t monitor_partial_bytes();
+hipError_t launch_monitor(int32_t problem, int64_t m, const double *alpha, const double *y,
+                          const double *v, double omega, int32_t loss, double C, double tol,
+                          int64_t outer, double *part, MonitorState *mon, hipStream_t st);
+hipError_t launch_rho_init(const double *Ka, const double *y, const double *alpha,
+                           double inv_lambda, double mdbl, int64_t m, double *rho, hipStream_t st);
 
 hipError_t launch_finish(const FinishDesc &d, int32_t sb, int32_t b, int32_t sk, double mdbl,
                          int32_t *status, hipStream_t st);

@@ -92,6 +92,7 @@ __global__ __launch_bounds__(256) void finish_kernel(const FinishDesc d, int32_t
                                                      int32_t sk, double mdbl, int32_t *status)
 {
     __shared__ double sh[kMaxB * kMaxB];
+    if (d.stop && *d.stop) return;
     const int tid = threadIdx.x;
     const int per = (sb + FIN_COLS - 1) / FIN_COLS;
     const int n_red = per * d.nprob;

@@ -48,8 +48,9 @@ __global__ __launch_bounds__(64 * WM * WN) void kblock_f64_kernel(
     const double *__restrict__ beta, const double *__restrict__ bscale,
     double *__restrict__ partial, double *__restrict__ W, int32_t n_u_tiles,
     int32_t n_row_groups, int32_t n_w_tiles, int32_t n_tiles_n, int32_t aligned,
-    const BatchDesc *__restrict__ bd, double *__restrict__ U)
+    const BatchDesc *__restrict__ bd, double *__restrict__ U, const int32_t *__restrict__ stop)
 {
+    if (stop && *stop) return;   // the solve has converged
     constexpr int NT = 64 * WM * WN;
     constexpr int BM = 16 * TM * WM;
     constexpr int BN = 16 * TN * WN;
@@ -380,7 +381,8 @@ hipError_t launch_cfg(const KBlockArgs &a, hipStream_t st)
     hipLaunchKernelGGL((kblock_f64_kernel<WM, WN, TM, TN, KIND, BATCH>), grid, block, 0, st,   \
                        A->values, A->ld, A->m, A->n, a.S, a.sb, a.norms, a.kp, a.beta,          \
                        a.beta_scale, a.partial, a.W, (int32_t)n_u, (int32_t)groups,            \
-                       (int32_t)n_w, (int32_t)n_n, aligned, a.batch, BATCH ? nullptr : a.U)
+                       (int32_t)n_w, (int32_t)n_n, aligned, a.batch, BATCH ? nullptr : a.U,   \
+                       a.stop)
     switch (a.kp.kind) {
     case KDCD_KERNEL_LINEAR: KDCD_LAUNCH(KDCD_KERNEL_LINEAR); break;
     case KDCD_KERNEL_POLY: KDCD_LAUNCH(KDCD_KERNEL_POLY); break;

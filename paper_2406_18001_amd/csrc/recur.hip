@@ -107,6 +107,7 @@ __global__ __launch_bounds__(NT) void ksvm_recur_kernel(const KsvmRecurDesc D,
                                                         const int32_t *__restrict__ S, int32_t sb,
                                                         int64_t m, int32_t *status)
 {
+    if (D.stop && *D.stop) return;             // converged: nothing more to do
     // problem of this workgroup (one workgroup per problem of a batch)
     const int pb = blockIdx.x;
     const double *__restrict__ r = D.r[pb];
@@ -208,6 +209,7 @@ __global__ __launch_bounds__(NT) void krr_recur_kernel(const KrrRecurDesc D,
                                                        int32_t sk, int64_t m, double mdbl,
                                                        int32_t *status)
 {
+    if (D.stop && *D.stop) return;             // converged: nothing more to do
     // problem of this workgroup (one workgroup per problem of a batch)
     const int pb = blockIdx.x;
     const double *__restrict__ r = D.r[pb];

@@ -508,33 +508,6 @@ __global__ __launch_bounds__(1024) void slots_kernel(const uint32_t *__restrict_
 
 // ------------------------------------------------------ gradient upkeep
 
-// g_i += y_i * sum_t U[t][i] * y_{S_t} theta_t + omega * sum_{t: S_t = i} theta_t
-__global__ __launch_bounds__(256) void grad_update_kernel(const double *__restrict__ U, int64_t m,
-                                                          int32_t sb, const int32_t *__restrict__ S,
-                                                          const double *__restrict__ theta,
-                                                          const double *__restrict__ y,
-                                                          double omega, double *__restrict__ g)
-{
-    __shared__ double w[kMaxSB], th[kMaxSB];
-    __shared__ int32_t Sl[kMaxSB];
-    for (int t = threadIdx.x; t < sb; t += blockDim.x) {
-        const int32_t j = S[t];
-        Sl[t] = j;
-        th[t] = theta[t];
-        w[t] = y[j] * theta[t];
-    }
-    __syncthreads();
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        double acc = 0.0, da = 0.0;
-        for (int t = 0; t < sb; ++t) {
-            acc = fma(U[(int64_t)t * m + i], w[t], acc);
-            if (Sl[t] == (int32_t)i) da += th[t];
-        }
-        g[i] += y[i] * acc + omega * da;
-    }
-}
-
 // g = y o (K (y o alpha)) - 1 + omega alpha from Kb = K (y o alpha).
 __global__ __launch_bounds__(256) void grad_init_kernel(const double *__restrict__ Kb,
                                                         const double *__restrict__ y,
@@ -842,9 +815,7 @@ hipError_t launch_grad_update(const double *U, int64_t m, int32_t sb, const int3
                               const double *theta, const double *y, double omega, double *g,
                               hipStream_t st)
 {
-    hipLaunchKernelGGL(grad_update_kernel, dim3(grid_for(m, 4096)), dim3(256), 0, st, U, m, sb, S,
-                       theta, y, omega, g);
-    return hipGetLastError();
+    return launch_dual_update(U, m, sb, S, theta, y, 1.0, y, omega, g, nullptr, st);
 }
 
 hipError_t launch_grad_init(const double *Kb, const double *y, const double *alpha, double omega,

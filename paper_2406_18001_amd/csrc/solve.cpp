@@ -94,7 +94,23 @@ size_t lowp_elem_bytes(int32_t compute) { return compute == KDCD_F32 ? 4 : 2; }
 struct Layout {
     size_t status, norms, partial, r, W, Dinv, iota, hi, lo, normlow, total;
     int64_t ldlow;
+    // convergence monitor (0 when off): state, partial sums, maintained
+    // gradient / residual (m), stored kernel block (s*b x m), updates (s*b),
+    // scratch m-vector
+    size_t mon, mon_part, mon_v, mon_U, mon_th, mon_tmp;
 };
+
+void add_monitor(Layout &L, int64_t m, int64_t sbmax)
+{
+    size_t off = L.total;
+    L.mon = off; off += 256;
+    L.mon_part = off; off += align256(monitor_partial_bytes());
+    L.mon_v = off; off += align256(sizeof(double) * (size_t)m);
+    L.mon_U = off; off += align256(sizeof(double) * (size_t)(sbmax * m));
+    L.mon_th = off; off += align256(sizeof(double) * (size_t)sbmax);
+    L.mon_tmp = off; off += align256(sizeof(double) * (size_t)m);
+    L.total = off;
+}
 
 Layout make_layout(int32_t problem, const kdcd_matrix *A, const kdcd_kernel *kernel, int32_t b,
                    int32_t s, int32_t compute)
@@ -246,6 +262,36 @@ kdcd_status prepare_lowp(const KBlockArgs &base, const Layout &L, Workspace &ws,
     return KDCD_OK;
 }
 
+}  // namespace
+
+static kdcd_status kernel_matvec(const kdcd_matrix *A, const kdcd_kernel *kernel,
+                                 const double *beta, std::vector<double> *host, double *dev,
+                                 hipStream_t st);
+
+namespace {
+
+// The maintained dual vector at the start: K-SVM g = Q a0 - 1 + omega a0,
+// K-RR rho = y - M a0; the kernel product only runs for a nonzero a0 (one
+// host round trip to find out).
+kdcd_status init_dual_vector(int32_t problem, const kdcd_matrix *A, const kdcd_kernel *kernel,
+                             const double *y, const double *alpha, double omega, double lambda,
+                             double *v, double *tmp, int32_t *flag, hipStream_t st)
+{
+    const int64_t m = A->m;
+    KDCD_HIP_TRY(launch_fill_i32(flag, 0, 1, st));
+    if (problem == 0) KDCD_HIP_TRY(launch_product(y, alpha, m, tmp, flag, st));
+    else KDCD_HIP_TRY(launch_product(alpha, alpha, m, tmp, flag, st));
+    int32_t nonzero = 0;
+    KDCD_HIP_TRY(hipMemcpyAsync(&nonzero, flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    KDCD_HIP_TRY(hipStreamSynchronize(st));
+    kdcd_status rc = KDCD_OK;
+    if (nonzero && (rc = kernel_matvec(A, kernel, problem == 0 ? tmp : alpha, nullptr, v, st)) != KDCD_OK)
+        return rc;
+    if (problem == 0) KDCD_HIP_TRY(launch_grad_init(nonzero ? v : nullptr, y, alpha, omega, m, v, st));
+    else KDCD_HIP_TRY(launch_rho_init(nonzero ? v : nullptr, y, alpha, 1.0 / lambda, (double)m, m, v, st));
+    return KDCD_OK;
+}
+
 // Everything a solve puts on its stream, in the workspace at `base`, without
 // the final status read (the status word is at offset L.status).
 kdcd_status enqueue_solve(const SolveArgs &sa, const Layout &L, char *wsbase, StageTimer &timer)
@@ -286,6 +332,20 @@ kdcd_status enqueue_solve(const SolveArgs &sa, const Layout &L, char *wsbase, St
     rc = prepare_lowp(base, L, ws, st, kb);
     if (rc != KDCD_OK) return rc;
 
+    const bool monitor = sa.opt.monitor_every > 0;
+    MonitorState *mon = monitor ? ws.at<MonitorState>(L.mon) : nullptr;
+    const int32_t *stop = monitor ? &mon->stop : nullptr;
+    double *dual = monitor ? ws.at<double>(L.mon_v) : nullptr;
+    if (monitor) {
+        KDCD_HIP_TRY(launch_fill_i32(reinterpret_cast<int32_t *>(mon),
+                                     0, (int64_t)(sizeof(MonitorState) / 4), st));
+        rc = init_dual_vector(sa.problem, A, sa.kernel, sa.y, sa.alpha, omega, sa.lambda, dual,
+                              ws.at<double>(L.mon_tmp), &mon->pad, st);
+        if (rc != KDCD_OK) return rc;
+        kb.U = ws.at<double>(L.mon_U);
+        kb.stop = stop;
+    }
+
     const int64_t n_outer = (sa.H + sa.s - 1) / sa.s;
     int64_t snap = 0;
     for (int64_t k = 0; k < n_outer; ++k) {
@@ -308,10 +368,12 @@ kdcd_status enqueue_solve(const SolveArgs &sa, const Layout &L, char *wsbase, St
         fd.W[0] = W;
         fd.Dinv[0] = Dinv;
         fd.inv_lambda[0] = svm ? 0.0 : 1.0 / sa.lambda;
+        fd.stop = stop;
         KDCD_HIP_TRY(launch_finish(fd, sb, sa.b, sk, (double)A->m, status, st));
         timer.end(1, st);
         timer.begin(2, st);
-        double *tr = sa.opt.trace ? sa.opt.trace + done * sa.b : nullptr;
+        double *tr = sa.opt.trace ? sa.opt.trace + done * sa.b
+                                  : (monitor ? ws.at<double>(L.mon_th) : nullptr);
         if (svm) {
             KsvmRecurDesc kd{};
             kd.r[0] = r;
@@ -321,6 +383,7 @@ kdcd_status enqueue_solve(const SolveArgs &sa, const Layout &L, char *wsbase, St
             kd.trace[0] = tr;
             kd.nu[0] = nu;
             kd.omega[0] = omega;
+            kd.stop = stop;
             KDCD_HIP_TRY(launch_ksvm_recur(kd, 1, S, sb, A->m, status, st));
         } else {
             KrrRecurDesc rd{};
@@ -331,7 +394,20 @@ kdcd_status enqueue_solve(const SolveArgs &sa, const Layout &L, char *wsbase, St
             rd.alpha[0] = sa.alpha;
             rd.trace[0] = tr;
             rd.lambda[0] = sa.lambda;
+            rd.stop = stop;
             KDCD_HIP_TRY(launch_krr_recur(rd, 1, S, sa.b, sk, A->m, (double)A->m, status, st));
+        }
+        if (monitor) {
+            if (svm)
+                KDCD_HIP_TRY(launch_dual_update(kb.U, A->m, sb, S, tr, sa.y, 1.0, sa.y, omega,
+                                                dual, stop, st));
+            else
+                KDCD_HIP_TRY(launch_dual_update(kb.U, A->m, sb, S, tr, nullptr, -1.0 / sa.lambda,
+                                                nullptr, -(double)A->m, dual, stop, st));
+            if ((k + 1) % sa.opt.monitor_every == 0 || k + 1 == n_outer)
+                KDCD_HIP_TRY(launch_monitor(sa.problem, A->m, sa.alpha, sa.y, dual, omega,
+                                            sa.opt.loss, sa.C, sa.opt.tol, k + 1,
+                                            ws.at<double>(L.mon_part), mon, st));
         }
         timer.end(2, st);
         if (sa.opt.snapshot_every > 0 && sa.opt.snapshots &&
@@ -481,9 +557,34 @@ kdcd_status run_graph(const std::string &key, size_t bytes, const kdcd_options &
     return rc;
 }
 
+// Host copy of the monitor's outcome into the caller's outputs.
+kdcd_status report_monitor(const kdcd_options &o, const MonitorState *dmon, int64_t n_outer,
+                           hipStream_t st)
+{
+    MonitorState h{};
+    KDCD_HIP_TRY(hipMemcpyAsync(&h, dmon, sizeof(MonitorState), hipMemcpyDeviceToHost, st));
+    KDCD_HIP_TRY(hipStreamSynchronize(st));
+    if (o.outer_done) *o.outer_done = h.stop ? h.outer_done : n_outer;
+    if (o.rel_err) *o.rel_err = h.rel;
+    return KDCD_OK;
+}
+
+kdcd_status check_monitor(const kdcd_matrix *A, const kdcd_options &o)
+{
+    if (o.monitor_every < 0) return KDCD_ERR_INVALID_ARG;
+    if (o.monitor_every == 0) return KDCD_OK;
+    if (!(o.tol >= 0.0) || !std::isfinite(o.tol)) return KDCD_ERR_INVALID_ARG;
+    if (A->format != KDCD_DENSE || o.compute != KDCD_F64 || (o.flags & KDCD_FLAG_GRAPH))
+        return KDCD_ERR_UNSUPPORTED;
+    return KDCD_OK;
+}
+
 kdcd_status run_solve(const SolveArgs &sa)
 {
-    const Layout L = make_layout(sa.problem, sa.A, sa.kernel, sa.b, sa.s, sa.opt.compute);
+    kdcd_status rc = check_monitor(sa.A, sa.opt);
+    if (rc != KDCD_OK) return rc;
+    Layout L = make_layout(sa.problem, sa.A, sa.kernel, sa.b, sa.s, sa.opt.compute);
+    if (sa.opt.monitor_every > 0) add_monitor(L, sa.A->m, (int64_t)sa.s * sa.b);
     if (sa.opt.flags & KDCD_FLAG_GRAPH) {
         KeyBuilder kb;
         kb.add('S');
@@ -503,13 +604,14 @@ kdcd_status run_solve(const SolveArgs &sa)
                          });
     }
     Workspace ws;
-    kdcd_status rc = acquire(ws, L, &sa.opt, sa.st);
-    if (rc != KDCD_OK) return rc;
+    if ((rc = acquire(ws, L, &sa.opt, sa.st)) != KDCD_OK) return rc;
     StageTimer timer;
     timer.on = sa.opt.profile != nullptr;
     if ((rc = enqueue_solve(sa, L, ws.base, timer)) != KDCD_OK) return rc;
     rc = read_status(ws.at<int32_t>(L.status), sa.st);
     timer.report(sa.opt.profile);
+    if (rc == KDCD_OK && sa.opt.monitor_every > 0)
+        rc = report_monitor(sa.opt, ws.at<MonitorState>(L.mon), (sa.H + sa.s - 1) / sa.s, sa.st);
     return rc;
 }
 
@@ -819,6 +921,8 @@ kdcd_status kdcd_ksvm_solve_sampled(const kdcd_matrix *A, const double *y,
     if (A->format != KDCD_DENSE || o.compute != KDCD_F64) return KDCD_ERR_UNSUPPORTED;
     if (s > kMaxSB || A->m >= ((int64_t)1 << 31)) return KDCD_ERR_UNSUPPORTED;
     if (o.flags & KDCD_FLAG_GRAPH) return KDCD_ERR_UNSUPPORTED;   // host-side decisions inside
+    if ((rc = check_monitor(A, o)) != KDCD_OK) return rc;
+    const bool monitor = o.monitor_every > 0;
     const int64_t m = A->m;
     const int64_t n_outer = (H + s - 1) / s;
     if (n_outer > (int64_t)0xFFFFFFFF) return KDCD_ERR_UNSUPPORTED;
@@ -845,6 +949,8 @@ kdcd_status kdcd_ksvm_solve_sampled(const kdcd_matrix *A, const double *y,
     const size_t o_tmp = off; off += align256(sizeof(double) * (size_t)m);
     const size_t o_flag = off; off += 256;
     const size_t o_sel = off; off += align256(select_workspace_bytes(m));
+    const size_t o_mon = off; off += 256;
+    const size_t o_monp = off; off += align256(monitor_partial_bytes());
     L.total = off;
     Workspace ws;
     if ((rc = acquire(ws, L, &o, st)) != KDCD_OK) return rc;
@@ -860,6 +966,10 @@ kdcd_status kdcd_ksvm_solve_sampled(const kdcd_matrix *A, const double *y,
     int32_t *flag = ws.at<int32_t>(o_flag);
     const SelectWs sel = select_workspace(ws.at<char>(o_sel), m);
     const KParams kp = to_params(kernel);
+    MonitorState *mon = ws.at<MonitorState>(o_mon);
+    const int32_t *stop = monitor ? &mon->stop : nullptr;
+    KDCD_HIP_TRY(launch_fill_i32(reinterpret_cast<int32_t *>(mon), 0,
+                                 (int64_t)(sizeof(MonitorState) / 4), st));
 
     KDCD_HIP_TRY(launch_fill_i32(status, 0, 1, st));
     KDCD_HIP_TRY(launch_fill_i32(flag, 0, 1, st));
@@ -889,6 +999,7 @@ kdcd_status kdcd_ksvm_solve_sampled(const kdcd_matrix *A, const double *y,
     kb.status = status;
     kb.compute = KDCD_F64;
     kb.U = U;
+    kb.stop = stop;
 
     StageTimer timer;
     timer.on = o.profile != nullptr;
@@ -933,6 +1044,7 @@ kdcd_status kdcd_ksvm_solve_sampled(const kdcd_matrix *A, const double *y,
         fd.groups = (int32_t)row_groups(A, sk, KDCD_F64);
         fd.partial[0] = partial;
         fd.r[0] = r;
+        fd.stop = stop;
         KDCD_HIP_TRY(launch_finish(fd, sk, 1, sk, (double)m, status, st));
         timer.end(1, st);
         timer.begin(2, st);
@@ -944,8 +1056,12 @@ kdcd_status kdcd_ksvm_solve_sampled(const kdcd_matrix *A, const double *y,
         kd.trace[0] = theta;
         kd.nu[0] = nu;
         kd.omega[0] = omega;
+        kd.stop = stop;
         KDCD_HIP_TRY(launch_ksvm_recur(kd, 1, S, sk, m, status, st));
-        KDCD_HIP_TRY(launch_grad_update(U, m, sk, S, theta, y, omega, g, st));
+        KDCD_HIP_TRY(launch_dual_update(U, m, sk, S, theta, y, 1.0, y, omega, g, stop, st));
+        if (monitor && ((k + 1) % o.monitor_every == 0 || k + 1 == n_outer))
+            KDCD_HIP_TRY(launch_monitor(0, m, alpha, y, g, omega, o.loss, C, o.tol, k + 1,
+                                        ws.at<double>(o_monp), mon, st));
         timer.end(2, st);
         if (o.trace)
             KDCD_HIP_TRY(hipMemcpyAsync(o.trace + done, theta, sizeof(double) * (size_t)sk,
@@ -958,6 +1074,7 @@ kdcd_status kdcd_ksvm_solve_sampled(const kdcd_matrix *A, const double *y,
     }
     rc = read_status(status, st);
     timer.report(o.profile);
+    if (rc == KDCD_OK && monitor) rc = report_monitor(o, mon, n_outer, st);
     return rc;
 }
 

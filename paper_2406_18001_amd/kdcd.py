@@ -97,7 +97,9 @@ class _Options(ctypes.Structure):
                 ("snapshot_every", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("snapshots", ctypes.c_void_p), ("trace", ctypes.c_void_p),
                 ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
-                ("profile", ctypes.c_void_p)]
+                ("profile", ctypes.c_void_p), ("monitor_every", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("outer_done", ctypes.c_void_p), ("rel_err", ctypes.c_void_p)]
 
 
 _P = ctypes.c_void_p
@@ -221,9 +223,20 @@ def _stream(stream) -> int:
     return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
 
 
+class _MonitorOut:
+    def __init__(self):
+        self.outer = ctypes.c_int64(-1)
+        self.rel = ctypes.c_double(float("nan"))
+
+
 def _options(compute, loss, snapshot_every, snapshots, trace, workspace, profile, flags,
-             m, n_outer, n_updates):
+             m, n_outer, n_updates, monitor_every=0, tol=0.0, mon=None):
     o = _Options()
+    o.monitor_every = int(monitor_every)
+    o.tol = float(tol)
+    if mon is not None:
+        o.outer_done = ctypes.cast(ctypes.pointer(mon.outer), ctypes.c_void_p)
+        o.rel_err = ctypes.cast(ctypes.pointer(mon.rel), ctypes.c_void_p)
     o.compute = COMPUTE[compute] if isinstance(compute, str) else int(compute)
     o.loss = int(loss)
     o.snapshot_every = int(snapshot_every)
@@ -243,41 +256,53 @@ def _options(compute, loss, snapshot_every, snapshots, trace, workspace, profile
     return o, prof
 
 
+def _result(prof, mon):
+    """Profile fields and / or the monitor's outcome as one dict, or None."""
+    if prof is None and mon is None:
+        return None
+    out = {f: getattr(prof, f) for f, _ in _Profile._fields_} if prof is not None else {}
+    if mon is not None:
+        out["outer_done"] = mon.outer.value
+        out["rel_err"] = mon.rel.value
+    return out
+
+
 def _solve(fn, name, A, y, kernel, param, b, s, H, idx, alpha, compute, loss, snapshot_every,
-           snapshots, trace, workspace, profile, flags, stream):
+           snapshots, trace, workspace, profile, flags, stream, monitor_every=0, tol=0.0):
     mat, m, _ = _matrix(A)
     _dev(y, torch.float64, m, "y")
     _dev(alpha, torch.float64, m, "alpha")
     _dev(idx, torch.int32, int(H) * int(b), "idx")
     n_outer = -(-int(H) // max(int(s), 1))
+    mon = _MonitorOut() if monitor_every else None
     opt, prof = _options(compute, loss, snapshot_every, snapshots, trace, workspace, profile,
-                         flags, m, n_outer, int(H) * int(b))
+                         flags, m, n_outer, int(H) * int(b), monitor_every, tol, mon)
     kern = _kernel(kernel)
     st = fn(ctypes.byref(mat), y.data_ptr(), ctypes.byref(kern), float(param), int(b), int(s),
             int(H), idx.data_ptr(), alpha.data_ptr(), ctypes.byref(opt), _stream(stream))
     if st != 0:
         raise KdcdError(st, name)
-    if prof is not None:
-        return {f: getattr(prof, f) for f, _ in _Profile._fields_}
-    return None
+    return _result(prof, mon)
 
 
 def kdcd_ksvm_solve(A, y, kernel, C, b, s, H, idx, alpha, *, compute="f64", loss=1,
                     snapshot_every=0, snapshots=None, trace=None, workspace=None, profile=False,
-                    flags=0, stream=None):
+                    flags=0, stream=None, monitor_every=0, tol=0.0):
     """s-step DCD for K-SVM (Algorithm 2); alpha is updated in place.
-    Returns the stage timings (dict) when profile=True, else None."""
+    Returns a dict with the stage timings (profile=True) and the monitor's
+    outer_done / rel_err (monitor_every > 0), else None."""
     return _solve(_lib.kdcd_ksvm_solve, "kdcd_ksvm_solve", A, y, kernel, C, b, s, H, idx, alpha,
                   compute, loss, snapshot_every, snapshots, trace, workspace, profile, flags,
-                  stream)
+                  stream, monitor_every, tol)
 
 
 def kdcd_krr_solve(A, y, kernel, lam, b, s, H, idx, alpha, *, compute="f64", snapshot_every=0,
                    snapshots=None, trace=None, workspace=None, profile=False, flags=0,
-                   stream=None):
+                   stream=None, monitor_every=0, tol=0.0):
     """s-step BDCD for K-RR (Algorithm 4); alpha is updated in place."""
     return _solve(_lib.kdcd_krr_solve, "kdcd_krr_solve", A, y, kernel, lam, b, s, H, idx, alpha,
-                  compute, 1, snapshot_every, snapshots, trace, workspace, profile, flags, stream)
+                  compute, 1, snapshot_every, snapshots, trace, workspace, profile, flags, stream,
+                  monitor_every, tol)
 
 
 class BatchProblem(NamedTuple):
@@ -472,7 +497,7 @@ def kdcd_sampler_select(keys: torch.Tensor, s: int, epsilon: float, seed: int, o
 def kdcd_ksvm_solve_sampled(A, y, kernel, C, s, H, alpha, *, model=None, epsilon=0.0, tau=1.0,
                             seed=0, pool=0, idx_out=None, features_out=None, grad_out=None, loss=1,
                             trace=None, snapshot_every=0, snapshots=None, workspace=None,
-                            profile=False, flags=0, stream=None):
+                            profile=False, flags=0, stream=None, monitor_every=0, tol=0.0):
     """Algorithm 2 (b = 1) with the coordinates drawn on the device by
     `model` (a Sampler; None draws uniformly).  Returns (idx_out, profile or
     None); alpha is updated in place."""
@@ -494,15 +519,15 @@ def kdcd_ksvm_solve_sampled(A, y, kernel, C, s, H, alpha, *, model=None, epsilon
     if grad_out is not None:
         smp.grad_out = _dev(grad_out, torch.float64, m, "grad_out")
     n_outer = -(-H // max(int(s), 1))
+    mon = _MonitorOut() if monitor_every else None
     opt, prof = _options("f64", loss, snapshot_every, snapshots, trace, workspace, profile, flags,
-                         m, n_outer, H)
+                         m, n_outer, H, monitor_every, tol, mon)
     kern = _kernel(kernel)
     st = _lib.kdcd_ksvm_solve_sampled(ctypes.byref(mat), y.data_ptr(), ctypes.byref(kern),
                                       float(C), int(s), H, ctypes.byref(smp), alpha.data_ptr(),
                                       ctypes.byref(opt), _stream(stream))
     _check(st, "kdcd_ksvm_solve_sampled")
-    p = {f: getattr(prof, f) for f, _ in _Profile._fields_} if prof is not None else None
-    return idx_out, p
+    return idx_out, _result(prof, mon)
 
 
 # ------------------------------------------------------------------ tuning

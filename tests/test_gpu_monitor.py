@@ -1,0 +1,143 @@
+"""On-device convergence monitor: the maintained dual vector, the certified
+bound it reports, early stopping, and the error paths.
+
+The monitor's quantities have closed forms in the oracle's objective
+evaluators: K-RR rel = (||y - M a||^2 / 2m) / (|f| - that) from
+(objective, residual norm); K-SVM rel = gap / |dual| from (dual, gap).
+Both are compared with the oracle at the final iterate; an early stop is
+checked against a plain solve of exactly the reported number of outer
+iterations (bit for bit: the monitor does not change the iteration)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2406_18001_amd import inputs
+from tests.helpers import assert_parity, dev, idx_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def K():
+    from paper_2406_18001_amd import kdcd
+    return kdcd
+
+
+def krr_rel(ev, m):
+    bound = 0.5 * ev["residual_norm"] ** 2 / m
+    return bound / (abs(ev["objective"]) - bound)
+
+
+@pytest.mark.parametrize("warm", [False, True])
+def test_krr_monitor_value_and_iterates(K, warm):
+    d = inputs.dense_krr_c2(m=2000, n=64, seed=8)
+    m, b, s, H = 2000, 8, 16, 16 * 12 + 5
+    idx = inputs.krr_indices(m, b, H, seed=3)
+    kern = (2, 1.0, 0.0, 1)
+    a0 = np.zeros(m)
+    if warm:     # start from a partly converged iterate: the initial residual needs K a0
+        w = torch.zeros(m, dtype=torch.float64, device="cuda")
+        K.kdcd_krr_solve(dev(d["A"]), dev(d["y"]), kern, 1e-3, b, s, 40 * s,
+                         idx_dev(inputs.krr_indices(m, b, 40 * s, seed=9)), w)
+        a0 = w.cpu().numpy()
+    a = dev(a0)
+    info = K.kdcd_krr_solve(dev(d["A"]), dev(d["y"]), kern, 1e-3, b, s, H, idx_dev(idx), a,
+                            monitor_every=4, tol=0.0)
+    plain = dev(a0)
+    K.kdcd_krr_solve(dev(d["A"]), dev(d["y"]), kern, 1e-3, b, s, H, idx_dev(idx), plain)
+    assert torch.equal(a, plain)
+    assert info["outer_done"] == -(-H // s)
+    ev = O.krr_eval(d["A"], d["y"], O.Kernel(O.RBF, sigma=1.0), 1e-3, a.cpu().numpy())
+    ref = krr_rel(ev, m)
+    assert ref > 0
+    assert abs(info["rel_err"] - ref) <= 1e-7 * ref
+
+
+@pytest.mark.parametrize("loss", [1, 2])
+def test_ksvm_monitor_value_and_early_stop(K, loss):
+    d = inputs.dense_ksvm_c1(m=1500, n=16, seed=9)
+    m, s, C = 1500, 32, 1.0
+    H = 40 * m
+    idx = inputs.ksvm_indices(m, H, seed=4)
+    kern = (2, 1.0 / 16, 0.0, 1)
+    okern = O.Kernel(O.RBF, sigma=1.0 / 16)
+    # no stop: the reported gap matches the oracle's at the end of 3 epochs
+    a = torch.zeros(m, dtype=torch.float64, device="cuda")
+    H3 = 3 * m
+    info = K.kdcd_ksvm_solve(dev(d["A"]), dev(d["y"]), kern, C, 1, s, H3, idx_dev(idx[:H3]), a,
+                             loss=loss, monitor_every=5, tol=0.0)
+    ev = O.ksvm_eval(d["A"], d["y"], okern, C, a.cpu().numpy(), loss=loss)
+    ref = ev["gap"] / abs(ev["dual"])
+    assert abs(info["rel_err"] - ref) <= 1e-7 * ref + 1e-12, (info["rel_err"], ref)
+    # stop at 1e-4: the result equals a plain solve of the reported outer iterations
+    a = torch.zeros(m, dtype=torch.float64, device="cuda")
+    info = K.kdcd_ksvm_solve(dev(d["A"]), dev(d["y"]), kern, C, 1, s, H, idx_dev(idx), a,
+                             loss=loss, monitor_every=10, tol=1e-4)
+    k = info["outer_done"]
+    assert 0 < k < H // s and k % 10 == 0 and info["rel_err"] <= 1e-4
+    plain = torch.zeros(m, dtype=torch.float64, device="cuda")
+    K.kdcd_ksvm_solve(dev(d["A"]), dev(d["y"]), kern, C, 1, s, k * s, idx_dev(idx[:k * s]), plain,
+                      loss=loss)
+    assert torch.equal(a, plain)
+    ev = O.ksvm_eval(d["A"], d["y"], okern, C, a.cpu().numpy(), loss=loss)
+    assert ev["gap"] / abs(ev["dual"]) <= 1e-4 * (1 + 1e-6)
+
+
+def test_krr_early_stop_and_snapshots(K):
+    d = inputs.dense_krr_c2(m=3000, n=64, seed=10)
+    m, b, s = 3000, 8, 32
+    H = 400 * s
+    idx = inputs.krr_indices(m, b, H, seed=5)
+    a = torch.zeros(m, dtype=torch.float64, device="cuda")
+    rows = -(-(H // s) // 50)
+    snaps = torch.full((rows * m,), 7.0, dtype=torch.float64, device="cuda")
+    info = K.kdcd_krr_solve(dev(d["A"]), dev(d["y"]), (2, 1.0, 0.0, 1), 1e-3, b, s, H,
+                            idx_dev(idx), a, monitor_every=8, tol=1e-6, snapshot_every=50,
+                            snapshots=snaps)
+    k = info["outer_done"]
+    assert k < H // s and info["rel_err"] <= 1e-6
+    ev = O.krr_eval(d["A"], d["y"], O.Kernel(O.RBF, sigma=1.0), 1e-3, a.cpu().numpy())
+    assert krr_rel(ev, m) <= 1e-6 * (1 + 1e-6)
+    # every snapshot taken after the stop holds the final iterate
+    sn = snaps.view(rows, m)
+    for r in range(rows):
+        if (r + 1) * 50 >= k:
+            assert torch.equal(sn[r], a)
+
+
+def test_sampled_solve_with_monitor(K):
+    d = inputs.dense_ksvm_c5(m=3000, n=32, seed=25)
+    m, C, s = 3000, 10.0, 64
+    kern = (2, 2.0 / 32, 0.0, 1)
+    a = torch.zeros(m, dtype=torch.float64, device="cuda")
+    idx, info = K.kdcd_ksvm_solve_sampled(dev(d["A"]), dev(d["y"]), kern, C, s, 60 * m, a,
+                                          seed=3, monitor_every=16, tol=1e-3)
+    k = info["outer_done"]
+    assert 0 < k < -(-60 * m // s) and info["rel_err"] <= 1e-3
+    a_ref, _ = O.dcd_ksvm(d["A"], d["y"], O.Kernel(O.RBF, sigma=2.0 / 32), C, k * s,
+                          idx.cpu().numpy()[:k * s], s=s)
+    assert_parity(a.cpu().numpy(), a_ref, 1e-9, "alpha")
+
+
+def test_monitor_errors(K):
+    d = inputs.dense_krr_c2(m=300, n=8, seed=1)
+    idx = idx_dev(inputs.krr_indices(300, 2, 20, seed=0))
+    a = torch.zeros(300, dtype=torch.float64, device="cuda")
+    args = (dev(d["A"]), dev(d["y"]), (2, 1.0, 0.0, 1), 1e-3, 2, 5, 20, idx, a)
+    with pytest.raises(K.KdcdError) as e:
+        K.kdcd_krr_solve(*args, monitor_every=2, tol=-1.0)
+    assert e.value.status == -1
+    with pytest.raises(K.KdcdError) as e:
+        K.kdcd_krr_solve(*args, monitor_every=2, tol=1e-6, compute="bf16")
+    assert e.value.status == -2
+    with pytest.raises(K.KdcdError) as e:
+        K.kdcd_krr_solve(*args, monitor_every=2, tol=1e-6, flags=K.FLAG_GRAPH)
+    assert e.value.status == -2
+    c = inputs.csr_ksvm_c3(m=300, n=100, nnz_per_row=5, seed=1)
+    A = K.CSR(torch.as_tensor(c["row_ptr"]).cuda(), torch.as_tensor(c["col_idx"]).cuda(),
+              torch.as_tensor(c["val"]).cuda(), 300, 100)
+    with pytest.raises(K.KdcdError) as e:
+        K.kdcd_ksvm_solve(A, dev(c["y"]), (1, 0.0, 1.0, 3), 1.0, 1, 4, 8,
+                          idx_dev(np.arange(8, dtype=np.int32)), a, monitor_every=2, tol=1e-6)
+    assert e.value.status == -2
