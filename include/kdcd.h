@@ -144,9 +144,11 @@ typedef struct {
  * certified bound on the relative objective error (f - f*) / |f*|:
  *   K-RR: ||y - M alpha||^2 / (2m) / (|f| - that), since lambda_min(M) >= m;
  *   K-SVM: the duality gap P(alpha) + f(alpha), divided by |f|.
- * Once the bound is <= tol every later launch of the solve returns at once
- * (no host round trip); alpha and the snapshots stop changing, trace entries
- * past that point are unspecified.  The monitor adds about
+ * Once the bound is <= tol every later launch of the solve returns at once,
+ * and the host, which checks the outcome of the evaluation two periods back
+ * before each period, stops enqueuing; alpha stops changing, every later
+ * snapshot holds the final iterate, and trace (and idx_out) entries past that
+ * point are unspecified.  The monitor adds about
  * 8 (m (s b + 2) + s b) bytes + 8 KiB to the workspace (not counted by
  * kdcd_workspace_bytes).
  * Costs per outer iteration: m*s*b*8 bytes written and read (the stored

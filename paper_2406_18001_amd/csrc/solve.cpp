@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 #include <functional>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -292,6 +293,49 @@ kdcd_status init_dual_vector(int32_t problem, const kdcd_matrix *A, const kdcd_k
     return KDCD_OK;
 }
 
+// Host side of an early stop: after every monitor evaluation the stop word is
+// copied to pinned host memory and an event recorded; before enqueuing the
+// next period the host waits for the copy of LAG periods earlier and stops
+// enqueuing once it reads 1.  The host so runs at most LAG periods ahead of
+// a stop instead of enqueuing every planned outer iteration.
+struct StopPoller {
+    static constexpr int LAG = 2;
+    int32_t *host = nullptr;           // pinned, one word per monitor period
+    hipEvent_t ev[LAG + 1] = {};
+    int64_t periods = 0;
+    bool ok = false;
+    explicit StopPoller(int64_t n_periods) : periods(n_periods)
+    {
+        if (hipHostMalloc(reinterpret_cast<void **>(&host), sizeof(int32_t) * (size_t)(periods + 1)) !=
+            hipSuccess)
+            return;
+        for (auto &e : ev)
+            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return;
+        ok = true;
+    }
+    ~StopPoller()
+    {
+        for (auto &e : ev)
+            if (e) (void)hipEventDestroy(e);
+        if (host) (void)hipHostFree(host);
+    }
+    // after the monitor launch of period j
+    hipError_t post(int64_t j, const MonitorState *mon, hipStream_t st)
+    {
+        if (!ok || j > periods) return hipSuccess;
+        hipError_t e = hipMemcpyAsync(host + j, &mon->stop, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipEventRecord(ev[j % (LAG + 1)], st);
+        return e;
+    }
+    // before enqueuing period j + 1: true when the device had stopped at period j - LAG
+    bool stopped(int64_t j)
+    {
+        if (!ok || j < LAG) return false;
+        if (hipEventSynchronize(ev[(j - LAG) % (LAG + 1)]) != hipSuccess) return false;
+        return host[j - LAG] != 0;
+    }
+};
+
 // Everything a solve puts on its stream, in the workspace at `base`, without
 // the final status read (the status word is at offset L.status).
 kdcd_status enqueue_solve(const SolveArgs &sa, const Layout &L, char *wsbase, StageTimer &timer)
@@ -348,7 +392,13 @@ kdcd_status enqueue_solve(const SolveArgs &sa, const Layout &L, char *wsbase, St
 
     const int64_t n_outer = (sa.H + sa.s - 1) / sa.s;
     int64_t snap = 0;
-    for (int64_t k = 0; k < n_outer; ++k) {
+    std::unique_ptr<StopPoller> poll;
+    if (monitor) poll.reset(new StopPoller(n_outer / sa.opt.monitor_every + 1));
+    int64_t k = 0;
+    for (; k < n_outer; ++k) {
+        if (monitor && k > 0 && k % sa.opt.monitor_every == 0 &&
+            poll->stopped(k / sa.opt.monitor_every - 1))
+            break;
         const int64_t done = k * sa.s;
         const int32_t sk = (int32_t)std::min<int64_t>(sa.s, sa.H - done);
         const int32_t sb = sk * sa.b;
@@ -404,10 +454,12 @@ kdcd_status enqueue_solve(const SolveArgs &sa, const Layout &L, char *wsbase, St
             else
                 KDCD_HIP_TRY(launch_dual_update(kb.U, A->m, sb, S, tr, nullptr, -1.0 / sa.lambda,
                                                 nullptr, -(double)A->m, dual, stop, st));
-            if ((k + 1) % sa.opt.monitor_every == 0 || k + 1 == n_outer)
+            if ((k + 1) % sa.opt.monitor_every == 0 || k + 1 == n_outer) {
                 KDCD_HIP_TRY(launch_monitor(sa.problem, A->m, sa.alpha, sa.y, dual, omega,
                                             sa.opt.loss, sa.C, sa.opt.tol, k + 1,
                                             ws.at<double>(L.mon_part), mon, st));
+                KDCD_HIP_TRY(poll->post((k + 1) / sa.opt.monitor_every - 1, mon, st));
+            }
         }
         timer.end(2, st);
         if (sa.opt.snapshot_every > 0 && sa.opt.snapshots &&
@@ -417,6 +469,14 @@ kdcd_status enqueue_solve(const SolveArgs &sa, const Layout &L, char *wsbase, St
                                         st));
             ++snap;
         }
+    }
+    // stopped early: the snapshots not yet taken all hold the final iterate
+    if (k < n_outer && sa.opt.snapshot_every > 0 && sa.opt.snapshots) {
+        const int64_t rows = (n_outer + sa.opt.snapshot_every - 1) / sa.opt.snapshot_every;
+        for (; snap < rows; ++snap)
+            KDCD_HIP_TRY(hipMemcpyAsync(sa.opt.snapshots + snap * A->m, sa.alpha,
+                                        sizeof(double) * (size_t)A->m, hipMemcpyDeviceToDevice,
+                                        st));
     }
     return KDCD_OK;
 }
@@ -1004,7 +1064,12 @@ kdcd_status kdcd_ksvm_solve_sampled(const kdcd_matrix *A, const double *y,
     StageTimer timer;
     timer.on = o.profile != nullptr;
     int64_t snap = 0;
-    for (int64_t k = 0; k < n_outer; ++k) {
+    std::unique_ptr<StopPoller> poll;
+    if (monitor) poll.reset(new StopPoller(n_outer / o.monitor_every + 1));
+    int64_t k = 0;
+    for (; k < n_outer; ++k) {
+        if (monitor && k > 0 && k % o.monitor_every == 0 && poll->stopped(k / o.monitor_every - 1))
+            break;
         const int64_t done = k * s;
         const int32_t sk = (int32_t)std::min<int64_t>(s, H - done);
         int32_t *S = smp->idx_out + done;
@@ -1059,9 +1124,11 @@ kdcd_status kdcd_ksvm_solve_sampled(const kdcd_matrix *A, const double *y,
         kd.stop = stop;
         KDCD_HIP_TRY(launch_ksvm_recur(kd, 1, S, sk, m, status, st));
         KDCD_HIP_TRY(launch_dual_update(U, m, sk, S, theta, y, 1.0, y, omega, g, stop, st));
-        if (monitor && ((k + 1) % o.monitor_every == 0 || k + 1 == n_outer))
+        if (monitor && ((k + 1) % o.monitor_every == 0 || k + 1 == n_outer)) {
             KDCD_HIP_TRY(launch_monitor(0, m, alpha, y, g, omega, o.loss, C, o.tol, k + 1,
                                         ws.at<double>(o_monp), mon, st));
+            KDCD_HIP_TRY(poll->post((k + 1) / o.monitor_every - 1, mon, st));
+        }
         timer.end(2, st);
         if (o.trace)
             KDCD_HIP_TRY(hipMemcpyAsync(o.trace + done, theta, sizeof(double) * (size_t)sk,
@@ -1071,6 +1138,12 @@ kdcd_status kdcd_ksvm_solve_sampled(const kdcd_matrix *A, const double *y,
                                         hipMemcpyDeviceToDevice, st));
             ++snap;
         }
+    }
+    if (k < n_outer && o.snapshot_every > 0) {   // stopped early: the rest hold the final iterate
+        const int64_t rows = (n_outer + o.snapshot_every - 1) / o.snapshot_every;
+        for (; snap < rows; ++snap)
+            KDCD_HIP_TRY(hipMemcpyAsync(o.snapshots + snap * m, alpha, sizeof(double) * (size_t)m,
+                                        hipMemcpyDeviceToDevice, st));
     }
     rc = read_status(status, st);
     timer.report(o.profile);
