@@ -134,6 +134,14 @@ struct KBlockArgs {
     const BatchDesc *batch;  // non-null: batched epilogue (dense F64 and mixed kernels)
     double *U;               // dense F64 only: non-null stores K(a_p, a_{S_j}) at U[j*m + p]
     const int32_t *stop;     // dense F64 only: non-null and set -> the launch does nothing
+    // dense F64 only: when non-null, W is taken from the U-part rows of the
+    // sampled rows (no W tiles).  pos[p] is the position t of row p in S (one
+    // of them for repeated rows) or -1; it must hold -1 everywhere except the
+    // entries of prevS (the previous index block, prev_sb entries), which the
+    // launch resets before marking S; rows of repeated indices are copied after.
+    int32_t *pos;
+    const int32_t *prevS;
+    int32_t prev_sb;
 };
 
 // Launchers (return hipError_t of the launch).

@@ -48,7 +48,8 @@ __global__ __launch_bounds__(64 * WM * WN) void kblock_f64_kernel(
     const double *__restrict__ beta, const double *__restrict__ bscale,
     double *__restrict__ partial, double *__restrict__ W, int32_t n_u_tiles,
     int32_t n_row_groups, int32_t n_w_tiles, int32_t n_tiles_n, int32_t aligned,
-    const BatchDesc *__restrict__ bd, double *__restrict__ U, const int32_t *__restrict__ stop)
+    const BatchDesc *__restrict__ bd, double *__restrict__ U, const int32_t *__restrict__ stop,
+    const int32_t *__restrict__ pos)
 {
     if (stop && *stop) return;   // the solve has converged
     constexpr int NT = 64 * WM * WN;
@@ -302,16 +303,16 @@ __global__ __launch_bounds__(64 * WM * WN) void kblock_f64_kernel(
                             double bval = beta[grow];
                             if (bscale) bval *= bscale[grow];
                             const double na = (KIND == KDCD_KERNEL_RBF) ? norms[grow] : 0.0;
+                            const int32_t wrow = pos ? pos[grow] : -1;   // row of W, if sampled
 #pragma unroll
                             for (int tn = 0; tn < TN; ++tn)
                                 if (colok[tn]) {
                                     const double kv = kernel_map<KIND>(acc[tm][tn][v], na, nb[tn],
                                                                        grow == Sc[tn], kp);
                                     colsum[tn] += bval * kv;
-                                    if (U) {
-                                        const int64_t gcol = col0 + (wn * TN + tn) * 16 + (lane & 15);
-                                        U[gcol * m + grow] = kv;
-                                    }
+                                    const int64_t gcol = col0 + (wn * TN + tn) * 16 + (lane & 15);
+                                    if (U) U[gcol * m + grow] = kv;
+                                    if (wrow >= 0 && wrow < sb) W[(int64_t)wrow * sb + gcol] = kv;
                                 }
                         }
                     } else if (grow < sb) {
@@ -358,6 +359,42 @@ __global__ __launch_bounds__(64 * WM * WN) void kblock_f64_kernel(
     }
 }
 
+// pos[] upkeep: clear the previous block's entries, then mark the new one
+// (one workgroup, so the clears are ordered before the marks).
+__global__ __launch_bounds__(1024) void pos_set_kernel(int32_t *__restrict__ pos, int64_t m,
+                                                       const int32_t *__restrict__ prevS,
+                                                       int32_t prev_sb,
+                                                       const int32_t *__restrict__ S, int32_t sb,
+                                                       const int32_t *__restrict__ stop)
+{
+    if (stop && *stop) return;
+    for (int t = threadIdx.x; t < prev_sb; t += blockDim.x) {
+        const int32_t p = prevS[t];
+        if (p >= 0 && p < m) pos[p] = -1;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < sb; t += blockDim.x) {
+        const int32_t p = S[t];
+        if (p >= 0 && p < m) pos[p] = t;
+    }
+}
+
+// Rows of W for repeated indices: row t copies the row written for S_t.
+__global__ __launch_bounds__(256) void w_dup_kernel(double *__restrict__ W, int64_t m,
+                                                    const int32_t *__restrict__ S, int32_t sb,
+                                                    const int32_t *__restrict__ pos,
+                                                    const int32_t *__restrict__ stop)
+{
+    if (stop && *stop) return;
+    const int t = blockIdx.x;
+    const int32_t p = S[t];
+    if (p < 0 || p >= m) return;
+    const int32_t r = pos[p];
+    if (r == t || r < 0) return;
+    for (int j = threadIdx.x; j < sb; j += blockDim.x)
+        W[(int64_t)t * sb + j] = W[(int64_t)r * sb + j];
+}
+
 struct Cfg {
     int bm, bn;
 };
@@ -371,7 +408,7 @@ hipError_t launch_cfg(const KBlockArgs &a, hipStream_t st)
     const kdcd_matrix *A = a.A;
     const int64_t n_u = a.w_only ? 0 : (A->m + BM - 1) / BM;
     const int64_t groups = n_u < kMaxRowGroups ? n_u : kMaxRowGroups;
-    const int64_t n_w = a.W ? (a.sb + BM - 1) / BM : 0;
+    const int64_t n_w = (a.W && !a.pos) ? (a.sb + BM - 1) / BM : 0;
     if (groups + n_w == 0) return hipSuccess;
     const int64_t n_n = (a.sb + BN - 1) / BN;
     const int64_t blocks = n_n * (groups + n_w);
@@ -382,7 +419,7 @@ hipError_t launch_cfg(const KBlockArgs &a, hipStream_t st)
                        A->values, A->ld, A->m, A->n, a.S, a.sb, a.norms, a.kp, a.beta,          \
                        a.beta_scale, a.partial, a.W, (int32_t)n_u, (int32_t)groups,            \
                        (int32_t)n_w, (int32_t)n_n, aligned, a.batch, BATCH ? nullptr : a.U,   \
-                       a.stop)
+                       a.stop, BATCH ? nullptr : a.pos)
     switch (a.kp.kind) {
     case KDCD_KERNEL_LINEAR: KDCD_LAUNCH(KDCD_KERNEL_LINEAR); break;
     case KDCD_KERNEL_POLY: KDCD_LAUNCH(KDCD_KERNEL_POLY); break;
@@ -464,14 +501,28 @@ hipError_t launch_kblock_f64(const KBlockArgs &a, hipStream_t st)
         if (c.bn == 32) return launch_cfg<4, 1, 2, 2, true>(a, st);
         return launch_cfg<2, 2, 2, 2, true>(a, st);
     }
-    switch (f64_config_id(a.A->n, a.sb)) {
-    case 0: return launch_cfg<4, 1, 2, 1, false>(a, st);
-    case 1: return launch_cfg<4, 1, 2, 2, false>(a, st);
-    case 2: return launch_cfg<2, 2, 2, 2, false>(a, st);
-    case 3: return launch_cfg<2, 2, 2, 4, false>(a, st);
-    case 4: return launch_cfg<2, 4, 2, 2, false>(a, st);
-    default: return launch_cfg<4, 2, 2, 2, false>(a, st);
+    const bool gather = a.W && a.pos && !a.w_only;
+    if (gather) {
+        hipLaunchKernelGGL(pos_set_kernel, dim3(1), dim3(1024), 0, st, a.pos, a.A->m, a.prevS,
+                           a.prevS ? a.prev_sb : 0, a.S, a.sb, a.stop);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
     }
+    KBlockArgs b = a;
+    if (!gather) b.pos = nullptr;
+    hipError_t e;
+    switch (f64_config_id(a.A->n, a.sb)) {
+    case 0: e = launch_cfg<4, 1, 2, 1, false>(b, st); break;
+    case 1: e = launch_cfg<4, 1, 2, 2, false>(b, st); break;
+    case 2: e = launch_cfg<2, 2, 2, 2, false>(b, st); break;
+    case 3: e = launch_cfg<2, 2, 2, 4, false>(b, st); break;
+    case 4: e = launch_cfg<2, 4, 2, 2, false>(b, st); break;
+    default: e = launch_cfg<4, 2, 2, 2, false>(b, st); break;
+    }
+    if (e != hipSuccess || !gather) return e;
+    hipLaunchKernelGGL(w_dup_kernel, dim3((unsigned)a.sb), dim3(256), 0, st, a.W, a.A->m, a.S, a.sb,
+                       a.pos, a.stop);
+    return hipGetLastError();
 }
 
 }  // namespace kdcd

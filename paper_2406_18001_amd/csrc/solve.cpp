@@ -93,7 +93,7 @@ size_t lowp_elem_bytes(int32_t compute) { return compute == KDCD_F32 ? 4 : 2; }
 
 // Workspace regions of one solve.
 struct Layout {
-    size_t status, norms, partial, r, W, Dinv, iota, hi, lo, normlow, total;
+    size_t status, norms, partial, r, W, Dinv, iota, hi, lo, normlow, pos, total;
     int64_t ldlow;
     // convergence monitor (0 when off): state, partial sums, maintained
     // gradient / residual (m), stored kernel block (s*b x m), updates (s*b),
@@ -126,6 +126,7 @@ Layout make_layout(int32_t problem, const kdcd_matrix *A, const kdcd_kernel *ker
     L.W = off; off += align256(sizeof(double) * (size_t)(sb * sb));
     L.Dinv = off; off += (problem == 1) ? align256(sizeof(double) * (size_t)(sb * b)) : 0;
     L.iota = off; off += (problem == 2) ? align256(sizeof(int32_t) * (size_t)A->m) : 0;
+    L.pos = off; off += align256(sizeof(int32_t) * (size_t)A->m);   // row -> position in S
     L.ldlow = 0;
     L.hi = L.lo = L.normlow = off;
     if (compute != KDCD_F64) {
@@ -372,6 +373,10 @@ kdcd_status enqueue_solve(const SolveArgs &sa, const Layout &L, char *wsbase, St
     base.W = W;
     base.status = status;
     base.compute = sa.opt.compute;
+    if (A->format == KDCD_DENSE && sa.opt.compute == KDCD_F64) {
+        base.pos = ws.at<int32_t>(L.pos);
+        KDCD_HIP_TRY(launch_fill_i32(base.pos, -1, A->m, st));
+    }
     KBlockArgs kb;
     rc = prepare_lowp(base, L, ws, st, kb);
     if (rc != KDCD_OK) return rc;
@@ -403,6 +408,8 @@ kdcd_status enqueue_solve(const SolveArgs &sa, const Layout &L, char *wsbase, St
         const int32_t sk = (int32_t)std::min<int64_t>(sa.s, sa.H - done);
         const int32_t sb = sk * sa.b;
         const int32_t *S = sa.idx + done * sa.b;
+        kb.prevS = kb.S;          // the previous block (null before the first)
+        kb.prev_sb = kb.sb;
         kb.S = S;
         kb.sb = sb;
         timer.begin(0, st);
@@ -1060,6 +1067,8 @@ kdcd_status kdcd_ksvm_solve_sampled(const kdcd_matrix *A, const double *y,
     kb.compute = KDCD_F64;
     kb.U = U;
     kb.stop = stop;
+    kb.pos = ws.at<int32_t>(L.pos);
+    KDCD_HIP_TRY(launch_fill_i32(kb.pos, -1, m, st));
 
     StageTimer timer;
     timer.on = o.profile != nullptr;
@@ -1098,6 +1107,8 @@ kdcd_status kdcd_ksvm_solve_sampled(const kdcd_matrix *A, const double *y,
             KDCD_HIP_TRY(launch_features(S, sk, alpha, g, norms, y, kp, 1.0 / C,
                                          smp->features_out + 4 * done, st));
         timer.end(2, st);
+        kb.prevS = kb.S;
+        kb.prev_sb = kb.sb;
         kb.S = S;
         kb.sb = sk;
         timer.begin(0, st);
@@ -1184,6 +1195,10 @@ kdcd_status kdcd_autotune(const kdcd_matrix *A, const kdcd_kernel *kernel, int32
     kb.W = ws.at<double>(L.W);
     kb.status = ws.at<int32_t>(L.status);
     kb.compute = KDCD_F64;
+    kb.pos = ws.at<int32_t>(L.pos);        // W from the U rows, as in the solves
+    KDCD_HIP_TRY(launch_fill_i32(kb.pos, -1, A->m, st));
+    kb.prevS = S;                          // every launch re-marks the same block
+    kb.prev_sb = sb;
     const int prev = tune_lookup(compute, A->n, sb);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return KDCD_ERR_HIP;
@@ -1261,6 +1276,10 @@ kdcd_status kdcd_kernel_rhs(const kdcd_matrix *A, const kdcd_kernel *kernel, con
     base.W = W;
     base.status = status;
     base.compute = compute;
+    if (W && A->format == KDCD_DENSE && compute == KDCD_F64) {
+        base.pos = ws.at<int32_t>(L.pos);
+        KDCD_HIP_TRY(launch_fill_i32(base.pos, -1, A->m, st));
+    }
     KBlockArgs kb;
     if ((rc = prepare_lowp(base, L, ws, st, kb)) != KDCD_OK) return rc;
     KDCD_HIP_TRY(launch_kblock(kb, st));
