@@ -113,8 +113,17 @@ typedef struct {
  * which then must stay valid while the entry lives.  Graph-mode calls are
  * serialised by one lock.  With a profile, only total_ms is reported.
  */
+/*
+ * KDCD_FLAG_OVERLAP (dense FP64 kdcd_ksvm_solve / kdcd_krr_solve, not with
+ * the monitor or graph replay): the recurrence of each outer iteration runs
+ * on a second stream of the device next to the next kernel-block product,
+ * which leaves out the rows the recurrence is changing; a small correction
+ * adds them afterwards (same result up to the order of the sums).  Two
+ * cross-stream event waits per outer iteration are on its critical path.
+ */
 enum {
-    KDCD_FLAG_GRAPH = 1
+    KDCD_FLAG_GRAPH = 1,
+    KDCD_FLAG_OVERLAP = 2
 };
 
 typedef struct {

@@ -142,6 +142,15 @@ struct KBlockArgs {
     int32_t *pos;
     const int32_t *prevS;
     int32_t prev_sb;
+    // dense F64 only, lookahead (requires pos): rows of prevS are left out of
+    // the reduction (a concurrent recurrence is updating their beta) and their
+    // kernel rows go to X[t][j] = K(a_{prevS_t}, a_{S_j}) instead, t the first
+    // position of the row in prevS (posX[p], or INT32_MAX when p is not in
+    // prevS; the launch clears the entries of prev2S and marks prevS).
+    int32_t *posX;
+    const int32_t *prev2S;
+    int32_t prev2_sb;
+    double *X;
 };
 
 // Launchers (return hipError_t of the launch).
@@ -211,6 +220,12 @@ hipError_t launch_monitor(int32_t problem, int64_t m, const double *alpha, const
                           int64_t outer, double *part, MonitorState *mon, hipStream_t st);
 hipError_t launch_rho_init(const double *Ka, const double *y, const double *alpha,
                            double inv_lambda, double mdbl, int64_t m, double *rho, hipStream_t st);
+
+// r[j] += sum over the first occurrences t in prevS of X[t][j] * beta(prevS_t),
+// beta = alpha (o bscale): the rows a lookahead launch left out.
+hipError_t launch_lookahead_fix(const double *X, const int32_t *prevS, int32_t xsb,
+                                const double *alpha, const double *bscale, double *r, int32_t sb,
+                                hipStream_t st);
 
 hipError_t launch_finish(const FinishDesc &d, int32_t sb, int32_t b, int32_t sk, double mdbl,
                          int32_t *status, hipStream_t st);

@@ -30,6 +30,7 @@ KERNEL_LINEAR, KERNEL_POLY, KERNEL_RBF = 0, 1, 2
 DENSE, CSR_FORMAT = 0, 1
 COMPUTE = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3, "bf16x3": 4}
 FLAG_GRAPH = 1
+FLAG_OVERLAP = 2
 
 STATUS = {0: "KDCD_OK", -1: "KDCD_ERR_INVALID_ARG", -2: "KDCD_ERR_UNSUPPORTED",
           -3: "KDCD_ERR_INDEX_RANGE", -4: "KDCD_ERR_INDEX_DUPLICATE", -5: "KDCD_ERR_NOT_SPD",
@@ -574,6 +575,7 @@ def kdcd_tune_load(path):
 
 
 FLAG_GRAPH = 1
+FLAG_OVERLAP = 2
 
 
 def kdcd_graph_cache_clear():

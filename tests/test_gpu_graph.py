@@ -1,5 +1,5 @@
 """KDCD_FLAG_GRAPH: the captured launch sequence, replayed, gives the eager
-result bit for bit.  Every replay is checked, with the program's own eager
+result of the same (serial) outer loop bit for bit.  Every replay is checked, with the program's own eager
 work (resets, in-place changes of the inputs, other solves) and
 synchronisations between the replays, so that a replay reading stale or
 wrongly cleared memory shows up."""

@@ -182,10 +182,18 @@ def test_determinism_and_resume(K):
         K.kdcd_krr_solve(A, y, RBF1, 1e-3, 8, 16, 96, I, a)
         runs.append(a.cpu().numpy())
     assert np.array_equal(runs[0], runs[1])
+    # resuming: two calls equal one call bit for bit (the overlapped loop sums
+    # r in another order across the split: equal to rounding)
+    one = torch.zeros(1500, dtype=torch.float64, device="cuda")
+    K.kdcd_krr_solve(A, y, RBF1, 1e-3, 8, 16, 96, I, one)
     a = torch.zeros(1500, dtype=torch.float64, device="cuda")
     K.kdcd_krr_solve(A, y, RBF1, 1e-3, 8, 16, 48, I, a)
     K.kdcd_krr_solve(A, y, RBF1, 1e-3, 8, 16, 48, idx_dev(idx[48 * 8:]), a)
-    assert np.array_equal(a.cpu().numpy(), runs[0])
+    assert torch.equal(a, one)
+    a = torch.zeros(1500, dtype=torch.float64, device="cuda")
+    K.kdcd_krr_solve(A, y, RBF1, 1e-3, 8, 16, 48, I, a, flags=K.FLAG_OVERLAP)
+    K.kdcd_krr_solve(A, y, RBF1, 1e-3, 8, 16, 48, idx_dev(idx[48 * 8:]), a, flags=K.FLAG_OVERLAP)
+    assert_parity(a.cpu().numpy(), runs[0], 1e-12, "resumed, overlapped")
 
 
 def test_snapshots(K):
