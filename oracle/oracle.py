@@ -222,3 +222,17 @@ def krr_eval(A, y, kernel, lam, alpha) -> dict:
     lib().orc_krr_eval(a.A, a.ptr(y, np.float64), a.K, float(lam), a.ptr(alpha, np.float64),
                        out.ctypes.data, res.ctypes.data)
     return {"objective": out[0], "residual_norm": out[1], "residual": res}
+
+
+def nystrom_features(A, kernel, landmarks, jitter) -> np.ndarray:
+    """Nystrom features Phi = K(A, A_L) L^{-T} with L L^T = K(A_L, A_L) + jitter I
+    (Cholesky), so that Phi Phi^T = K_AL (K_LL + jitter I)^{-1} K_LA: the
+    approximation of the kernel matrix from the landmark rows L that the
+    paper's conclusion proposes for the sampled kernel block.  Solving with
+    Phi and the linear kernel solves the approximated problem."""
+    L = np.asarray(landmarks)
+    m = A[3] if isinstance(A, tuple) else A.shape[0]
+    K_AL = kernel_block(A, kernel, np.arange(m), L)
+    K_LL = kernel_block(A, kernel, L, L) + jitter * np.eye(L.size)
+    C = np.linalg.cholesky(K_LL)                  # lower triangular
+    return np.linalg.solve(C, K_AL.T).T           # rows phi_i = C^{-1} k_i

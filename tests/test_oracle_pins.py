@@ -320,3 +320,24 @@ def test_ksvm_sstep_csr_poly_equals_classical():
     a_ref, _ = O.dcd_ksvm(csr, c["y"], poly(1.0, 3), 1.0, 96, idx)
     a_s, _ = O.dcd_ksvm(csr, c["y"], poly(1.0, 3), 1.0, 96, idx, s=32)
     assert np.linalg.norm(a_s - a_ref) <= 1e-10 * np.linalg.norm(a_ref)
+
+
+def test_nystrom_features_properties():
+    """Phi Phi^T restricted to the landmarks is K_LL (K_LL + jI)^{-1} K_LL;
+    with every row a landmark and j -> 0 it is K itself; K - Phi Phi^T is PSD
+    (a Schur complement); the rank is at most the number of landmarks."""
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((60, 5))
+    kern = O.Kernel(O.RBF, sigma=0.3)
+    K = O.kernel_matrix(A, kern)
+    L = rng.choice(60, 12, replace=False)
+    j = 1e-8
+    Phi = O.nystrom_features(A, kern, L, j)
+    Kt = Phi @ Phi.T
+    KLL = K[np.ix_(L, L)]
+    np.testing.assert_allclose(Kt[np.ix_(L, L)], KLL @ np.linalg.solve(KLL + j * np.eye(12), KLL),
+                               atol=1e-10)
+    assert np.linalg.eigvalsh(K - Kt).min() > -1e-9
+    assert np.linalg.matrix_rank(Kt, tol=1e-8) <= 12
+    Phi_all = O.nystrom_features(A, kern, np.arange(60), 1e-12)
+    np.testing.assert_allclose(Phi_all @ Phi_all.T, K, atol=1e-7)
