@@ -275,6 +275,64 @@ kdcd_status kdcd_krr_eval(const kdcd_matrix *A, const double *y, const kdcd_kern
                           double lambda, const double *alpha, double *out, kdcd_stream stream);
 
 /* ---------------------------------------------------------------------------
+ * Low-rank kernel blocks.  The conclusion proposes approximating the sampled
+ * kernel matrix (for instance by the Nystrom method) to cut the cost of the
+ * kernel computation and of the Gram correction per outer iteration.  Given a
+ * factor Phi (m x r) with K ~ Phi Phi^T, Algorithms 2 and 4 need per outer
+ * iteration only Phi_S z and Phi_S Phi_S^T, where z = Phi^T beta is kept
+ * current on the device: O((s b)^2 r) work instead of O(m n s b), independent
+ * of m, which is what allows large blocks; the price is that the solve
+ * converges to the minimiser of the approximated problem.
+ * ------------------------------------------------------------------------- */
+
+/*
+ * kdcd_nystrom_features -- Nystrom factor from r landmark rows L of A:
+ *   phi(x) = C^{-1} [K(x, a_{L_1}), ..., K(x, a_{L_r})]^T,
+ *   C C^T = K(A_L, A_L) + jitter I  (Cholesky, C lower with positive diagonal)
+ * so phi(x) . phi(x') = k_L(x)^T (K_LL + jitter I)^{-1} k_L(x').
+ *   A       device dense matrix, m x n (the training rows)
+ *   kernel  host, kernel function
+ *   L       device, r landmark rows in [0, m) (repeats need jitter > 0);
+ *           1 <= r <= min(m, 4096)
+ *   jitter  >= 0, added to the diagonal of K(A_L, A_L)
+ *   X       device dense matrix with X->n == A->n whose rows are featurised,
+ *           or NULL for the rows of A itself
+ *   Phi     device, rows(X) x ldphi row-major (ldphi >= r): row i = phi(x_i)
+ * Work: rows(X) * r * (n + r) multiply-adds; workspace r*r doubles plus norms,
+ * allocated on `stream`.  Synchronises `stream`.
+ * Errors: INVALID_ARG, UNSUPPORTED (CSR, r > 4096), INDEX_RANGE, NOT_SPD (a
+ * pivot of the Cholesky <= 0 or non-finite), HIP, ALLOC.
+ */
+kdcd_status kdcd_nystrom_features(const kdcd_matrix *A, const kdcd_kernel *kernel,
+                                  const int32_t *L, int32_t r, double jitter,
+                                  const kdcd_matrix *X, double *Phi, int64_t ldphi,
+                                  kdcd_stream stream);
+
+/*
+ * kdcd_lowrank_solve -- Algorithm 2 (problem 0, K-SVM; b must be 1) or
+ * Algorithm 4 (problem 1, K-RR) with the kernel matrix replaced by
+ * Phi Phi^T.  The result equals kdcd_ksvm_solve / kdcd_krr_solve on the
+ * matrix Phi with the linear kernel, up to the order of the sums.
+ *   Phi     device dense matrix m x r (r <= 4096), e.g. from
+ *           kdcd_nystrom_features
+ *   y, param (C or lambda), b, s, H, idx, alpha   as in kdcd_ksvm_solve /
+ *           kdcd_krr_solve
+ *   z       device, r doubles, or NULL: on exit Phi^T beta_H with beta =
+ *           y o alpha (K-SVM) or alpha (K-RR); phi(x) . z is then the sum
+ *           sum_i beta_i phi(x) . phi(a_i) for a new row x
+ *   opt     loss, snapshots, trace, profile; compute must be F64 and flags,
+ *           monitor_every and workspace zero (UNSUPPORTED otherwise)
+ * Per outer iteration: the Gram of Phi_S (lower tiles, mirrored), Phi_S z,
+ * the finish and recurrence passes of the full solve, and z += Phi_S^T
+ * (c o theta) with c = y_S (K-SVM) or 1 (K-RR), theta the updates.
+ * Errors: as kdcd_ksvm_solve / kdcd_krr_solve.
+ */
+kdcd_status kdcd_lowrank_solve(int32_t problem, const kdcd_matrix *Phi, const double *y,
+                               double param, int32_t b, int32_t s, int64_t H, const int32_t *idx,
+                               double *alpha, double *z, const kdcd_options *opt,
+                               kdcd_stream stream);
+
+/* ---------------------------------------------------------------------------
  * Learned coordinate sampler.  Algorithms 1-4 take their coordinate sequence
  * as an input and the paper draws it uniformly (Section 3); here a small MLP
  * (4 -> 64 -> 64 -> 1, tanh hidden units, FP32) scores every coordinate of a

@@ -24,6 +24,21 @@ int64_t kblock_csr_row_groups(int64_t m, int32_t sb);
 hipError_t launch_convert_lowp(const kdcd_matrix *A, int32_t compute, void *hi, void *lo,
                                int64_t ldlow, float *normlow, hipStream_t st);
 int krr_recur_threads(int32_t b, int32_t sk);
+int32_t lowrank_zinit_chunks();
+hipError_t launch_nystrom(const double *Av, int64_t lda, int64_t m, int64_t n, const int32_t *L,
+                          int32_t r, const KParams &kp, double jitter, const double *normsA,
+                          const double *Xv, int64_t ldx, int64_t mx, const double *normsX,
+                          bool x_is_a, double *Cw, double *Phi, int64_t ldp, int32_t *status,
+                          hipStream_t st);
+hipError_t launch_lowrank_block(const double *Phi, int64_t ldp, int64_t m, int32_t r,
+                                const int32_t *S, int32_t sb, const double *z, double *W,
+                                double *v, hipStream_t st);
+hipError_t launch_lowrank_z_update(const double *Phi, int64_t ldp, int64_t m, int32_t r,
+                                   const int32_t *S, int32_t sb, const double *theta,
+                                   const double *coef, double *z, hipStream_t st);
+hipError_t launch_lowrank_z_init(const double *Phi, int64_t ldp, int64_t m, int32_t r,
+                                 const double *alpha, const double *coef, double *part, double *z,
+                                 hipStream_t st);
 }  // namespace kdcd
 
 namespace {
@@ -33,6 +48,8 @@ constexpr int64_t kMaxGroups = 1024;   // upper bound on row groups of any kerne
 // launches per outer iteration) instead of tiles of their own, which at
 // these widths add a round of workgroups.
 constexpr int64_t kGatherMinSB = 256;
+// Largest rank of a low-rank factor (Nystrom landmarks, columns of Phi).
+constexpr int64_t kMaxRank = 4096;
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -1645,6 +1662,166 @@ kdcd_status kdcd_krr_eval(const kdcd_matrix *A, const double *y, const kdcd_kern
     out[0] = (double)(0.5L * aMa - ya);
     out[1] = std::sqrt((double)rr);
     return KDCD_OK;
+}
+
+// ------------------------------------------------------------ low rank
+// Nystrom factor and solves on an explicit factor Phi (K ~ Phi Phi^T).
+
+kdcd_status kdcd_nystrom_features(const kdcd_matrix *A, const kdcd_kernel *kernel,
+                                  const int32_t *L, int32_t r, double jitter,
+                                  const kdcd_matrix *X, double *Phi, int64_t ldphi,
+                                  kdcd_stream stream)
+{
+    kdcd_status rc = check_matrix(A);
+    if (rc != KDCD_OK) return rc;
+    if ((rc = check_kernel(kernel)) != KDCD_OK) return rc;
+    if (A->format != KDCD_DENSE) return KDCD_ERR_UNSUPPORTED;
+    if (X) {
+        if ((rc = check_matrix(X)) != KDCD_OK) return rc;
+        if (X->format != KDCD_DENSE) return KDCD_ERR_UNSUPPORTED;
+        if (X->n != A->n) return KDCD_ERR_INVALID_ARG;
+    }
+    if (!L || !Phi || r < 1 || r > A->m || ldphi < r) return KDCD_ERR_INVALID_ARG;
+    if (r > kMaxRank) return KDCD_ERR_UNSUPPORTED;
+    if (!std::isfinite(jitter) || jitter < 0.0) return KDCD_ERR_INVALID_ARG;
+    const hipStream_t st = (hipStream_t)stream;
+    const kdcd_matrix *Xm = X ? X : A;
+    const bool rbf = kernel->kind == KDCD_KERNEL_RBF;
+    size_t off = 0;
+    const size_t o_status = off; off += 256;
+    const size_t o_na = off; off += rbf ? align256(sizeof(double) * (size_t)A->m) : 0;
+    const size_t o_nx = off; off += (rbf && X) ? align256(sizeof(double) * (size_t)Xm->m) : 0;
+    const size_t o_cw = off; off += align256(sizeof(double) * (size_t)r * (size_t)r);
+    Layout L0{};
+    L0.total = off;
+    Workspace ws;
+    if ((rc = acquire(ws, L0, nullptr, st)) != KDCD_OK) return rc;
+    int32_t *status = ws.at<int32_t>(o_status);
+    double *na = rbf ? ws.at<double>(o_na) : nullptr;
+    double *nx = rbf ? (X ? ws.at<double>(o_nx) : na) : nullptr;
+    KDCD_HIP_TRY(launch_fill_i32(status, 0, 1, st));
+    if (rbf) {
+        KDCD_HIP_TRY(launch_norms(A, na, st));
+        if (X) KDCD_HIP_TRY(launch_norms(X, nx, st));
+    }
+    KDCD_HIP_TRY(launch_nystrom(A->values, A->ld, A->m, A->n, L, r, to_params(kernel), jitter, na,
+                                Xm->values, Xm->ld, Xm->m, nx, X == nullptr, ws.at<double>(o_cw),
+                                Phi, ldphi, status, st));
+    return read_status(status, st);
+}
+
+kdcd_status kdcd_lowrank_solve(int32_t problem, const kdcd_matrix *Phi, const double *y,
+                               double param, int32_t b, int32_t s, int64_t H, const int32_t *idx,
+                               double *alpha, double *z, const kdcd_options *opt,
+                               kdcd_stream stream)
+{
+    if (problem != 0 && problem != 1) return KDCD_ERR_INVALID_ARG;
+    kdcd_status rc = check_matrix(Phi);
+    if (rc != KDCD_OK) return rc;
+    if (Phi->format != KDCD_DENSE) return KDCD_ERR_UNSUPPORTED;
+    if (Phi->n > kMaxRank) return KDCD_ERR_UNSUPPORTED;
+    if (!y || !idx || !alpha || b < 1 || s < 1 || H < 1 || b > Phi->m) return KDCD_ERR_INVALID_ARG;
+    if (!finite_pos(param)) return KDCD_ERR_INVALID_ARG;
+    kdcd_options o = defaults(opt);
+    if (o.snapshot_every < 0 || (o.snapshot_every > 0 && !o.snapshots)) return KDCD_ERR_INVALID_ARG;
+    if (o.compute != KDCD_F64 || o.flags != 0 || o.monitor_every != 0 || o.workspace)
+        return KDCD_ERR_UNSUPPORTED;
+    if ((int64_t)s * b > kMaxSB) return KDCD_ERR_UNSUPPORTED;
+    const bool svm = problem == 0;
+    if (svm) {
+        if (b != 1 || (o.loss != 1 && o.loss != 2)) return KDCD_ERR_INVALID_ARG;
+    } else {
+        if (b > kMaxB) return KDCD_ERR_UNSUPPORTED;
+        const int nt = krr_recur_threads(b, s);
+        if (nt > 1024 || (b > 16 && nt > 512)) return KDCD_ERR_UNSUPPORTED;
+    }
+    const hipStream_t st = (hipStream_t)stream;
+    const int64_t m = Phi->m;
+    const int32_t r = (int32_t)Phi->n;
+    const int64_t sbmax = (int64_t)s * b;
+    size_t off = 0;
+    const size_t o_status = off; off += 256;
+    const size_t o_v = off; off += align256(sizeof(double) * (size_t)sbmax);
+    const size_t o_r = off; off += align256(sizeof(double) * (size_t)sbmax);
+    const size_t o_W = off; off += align256(sizeof(double) * (size_t)(sbmax * sbmax));
+    const size_t o_D = off; off += svm ? 0 : align256(sizeof(double) * (size_t)(sbmax * b));
+    const size_t o_th = off; off += align256(sizeof(double) * (size_t)sbmax);
+    const size_t o_z = off; off += align256(sizeof(double) * (size_t)r);
+    const size_t o_zp = off; off += align256(sizeof(double) * (size_t)lowrank_zinit_chunks() * r);
+    Layout L0{};
+    L0.total = off;
+    Workspace ws;
+    if ((rc = acquire(ws, L0, nullptr, st)) != KDCD_OK) return rc;
+    int32_t *status = ws.at<int32_t>(o_status);
+    double *v = ws.at<double>(o_v), *rr = ws.at<double>(o_r), *W = ws.at<double>(o_W);
+    double *Dinv = svm ? nullptr : ws.at<double>(o_D);
+    double *zz = z ? z : ws.at<double>(o_z);
+    const double nu = svm ? (o.loss == 2 ? INFINITY : param) : 0.0;
+    const double omega = (svm && o.loss == 2) ? 1.0 / (2.0 * param) : 0.0;
+    const double *coef = svm ? y : nullptr;
+
+    StageTimer timer;
+    timer.on = o.profile != nullptr;
+    KDCD_HIP_TRY(launch_fill_i32(status, 0, 1, st));
+    KDCD_HIP_TRY(launch_validate(idx, H * b, m, y, alpha, m, problem, nu, status, st));
+    KDCD_HIP_TRY(launch_lowrank_z_init(Phi->values, Phi->ld, m, r, alpha, coef,
+                                       ws.at<double>(o_zp), zz, st));
+    const int64_t n_outer = (H + s - 1) / s;
+    int64_t snap = 0;
+    for (int64_t k = 0; k < n_outer; ++k) {
+        const int64_t done = k * s;
+        const int32_t sk = (int32_t)std::min<int64_t>(s, H - done);
+        const int32_t sb = sk * b;
+        const int32_t *S = idx + done * b;
+        timer.begin(0, st);
+        KDCD_HIP_TRY(launch_lowrank_block(Phi->values, Phi->ld, m, r, S, sb, zz, W, v, st));
+        timer.end(0, st);
+        timer.begin(1, st);
+        FinishDesc fd{};
+        fd.nprob = 1;
+        fd.nkrr = svm ? 0 : 1;
+        fd.groups = 1;
+        fd.partial[0] = v;
+        fd.r[0] = rr;
+        fd.W[0] = W;
+        fd.Dinv[0] = Dinv;
+        fd.inv_lambda[0] = svm ? 0.0 : 1.0 / param;
+        KDCD_HIP_TRY(launch_finish(fd, sb, b, sk, (double)m, status, st));
+        timer.end(1, st);
+        timer.begin(2, st);
+        double *th = o.trace ? o.trace + done * b : ws.at<double>(o_th);
+        if (svm) {
+            KsvmRecurDesc kd{};
+            kd.r[0] = rr;
+            kd.W[0] = W;
+            kd.y[0] = y;
+            kd.alpha[0] = alpha;
+            kd.trace[0] = th;
+            kd.nu[0] = nu;
+            kd.omega[0] = omega;
+            KDCD_HIP_TRY(launch_ksvm_recur(kd, 1, S, sb, m, status, st));
+        } else {
+            KrrRecurDesc rd{};
+            rd.r[0] = rr;
+            rd.W[0] = W;
+            rd.Dinv[0] = Dinv;
+            rd.y[0] = y;
+            rd.alpha[0] = alpha;
+            rd.trace[0] = th;
+            rd.lambda[0] = param;
+            KDCD_HIP_TRY(launch_krr_recur(rd, 1, S, b, sk, m, (double)m, status, st));
+        }
+        KDCD_HIP_TRY(launch_lowrank_z_update(Phi->values, Phi->ld, m, r, S, sb, th, coef, zz, st));
+        timer.end(2, st);
+        if (o.snapshot_every > 0 && ((k + 1) % o.snapshot_every == 0 || k + 1 == n_outer)) {
+            KDCD_HIP_TRY(hipMemcpyAsync(o.snapshots + snap * m, alpha, sizeof(double) * (size_t)m,
+                                        hipMemcpyDeviceToDevice, st));
+            ++snap;
+        }
+    }
+    rc = read_status(status, st);
+    timer.report(o.profile);
+    return rc;
 }
 
 size_t kdcd_workspace_bytes(int32_t problem, const kdcd_matrix *A, const kdcd_kernel *kernel,

@@ -73,6 +73,15 @@ def krr_indices(m: int, b: int, H: int, seed: int = 0) -> np.ndarray:
     return out.reshape(-1).astype(np.int32)
 
 
+def landmarks(m: int, r: int, seed: int = 0) -> np.ndarray:
+    """r distinct rows of [0, m), uniformly without replacement (Nystrom
+    landmarks), in draw order."""
+    if r > m:
+        raise ValueError("cannot draw more landmarks than rows")
+    rng = np.random.default_rng(seed)
+    return rng.choice(m, size=r, replace=False).astype(np.int32)
+
+
 def dense_ksvm_c1(m: int = 2000, n: int = 64, flip: float = 0.05, seed: int = 101) -> dict:
     """C1: A ~ N(0,1); y = sign(A w), w ~ N(0, I); `flip` of the labels flipped."""
     rng = np.random.default_rng(seed)

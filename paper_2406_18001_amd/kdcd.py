@@ -159,6 +159,12 @@ _lib.kdcd_krr_eval.argtypes = [_P, _P, _P, ctypes.c_double, _P, _P, _P]
 _lib.kdcd_workspace_bytes.restype = ctypes.c_size_t
 _lib.kdcd_workspace_bytes.argtypes = [ctypes.c_int32, _P, _P, ctypes.c_int32, ctypes.c_int32,
                                       ctypes.c_int32]
+_lib.kdcd_nystrom_features.restype = ctypes.c_int
+_lib.kdcd_nystrom_features.argtypes = [_P, _P, _P, ctypes.c_int32, ctypes.c_double, _P, _P,
+                                       ctypes.c_int64, _P]
+_lib.kdcd_lowrank_solve.restype = ctypes.c_int
+_lib.kdcd_lowrank_solve.argtypes = [ctypes.c_int32, _P, _P, ctypes.c_double, ctypes.c_int32,
+                                    ctypes.c_int32, ctypes.c_int64, _P, _P, _P, _P, _P]
 _lib.kdcd_status_string.restype = ctypes.c_char_p
 _lib.kdcd_status_string.argtypes = [ctypes.c_int]
 _lib.kdcd_version.restype = ctypes.c_char_p
@@ -304,6 +310,49 @@ def kdcd_krr_solve(A, y, kernel, lam, b, s, H, idx, alpha, *, compute="f64", sna
     return _solve(_lib.kdcd_krr_solve, "kdcd_krr_solve", A, y, kernel, lam, b, s, H, idx, alpha,
                   compute, 1, snapshot_every, snapshots, trace, workspace, profile, flags, stream,
                   monitor_every, tol)
+
+
+def kdcd_nystrom_features(A, kernel, L, jitter, Phi, X=None, stream=None):
+    """Nystrom factor of K from the landmark rows L of A into Phi (rows of X,
+    or of A when X is None): Phi Phi'^T = K(X, A_L) (K_LL + jitter I)^{-1} K(A_L, X')."""
+    mat, m, n = _matrix(A)
+    r = int(L.numel())
+    _dev(L, torch.int32, r, "L")
+    xm = None
+    rows = m
+    if X is not None:
+        xm, rows, _ = _matrix(X)
+    if Phi.dim() != 2 or Phi.shape[0] < rows or Phi.stride(1) != 1 or Phi.shape[1] < r:
+        raise ValueError("Phi must be a row-major (rows x >= r) float64 GPU tensor")
+    if Phi.device.type != "cuda" or Phi.dtype != torch.float64:
+        raise TypeError("Phi must be a float64 GPU tensor")
+    kern = _kernel(kernel)
+    st = _lib.kdcd_nystrom_features(ctypes.byref(mat), ctypes.byref(kern), L.data_ptr(), r,
+                                    float(jitter), ctypes.byref(xm) if xm is not None else None,
+                                    Phi.data_ptr(), Phi.stride(0), _stream(stream))
+    if st != 0:
+        raise KdcdError(st, "kdcd_nystrom_features")
+
+
+def kdcd_lowrank_solve(problem, Phi, y, param, b, s, H, idx, alpha, *, z=None, loss=1,
+                       snapshot_every=0, snapshots=None, trace=None, profile=False, stream=None):
+    """Algorithm 2 ("ksvm") or 4 ("krr") with K replaced by Phi Phi^T; alpha
+    is updated in place, z (r doubles, optional) receives Phi^T beta."""
+    pid = {"ksvm": 0, "krr": 1}[problem] if isinstance(problem, str) else int(problem)
+    mat, m, r = _matrix(Phi)
+    _dev(y, torch.float64, m, "y")
+    _dev(alpha, torch.float64, m, "alpha")
+    _dev(idx, torch.int32, int(H) * int(b), "idx")
+    zp = _dev(z, torch.float64, r, "z") if z is not None else None
+    n_outer = -(-int(H) // max(int(s), 1))
+    opt, prof = _options("f64", loss, snapshot_every, snapshots, trace, None, profile, 0, m,
+                         n_outer, int(H) * int(b))
+    st = _lib.kdcd_lowrank_solve(pid, ctypes.byref(mat), y.data_ptr(), float(param), int(b),
+                                 int(s), int(H), idx.data_ptr(), alpha.data_ptr(), zp,
+                                 ctypes.byref(opt), _stream(stream))
+    if st != 0:
+        raise KdcdError(st, "kdcd_lowrank_solve")
+    return _result(prof, None)
 
 
 class BatchProblem(NamedTuple):

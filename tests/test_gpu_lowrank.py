@@ -1,0 +1,185 @@
+"""Low-rank (Nystrom) kernel blocks against the FP64 oracle.
+
+The factor Phi = K(X, A_L) C^{-T}, C C^T = K(A_L, A_L) + jitter I, is
+compared element by element with the oracle's Cholesky and triangular solve
+(both are backward-stable, so the difference is a few ulps times cond(C));
+the solve on Phi is compared with the oracle's Algorithm 2 / 4 on the matrix
+Phi with the linear kernel (the same problem), at the FP64 parity bound, and
+with the library's own full solve on Phi (same arithmetic up to the order of
+the sums).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2406_18001_amd import inputs
+from tests.helpers import assert_parity, dev, idx_dev
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-9
+
+
+@pytest.fixture(scope="module")
+def K():
+    from paper_2406_18001_amd import kdcd
+    return kdcd
+
+
+def rbf_data(m, n, seed):
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((m, n)) / np.sqrt(n)
+    y = np.sin(A @ rng.standard_normal(n)) + 0.01 * rng.standard_normal(m)
+    return A, y
+
+
+def features(K, A, kern, L, jitter, X=None):
+    rows = (X if X is not None else A).shape[0]
+    Phi = torch.empty(rows, L.size, dtype=torch.float64, device="cuda")
+    K.kdcd_nystrom_features(dev(A), kern, idx_dev(L), jitter, Phi,
+                            X=dev(X) if X is not None else None)
+    return Phi
+
+
+@pytest.mark.parametrize("m,n,r", [(700, 37, 1), (700, 37, 64), (700, 37, 100), (1000, 64, 333),
+                                   (300, 20, 300)])
+@pytest.mark.parametrize("kk", [(2, 1.0, 0.0, 1), (1, 0.0, 1.0, 3)])
+def test_nystrom_features_match_oracle(K, m, n, r, kk):
+    A, _ = rbf_data(m, n, seed=m + r)
+    L = inputs.landmarks(m, r, seed=r)
+    jitter = 1e-6
+    Phi = features(K, A, kk, L, jitter).cpu().numpy()
+    ok = O.Kernel(kk[0], degree=kk[3], sigma=kk[1], c=kk[2])
+    ref = O.nystrom_features(A, ok, L, jitter)
+    assert_parity(Phi, ref, 1e-9, "Phi")
+    assert_parity(Phi @ Phi.T, ref @ ref.T, 1e-10, "Phi Phi^T")
+
+
+def test_nystrom_features_of_new_rows(K):
+    A, _ = rbf_data(900, 48, seed=5)
+    X, _ = rbf_data(257, 48, seed=6)
+    L = inputs.landmarks(900, 150, seed=2)
+    kk = (2, 0.7, 0.0, 1)
+    Phi = features(K, A, kk, L, 1e-8, X=X).cpu().numpy()
+    ok = O.Kernel(O.RBF, sigma=0.7)
+    KLL = O.kernel_block(A, ok, L, L) + 1e-8 * np.eye(150)
+    C = np.linalg.cholesky(KLL)
+    ref = np.linalg.solve(C, O.kernel_block(np.vstack([X, A]), ok, np.arange(257),
+                                            257 + L).T).T
+    assert_parity(Phi, ref, 1e-9, "Phi(X)")
+
+
+def test_nystrom_all_rows_reproduces_kernel(K):
+    """Every row a landmark: Phi Phi^T = K (K + jI)^{-1} K, which is K up to O(jitter)."""
+    A, _ = rbf_data(256, 16, seed=1)
+    L = inputs.landmarks(256, 256, seed=3)
+    Phi = features(K, A, (2, 1.0, 0.0, 1), L, 1e-10).cpu().numpy()
+    Kf = O.kernel_matrix(A, O.Kernel(O.RBF, sigma=1.0))
+    assert np.abs(Phi @ Phi.T - Kf).max() < 1e-6
+
+
+@pytest.mark.parametrize("b,s,H", [(4, 16, 75), (8, 64, 40), (1, 32, 130), (16, 8, 21)])
+def test_lowrank_krr_matches_oracle_and_full_solve(K, b, s, H):
+    m, n, r = 1200, 40, 200
+    A, y = rbf_data(m, n, seed=11)
+    L = inputs.landmarks(m, r, seed=4)
+    Phi_t = features(K, A, (2, 1.0, 0.0, 1), L, 1e-6)
+    ok = O.Kernel(O.RBF, sigma=1.0)
+    Phi_h = O.nystrom_features(A, ok, L, 1e-6)
+    idx_h = inputs.krr_indices(m, b, H, seed=b * s)
+    idx = idx_dev(idx_h)
+    lam = 1e-3
+    alpha = torch.zeros(m, dtype=torch.float64, device="cuda")
+    z = torch.zeros(r, dtype=torch.float64, device="cuda")
+    tr = torch.zeros(H * b, dtype=torch.float64, device="cuda")
+    K.kdcd_lowrank_solve("krr", Phi_t, dev(y), lam, b, s, H, idx, alpha, z=z, trace=tr)
+    ref, ref_tr = O.bdcd_krr(Phi_h, y, O.Kernel(O.LINEAR), lam, b, H, idx_h, s=s)
+    assert_parity(alpha.cpu().numpy(), ref, TOL, "alpha vs oracle")
+    assert_parity(tr.cpu().numpy(), ref_tr, TOL, "trace vs oracle")
+    a_full = torch.zeros(m, dtype=torch.float64, device="cuda")
+    K.kdcd_krr_solve(Phi_t, dev(y), (0, 0.0, 0.0, 1), lam, b, s, H, idx, a_full)
+    assert_parity(alpha.cpu().numpy(), a_full.cpu().numpy(), 1e-11, "alpha vs full solve")
+    assert_parity(z.cpu().numpy(), Phi_h.T @ alpha.cpu().numpy(), 1e-11, "z = Phi^T alpha")
+
+
+@pytest.mark.parametrize("loss", [1, 2])
+@pytest.mark.parametrize("s,H", [(1, 300), (64, 1000), (256, 777)])
+def test_lowrank_ksvm_matches_oracle_and_full_solve(K, loss, s, H):
+    m, n, r = 1500, 24, 128
+    rng = np.random.default_rng(7)
+    A = rng.standard_normal((m, n))
+    y = np.sign(A @ rng.standard_normal(n))
+    y[y == 0] = 1.0
+    y[rng.random(m) < 0.05] *= -1
+    L = inputs.landmarks(m, r, seed=9)
+    kk = (2, 0.05, 0.0, 1)
+    Phi_t = features(K, A, kk, L, 1e-7)
+    Phi_h = O.nystrom_features(A, O.Kernel(O.RBF, sigma=0.05), L, 1e-7)
+    idx_h = inputs.ksvm_indices(m, H, seed=s)
+    idx = idx_dev(idx_h)
+    C = 1.0
+    alpha = torch.zeros(m, dtype=torch.float64, device="cuda")
+    z = torch.zeros(r, dtype=torch.float64, device="cuda")
+    th = torch.zeros(H, dtype=torch.float64, device="cuda")
+    K.kdcd_lowrank_solve("ksvm", Phi_t, dev(y), C, 1, s, H, idx, alpha, z=z, loss=loss, trace=th)
+    ref, ref_th = O.dcd_ksvm(Phi_h, y, O.Kernel(O.LINEAR), C, H, idx_h, loss=loss, s=s)
+    assert_parity(alpha.cpu().numpy(), ref, TOL, "alpha vs oracle")
+    assert_parity(th.cpu().numpy(), ref_th, TOL, "theta vs oracle")
+    a_full = torch.zeros(m, dtype=torch.float64, device="cuda")
+    K.kdcd_ksvm_solve(Phi_t, dev(y), (0, 0.0, 0.0, 1), C, 1, s, H, idx, a_full, loss=loss)
+    assert_parity(alpha.cpu().numpy(), a_full.cpu().numpy(), 1e-11, "alpha vs full solve")
+    assert_parity(z.cpu().numpy(), Phi_h.T @ (y * alpha.cpu().numpy()), 1e-11, "z")
+
+
+def test_lowrank_warm_start_and_snapshots(K):
+    m, r, b, s, H = 800, 96, 8, 8, 50
+    A, y = rbf_data(m, 30, seed=3)
+    L = inputs.landmarks(m, r, seed=1)
+    Phi_t = features(K, A, (2, 1.0, 0.0, 1), L, 1e-6)
+    idx = idx_dev(inputs.krr_indices(m, b, H, seed=2))
+    a0 = np.random.default_rng(0).uniform(0, 0.01, m)
+    alpha = dev(a0)
+    n_outer = -(-H // s)
+    snaps = torch.zeros(-(-n_outer // 2) * m, dtype=torch.float64, device="cuda")
+    K.kdcd_lowrank_solve("krr", Phi_t, dev(y), 1e-2, b, s, H, idx, alpha, snapshot_every=2,
+                         snapshots=snaps)
+    full = dev(a0)
+    fs = torch.zeros_like(snaps)
+    K.kdcd_krr_solve(Phi_t, dev(y), (0, 0.0, 0.0, 1), 1e-2, b, s, H, idx, full, snapshot_every=2,
+                     snapshots=fs)
+    assert_parity(alpha.cpu().numpy(), full.cpu().numpy(), 1e-11, "alpha")
+    assert_parity(snaps.cpu().numpy(), fs.cpu().numpy(), 1e-11, "snapshots")
+
+
+def test_lowrank_errors(K):
+    m = 300
+    A, y = rbf_data(m, 10, seed=0)
+    kk = (2, 1.0, 0.0, 1)
+    Phi = torch.zeros(m, 32, dtype=torch.float64, device="cuda")
+    bad = inputs.landmarks(m, 32, seed=0)
+    bad[7] = m
+    with pytest.raises(K.KdcdError) as e:
+        K.kdcd_nystrom_features(dev(A), kk, idx_dev(bad), 1e-6, Phi)
+    assert e.value.status == -3
+    dup = inputs.landmarks(m, 32, seed=0)
+    dup[5] = dup[6]
+    with pytest.raises(K.KdcdError) as e:     # repeated landmark, no jitter: singular K_LL
+        K.kdcd_nystrom_features(dev(A), kk, idx_dev(dup), 0.0, Phi)
+    assert e.value.status == -5
+    K.kdcd_nystrom_features(dev(A), kk, idx_dev(dup), 1e-6, Phi)   # fine with jitter
+    assert torch.isfinite(Phi).all()
+    idx = idx_dev(inputs.krr_indices(m, 4, 10, seed=0))
+    alpha = torch.zeros(m, dtype=torch.float64, device="cuda")
+    with pytest.raises(K.KdcdError) as e:
+        K.kdcd_lowrank_solve("ksvm", Phi, dev(y), 1.0, 4, 2, 10, idx, alpha)   # b must be 1
+    assert e.value.status == -1
+    badi = idx.clone()
+    badi[3] = -1
+    with pytest.raises(K.KdcdError) as e:
+        K.kdcd_lowrank_solve("krr", Phi, dev(y), 1e-3, 4, 2, 10, badi, alpha)
+    assert e.value.status == -3
+    big = torch.zeros(m, 4097, dtype=torch.float64, device="cuda")
+    with pytest.raises(K.KdcdError) as e:
+        K.kdcd_lowrank_solve("krr", big, dev(y), 1e-3, 4, 2, 10, idx, alpha)
+    assert e.value.status == -2
