@@ -50,10 +50,11 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the built-in tile rule instead of timing the configurations")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the oracle sample")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c4-sweep", "c5s-sampler"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c4-sweep", "c5s-sampler", "c2-nystrom"],
                     help="c2: the headline line; c4-sweep: batched (lambda, sigma) sweep and "
                          "one-vs-rest K-SVMs against sequential solves; c5s-sampler: learned "
-                         "against uniform coordinate sampling")
+                         "against uniform coordinate sampling; c2-nystrom: the C2 K-RR on "
+                         "Nystrom factors of several ranks")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy 4 times (byte-counter calibration)")
     return ap.parse_args()
@@ -418,6 +419,106 @@ def bench_c5s_sampler(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_c2_nystrom(args):
+    """The C2 K-RR (20000 x 512, RBF sigma=1, lambda=1e-3, b=8) on Nystrom
+    factors of rank r from uniformly drawn landmarks: factor build time, time
+    per outer iteration of the low-rank solve at s*b = 512 and 1024, outer
+    iterations and wall time until the certified relative objective error of
+    the approximated problem drops below 1e-6, and the error of that solution
+    under the exact problem (what the approximation costs)."""
+    import torch
+
+    from paper_2406_18001_amd import inputs
+    from paper_2406_18001_amd import kdcd as K
+
+    dev = torch.device("cuda:0")
+    d = inputs.dense_krr_c2(m=M, n=N)
+    A = torch.tensor(d["A"], device=dev)
+    y = torch.tensor(d["y"], device=dev)
+    kern = K.Kernel(K.KERNEL_RBF, sigma=SIGMA)
+    jitter = 1e-8
+    every = 4
+    runs = []
+    for r in (256, 1024, 4096):
+        L = torch.tensor(inputs.landmarks(M, r, seed=1), device=dev)
+        Phi = torch.empty(M, r, dtype=torch.float64, device=dev)
+        K.kdcd_nystrom_features(A, kern, L, jitter, Phi)        # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        K.kdcd_nystrom_features(A, kern, L, jitter, Phi)
+        torch.cuda.synchronize()
+        build_s = time.perf_counter() - t0
+        log(f"nystrom r={r}: factor {build_s * 1e3:.1f} ms")
+        for s in (64, 128):
+            sb = s * B
+            n_outer_max = 2000
+            idx_long = torch.tensor(inputs.krr_indices(M, B, n_outer_max * s, seed=0), device=dev)
+            # time per outer iteration: 32 outer iterations, profiled
+            alpha = torch.zeros(M, dtype=torch.float64, device=dev)
+            I = idx_long[:32 * sb]
+            K.kdcd_lowrank_solve("krr", Phi, y, LAM, B, s, 32 * s, I, alpha)
+            reps, kb_ms, kb_n = 5, 0.0, 0
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                alpha.zero_()
+                p = K.kdcd_lowrank_solve("krr", Phi, y, LAM, B, s, 32 * s, I, alpha, profile=True)
+                kb_ms += p["kblock_ms"]
+                kb_n += p["kblock_launches"]
+            torch.cuda.synchronize()
+            per_outer_ms = (time.perf_counter() - t0) / reps / 32 * 1e3
+            gram_us = kb_ms / kb_n * 1e3
+            gram_flops = sb * (sb + 1) * r          # symmetric rank-r Gram, 2 flops per term
+            # outer iterations to 1e-6 on the approximated problem
+            alpha.zero_()
+            z = torch.zeros(r, dtype=torch.float64, device=dev)
+            hit, rel = None, None
+            for k0 in range(0, n_outer_max, every):
+                I = idx_long[k0 * sb:(k0 + every) * sb]
+                K.kdcd_lowrank_solve("krr", Phi, y, LAM, B, s, every * s, I, alpha, z=z)
+                Ma = Phi @ (Phi.t() @ alpha) / LAM + M * alpha
+                res = y - Ma
+                f = float(0.5 * alpha @ Ma - y @ alpha)
+                bound = 0.5 * float(res @ res) / M
+                rel = bound / max(abs(f) - bound, 1e-300)
+                if rel <= 1e-6:
+                    hit = k0 + every
+                    break
+            entry = {"rank": r, "s": s, "sb": sb, "factor_ms": round(build_s * 1e3, 3),
+                     "ms_per_outer_iteration": round(per_outer_ms, 4),
+                     "gram_launch_us": round(gram_us, 2),
+                     "gram_tflops": round(gram_flops / (gram_us * 1e-6) / 1e12, 3)}
+            if hit is None:
+                entry.update({"outer_iterations": None, "rel_obj_err_bound": rel})
+            else:
+                a_fin = torch.zeros(M, dtype=torch.float64, device=dev)
+                Ihit = idx_long[:hit * sb]
+                K.kdcd_lowrank_solve("krr", Phi, y, LAM, B, s, hit * s, Ihit, a_fin)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                a_fin.zero_()
+                K.kdcd_lowrank_solve("krr", Phi, y, LAM, B, s, hit * s, Ihit, a_fin)
+                torch.cuda.synchronize()
+                solve_s = time.perf_counter() - t0
+                ev = K.kdcd_krr_eval(A, y, kern, LAM, a_fin)
+                eb = 0.5 * ev["residual_norm"] ** 2 / M
+                entry.update({"outer_iterations": hit, "rel_obj_err_bound": rel,
+                              "solve_s": round(solve_s, 5),
+                              "factor_plus_solve_s": round(solve_s + build_s, 5),
+                              "exact_problem_rel_err_bound": eb / max(abs(ev["objective"]) - eb,
+                                                                      1e-300)})
+            log(f"nystrom {entry}")
+            runs.append(entry)
+        del Phi
+    out = {"metric": "time to rel obj err 1e-6 of the Nystrom-approximated K-RR; error under the "
+                     "exact problem", "unit": "s", "n_gpus": 1, "higher_is_better": False,
+           "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"C2 K-RR {M}x{N} RBF sigma={SIGMA} lambda={LAM} b={B}, "
+                                  f"Nystrom factor from uniform landmarks, jitter={jitter}"},
+           "runs": runs}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -433,6 +534,9 @@ def main():
         return
     if args.workload == "c5s-sampler":
         bench_c5s_sampler(args)
+        return
+    if args.workload == "c2-nystrom":
+        bench_c2_nystrom(args)
         return
     import torch
 

@@ -25,17 +25,18 @@ hipError_t launch_convert_lowp(const kdcd_matrix *A, int32_t compute, void *hi, 
                                int64_t ldlow, float *normlow, hipStream_t st);
 int krr_recur_threads(int32_t b, int32_t sk);
 int32_t lowrank_zinit_chunks();
+size_t lowrank_part_bytes();
 hipError_t launch_nystrom(const double *Av, int64_t lda, int64_t m, int64_t n, const int32_t *L,
                           int32_t r, const KParams &kp, double jitter, const double *normsA,
                           const double *Xv, int64_t ldx, int64_t mx, const double *normsX,
-                          bool x_is_a, double *Cw, double *Phi, int64_t ldp, int32_t *status,
-                          hipStream_t st);
+                          bool x_is_a, double *Cw, double *Dinv, double *Phi, int64_t ldp,
+                          double *part, size_t part_bytes, int32_t *status, hipStream_t st);
 hipError_t launch_lowrank_block(const double *Phi, int64_t ldp, int64_t m, int32_t r,
                                 const int32_t *S, int32_t sb, const double *z, double *W,
-                                double *v, hipStream_t st);
+                                double *v, double *part, size_t part_bytes, hipStream_t st);
 hipError_t launch_lowrank_z_update(const double *Phi, int64_t ldp, int64_t m, int32_t r,
                                    const int32_t *S, int32_t sb, const double *theta,
-                                   const double *coef, double *z, hipStream_t st);
+                                   const double *coef, double *part, double *z, hipStream_t st);
 hipError_t launch_lowrank_z_init(const double *Phi, int64_t ldp, int64_t m, int32_t r,
                                  const double *alpha, const double *coef, double *part, double *z,
                                  hipStream_t st);
@@ -1692,6 +1693,8 @@ kdcd_status kdcd_nystrom_features(const kdcd_matrix *A, const kdcd_kernel *kerne
     const size_t o_na = off; off += rbf ? align256(sizeof(double) * (size_t)A->m) : 0;
     const size_t o_nx = off; off += (rbf && X) ? align256(sizeof(double) * (size_t)Xm->m) : 0;
     const size_t o_cw = off; off += align256(sizeof(double) * (size_t)r * (size_t)r);
+    const size_t o_dinv = off; off += align256(sizeof(double) * 4096 * (size_t)((r + 63) / 64));
+    const size_t o_part = off; off += lowrank_part_bytes();
     Layout L0{};
     L0.total = off;
     Workspace ws;
@@ -1706,7 +1709,8 @@ kdcd_status kdcd_nystrom_features(const kdcd_matrix *A, const kdcd_kernel *kerne
     }
     KDCD_HIP_TRY(launch_nystrom(A->values, A->ld, A->m, A->n, L, r, to_params(kernel), jitter, na,
                                 Xm->values, Xm->ld, Xm->m, nx, X == nullptr, ws.at<double>(o_cw),
-                                Phi, ldphi, status, st));
+                                ws.at<double>(o_dinv), Phi, ldphi, ws.at<double>(o_part), lowrank_part_bytes(), status,
+                                st));
     return read_status(status, st);
 }
 
@@ -1748,6 +1752,11 @@ kdcd_status kdcd_lowrank_solve(int32_t problem, const kdcd_matrix *Phi, const do
     const size_t o_th = off; off += align256(sizeof(double) * (size_t)sbmax);
     const size_t o_z = off; off += align256(sizeof(double) * (size_t)r);
     const size_t o_zp = off; off += align256(sizeof(double) * (size_t)lowrank_zinit_chunks() * r);
+    // partial Gram tiles of a split-K product: at most 64 slices of the lower tiles
+    const int64_t gt = (sbmax + 63) / 64;
+    const size_t part_bytes =
+        std::min(lowrank_part_bytes(), sizeof(double) * 4096 * (size_t)(64 * gt * (gt + 1) / 2));
+    const size_t o_part = off; off += align256(part_bytes);
     Layout L0{};
     L0.total = off;
     Workspace ws;
@@ -1774,7 +1783,8 @@ kdcd_status kdcd_lowrank_solve(int32_t problem, const kdcd_matrix *Phi, const do
         const int32_t sb = sk * b;
         const int32_t *S = idx + done * b;
         timer.begin(0, st);
-        KDCD_HIP_TRY(launch_lowrank_block(Phi->values, Phi->ld, m, r, S, sb, zz, W, v, st));
+        KDCD_HIP_TRY(launch_lowrank_block(Phi->values, Phi->ld, m, r, S, sb, zz, W, v,
+                                          ws.at<double>(o_part), part_bytes, st));
         timer.end(0, st);
         timer.begin(1, st);
         FinishDesc fd{};
@@ -1811,7 +1821,8 @@ kdcd_status kdcd_lowrank_solve(int32_t problem, const kdcd_matrix *Phi, const do
             rd.lambda[0] = param;
             KDCD_HIP_TRY(launch_krr_recur(rd, 1, S, b, sk, m, (double)m, status, st));
         }
-        KDCD_HIP_TRY(launch_lowrank_z_update(Phi->values, Phi->ld, m, r, S, sb, th, coef, zz, st));
+        KDCD_HIP_TRY(launch_lowrank_z_update(Phi->values, Phi->ld, m, r, S, sb, th, coef,
+                                             ws.at<double>(o_zp), zz, st));
         timer.end(2, st);
         if (o.snapshot_every > 0 && ((k + 1) % o.snapshot_every == 0 || k + 1 == n_outer)) {
             KDCD_HIP_TRY(hipMemcpyAsync(o.snapshots + snap * m, alpha, sizeof(double) * (size_t)m,
