@@ -93,8 +93,12 @@ typedef struct {
  * call's stream around every launch of the named stage. */
 typedef struct {
     double kblock_ms;        /* kernel-block product + map + r partials + Gram    */
+                             /* (the product kernel alone where the Gram rows are */
+                             /* gathered from it, s*b >= 256 dense FP64)          */
     int64_t kblock_launches;
-    double finish_ms;        /* partial reduction of r, K-RR block inverses        */
+    double finish_ms;        /* partial reduction of r, K-RR block inverses, and  */
+                             /* the row-position / repeated-row kernels of the    */
+                             /* gathered Gram                                     */
     int64_t finish_launches;
     double recur_ms;         /* s-step recurrence + scatter                         */
     int64_t recur_launches;
@@ -121,9 +125,19 @@ typedef struct {
  * adds them afterwards (same result up to the order of the sums).  Two
  * cross-stream event waits per outer iteration are on its critical path.
  */
+/*
+ * KDCD_FLAG_TIME_PRODUCT (with a profile; dense FP64 kdcd_ksvm_solve /
+ * kdcd_krr_solve on the serial loop): only the kernel-block product is timed
+ * (kblock_ms, kblock_launches and total_ms from its first start to its last
+ * end; the other stages report 0).  Stage kernels record their own
+ * timestamps in their dispatch (hipExtLaunchKernelGGL), and each timed
+ * dispatch costs a few microseconds of device time, so a timed measurement
+ * of whole-solve throughput times the product only.
+ */
 enum {
     KDCD_FLAG_GRAPH = 1,
-    KDCD_FLAG_OVERLAP = 2
+    KDCD_FLAG_OVERLAP = 2,
+    KDCD_FLAG_TIME_PRODUCT = 4
 };
 
 typedef struct {

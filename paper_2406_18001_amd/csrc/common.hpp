@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <cstddef>
 #include <cstdint>
 
@@ -91,6 +92,28 @@ __device__ __forceinline__ double wave_sum_xor16_32(double v)
 
 // ------------------------------------------------------------------ host side
 
+// Kernel timing without marker packets: a profiled solve arms a start / stop
+// event pair for the calling thread, and the next kernel started through
+// KDCD_TIMED_LAUNCH records both in its own dispatch (hipExtLaunchKernelGGL);
+// unarmed launches are plain hipLaunchKernelGGL launches.
+struct ArmedEvents {
+    hipEvent_t start;
+    hipEvent_t stop;
+};
+ArmedEvents &armed_events();   // per host thread
+
+#define KDCD_TIMED_LAUNCH(kernel, grid, block, shmem, st, ...)                                 \
+    do {                                                                                        \
+        ::kdcd::ArmedEvents &ev_ = ::kdcd::armed_events();                                      \
+        if (ev_.start) {                                                                        \
+            hipEvent_t a_ = ev_.start, b_ = ev_.stop;                                           \
+            ev_.start = ev_.stop = nullptr;                                                     \
+            hipExtLaunchKernelGGL(kernel, grid, block, shmem, st, a_, b_, 0, __VA_ARGS__);      \
+        } else {                                                                                \
+            hipLaunchKernelGGL(kernel, grid, block, shmem, st, __VA_ARGS__);                    \
+        }                                                                                       \
+    } while (0)
+
 #define KDCD_HIP_TRY(expr)                                   \
     do {                                                     \
         hipError_t e_ = (expr);                              \
@@ -163,6 +186,12 @@ int tune_lookup(int32_t compute, int64_t n, int32_t sb);   // -1: no entry
 void tune_store(int32_t compute, int64_t n, int32_t sb, int id);   // id < 0 removes
 int64_t kblock_mixed_row_groups(int64_t m, int32_t sb, bool batch = false);
 hipError_t launch_kblock_f64(const KBlockArgs &a, hipStream_t st);
+// launch_kblock_f64 = pre (row positions of the gathered Gram) + main (the
+// product) + post (repeated Gram rows); pre and post do nothing outside the
+// gathered single-problem mode.
+hipError_t launch_kblock_f64_pre(const KBlockArgs &a, hipStream_t st);
+hipError_t launch_kblock_f64_main(const KBlockArgs &a, hipStream_t st);
+hipError_t launch_kblock_f64_post(const KBlockArgs &a, hipStream_t st);
 hipError_t launch_norms(const kdcd_matrix *A, double *norms, hipStream_t st);
 // Per-problem arguments of the finish pass and of the recurrences; one entry
 // per workgroup-problem (blockIdx.x), passed by value.

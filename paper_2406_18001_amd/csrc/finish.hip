@@ -203,7 +203,7 @@ hipError_t launch_finish(const FinishDesc &d, int32_t sb, int32_t b, int32_t sk,
 {
     const int per = (sb + FIN_COLS - 1) / FIN_COLS;
     const int blocks = per * d.nprob + d.nkrr * sk;
-    hipLaunchKernelGGL(finish_kernel, dim3(blocks), dim3(256), 0, st, d, sb, b, sk, mdbl, status);
+    KDCD_TIMED_LAUNCH(finish_kernel, dim3(blocks), dim3(256), 0, st, d, sb, b, sk, mdbl, status);
     return hipGetLastError();
 }
 

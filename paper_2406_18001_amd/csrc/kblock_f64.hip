@@ -471,7 +471,7 @@ hipError_t launch_cfg(const KBlockArgs &a, hipStream_t st)
     const int aligned = (A->ld % 2 == 0) && ((reinterpret_cast<uintptr_t>(A->values) & 15) == 0);
     dim3 grid((unsigned)blocks), block(64 * WM * WN);
 #define KDCD_LAUNCH(KIND)                                                                      \
-    hipLaunchKernelGGL((kblock_f64_kernel<WM, WN, TM, TN, KIND, BATCH>), grid, block, 0, st,   \
+    KDCD_TIMED_LAUNCH((kblock_f64_kernel<WM, WN, TM, TN, KIND, BATCH>), grid, block, 0, st,    \
                        A->values, A->ld, A->m, A->n, a.S, a.sb, a.norms, a.kp, a.beta,          \
                        a.beta_scale, a.partial, a.W, (int32_t)n_u, (int32_t)groups,            \
                        (int32_t)n_w, (int32_t)n_n, aligned, a.batch, BATCH ? nullptr : a.U,   \
@@ -559,7 +559,18 @@ int64_t kblock_f64_row_groups(int64_t m, int64_t n, int32_t sb, bool batch)
     return n_u < kMaxRowGroups ? n_u : kMaxRowGroups;
 }
 
-hipError_t launch_kblock_f64(const KBlockArgs &a, hipStream_t st)
+// The three parts of a single-problem launch: the row-position update of the
+// gathered-Gram mode, the product, and the copies of repeated Gram rows.
+hipError_t launch_kblock_f64_pre(const KBlockArgs &a, hipStream_t st)
+{
+    if (a.batch || !(a.W && a.pos && !a.w_only)) return hipSuccess;
+    hipLaunchKernelGGL(pos_set_kernel, dim3(1), dim3(1024), 0, st, a.pos, a.A->m, a.prevS,
+                       a.prevS ? a.prev_sb : 0, a.S, a.sb, a.posX, a.prev2S,
+                       a.prev2S ? a.prev2_sb : 0, a.stop);
+    return hipGetLastError();
+}
+
+hipError_t launch_kblock_f64_main(const KBlockArgs &a, hipStream_t st)
 {
     if (a.batch) {
         const Cfg c = pick_cfg_batch(a.sb);
@@ -567,32 +578,35 @@ hipError_t launch_kblock_f64(const KBlockArgs &a, hipStream_t st)
         if (c.bn == 32) return launch_cfg<4, 1, 2, 2, true>(a, st);
         return launch_cfg<2, 2, 2, 2, true>(a, st);
     }
-    const bool gather = a.W && a.pos && !a.w_only;
-    if (gather) {
-        hipLaunchKernelGGL(pos_set_kernel, dim3(1), dim3(1024), 0, st, a.pos, a.A->m, a.prevS,
-                           a.prevS ? a.prev_sb : 0, a.S, a.sb, a.posX, a.prev2S,
-                           a.prev2S ? a.prev2_sb : 0, a.stop);
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
     KBlockArgs b = a;
-    if (!gather) {
+    if (!(a.W && a.pos && !a.w_only)) {
         b.pos = nullptr;
         b.posX = nullptr;
     }
-    hipError_t e;
     switch (f64_config_id(a.A->n, a.sb)) {
-    case 0: e = launch_cfg<4, 1, 2, 1, false>(b, st); break;
-    case 1: e = launch_cfg<4, 1, 2, 2, false>(b, st); break;
-    case 2: e = launch_cfg<2, 2, 2, 2, false>(b, st); break;
-    case 3: e = launch_cfg<2, 2, 2, 4, false>(b, st); break;
-    case 4: e = launch_cfg<2, 4, 2, 2, false>(b, st); break;
-    default: e = launch_cfg<4, 2, 2, 2, false>(b, st); break;
+    case 0: return launch_cfg<4, 1, 2, 1, false>(b, st);
+    case 1: return launch_cfg<4, 1, 2, 2, false>(b, st);
+    case 2: return launch_cfg<2, 2, 2, 2, false>(b, st);
+    case 3: return launch_cfg<2, 2, 2, 4, false>(b, st);
+    case 4: return launch_cfg<2, 4, 2, 2, false>(b, st);
+    default: return launch_cfg<4, 2, 2, 2, false>(b, st);
     }
-    if (e != hipSuccess || !gather) return e;
+}
+
+hipError_t launch_kblock_f64_post(const KBlockArgs &a, hipStream_t st)
+{
+    if (a.batch || !(a.W && a.pos && !a.w_only)) return hipSuccess;
     hipLaunchKernelGGL(w_dup_kernel, dim3((unsigned)a.sb), dim3(256), 0, st, a.W, a.A->m, a.S, a.sb,
                        a.pos, a.stop);
     return hipGetLastError();
+}
+
+hipError_t launch_kblock_f64(const KBlockArgs &a, hipStream_t st)
+{
+    hipError_t e = launch_kblock_f64_pre(a, st);
+    if (e == hipSuccess) e = launch_kblock_f64_main(a, st);
+    if (e == hipSuccess) e = launch_kblock_f64_post(a, st);
+    return e;
 }
 
 }  // namespace kdcd

@@ -383,11 +383,11 @@ hipError_t launch_ksvm_recur(const KsvmRecurDesc &d, int32_t nprob, const int32_
                              int64_t m, int32_t *status, hipStream_t st)
 {
     if (sb <= 512)
-        hipLaunchKernelGGL((ksvm_recur_kernel<512>), dim3(nprob), dim3(512), 0, st, d, S, sb, m,
-                           status);
+        KDCD_TIMED_LAUNCH((ksvm_recur_kernel<512>), dim3(nprob), dim3(512), 0, st, d, S, sb, m,
+                          status);
     else
-        hipLaunchKernelGGL((ksvm_recur_kernel<1024>), dim3(nprob), dim3(1024), 0, st, d, S, sb, m,
-                           status);
+        KDCD_TIMED_LAUNCH((ksvm_recur_kernel<1024>), dim3(nprob), dim3(1024), 0, st, d, S, sb, m,
+                          status);
     return hipGetLastError();
 }
 
@@ -397,8 +397,8 @@ hipError_t launch_krr_recur(const KrrRecurDesc &d, int32_t nprob, const int32_t 
     const int nt = krr_recur_threads(b, sk);
     if (nt > 1024 || b > kMaxB) return hipErrorInvalidValue;
 #define KDCD_KRR(BM_, NT_, BX_)                                                                 \
-    hipLaunchKernelGGL((krr_recur_kernel<BM_, NT_, BX_>), dim3(nprob), dim3(NT_), 0, st, d, S, b, \
-                       sk, m, mdbl, status)
+    KDCD_TIMED_LAUNCH((krr_recur_kernel<BM_, NT_, BX_>), dim3(nprob), dim3(NT_), 0, st, d, S, b, \
+                      sk, m, mdbl, status)
     if (nt <= 512) {
         switch (b) {
         case 1: KDCD_KRR(1, 512, 1); break;

@@ -208,21 +208,74 @@ kdcd_status acquire(Workspace &ws, const Layout &L, const kdcd_options *opt, hip
     return KDCD_OK;
 }
 
-// Event pairs around launches of one stage.
+}  // namespace
+
+namespace kdcd {
+ArmedEvents &armed_events()
+{
+    static thread_local ArmedEvents ev{nullptr, nullptr};
+    return ev;
+}
+}  // namespace kdcd
+
+namespace {
+
+// Event pairs of the launches of one stage: recorded around the launches
+// (begin / end), or inside a kernel's own dispatch (arm).
+// Timing events are kept per host thread and device and reused by later
+// solves (a solve reads its timings before it returns); timers that are alive
+// at the same time take disjoint ranges of the pool.
+struct EventPool {
+    int device = -1;
+    size_t in_use = 0;
+    std::vector<hipEvent_t> ev;
+};
+
+EventPool &event_pool()
+{
+    static thread_local EventPool p;
+    return p;
+}
+
 struct StageTimer {
     bool on = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[3];
-    hipEvent_t first = nullptr;   // alias of the first recorded event (owned by ev)
+    hipEvent_t first = nullptr;   // alias of the first recorded event
+    bool pooled = false;
+    size_t pool_base = 0;
+    std::vector<hipEvent_t> own;  // events made outside the pool (another device)
     ~StageTimer()
     {
-        for (auto &v : ev)
-            for (auto &p : v) { (void)hipEventDestroy(p.first); (void)hipEventDestroy(p.second); }
+        if (pooled) event_pool().in_use = pool_base;
+        for (hipEvent_t e : own) (void)hipEventDestroy(e);
     }
     hipEvent_t mk()
     {
+        EventPool &p = event_pool();
+        int dev = -1;
+        if (!pooled) {
+            (void)hipGetDevice(&dev);
+            if (p.device != dev && p.in_use == 0) {
+                for (hipEvent_t e : p.ev) (void)hipEventDestroy(e);
+                p.ev.clear();
+                p.device = dev;
+            }
+            if (p.device == dev) {
+                pooled = true;
+                pool_base = p.in_use;
+            }
+        }
         hipEvent_t e = nullptr;
-        (void)hipEventCreate(&e);
-        return e;
+        if (!pooled) {
+            (void)hipEventCreate(&e);
+            own.push_back(e);
+            return e;
+        }
+        if (p.in_use == p.ev.size()) {
+            (void)hipEventCreate(&e);
+            p.ev.push_back(e);
+        }
+        return p.ev[p.in_use++];
     }
     void begin(int stage, hipStream_t st)
     {
@@ -235,6 +288,20 @@ struct StageTimer {
     {
         if (!on) return;
         (void)hipEventRecord(ev[stage].back().second, st);
+    }
+    // The next KDCD_TIMED_LAUNCH of this thread records a new pair of `stage`
+    // inside its own dispatch; disarm() after the launcher returns, so that a
+    // launcher that started nothing leaves no pair armed.
+    void arm(int stage)
+    {
+        if (!on) return;
+        ev[stage].push_back({mk(), mk()});
+        if (!first) { first = ev[stage].back().first; }
+        armed_events() = ArmedEvents{ev[stage].back().first, ev[stage].back().second};
+    }
+    void disarm()
+    {
+        if (on) armed_events() = ArmedEvents{nullptr, nullptr};
     }
     void report(kdcd_profile *p)
     {
@@ -390,6 +457,7 @@ kdcd_status enqueue_solve(const SolveArgs &sa, const Layout &L, char *wsbase, St
     double *Dinv = sa.problem == 1 ? ws.at<double>(L.Dinv) : nullptr;
 
     const bool svm = sa.problem == 0;
+    const bool product_only = (sa.opt.flags & KDCD_FLAG_TIME_PRODUCT) != 0;
     const double nu = svm ? (sa.opt.loss == 2 ? INFINITY : sa.C) : 0.0;
     const double omega = (svm && sa.opt.loss == 2) ? 1.0 / (2.0 * sa.C) : 0.0;
 
@@ -449,10 +517,20 @@ kdcd_status enqueue_solve(const SolveArgs &sa, const Layout &L, char *wsbase, St
         kb.prev_sb = kb.sb;
         kb.S = S;
         kb.sb = sb;
-        timer.begin(0, st);
-        KDCD_HIP_TRY(launch_kblock(kb, st));
-        timer.end(0, st);
-        timer.begin(1, st);
+        if (A->format == KDCD_DENSE && sa.opt.compute == KDCD_F64) {
+            // the product kernel times itself (the row-position update and
+            // the repeated-row copies of the gathered Gram are not timed)
+            KDCD_HIP_TRY(launch_kblock_f64_pre(kb, st));
+            timer.arm(0);
+            const hipError_t e = launch_kblock_f64_main(kb, st);
+            timer.disarm();
+            KDCD_HIP_TRY(e);
+            KDCD_HIP_TRY(launch_kblock_f64_post(kb, st));
+        } else {
+            timer.begin(0, st);
+            KDCD_HIP_TRY(launch_kblock(kb, st));
+            timer.end(0, st);
+        }
         FinishDesc fd{};
         fd.nprob = 1;
         fd.nkrr = svm ? 0 : 1;
@@ -463,9 +541,12 @@ kdcd_status enqueue_solve(const SolveArgs &sa, const Layout &L, char *wsbase, St
         fd.Dinv[0] = Dinv;
         fd.inv_lambda[0] = svm ? 0.0 : 1.0 / sa.lambda;
         fd.stop = stop;
-        KDCD_HIP_TRY(launch_finish(fd, sb, sa.b, sk, (double)A->m, status, st));
-        timer.end(1, st);
-        timer.begin(2, st);
+        if (!product_only) timer.arm(1);
+        {
+            const hipError_t e = launch_finish(fd, sb, sa.b, sk, (double)A->m, status, st);
+            timer.disarm();
+            KDCD_HIP_TRY(e);
+        }
         double *tr = sa.opt.trace ? sa.opt.trace + done * sa.b
                                   : (monitor ? ws.at<double>(L.mon_th) : nullptr);
         if (svm) {
@@ -478,7 +559,10 @@ kdcd_status enqueue_solve(const SolveArgs &sa, const Layout &L, char *wsbase, St
             kd.nu[0] = nu;
             kd.omega[0] = omega;
             kd.stop = stop;
-            KDCD_HIP_TRY(launch_ksvm_recur(kd, 1, S, sb, A->m, status, st));
+            if (!product_only) timer.arm(2);
+            const hipError_t e = launch_ksvm_recur(kd, 1, S, sb, A->m, status, st);
+            timer.disarm();
+            KDCD_HIP_TRY(e);
         } else {
             KrrRecurDesc rd{};
             rd.r[0] = r;
@@ -489,7 +573,11 @@ kdcd_status enqueue_solve(const SolveArgs &sa, const Layout &L, char *wsbase, St
             rd.trace[0] = tr;
             rd.lambda[0] = sa.lambda;
             rd.stop = stop;
-            KDCD_HIP_TRY(launch_krr_recur(rd, 1, S, sa.b, sk, A->m, (double)A->m, status, st));
+            if (!product_only) timer.arm(2);
+            const hipError_t e = launch_krr_recur(rd, 1, S, sa.b, sk, A->m, (double)A->m, status,
+                                                  st);
+            timer.disarm();
+            KDCD_HIP_TRY(e);
         }
         if (monitor) {
             if (svm)
@@ -505,7 +593,6 @@ kdcd_status enqueue_solve(const SolveArgs &sa, const Layout &L, char *wsbase, St
                 KDCD_HIP_TRY(poll->post((k + 1) / sa.opt.monitor_every - 1, mon, st));
             }
         }
-        timer.end(2, st);
         if (sa.opt.snapshot_every > 0 && sa.opt.snapshots &&
             ((k + 1) % sa.opt.snapshot_every == 0 || k + 1 == n_outer)) {
             KDCD_HIP_TRY(hipMemcpyAsync(sa.opt.snapshots + snap * A->m, sa.alpha,

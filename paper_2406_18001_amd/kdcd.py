@@ -31,6 +31,7 @@ DENSE, CSR_FORMAT = 0, 1
 COMPUTE = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3, "bf16x3": 4}
 FLAG_GRAPH = 1
 FLAG_OVERLAP = 2
+FLAG_TIME_PRODUCT = 4
 
 STATUS = {0: "KDCD_OK", -1: "KDCD_ERR_INVALID_ARG", -2: "KDCD_ERR_UNSUPPORTED",
           -3: "KDCD_ERR_INDEX_RANGE", -4: "KDCD_ERR_INDEX_DUPLICATE", -5: "KDCD_ERR_NOT_SPD",
@@ -621,10 +622,6 @@ def kdcd_tune_save(path):
 
 def kdcd_tune_load(path):
     _check(_lib.kdcd_tune_load(str(path).encode()), "kdcd_tune_load")
-
-
-FLAG_GRAPH = 1
-FLAG_OVERLAP = 2
 
 
 def kdcd_graph_cache_clear():
