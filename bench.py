@@ -50,11 +50,12 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the built-in tile rule instead of timing the configurations")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the oracle sample")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c4-sweep", "c5s-sampler", "c2-nystrom"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c4-sweep", "c5s-sampler", "c2-nystrom", "news20-krr"],
                     help="c2: the headline line; c4-sweep: batched (lambda, sigma) sweep and "
                          "one-vs-rest K-SVMs against sequential solves; c5s-sampler: learned "
                          "against uniform coordinate sampling; c2-nystrom: the C2 K-RR on "
-                         "Nystrom factors of several ranks")
+                         "Nystrom factors of several ranks; news20-krr: sparse K-RR with RBF "
+                         "on news20-shaped rows, s-step against s = 1")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy 4 times (byte-counter calibration)")
     return ap.parse_args()
@@ -519,6 +520,102 @@ def bench_c2_nystrom(args):
     print(json.dumps(out), flush=True)
 
 
+def csr_passes(lens, idx, b, s, lpr_of):
+    """Passes of the CSR product over A for one solve: the sampled rows of an
+    outer iteration are cut greedily into chunks of at most LPR rows and 3072
+    stored entries, and every chunk streams A once."""
+    total, H = 0, idx.size // b
+    for k0 in range(0, H, s):
+        S = idx[k0 * b:min(H, k0 + s) * b]
+        lpr = lpr_of(S.size)
+        j = 0
+        while j < S.size:
+            tot, cnt = 0, 0
+            while j < S.size and cnt < lpr and tot + lens[S[j]] <= 3072:
+                tot += lens[S[j]]
+                cnt += 1
+                j += 1
+            total += 1
+    return total
+
+
+def bench_news20_krr(args):
+    """Sparse K-RR with the RBF kernel on news20-shaped rows (the Table 4
+    workload, 19996 x 1355191, 9.2e6 stored entries): wall time per block
+    update of s-step BDCD for b in {1, 2, 4} and s in {1, 4, 16, 64}, the
+    speedup of the best s over s = 1 (Table 4 reports it on up to 4096 cores),
+    and the CSR product's rate against HBM."""
+    import numpy as np
+    import torch
+
+    from paper_2406_18001_amd import inputs
+    from paper_2406_18001_amd import kdcd as K
+
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    c = inputs.csr_news20()
+    log(f"news20-shaped matrix generated in {time.perf_counter() - t0:.1f} s, nnz {c['row_ptr'][-1]}")
+    m, n, nnz = c["m"], c["n"], int(c["row_ptr"][-1])
+    lens = np.diff(c["row_ptr"])
+    A = K.CSR(torch.as_tensor(c["row_ptr"], device=dev), torch.as_tensor(c["col_idx"], device=dev),
+              torch.as_tensor(c["val"], device=dev), m, n)
+    y = torch.as_tensor(c["y"], device=dev)
+    kern = (2, 1.0, 0.0, 1)
+    lam = 1e-3
+    avg = nnz / m
+
+    def lpr_of(sb):
+        lpr = 8 if sb <= 8 else (16 if sb <= 16 else (32 if sb <= 32 else 64))
+        while lpr > 8 and avg * lpr > 3072:
+            lpr //= 2
+        return lpr
+
+    pass_bytes = nnz * 12 + (m + 1) * 8      # col_idx + values + row pointers
+    runs = []
+    for b in (1, 2, 4):
+        H = 256 // b * 2                          # 512 coordinate updates
+        idx_h = inputs.krr_indices(m, b, H, seed=b)
+        idx = torch.as_tensor(idx_h, device=dev)
+        base = None
+        for s in (1, 4, 16, 64):
+            alpha = torch.zeros(m, dtype=torch.float64, device=dev)
+            K.kdcd_krr_solve(A, y, kern, lam, b, s, H, idx, alpha)       # warm-up
+            times, kb_ms, kb_n = [], 0.0, 0
+            for _ in range(2):
+                alpha.zero_()
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                p = K.kdcd_krr_solve(A, y, kern, lam, b, s, H, idx, alpha, profile=True)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t1)
+                kb_ms += p["kblock_ms"]
+                kb_n += p["kblock_launches"]
+            t = min(times)
+            passes = csr_passes(lens, idx_h, b, s, lpr_of)
+            kb_s = kb_ms / 2 / 1e3
+            e = {"b": b, "s": s, "block_updates": H, "solve_s": round(t, 5),
+                 "us_per_block_update": round(t / H * 1e6, 2),
+                 "passes_over_A": passes, "product_ms": round(kb_s * 1e3, 3),
+                 "product_GBps": round(passes * pass_bytes / kb_s / 1e9, 1)}
+            if s == 1:
+                base = t
+            e["speedup_vs_s1"] = round(base / t, 3)
+            log(f"news20 {e}")
+            runs.append(e)
+    best = {b: max(r["speedup_vs_s1"] for r in runs if r["b"] == b) for b in (1, 2, 4)}
+    out = {"metric": "s-step BDCD speedup over BDCD, sparse K-RR RBF (Table 4 workload)",
+           "unit": "x", "n_gpus": 1, "higher_is_better": True, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": f"news20-shaped CSR {m}x{n}, {nnz} stored entries (lognormal "
+                                  f"row lengths, mean {avg:.0f}, at most 3072), RBF sigma=1, "
+                                  f"lambda={lam}, 512 coordinate updates per solve"},
+           "best_speedup": best, "paper_table4_rbf": {"1": 1.63, "2": 1.17, "4": 1.11},
+           "roofline": {"bound": "hbm", "peak": 8000.0, "unit": "GB/s",
+                        "note": "per pass over A: 12 bytes per stored entry + row pointers"},
+           "runs": runs}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -537,6 +634,9 @@ def main():
         return
     if args.workload == "c2-nystrom":
         bench_c2_nystrom(args)
+        return
+    if args.workload == "news20-krr":
+        bench_news20_krr(args)
         return
     import torch
 

@@ -18,10 +18,13 @@
 // outer iterations.
 //
 // Rows.  A wave processes RPW rows at once, LPR = 64/RPW lanes per row, lane
-// jl <-> sampled row j0 + jl.  The lanes of a row first look up one stored
+// jl <-> sampled row j0 + jl; RPW in {1, 2, 4, 8} is picked from s*b and the
+// average row length.  The lanes of a row first look up one stored
 // entry each; the entries' (value, mask, offset) are then broadcast to the
 // row's lanes in storage order, and lane jl accumulates a * B[c][jl] whenever
 // its bit is set.  Every sum runs in a fixed order: results are deterministic.
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace kdcd {
@@ -54,14 +57,34 @@ __device__ __forceinline__ int hash_find(const int32_t *keys, int32_t c)
     }
 }
 
-__device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src)
+__device__ __forceinline__ uint64_t shfl_mask(uint64_t v, int src)
 {
     const uint32_t lo = __shfl((int)(uint32_t)v, src), hi = __shfl((int)(uint32_t)(v >> 32), src);
     return ((uint64_t)hi << 32) | lo;
 }
+__device__ __forceinline__ uint32_t shfl_mask(uint32_t v, int src)
+{
+    return (uint32_t)__shfl((int)v, src);
+}
+__device__ __forceinline__ int popc(uint64_t v) { return __popcll(v); }
+__device__ __forceinline__ int popc(uint32_t v) { return __popc(v); }
+__device__ __forceinline__ void atomic_or_mask(uint64_t *p, uint64_t v)
+{
+    atomicOr((unsigned long long *)p, (unsigned long long)v);
+}
+__device__ __forceinline__ void atomic_or_mask(uint32_t *p, uint32_t v)
+{
+    atomicOr((unsigned int *)p, (unsigned int)v);
+}
+
+// Entries a lane loads per batch of a row walk (one batch in flight while the
+// previous one is multiplied out); sized so that the kernel stays within 128
+// VGPRs (four waves per SIMD, two workgroups per CU) without spilling.
+template <int KIND, int RPW>
+constexpr int csr_nbatch() { return KIND == KDCD_KERNEL_RBF ? 2 : (RPW == 8 ? 3 : 4); }
 
 template <int RPW, int KIND>
-__global__ __launch_bounds__(CSR_NT) void kblock_csr_kernel(
+__global__ __launch_bounds__(CSR_NT) __attribute__((amdgpu_waves_per_eu(RPW > 1 ? 4 : 2))) void kblock_csr_kernel(
     const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx,
     const double *__restrict__ val, int64_t m, int64_t nnz, const int32_t *__restrict__ S,
     int32_t sb, const double *__restrict__ norms, KParams kp, const double *__restrict__ beta,
@@ -71,8 +94,11 @@ __global__ __launch_bounds__(CSR_NT) void kblock_csr_kernel(
     constexpr int LPR = 64 / RPW;                  // lanes per row = sampled rows per chunk
     constexpr int NW = CSR_NT / 64;
     constexpr int ROWS = NW * RPW;                 // rows per workgroup step
+    // one bit per sampled row of a chunk; 32-bit masks keep the panel small
+    // enough for two workgroups per CU
+    using MaskT = typename std::conditional<(LPR > 32), uint64_t, uint32_t>::type;
     __shared__ int32_t hkey[CSR_HS];
-    __shared__ uint64_t hmask[CSR_HS];
+    __shared__ MaskT hmask[CSR_HS];
     __shared__ int32_t hbase[CSR_HS];
     __shared__ double hval[CSR_VMAX];
     __shared__ int32_t rowoff[LPR + 1];            // entry offsets of the chunk's sampled rows
@@ -121,14 +147,14 @@ __global__ __launch_bounds__(CSR_NT) void kblock_csr_kernel(
                 if (old == -1 || old == c) break;
                 h = (h + 1) & (CSR_HS - 1);
             }
-            atomicOr((unsigned long long *)&hmask[h], 1ull << jj);
+            atomic_or_mask(&hmask[h], (MaskT)1 << jj);
         }
         __syncthreads();
         // 2. offsets of each column's values: exclusive scan of popcounts over the slots
         constexpr int PER = CSR_HS / CSR_NT;
         int cnt = 0;
 #pragma unroll
-        for (int q = 0; q < PER; ++q) cnt += __popcll(hmask[tid * PER + q]);
+        for (int q = 0; q < PER; ++q) cnt += popc(hmask[tid * PER + q]);
         scan[tid] = cnt;
         __syncthreads();
         for (int off = 1; off < CSR_NT; off <<= 1) {   // Hillis-Steele inclusive scan
@@ -141,7 +167,7 @@ __global__ __launch_bounds__(CSR_NT) void kblock_csr_kernel(
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             hbase[tid * PER + q] = base;
-            base += __popcll(hmask[tid * PER + q]);
+            base += popc(hmask[tid * PER + q]);
         }
         __syncthreads();
         // 3. place the values, in sampled-row order inside each column
@@ -152,8 +178,8 @@ __global__ __launch_bounds__(CSR_NT) void kblock_csr_kernel(
             const int64_t e = clampi(rp(r) + (f - rowoff[jj]), 0, nnz - 1);
             const int h = hash_find(hkey, col_idx[e]);
             if (h >= 0) {
-                const uint64_t msk = hmask[h];
-                hval[hbase[h] + __popcll(msk & ((1ull << jj) - 1))] = val[e];
+                const MaskT msk = hmask[h];
+                hval[hbase[h] + popc((MaskT)(msk & (((MaskT)1 << jj) - 1)))] = val[e];
             }
         }
         __syncthreads();
@@ -162,7 +188,7 @@ __global__ __launch_bounds__(CSR_NT) void kblock_csr_kernel(
         const bool jok = jl < nj;
         const int64_t Sj = clampi(S[j0 + (jok ? jl : 0)], 0, m - 1);
         const double nb = (KIND == KDCD_KERNEL_RBF) ? norms[Sj] : 0.0;
-        const uint64_t below = (1ull << jl) - 1;
+        const MaskT below = ((MaskT)1 << jl) - 1;
         double colsum = 0.0;
         const int64_t nsteps = is_w ? 1 : (m + ROWS - 1) / ROWS;
         for (int64_t st = is_w ? 0 : blockIdx.x; st < nsteps; st += is_w ? 1 : n_row_groups) {
@@ -178,27 +204,52 @@ __global__ __launch_bounds__(CSR_NT) void kblock_csr_kernel(
                 const int64_t other = __shfl_xor(lmax, o);
                 lmax = other > lmax ? other : lmax;
             }
-            for (int64_t e0 = 0; e0 < lmax; e0 += LPR) {
-                const int64_t e = e_beg + e0 + jl;
-                double a = 0.0;
-                uint64_t msk = 0;
-                int bs = 0;
-                if (e0 + jl < len) {
-                    const int64_t ec = clampi(e, 0, nnz - 1);
-                    const int h = hash_find(hkey, col_idx[ec]);
-                    if (h >= 0) {
-                        a = val[ec];
-                        msk = hmask[h];
-                        bs = hbase[h];
+            // entries are loaded CSR_NBATCH per lane at a time, the next batch
+            // in flight while the current one is multiplied out
+            constexpr int CSR_NBATCH = csr_nbatch<KIND, RPW>();
+            int32_t cb[CSR_NBATCH], nc[CSR_NBATCH];
+            double vb[CSR_NBATCH], nv[CSR_NBATCH];
+            auto load_batch = [&](int64_t eb, int32_t (&c)[CSR_NBATCH], double (&v)[CSR_NBATCH]) {
+#pragma unroll
+                for (int u = 0; u < CSR_NBATCH; ++u) {
+                    const int64_t off = eb + (int64_t)u * LPR + jl;
+                    const int64_t ec = clampi(e_beg + off, 0, nnz - 1);
+                    const bool ok = off < len;
+                    c[u] = ok ? col_idx[ec] : -1;
+                    v[u] = ok ? val[ec] : 0.0;
+                }
+            };
+            constexpr int64_t STEP = (int64_t)CSR_NBATCH * LPR;
+            if (lmax > 0) load_batch(0, cb, vb);
+            for (int64_t eb = 0; eb < lmax; eb += STEP) {
+                if (eb + STEP < lmax) load_batch(eb + STEP, nc, nv);
+#pragma unroll
+                for (int u = 0; u < CSR_NBATCH; ++u) {
+                    if (eb + (int64_t)u * LPR >= lmax) break;   // uniform over the wave
+                    double a = 0.0;
+                    MaskT msk = 0;
+                    int bs = 0;
+                    if (cb[u] >= 0) {
+                        const int h = hash_find(hkey, cb[u]);
+                        if (h >= 0) {
+                            a = vb[u];
+                            msk = hmask[h];
+                            bs = hbase[h];
+                        }
+                    }
+#pragma unroll 8
+                    for (int t = 0; t < LPR; ++t) {
+                        const int src = rslot * LPR + t;
+                        const double at = __shfl(a, src);
+                        const MaskT mt = shfl_mask(msk, src);
+                        const int bt = __shfl(bs, src);
+                        if ((mt >> jl) & 1) acc += at * hval[bt + popc((MaskT)(mt & below))];
                     }
                 }
-#pragma unroll 8
-                for (int t = 0; t < LPR; ++t) {
-                    const int src = rslot * LPR + t;
-                    const double at = __shfl(a, src);
-                    const uint64_t mt = shfl_u64(msk, src);
-                    const int bt = __shfl(bs, src);
-                    if ((mt >> jl) & 1ull) acc += at * hval[bt + __popcll(mt & below)];
+#pragma unroll
+                for (int u = 0; u < CSR_NBATCH; ++u) {
+                    cb[u] = nc[u];
+                    vb[u] = nv[u];
                 }
             }
             if (rok && jok) {
@@ -241,11 +292,22 @@ int64_t kblock_csr_row_groups(int64_t m, int32_t sb)
     return groups_for(m);
 }
 
+// Lanes per row (LPR = 64 / RPW): no more than the sampled rows need, and
+// few enough that a chunk of LPR average-length sampled rows fits the panel
+// (long rows: narrow chunks, several data rows per wave).
+int csr_rows_per_wave(const kdcd_matrix *A, int32_t sb)
+{
+    int lpr = sb <= 8 ? 8 : (sb <= 16 ? 16 : (sb <= 32 ? 32 : 64));
+    const double avg = A->m > 0 ? (double)A->nnz / (double)A->m : 0.0;
+    while (lpr > 8 && avg * lpr > CSR_VMAX) lpr >>= 1;
+    return 64 / lpr;
+}
+
 hipError_t launch_kblock_csr(const KBlockArgs &a, hipStream_t st)
 {
     const kdcd_matrix *A = a.A;
-    const bool narrow = a.sb <= 32;     // two rows per wave, 32 lanes per row
-    const int rows_per_wg = (CSR_NT / 64) * (narrow ? 2 : 1);
+    const int rpw = csr_rows_per_wave(A, a.sb);
+    const int rows_per_wg = (CSR_NT / 64) * rpw;
     const int64_t groups = groups_for(A->m);
     const int64_t n_w = a.W ? (a.sb + rows_per_wg - 1) / rows_per_wg : 0;
     dim3 grid((unsigned)(groups + n_w)), block(CSR_NT);
@@ -259,10 +321,11 @@ hipError_t launch_kblock_csr(const KBlockArgs &a, hipStream_t st)
     case KDCD_KERNEL_POLY: KDCD_CSR(RPW, KDCD_KERNEL_POLY); break;                            \
     default: KDCD_CSR(RPW, KDCD_KERNEL_RBF); break;                                           \
     }
-    if (narrow) {
-        KDCD_CSR_KIND(2)
-    } else {
-        KDCD_CSR_KIND(1)
+    switch (rpw) {
+    case 1: KDCD_CSR_KIND(1) break;
+    case 2: KDCD_CSR_KIND(2) break;
+    case 4: KDCD_CSR_KIND(4) break;
+    default: KDCD_CSR_KIND(8) break;
     }
 #undef KDCD_CSR_KIND
 #undef KDCD_CSR

@@ -158,6 +158,50 @@ def csr_ksvm_c3(m: int = 100000, n: int = 50000, nnz_per_row: int = 50,
             "val": vals.reshape(-1).copy(), "m": m, "n": n, "y": y}
 
 
+def csr_news20(m: int = 19996, n: int = 1355191, mean_nnz: float = 455.0,
+               sigma_len: float = 0.8, max_nnz: int = 3072, zipf_a: float = 1.1,
+               flip: float = 0.05, seed: int = 106) -> dict:
+    """Sparse rows shaped like news20.binary (19996 x 1355191, about 9.1e6
+    stored entries, Table 3): row lengths lognormal with mean `mean_nnz` and
+    log-spread `sigma_len`, clipped to [1, max_nnz]; distinct columns per row
+    drawn from a Zipf(zipf_a) law over a seeded permutation of the columns;
+    values (0.1 + U(0,1)) * log(1 + n / rank), rows L2-normalised; labels
+    sign(A w) for w ~ N(0,1) on a random 10% of the columns, `flip` of them
+    flipped (the targets of K-RR as well).  Columns sorted within each row."""
+    rng = np.random.default_rng(seed)
+    mu = np.log(mean_nnz) - 0.5 * sigma_len ** 2
+    lens = np.clip(np.rint(np.exp(rng.normal(mu, sigma_len, m))), 1, min(max_nnz, n))
+    lens = lens.astype(np.int64)
+    cdf = _zipf_cdf(n, zipf_a)
+    perm = rng.permutation(n)
+    row_ptr = np.zeros(m + 1, dtype=np.int64)
+    row_ptr[1:] = np.cumsum(lens)
+    col_idx = np.empty(row_ptr[-1], dtype=np.int32)
+    val = np.empty(row_ptr[-1], dtype=np.float64)
+    for i in range(m):
+        L = int(lens[i])
+        draws = np.empty(0, dtype=np.int64)
+        while True:
+            r = np.minimum(np.searchsorted(cdf, rng.random(2 * L + 32), side="right"), n - 1)
+            draws = np.concatenate([draws, r])
+            uniq, first = np.unique(draws, return_index=True)
+            if uniq.size >= L:
+                break
+        ranks = draws[np.sort(first)[:L]]          # the first L distinct ranks, in draw order
+        c = perm[ranks]
+        order = np.argsort(c)
+        v = (0.1 + rng.random(L)) * np.log1p(n / (ranks + 1.0))
+        v = v[order]
+        col_idx[row_ptr[i]:row_ptr[i + 1]] = c[order]
+        val[row_ptr[i]:row_ptr[i + 1]] = v / np.sqrt(np.dot(v, v))
+    w = np.zeros(n)
+    support = rng.choice(n, size=max(1, n // 10), replace=False)
+    w[support] = rng.standard_normal(support.size)
+    margin = np.add.reduceat(val * w[col_idx], row_ptr[:-1])
+    y = flip_labels(sign_pm1(margin), flip, rng)
+    return {"row_ptr": row_ptr, "col_idx": col_idx, "val": val, "m": m, "n": n, "y": y}
+
+
 def csr_to_dense(row_ptr: np.ndarray, col_idx: np.ndarray, val: np.ndarray,
                  m: int, n: int) -> np.ndarray:
     """Densify a CSR matrix (small cases only)."""

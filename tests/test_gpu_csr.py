@@ -42,7 +42,7 @@ def c3_small():
     return inputs.csr_ksvm_c3(m=3000, n=2000, nnz_per_row=20, seed=31)
 
 
-@pytest.mark.parametrize("sb", [1, 7, 32, 33, 64, 100])
+@pytest.mark.parametrize("sb", [1, 7, 12, 16, 32, 33, 64, 100])
 @pytest.mark.parametrize("kk", [POLY13, (2, 0.7, 0.0, 1), (0, 0.0, 0.0, 1)])
 def test_csr_kernel_rhs_and_gram(K, c3_small, sb, kk):
     c = c3_small
