@@ -34,6 +34,7 @@ constexpr int CSR_NT = 512;           // threads per workgroup (8 waves)
 constexpr int CSR_VMAX = 3072;        // stored entries of one chunk of sampled rows
 constexpr int CSR_HS = 4096;          // hash slots (power of two, > CSR_VMAX)
 constexpr int CSR_MAXGROUPS = 512;    // row groups of the U-part
+constexpr double kCsrWaveMinAvg = 128.0;   // average row length from which rows get a wave each
 
 __device__ __forceinline__ int64_t clampi(int64_t v, int64_t lo, int64_t hi)
 {
@@ -83,6 +84,92 @@ __device__ __forceinline__ void atomic_or_mask(uint32_t *p, uint32_t v)
 template <int KIND, int RPW>
 constexpr int csr_nbatch() { return KIND == KDCD_KERNEL_RBF ? 2 : (RPW == 8 ? 3 : 4); }
 
+// The sampled-row panel of the chunk starting at j0: at most LPR sampled rows
+// whose stored entries fit CSR_VMAX, hashed by column in LDS (slot: column,
+// bit mask of the chunk's rows that store it, offset of their values), the
+// values of one column stored in sampled-row order.  Returns the end j1 of
+// the chunk, or -1 (status UNSUPPORTED) when one sampled row alone exceeds the
+// panel.  Called by every thread of the workgroup; ends with a barrier.
+template <class MaskT, int LPR>
+__device__ int build_panel(int j0, const int64_t *__restrict__ row_ptr,
+                           const int32_t *__restrict__ col_idx, const double *__restrict__ val,
+                           int64_t m, int64_t nnz, const int32_t *__restrict__ S, int32_t sb,
+                           int32_t *hkey, MaskT *hmask, int32_t *hbase, double *hval,
+                           int32_t *rowoff, int32_t *scan, int32_t *status)
+{
+    const int tid = threadIdx.x;
+    auto rp = [&](int64_t r) { return clampi(row_ptr[clampi(r, 0, m)], 0, nnz); };
+    int j1 = j0, tot = 0;
+    if (tid == 0) rowoff[0] = 0;
+    while (j1 < sb && j1 - j0 < LPR) {
+        const int64_t r = clampi(S[j1], 0, m - 1);
+        const int len = (int)(rp(r + 1) - rp(r));
+        if (tot + len > CSR_VMAX) break;
+        tot += len;
+        ++j1;
+        if (tid == 0) rowoff[j1 - j0] = tot;
+    }
+    if (j1 == j0) {                       // one sampled row alone exceeds the panel
+        if (tid == 0) set_status(status, KDCD_ERR_UNSUPPORTED);
+        return -1;
+    }
+    for (int x = tid; x < CSR_HS; x += CSR_NT) {
+        hkey[x] = -1;
+        hmask[x] = 0;
+    }
+    __syncthreads();
+    // 1. insert every stored entry's column, mark which sampled row holds it
+    for (int f = tid; f < tot; f += CSR_NT) {
+        int jj = 0;
+        while (rowoff[jj + 1] <= f) ++jj;
+        const int64_t r = clampi(S[j0 + jj], 0, m - 1);
+        const int64_t e = clampi(rp(r) + (f - rowoff[jj]), 0, nnz - 1);
+        const int32_t c = col_idx[e];
+        uint32_t h = hash_col(c);
+        for (;;) {
+            const int32_t old = atomicCAS(&hkey[h], -1, c);
+            if (old == -1 || old == c) break;
+            h = (h + 1) & (CSR_HS - 1);
+        }
+        atomic_or_mask(&hmask[h], (MaskT)1 << jj);
+    }
+    __syncthreads();
+    // 2. offsets of each column's values: exclusive scan of popcounts over the slots
+    constexpr int PER = CSR_HS / CSR_NT;
+    int cnt = 0;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) cnt += popc(hmask[tid * PER + q]);
+    scan[tid] = cnt;
+    __syncthreads();
+    for (int off = 1; off < CSR_NT; off <<= 1) {   // Hillis-Steele inclusive scan
+        const int v = tid >= off ? scan[tid - off] : 0;
+        __syncthreads();
+        scan[tid] += v;
+        __syncthreads();
+    }
+    int base = scan[tid] - cnt;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        hbase[tid * PER + q] = base;
+        base += popc(hmask[tid * PER + q]);
+    }
+    __syncthreads();
+    // 3. place the values, in sampled-row order inside each column
+    for (int f = tid; f < tot; f += CSR_NT) {
+        int jj = 0;
+        while (rowoff[jj + 1] <= f) ++jj;
+        const int64_t r = clampi(S[j0 + jj], 0, m - 1);
+        const int64_t e = clampi(rp(r) + (f - rowoff[jj]), 0, nnz - 1);
+        const int h = hash_find(hkey, col_idx[e]);
+        if (h >= 0) {
+            const MaskT msk = hmask[h];
+            hval[hbase[h] + popc((MaskT)(msk & (((MaskT)1 << jj) - 1)))] = val[e];
+        }
+    }
+    __syncthreads();
+    return j1;
+}
+
 template <int RPW, int KIND>
 __global__ __launch_bounds__(CSR_NT) __attribute__((amdgpu_waves_per_eu(RPW > 1 ? 4 : 2))) void kblock_csr_kernel(
     const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx,
@@ -113,76 +200,10 @@ __global__ __launch_bounds__(CSR_NT) __attribute__((amdgpu_waves_per_eu(RPW > 1 
     auto rp = [&](int64_t r) { return clampi(row_ptr[clampi(r, 0, m)], 0, nnz); };
 
     for (int j0 = 0; j0 < sb;) {
-        // chunk [j0, j1): at most LPR sampled rows whose stored entries fit CSR_VMAX
-        int j1 = j0, tot = 0;
-        if (tid == 0) rowoff[0] = 0;
-        while (j1 < sb && j1 - j0 < LPR) {
-            const int64_t r = clampi(S[j1], 0, m - 1);
-            const int len = (int)(rp(r + 1) - rp(r));
-            if (tot + len > CSR_VMAX) break;
-            tot += len;
-            ++j1;
-            if (tid == 0) rowoff[j1 - j0] = tot;
-        }
-        if (j1 == j0) {                       // one sampled row alone exceeds the panel
-            if (tid == 0) set_status(status, KDCD_ERR_UNSUPPORTED);
-            return;
-        }
+        const int j1 = build_panel<MaskT, LPR>(j0, row_ptr, col_idx, val, m, nnz, S, sb, hkey, hmask,
+                                                hbase, hval, rowoff, scan, status);
+        if (j1 < 0) return;
         const int nj = j1 - j0;
-        for (int x = tid; x < CSR_HS; x += CSR_NT) {
-            hkey[x] = -1;
-            hmask[x] = 0ull;
-        }
-        __syncthreads();
-        // 1. insert every stored entry's column, mark which sampled row holds it
-        for (int f = tid; f < tot; f += CSR_NT) {
-            int jj = 0;
-            while (rowoff[jj + 1] <= f) ++jj;
-            const int64_t r = clampi(S[j0 + jj], 0, m - 1);
-            const int64_t e = clampi(rp(r) + (f - rowoff[jj]), 0, nnz - 1);
-            const int32_t c = col_idx[e];
-            uint32_t h = hash_col(c);
-            for (;;) {
-                const int32_t old = atomicCAS(&hkey[h], -1, c);
-                if (old == -1 || old == c) break;
-                h = (h + 1) & (CSR_HS - 1);
-            }
-            atomic_or_mask(&hmask[h], (MaskT)1 << jj);
-        }
-        __syncthreads();
-        // 2. offsets of each column's values: exclusive scan of popcounts over the slots
-        constexpr int PER = CSR_HS / CSR_NT;
-        int cnt = 0;
-#pragma unroll
-        for (int q = 0; q < PER; ++q) cnt += popc(hmask[tid * PER + q]);
-        scan[tid] = cnt;
-        __syncthreads();
-        for (int off = 1; off < CSR_NT; off <<= 1) {   // Hillis-Steele inclusive scan
-            const int v = tid >= off ? scan[tid - off] : 0;
-            __syncthreads();
-            scan[tid] += v;
-            __syncthreads();
-        }
-        int base = scan[tid] - cnt;
-#pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            hbase[tid * PER + q] = base;
-            base += popc(hmask[tid * PER + q]);
-        }
-        __syncthreads();
-        // 3. place the values, in sampled-row order inside each column
-        for (int f = tid; f < tot; f += CSR_NT) {
-            int jj = 0;
-            while (rowoff[jj + 1] <= f) ++jj;
-            const int64_t r = clampi(S[j0 + jj], 0, m - 1);
-            const int64_t e = clampi(rp(r) + (f - rowoff[jj]), 0, nnz - 1);
-            const int h = hash_find(hkey, col_idx[e]);
-            if (h >= 0) {
-                const MaskT msk = hmask[h];
-                hval[hbase[h] + popc((MaskT)(msk & (((MaskT)1 << jj) - 1)))] = val[e];
-            }
-        }
-        __syncthreads();
 
         // 4. rows: sparse row i against the panel, map, reduce or store
         const bool jok = jl < nj;
@@ -278,6 +299,127 @@ __global__ __launch_bounds__(CSR_NT) __attribute__((amdgpu_waves_per_eu(RPW > 1 
     }
 }
 
+// Long rows (chunks of at most WJ = 8 sampled rows): one wave walks one data
+// row, 64 stored entries at a time (coalesced loads), each lane keeping its
+// own partial sums for the chunk's sampled rows; the lanes' sums meet in a
+// fixed xor tree at the end of the row, so the result is deterministic.
+constexpr int WJ = 8;
+
+template <int KIND>
+__global__ __launch_bounds__(CSR_NT) __attribute__((amdgpu_waves_per_eu(4))) void kblock_csr_wave_kernel(
+    const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx,
+    const double *__restrict__ val, int64_t m, int64_t nnz, const int32_t *__restrict__ S,
+    int32_t sb, const double *__restrict__ norms, KParams kp, const double *__restrict__ beta,
+    const double *__restrict__ bscale, double *__restrict__ partial, double *__restrict__ W,
+    int32_t n_row_groups, int32_t *status)
+{
+    constexpr int NW = CSR_NT / 64;
+    constexpr int NB = KIND == KDCD_KERNEL_RBF ? 2 : 4;   // entries per lane per batch
+    using MaskT = uint32_t;
+    __shared__ int32_t hkey[CSR_HS];
+    __shared__ MaskT hmask[CSR_HS];
+    __shared__ int32_t hbase[CSR_HS];
+    __shared__ double hval[CSR_VMAX];
+    __shared__ int32_t rowoff[WJ + 1];
+    __shared__ int32_t scan[CSR_NT];
+    __shared__ double red[NW][WJ];
+
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const bool is_w = (int)blockIdx.x >= n_row_groups;
+    if (is_w && W == nullptr) return;
+    const int wblk = (int)blockIdx.x - n_row_groups;   // W-part: sampled rows [wblk*NW, +NW)
+    auto rp = [&](int64_t r) { return clampi(row_ptr[clampi(r, 0, m)], 0, nnz); };
+
+    for (int j0 = 0; j0 < sb;) {
+        const int j1 = build_panel<MaskT, WJ>(j0, row_ptr, col_idx, val, m, nnz, S, sb, hkey, hmask,
+                                              hbase, hval, rowoff, scan, status);
+        if (j1 < 0) return;
+        const int nj = j1 - j0;
+        // lane j < nj owns sampled row j0 + j for the map and the reduction
+        const bool jok = lane < nj;
+        const int64_t Sj = clampi(S[j0 + (jok ? lane : 0)], 0, m - 1);
+        const double nbj = (KIND == KDCD_KERNEL_RBF) ? norms[Sj] : 0.0;
+        double colsum = 0.0;
+        const int64_t r_first = is_w ? (int64_t)wblk * NW + wid : (int64_t)blockIdx.x * NW + wid;
+        const int64_t r_end = is_w ? min((int64_t)sb, (int64_t)(wblk + 1) * NW) : m;
+        const int64_t r_step = is_w ? NW : (int64_t)n_row_groups * NW;
+        for (int64_t rix = r_first; rix < r_end; rix += r_step) {
+            const int64_t row = is_w ? clampi(S[rix], 0, m - 1) : rix;
+            const int64_t e_beg = rp(row), len = rp(row + 1) - e_beg;
+            double acc[WJ];
+#pragma unroll
+            for (int j = 0; j < WJ; ++j) acc[j] = 0.0;
+            int32_t cb[NB], nc[NB];
+            double vb[NB], nv[NB];
+            auto load_batch = [&](int64_t eb, int32_t (&c)[NB], double (&v)[NB]) {
+#pragma unroll
+                for (int u = 0; u < NB; ++u) {
+                    const int64_t off = eb + (int64_t)u * 64 + lane;
+                    const int64_t ec = clampi(e_beg + off, 0, nnz - 1);
+                    const bool ok = off < len;
+                    c[u] = ok ? col_idx[ec] : -1;
+                    v[u] = ok ? val[ec] : 0.0;
+                }
+            };
+            constexpr int64_t STEP = (int64_t)NB * 64;
+            if (len > 0) load_batch(0, cb, vb);
+            for (int64_t eb = 0; eb < len; eb += STEP) {
+                if (eb + STEP < len) load_batch(eb + STEP, nc, nv);
+#pragma unroll
+                for (int u = 0; u < NB; ++u) {
+                    if (cb[u] >= 0) {
+                        const int h = hash_find(hkey, cb[u]);
+                        if (h >= 0) {
+                            const MaskT msk = hmask[h];
+                            const int bs = hbase[h];
+                            const double a = vb[u];
+#pragma unroll
+                            for (int j = 0; j < WJ; ++j)
+                                if ((msk >> j) & 1u)
+                                    acc[j] += a * hval[bs + popc((MaskT)(msk & ((1u << j) - 1u)))];
+                        }
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < NB; ++u) {
+                    cb[u] = nc[u];
+                    vb[u] = nv[u];
+                }
+            }
+            double mine = 0.0;
+#pragma unroll
+            for (int j = 0; j < WJ; ++j) {
+                double v = acc[j];
+#pragma unroll
+                for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+                if (lane == j) mine = v;
+            }
+            if (jok) {
+                const double na = (KIND == KDCD_KERNEL_RBF) ? norms[row] : 0.0;
+                const double kv = kernel_map<KIND>(mine, na, nbj, row == Sj, kp);
+                if (is_w) {
+                    W[rix * sb + j0 + lane] = kv;
+                } else {
+                    double bv = beta[row];
+                    if (bscale) bv *= bscale[row];
+                    colsum += bv * kv;
+                }
+            }
+        }
+        if (!is_w) {
+            if (lane < WJ) red[wid][lane] = colsum;
+            __syncthreads();
+            if (tid < nj) {
+                double t = 0.0;
+                for (int w = 0; w < NW; ++w) t += red[w][tid];
+                partial[(int64_t)blockIdx.x * sb + j0 + tid] = t;
+            }
+        }
+        __syncthreads();
+        j0 = j1;
+    }
+}
+
 int64_t groups_for(int64_t m)
 {
     const int64_t steps = (m + 15) / 16;
@@ -307,7 +449,9 @@ hipError_t launch_kblock_csr(const KBlockArgs &a, hipStream_t st)
 {
     const kdcd_matrix *A = a.A;
     const int rpw = csr_rows_per_wave(A, a.sb);
-    const int rows_per_wg = (CSR_NT / 64) * rpw;
+    // long rows: one wave per data row and per-lane sums (chunks of <= 8 rows)
+    const bool wave = rpw == 8 && (double)A->nnz >= kCsrWaveMinAvg * (double)A->m;
+    const int rows_per_wg = (CSR_NT / 64) * (wave ? 1 : rpw);
     const int64_t groups = groups_for(A->m);
     const int64_t n_w = a.W ? (a.sb + rows_per_wg - 1) / rows_per_wg : 0;
     dim3 grid((unsigned)(groups + n_w)), block(CSR_NT);
@@ -320,6 +464,26 @@ hipError_t launch_kblock_csr(const KBlockArgs &a, hipStream_t st)
     case KDCD_KERNEL_LINEAR: KDCD_CSR(RPW, KDCD_KERNEL_LINEAR); break;                        \
     case KDCD_KERNEL_POLY: KDCD_CSR(RPW, KDCD_KERNEL_POLY); break;                            \
     default: KDCD_CSR(RPW, KDCD_KERNEL_RBF); break;                                           \
+    }
+    if (wave) {
+        switch (a.kp.kind) {
+        case KDCD_KERNEL_LINEAR:
+            hipLaunchKernelGGL((kblock_csr_wave_kernel<KDCD_KERNEL_LINEAR>), grid, block, 0, st,
+                               A->row_ptr, A->col_idx, A->values, A->m, A->nnz, a.S, a.sb, a.norms,
+                               a.kp, a.beta, a.beta_scale, a.partial, a.W, (int32_t)groups, a.status);
+            break;
+        case KDCD_KERNEL_POLY:
+            hipLaunchKernelGGL((kblock_csr_wave_kernel<KDCD_KERNEL_POLY>), grid, block, 0, st,
+                               A->row_ptr, A->col_idx, A->values, A->m, A->nnz, a.S, a.sb, a.norms,
+                               a.kp, a.beta, a.beta_scale, a.partial, a.W, (int32_t)groups, a.status);
+            break;
+        default:
+            hipLaunchKernelGGL((kblock_csr_wave_kernel<KDCD_KERNEL_RBF>), grid, block, 0, st,
+                               A->row_ptr, A->col_idx, A->values, A->m, A->nnz, a.S, a.sb, a.norms,
+                               a.kp, a.beta, a.beta_scale, a.partial, a.W, (int32_t)groups, a.status);
+            break;
+        }
+        return hipGetLastError();
     }
     switch (rpw) {
     case 1: KDCD_CSR_KIND(1) break;

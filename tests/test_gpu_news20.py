@@ -52,15 +52,19 @@ def test_news20_krr_small(K, small, b, s):
     assert_parity(tr.cpu().numpy(), ref_tr, TOL, "trace")
 
 
-def test_news20_kernel_rhs_long_rows(K, small):
-    """The longest rows (several chunks of the sampled-row panel) and short
-    ones in one block."""
+@pytest.mark.parametrize("kk", [RBF1, (1, 0.0, 1.0, 3), (0, 0.0, 0.0, 1)])
+@pytest.mark.parametrize("sb", [1, 5, 8, 13, 40])
+def test_news20_kernel_rhs(K, small, kk, sb):
+    """r and W of one block for every kernel, with the longest rows (several
+    chunks of the sampled-row panel) and short ones in the block."""
     c = small
     lens = np.diff(c["row_ptr"])
-    S = np.concatenate([np.argsort(lens)[-6:], np.argsort(lens)[:10]]).astype(np.int32)
-    beta = np.random.default_rng(0).standard_normal(c["m"])
-    ok = O.Kernel(O.RBF, sigma=1.0)
-    r, W = K.kdcd_kernel_rhs(to_gpu(K, c), RBF1, idx_dev(S), dev(beta), want_W=True)
+    order = np.argsort(lens)
+    S = np.concatenate([order[-(sb // 2):] if sb > 1 else order[-1:], order[:sb - max(sb // 2, 1)]])
+    S = S.astype(np.int32)
+    beta = np.random.default_rng(sb).standard_normal(c["m"])
+    ok = O.Kernel(kk[0], sigma=kk[1], c=kk[2], degree=kk[3])
+    r, W = K.kdcd_kernel_rhs(to_gpu(K, c), kk, idx_dev(S), dev(beta), want_W=True)
     assert_parity(r.cpu().numpy(), O.kernel_rhs(as_oracle(c), ok, S, beta), 1e-11, "r")
     assert_parity(W.cpu().numpy().reshape(S.size, S.size), O.kernel_block(as_oracle(c), ok, S, S),
                   1e-12, "W")
