@@ -174,6 +174,9 @@ struct KBlockArgs {
     const int32_t *prev2S;
     int32_t prev2_sb;
     double *X;
+    // CSR only: m + s*b doubles of scratch for sampled rows longer than the
+    // LDS panel (their dot products are summed over pieces); null refuses them
+    double *carry;
 };
 
 // Launchers (return hipError_t of the launch).

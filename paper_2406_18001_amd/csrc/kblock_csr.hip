@@ -101,10 +101,12 @@ constexpr int csr_nbatch() { return KIND == KDCD_KERNEL_RBF ? 2 : (RPW == 8 ? 3 
 // whose stored entries fit CSR_VMAX, hashed by column in LDS (slot: column,
 // bit mask of the chunk's rows that store it, offset of their values), the
 // values of one column stored in sampled-row order.  Returns the end j1 of
-// the chunk, or -1 (status UNSUPPORTED) when one sampled row alone exceeds the
-// panel.  Called by every thread of the workgroup; ends with a barrier.
+// the chunk, or -2 when the sampled row j0 alone exceeds the panel; such a row
+// is then hashed in pieces of CSR_VMAX consecutive entries (piece >= 0: the
+// panel holds entries [piece * CSR_VMAX, ...) of row j0 only).  Called by
+// every thread of the workgroup; ends with a barrier.
 template <class MaskT, int LPR>
-__device__ int build_panel(int j0, const int64_t *__restrict__ row_ptr,
+__device__ int build_panel(int j0, int piece, const int64_t *__restrict__ row_ptr,
                            const int32_t *__restrict__ col_idx, const double *__restrict__ val,
                            int64_t m, int64_t nnz, const int32_t *__restrict__ S, int32_t sb,
                            int32_t *hkey, uint32_t *hfilt, MaskT *hmask, int16_t *hbase,
@@ -114,18 +116,28 @@ __device__ int build_panel(int j0, const int64_t *__restrict__ row_ptr,
     const int tid = threadIdx.x;
     auto rp = [&](int64_t r) { return clampi(row_ptr[clampi(r, 0, m)], 0, nnz); };
     int j1 = j0, tot = 0;
-    if (tid == 0) rowoff[0] = 0;
-    while (j1 < sb && j1 - j0 < LPR) {
-        const int64_t r = clampi(S[j1], 0, m - 1);
-        const int len = (int)(rp(r + 1) - rp(r));
-        if (tot + len > CSR_VMAX) break;
-        tot += len;
-        ++j1;
-        if (tid == 0) rowoff[j1 - j0] = tot;
-    }
-    if (j1 == j0) {                       // one sampled row alone exceeds the panel
-        if (tid == 0) set_status(status, KDCD_ERR_UNSUPPORTED);
-        return -1;
+    int64_t skip = 0;                     // entries of the row before this piece
+    if (piece >= 0) {
+        const int64_t r = clampi(S[j0], 0, m - 1);
+        skip = (int64_t)piece * CSR_VMAX;
+        const int64_t rest = rp(r + 1) - rp(r) - skip;
+        tot = (int)(rest < CSR_VMAX ? (rest > 0 ? rest : 0) : CSR_VMAX);
+        j1 = j0 + 1;
+        if (tid == 0) {
+            rowoff[0] = 0;
+            rowoff[1] = tot;
+        }
+    } else {
+        if (tid == 0) rowoff[0] = 0;
+        while (j1 < sb && j1 - j0 < LPR) {
+            const int64_t r = clampi(S[j1], 0, m - 1);
+            const int len = (int)(rp(r + 1) - rp(r));
+            if (tot + len > CSR_VMAX) break;
+            tot += len;
+            ++j1;
+            if (tid == 0) rowoff[j1 - j0] = tot;
+        }
+        if (j1 == j0) return -2;          // one sampled row alone exceeds the panel
     }
     for (int x = tid; x < CSR_HS; x += CSR_NT) {
         hkey[x] = -1;
@@ -138,7 +150,7 @@ __device__ int build_panel(int j0, const int64_t *__restrict__ row_ptr,
         int jj = 0;
         while (rowoff[jj + 1] <= f) ++jj;
         const int64_t r = clampi(S[j0 + jj], 0, m - 1);
-        const int64_t e = clampi(rp(r) + (f - rowoff[jj]), 0, nnz - 1);
+        const int64_t e = clampi(rp(r) + skip + (f - rowoff[jj]), 0, nnz - 1);
         const int32_t c = col_idx[e];
         uint32_t h = hash_col(c);
         for (;;) {
@@ -176,7 +188,7 @@ __device__ int build_panel(int j0, const int64_t *__restrict__ row_ptr,
         int jj = 0;
         while (rowoff[jj + 1] <= f) ++jj;
         const int64_t r = clampi(S[j0 + jj], 0, m - 1);
-        const int64_t e = clampi(rp(r) + (f - rowoff[jj]), 0, nnz - 1);
+        const int64_t e = clampi(rp(r) + skip + (f - rowoff[jj]), 0, nnz - 1);
         const int h = hash_find(hkey, hfilt, col_idx[e]);
         if (h >= 0) {
             const MaskT msk = hmask[h];
@@ -193,7 +205,7 @@ __global__ __launch_bounds__(CSR_NT) __attribute__((amdgpu_waves_per_eu(RPW > 1 
     const double *__restrict__ val, int64_t m, int64_t nnz, const int32_t *__restrict__ S,
     int32_t sb, const double *__restrict__ norms, KParams kp, const double *__restrict__ beta,
     const double *__restrict__ bscale, double *__restrict__ partial, double *__restrict__ W,
-    int32_t n_row_groups, int32_t *status)
+    int32_t n_row_groups, double *__restrict__ carry, int32_t *status)
 {
     constexpr int LPR = 64 / RPW;                  // lanes per row = sampled rows per chunk
     constexpr int NW = CSR_NT / 64;
@@ -218,9 +230,18 @@ __global__ __launch_bounds__(CSR_NT) __attribute__((amdgpu_waves_per_eu(RPW > 1 
     auto rp = [&](int64_t r) { return clampi(row_ptr[clampi(r, 0, m)], 0, nnz); };
 
     for (int j0 = 0; j0 < sb;) {
-        const int j1 = build_panel<MaskT, LPR>(j0, row_ptr, col_idx, val, m, nnz, S, sb, hkey, hfilt,
-                                                hmask, hbase, hval, rowoff, scan, status);
-        if (j1 < 0) return;
+        int j1 = build_panel<MaskT, LPR>(j0, -1, row_ptr, col_idx, val, m, nnz, S, sb, hkey, hfilt,
+                                          hmask, hbase, hval, rowoff, scan, status);
+        int npieces = 1;
+        if (j1 == -2) {                  // a sampled row longer than the panel: in pieces
+            if (!carry) {
+                if (tid == 0) set_status(status, KDCD_ERR_UNSUPPORTED);
+                return;
+            }
+            const int64_t r = clampi(S[j0], 0, m - 1);
+            npieces = (int)((rp(r + 1) - rp(r) + CSR_VMAX - 1) / CSR_VMAX);
+            j1 = j0 + 1;
+        }
         const int nj = j1 - j0;
 
         // 4. rows: sparse row i against the panel, map, reduce or store
@@ -229,6 +250,16 @@ __global__ __launch_bounds__(CSR_NT) __attribute__((amdgpu_waves_per_eu(RPW > 1 
         const double nb = (KIND == KDCD_KERNEL_RBF) ? norms[Sj] : 0.0;
         const MaskT below = ((MaskT)1 << jl) - 1;
         double colsum = 0.0;
+        for (int pc = 0; pc < npieces; ++pc) {
+        if (npieces > 1) {
+            // the dot products of a long row are summed over its pieces in
+            // carry[] (data rows of the U-part at [row], sampled rows of the
+            // Gram part at [m + t]) before the map
+            __syncthreads();             // every wave is done with the previous piece
+            build_panel<MaskT, LPR>(j0, pc, row_ptr, col_idx, val, m, nnz, S, sb, hkey, hfilt, hmask,
+                                    hbase, hval, rowoff, scan, status);
+        }
+        const bool last = pc + 1 == npieces;
         const int64_t nsteps = is_w ? 1 : (m + ROWS - 1) / ROWS;
         for (int64_t st = is_w ? 0 : blockIdx.x; st < nsteps; st += is_w ? 1 : n_row_groups) {
             const int64_t rix = (is_w ? (int64_t)wblk * ROWS : st * ROWS) + wid * RPW + rslot;
@@ -292,17 +323,25 @@ __global__ __launch_bounds__(CSR_NT) __attribute__((amdgpu_waves_per_eu(RPW > 1 
                 }
             }
             if (rok && jok) {
-                const double na = (KIND == KDCD_KERNEL_RBF) ? norms[row] : 0.0;
-                const double kv = kernel_map<KIND>(acc, na, nb, row == Sj, kp);
-                if (is_w) {
-                    W[rix * sb + j0 + jl] = kv;
-                } else {
-                    double bv = beta[row];
-                    if (bscale) bv *= bscale[row];
-                    colsum += bv * kv;
+                if (npieces > 1) {
+                    const int64_t ci = is_w ? m + rix : row;
+                    if (pc > 0) acc += carry[ci];
+                    if (!last) carry[ci] = acc;
+                }
+                if (last) {
+                    const double na = (KIND == KDCD_KERNEL_RBF) ? norms[row] : 0.0;
+                    const double kv = kernel_map<KIND>(acc, na, nb, row == Sj, kp);
+                    if (is_w) {
+                        W[rix * sb + j0 + jl] = kv;
+                    } else {
+                        double bv = beta[row];
+                        if (bscale) bv *= bscale[row];
+                        colsum += bv * kv;
+                    }
                 }
             }
         }
+        }   // pieces
         if (!is_w) {
             red[wid * RPW + rslot][jl] = colsum;
             __syncthreads();
@@ -329,7 +368,7 @@ __global__ __launch_bounds__(CSR_NT) __attribute__((amdgpu_waves_per_eu(4))) voi
     const double *__restrict__ val, int64_t m, int64_t nnz, const int32_t *__restrict__ S,
     int32_t sb, const double *__restrict__ norms, KParams kp, const double *__restrict__ beta,
     const double *__restrict__ bscale, double *__restrict__ partial, double *__restrict__ W,
-    int32_t n_row_groups, int32_t *status)
+    int32_t n_row_groups, double *__restrict__ carry, int32_t *status)
 {
     constexpr int NW = CSR_NT / 64;
     constexpr int NB = KIND == KDCD_KERNEL_RBF ? 2 : 4;   // entries per lane per batch
@@ -350,15 +389,31 @@ __global__ __launch_bounds__(CSR_NT) __attribute__((amdgpu_waves_per_eu(4))) voi
     auto rp = [&](int64_t r) { return clampi(row_ptr[clampi(r, 0, m)], 0, nnz); };
 
     for (int j0 = 0; j0 < sb;) {
-        const int j1 = build_panel<MaskT, WJ>(j0, row_ptr, col_idx, val, m, nnz, S, sb, hkey, hfilt,
-                                              hmask, hbase, hval, rowoff, scan, status);
-        if (j1 < 0) return;
+        int j1 = build_panel<MaskT, WJ>(j0, -1, row_ptr, col_idx, val, m, nnz, S, sb, hkey, hfilt,
+                                        hmask, hbase, hval, rowoff, scan, status);
+        int npieces = 1;
+        if (j1 == -2) {                  // a sampled row longer than the panel: in pieces
+            if (!carry) {
+                if (tid == 0) set_status(status, KDCD_ERR_UNSUPPORTED);
+                return;
+            }
+            const int64_t r = clampi(S[j0], 0, m - 1);
+            npieces = (int)((rp(r + 1) - rp(r) + CSR_VMAX - 1) / CSR_VMAX);
+            j1 = j0 + 1;
+        }
         const int nj = j1 - j0;
         // lane j < nj owns sampled row j0 + j for the map and the reduction
         const bool jok = lane < nj;
         const int64_t Sj = clampi(S[j0 + (jok ? lane : 0)], 0, m - 1);
         const double nbj = (KIND == KDCD_KERNEL_RBF) ? norms[Sj] : 0.0;
         double colsum = 0.0;
+        for (int pc = 0; pc < npieces; ++pc) {
+        if (npieces > 1) {               // dot products summed over the pieces in carry[]
+            __syncthreads();
+            build_panel<MaskT, WJ>(j0, pc, row_ptr, col_idx, val, m, nnz, S, sb, hkey, hfilt, hmask,
+                                   hbase, hval, rowoff, scan, status);
+        }
+        const bool last = pc + 1 == npieces;
         const int64_t r_first = is_w ? (int64_t)wblk * NW + wid : (int64_t)blockIdx.x * NW + wid;
         const int64_t r_end = is_w ? min((int64_t)sb, (int64_t)(wblk + 1) * NW) : m;
         const int64_t r_step = is_w ? NW : (int64_t)n_row_groups * NW;
@@ -414,17 +469,25 @@ __global__ __launch_bounds__(CSR_NT) __attribute__((amdgpu_waves_per_eu(4))) voi
                 if (lane == j) mine = v;
             }
             if (jok) {
-                const double na = (KIND == KDCD_KERNEL_RBF) ? norms[row] : 0.0;
-                const double kv = kernel_map<KIND>(mine, na, nbj, row == Sj, kp);
-                if (is_w) {
-                    W[rix * sb + j0 + lane] = kv;
-                } else {
-                    double bv = beta[row];
-                    if (bscale) bv *= bscale[row];
-                    colsum += bv * kv;
+                if (npieces > 1) {
+                    const int64_t ci = is_w ? m + rix : row;
+                    if (pc > 0) mine += carry[ci];
+                    if (!last) carry[ci] = mine;
+                }
+                if (last) {
+                    const double na = (KIND == KDCD_KERNEL_RBF) ? norms[row] : 0.0;
+                    const double kv = kernel_map<KIND>(mine, na, nbj, row == Sj, kp);
+                    if (is_w) {
+                        W[rix * sb + j0 + lane] = kv;
+                    } else {
+                        double bv = beta[row];
+                        if (bscale) bv *= bscale[row];
+                        colsum += bv * kv;
+                    }
                 }
             }
         }
+        }   // pieces
         if (!is_w) {
             if (lane < WJ) red[wid][lane] = colsum;
             __syncthreads();
@@ -477,7 +540,7 @@ hipError_t launch_kblock_csr(const KBlockArgs &a, hipStream_t st)
 #define KDCD_CSR(RPW, KIND)                                                                   \
     hipLaunchKernelGGL((kblock_csr_kernel<RPW, KIND>), grid, block, 0, st, A->row_ptr,         \
                        A->col_idx, A->values, A->m, A->nnz, a.S, a.sb, a.norms, a.kp, a.beta,  \
-                       a.beta_scale, a.partial, a.W, (int32_t)groups, a.status)
+                       a.beta_scale, a.partial, a.W, (int32_t)groups, a.carry, a.status)
 #define KDCD_CSR_KIND(RPW)                                                                    \
     switch (a.kp.kind) {                                                                      \
     case KDCD_KERNEL_LINEAR: KDCD_CSR(RPW, KDCD_KERNEL_LINEAR); break;                        \
@@ -489,17 +552,17 @@ hipError_t launch_kblock_csr(const KBlockArgs &a, hipStream_t st)
         case KDCD_KERNEL_LINEAR:
             hipLaunchKernelGGL((kblock_csr_wave_kernel<KDCD_KERNEL_LINEAR>), grid, block, 0, st,
                                A->row_ptr, A->col_idx, A->values, A->m, A->nnz, a.S, a.sb, a.norms,
-                               a.kp, a.beta, a.beta_scale, a.partial, a.W, (int32_t)groups, a.status);
+                               a.kp, a.beta, a.beta_scale, a.partial, a.W, (int32_t)groups, a.carry, a.status);
             break;
         case KDCD_KERNEL_POLY:
             hipLaunchKernelGGL((kblock_csr_wave_kernel<KDCD_KERNEL_POLY>), grid, block, 0, st,
                                A->row_ptr, A->col_idx, A->values, A->m, A->nnz, a.S, a.sb, a.norms,
-                               a.kp, a.beta, a.beta_scale, a.partial, a.W, (int32_t)groups, a.status);
+                               a.kp, a.beta, a.beta_scale, a.partial, a.W, (int32_t)groups, a.carry, a.status);
             break;
         default:
             hipLaunchKernelGGL((kblock_csr_wave_kernel<KDCD_KERNEL_RBF>), grid, block, 0, st,
                                A->row_ptr, A->col_idx, A->values, A->m, A->nnz, a.S, a.sb, a.norms,
-                               a.kp, a.beta, a.beta_scale, a.partial, a.W, (int32_t)groups, a.status);
+                               a.kp, a.beta, a.beta_scale, a.partial, a.W, (int32_t)groups, a.carry, a.status);
             break;
         }
         return hipGetLastError();

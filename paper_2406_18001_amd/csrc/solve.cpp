@@ -115,7 +115,7 @@ size_t lowp_elem_bytes(int32_t compute) { return compute == KDCD_F32 ? 4 : 2; }
 
 // Workspace regions of one solve.
 struct Layout {
-    size_t status, norms, partial, r, W, Dinv, iota, hi, lo, normlow, pos, total;
+    size_t status, norms, partial, r, W, Dinv, iota, hi, lo, normlow, pos, carry, total;
     int64_t ldlow;
     // lookahead (0 when off): second partial and W buffers, two cross blocks,
     // the previous-block row table
@@ -163,6 +163,8 @@ Layout make_layout(int32_t problem, const kdcd_matrix *A, const kdcd_kernel *ker
     L.Dinv = off; off += (problem == 1) ? align256(sizeof(double) * (size_t)(sb * b)) : 0;
     L.iota = off; off += (problem == 2) ? align256(sizeof(int32_t) * (size_t)A->m) : 0;
     L.pos = off; off += align256(sizeof(int32_t) * (size_t)A->m);   // row -> position in S
+    L.carry = off;   // CSR: partial dot products of sampled rows longer than the panel
+    off += (A->format == KDCD_CSR) ? align256(sizeof(double) * (size_t)(A->m + sb)) : 0;
     L.ldlow = 0;
     L.hi = L.lo = L.normlow = off;
     if (compute != KDCD_F64) {
@@ -482,6 +484,7 @@ kdcd_status enqueue_solve(const SolveArgs &sa, const Layout &L, char *wsbase, St
         base.pos = ws.at<int32_t>(L.pos);
         KDCD_HIP_TRY(launch_fill_i32(base.pos, -1, A->m, st));
     }
+    if (A->format == KDCD_CSR) base.carry = ws.at<double>(L.carry);
     KBlockArgs kb;
     rc = prepare_lowp(base, L, ws, st, kb);
     if (rc != KDCD_OK) return rc;
@@ -1611,6 +1614,7 @@ kdcd_status kdcd_kernel_rhs(const kdcd_matrix *A, const kdcd_kernel *kernel, con
         base.pos = ws.at<int32_t>(L.pos);
         KDCD_HIP_TRY(launch_fill_i32(base.pos, -1, A->m, st));
     }
+    if (A->format == KDCD_CSR) base.carry = ws.at<double>(L.carry);
     KBlockArgs kb;
     if ((rc = prepare_lowp(base, L, ws, st, kb)) != KDCD_OK) return rc;
     KDCD_HIP_TRY(launch_kblock(kb, st));
@@ -1658,6 +1662,7 @@ static kdcd_status kernel_matvec(const kdcd_matrix *A, const kdcd_kernel *kernel
         a.W = nullptr;
         a.status = status;
         a.compute = KDCD_F64;
+        if (A->format == KDCD_CSR) a.carry = ws.at<double>(L.carry);
         KDCD_HIP_TRY(launch_kblock(a, st));
         FinishDesc fd{};
         fd.nprob = 1;

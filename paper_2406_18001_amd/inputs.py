@@ -159,7 +159,7 @@ def csr_ksvm_c3(m: int = 100000, n: int = 50000, nnz_per_row: int = 50,
 
 
 def csr_news20(m: int = 19996, n: int = 1355191, mean_nnz: float = 455.0,
-               sigma_len: float = 0.8, max_nnz: int = 3072, zipf_a: float = 1.1,
+               sigma_len: float = 0.8, max_nnz: int = 16384, zipf_a: float = 1.1,
                flip: float = 0.05, seed: int = 106) -> dict:
     """Sparse rows shaped like news20.binary (19996 x 1355191, about 9.1e6
     stored entries, Table 3): row lengths lognormal with mean `mean_nnz` and

@@ -122,13 +122,28 @@ def test_csr_errors(K):
     with pytest.raises(K.KdcdError) as e:
         K.kdcd_kernel_rhs(to_gpu(K, badc), POLY13, idx_dev([0, 1]), dev(np.ones(200)))
     assert e.value.status == -1
-    # a sampled row with more stored entries than the panel holds is refused
-    m, n = 50, 5000
-    rows = [np.arange(0, 4000, dtype=np.int32)] + [np.array([i], dtype=np.int32) for i in range(1, m)]
-    row_ptr = np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int64)
-    col = np.concatenate(rows).astype(np.int32)
-    v = np.ones(col.size)
-    big = {"row_ptr": row_ptr, "col_idx": col, "val": v, "m": m, "n": n}
-    with pytest.raises(K.KdcdError) as e:
-        K.kdcd_kernel_rhs(to_gpu(K, big), POLY13, idx_dev([0, 3]), dev(np.ones(m)))
-    assert e.value.status == -2
+
+
+@pytest.mark.parametrize("kk", [POLY13, (2, 0.5, 0.0, 1)])
+def test_csr_rows_longer_than_panel(K, kk):
+    """Sampled rows with more stored entries than the LDS panel holds (3072)
+    are hashed in pieces and their dot products summed before the map: r and
+    W against the oracle, with the long rows alone and among short ones."""
+    m, n = 300, 20000
+    rng = np.random.default_rng(4)
+    lens = [4000, 7000, 3073] + list(rng.integers(1, 60, m - 3))
+    rows = [np.sort(rng.choice(n, L, replace=False)).astype(np.int32) for L in lens]
+    row_ptr = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    col = np.concatenate(rows)
+    v = rng.random(col.size)
+    for i in range(m):
+        seg = slice(row_ptr[i], row_ptr[i + 1])
+        v[seg] /= np.linalg.norm(v[seg])
+    c = {"row_ptr": row_ptr, "col_idx": col, "val": v, "m": m, "n": n}
+    ok = O.Kernel(kk[0], sigma=kk[1], c=kk[2], degree=kk[3])
+    beta = rng.standard_normal(m)
+    for S in ([0], [1, 5], [3, 0, 7, 1, 2], list(range(10, 50)) + [1]):
+        S = np.asarray(S, dtype=np.int32)
+        r, W = K.kdcd_kernel_rhs(to_gpu(K, c), kk, idx_dev(S), dev(beta), want_W=True)
+        assert_parity(r.cpu().numpy(), O.kernel_rhs(as_oracle(c), ok, S, beta), 1e-11, f"r {S[:3]}")
+        assert_parity(W.cpu().numpy(), O.kernel_block(as_oracle(c), ok, S, S), 1e-12, f"W {S[:3]}")

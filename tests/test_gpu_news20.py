@@ -80,3 +80,35 @@ def test_news20_full_size_first_outer_iterations(K):
     alpha = torch.zeros(c["m"], dtype=torch.float64, device="cuda")
     K.kdcd_krr_solve(to_gpu(K, c), dev(c["y"]), RBF1, 1e-3, b, s, H, idx_dev(idx), alpha)
     assert_parity(alpha.cpu().numpy(), ref, TOL, "alpha")
+
+
+@pytest.fixture(scope="module")
+def longrows():
+    # news20-shaped rows without the clip at the panel size: many rows longer
+    # than 3072 stored entries, summed over pieces
+    return inputs.csr_news20(m=700, n=60000, mean_nnz=1200.0, max_nnz=9000, seed=11)
+
+
+def test_news20_rows_longer_than_panel_rhs(K, longrows):
+    c = longrows
+    lens = np.diff(c["row_ptr"])
+    assert (lens > 3072).sum() >= 20
+    ok = O.Kernel(O.RBF, sigma=1.0)
+    beta = np.random.default_rng(1).standard_normal(c["m"])
+    order = np.argsort(lens)
+    for S in (order[-1:], order[-3:], np.concatenate([order[-4:], order[:6]]), order[::35]):
+        S = np.asarray(S, dtype=np.int32)
+        r, W = K.kdcd_kernel_rhs(to_gpu(K, c), RBF1, idx_dev(S), dev(beta), want_W=True)
+        assert_parity(r.cpu().numpy(), O.kernel_rhs(as_oracle(c), ok, S, beta), 1e-11, "r")
+        assert_parity(W.cpu().numpy(), O.kernel_block(as_oracle(c), ok, S, S), 1e-12, "W")
+
+
+@pytest.mark.parametrize("b,s", [(1, 8), (2, 4), (4, 1)])
+def test_news20_rows_longer_than_panel_krr(K, longrows, b, s):
+    c = longrows
+    H = 24
+    idx = inputs.krr_indices(c["m"], b, H, seed=3)
+    ref, _ = O.bdcd_krr(as_oracle(c), c["y"], O.Kernel(O.RBF, sigma=1.0), 1e-3, b, H, idx, s=s)
+    alpha = torch.zeros(c["m"], dtype=torch.float64, device="cuda")
+    K.kdcd_krr_solve(to_gpu(K, c), dev(c["y"]), RBF1, 1e-3, b, s, H, idx_dev(idx), alpha)
+    assert_parity(alpha.cpu().numpy(), ref, TOL, "alpha")
