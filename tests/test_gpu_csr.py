@@ -131,18 +131,21 @@ def test_csr_rows_longer_than_panel(K, kk):
     W against the oracle, with the long rows alone and among short ones."""
     m, n = 300, 20000
     rng = np.random.default_rng(4)
-    lens = [4000, 7000, 3073] + list(rng.integers(1, 60, m - 3))
+    lens = [4000, 7000, 3073] + list(rng.integers(0, 60, m - 3))   # some rows empty
     rows = [np.sort(rng.choice(n, L, replace=False)).astype(np.int32) for L in lens]
     row_ptr = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
     col = np.concatenate(rows)
     v = rng.random(col.size)
     for i in range(m):
         seg = slice(row_ptr[i], row_ptr[i + 1])
-        v[seg] /= np.linalg.norm(v[seg])
+        if lens[i]:
+            v[seg] /= np.linalg.norm(v[seg])
     c = {"row_ptr": row_ptr, "col_idx": col, "val": v, "m": m, "n": n}
     ok = O.Kernel(kk[0], sigma=kk[1], c=kk[2], degree=kk[3])
     beta = rng.standard_normal(m)
-    for S in ([0], [1, 5], [3, 0, 7, 1, 2], list(range(10, 50)) + [1]):
+    empty = [i for i in range(3, m) if lens[i] == 0][:2]
+    assert empty
+    for S in ([0], [1, 5], [3, 0, 7, 1, 2], list(range(10, 50)) + [1], empty + [2, 4]):
         S = np.asarray(S, dtype=np.int32)
         r, W = K.kdcd_kernel_rhs(to_gpu(K, c), kk, idx_dev(S), dev(beta), want_W=True)
         assert_parity(r.cpu().numpy(), O.kernel_rhs(as_oracle(c), ok, S, beta), 1e-11, f"r {S[:3]}")

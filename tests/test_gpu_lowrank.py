@@ -183,3 +183,19 @@ def test_lowrank_errors(K):
     with pytest.raises(K.KdcdError) as e:
         K.kdcd_lowrank_solve("krr", big, dev(y), 1e-3, 4, 2, 10, idx, alpha)
     assert e.value.status == -2
+
+
+@pytest.mark.parametrize("r", [1, 7])
+def test_lowrank_tiny_rank_and_ragged(K, r):
+    """Rank below one MFMA block and m not a multiple of any tile."""
+    m, b, s, H = 97, 3, 5, 23
+    A, y = rbf_data(m, 6, seed=r)
+    L = inputs.landmarks(m, r, seed=2)
+    Phi_t = features(K, A, (2, 1.0, 0.0, 1), L, 1e-6)
+    Phi_h = O.nystrom_features(A, O.Kernel(O.RBF, sigma=1.0), L, 1e-6)
+    assert_parity(Phi_t.cpu().numpy(), Phi_h, 1e-9, "Phi")
+    idx_h = inputs.krr_indices(m, b, H, seed=1)
+    alpha = torch.zeros(m, dtype=torch.float64, device="cuda")
+    K.kdcd_lowrank_solve("krr", Phi_t, dev(y), 1e-2, b, s, H, idx_dev(idx_h), alpha)
+    ref, _ = O.bdcd_krr(Phi_h, y, O.Kernel(O.LINEAR), 1e-2, b, H, idx_h, s=s)
+    assert_parity(alpha.cpu().numpy(), ref, TOL, "alpha")
