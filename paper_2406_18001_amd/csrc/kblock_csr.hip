@@ -307,8 +307,16 @@ __global__ __launch_bounds__(CSR_NT) __attribute__((amdgpu_waves_per_eu(RPW > 1 
                             bs = hbase[h];
                         }
                     }
-#pragma unroll 8
-                    for (int t = 0; t < LPR; ++t) {
+                    // positions t whose entry hits the panel in some row of the wave
+                    // (a position that misses everywhere would add nothing)
+                    const uint64_t hits = __ballot(msk != 0);
+                    uint64_t pos = 0;
+#pragma unroll
+                    for (int g = 0; g < RPW; ++g) pos |= (hits >> (g * LPR));
+                    if constexpr (LPR < 64) pos &= (1ull << LPR) - 1;
+                    while (pos) {
+                        const int t = __builtin_ctzll(pos);
+                        pos &= pos - 1;
                         const int src = rslot * LPR + t;
                         const double at = __shfl(a, src);
                         const MaskT mt = shfl_mask(msk, src);
