@@ -76,10 +76,6 @@ __device__ __forceinline__ uint64_t shfl_mask(uint64_t v, int src)
     const uint32_t lo = __shfl((int)(uint32_t)v, src), hi = __shfl((int)(uint32_t)(v >> 32), src);
     return ((uint64_t)hi << 32) | lo;
 }
-__device__ __forceinline__ uint32_t shfl_mask(uint32_t v, int src)
-{
-    return (uint32_t)__shfl((int)v, src);
-}
 __device__ __forceinline__ int popc(uint64_t v) { return __popcll(v); }
 __device__ __forceinline__ int popc(uint32_t v) { return __popc(v); }
 __device__ __forceinline__ void atomic_or_mask(uint64_t *p, uint64_t v)
@@ -219,8 +215,17 @@ __global__ __launch_bounds__(CSR_NT) __attribute__((amdgpu_waves_per_eu(RPW > 1 
     __shared__ uint32_t hfilt[CSR_FBITS / 32];
     __shared__ double hval[CSR_VMAX];
     __shared__ int32_t rowoff[LPR + 1];            // entry offsets of the chunk's sampled rows
-    __shared__ int32_t scan[CSR_NT];
-    __shared__ double red[NW * RPW][LPR];
+    // Per-wave scratch of SW doubles: the broadcast stages each position's
+    // entries here (value, and mask | offset << 32 when masks are 32-bit);
+    // the panel build's prefix sums and the cross-wave column sums use the
+    // same memory at times when no wave is broadcasting.
+    constexpr int SW = 128;
+    constexpr bool STAGE = LPR <= 32;
+    __shared__ double wbuf[NW * SW];
+    int32_t *scan = reinterpret_cast<int32_t *>(wbuf);   // CSR_NT ints
+    static_assert(CSR_NT * sizeof(int32_t) <= NW * SW * sizeof(double), "scan fits");
+    static_assert(RPW * LPR <= SW, "column sums fit");
+    auto red = [&](int w, int j) -> double & { return wbuf[(w / RPW) * SW + (w % RPW) * LPR + j]; };
 
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int rslot = lane / LPR, jl = lane % LPR;
@@ -314,14 +319,33 @@ __global__ __launch_bounds__(CSR_NT) __attribute__((amdgpu_waves_per_eu(RPW > 1 
 #pragma unroll
                     for (int g = 0; g < RPW; ++g) pos |= (hits >> (g * LPR));
                     if constexpr (LPR < 64) pos &= (1ull << LPR) - 1;
-                    while (pos) {
-                        const int t = __builtin_ctzll(pos);
-                        pos &= pos - 1;
-                        const int src = rslot * LPR + t;
-                        const double at = __shfl(a, src);
-                        const MaskT mt = shfl_mask(msk, src);
-                        const int bt = __shfl(bs, src);
-                        if ((mt >> jl) & 1) acc += at * hval[bt + popc((MaskT)(mt & below))];
+                    if constexpr (STAGE) {
+                        double *sa = wbuf + wid * SW;
+                        uint64_t *sp = reinterpret_cast<uint64_t *>(wbuf + wid * SW + 64);
+                        wave_lds_sync();          // the previous position's reads are done
+                        sa[lane] = a;
+                        sp[lane] = (uint64_t)(uint32_t)msk | ((uint64_t)(uint32_t)bs << 32);
+                        wave_lds_sync();
+                        while (pos) {
+                            const int t = __builtin_ctzll(pos);
+                            pos &= pos - 1;
+                            const int src = rslot * LPR + t;
+                            const double at = sa[src];
+                            const uint64_t pk = sp[src];
+                            const MaskT mt = (MaskT)(uint32_t)pk;
+                            const int bt = (int)(pk >> 32);
+                            if ((mt >> jl) & 1) acc += at * hval[bt + popc((MaskT)(mt & below))];
+                        }
+                    } else {
+                        while (pos) {
+                            const int t = __builtin_ctzll(pos);
+                            pos &= pos - 1;
+                            const int src = rslot * LPR + t;
+                            const double at = __shfl(a, src);
+                            const MaskT mt = shfl_mask(msk, src);
+                            const int bt = __shfl(bs, src);
+                            if ((mt >> jl) & 1) acc += at * hval[bt + popc((MaskT)(mt & below))];
+                        }
                     }
                 }
 #pragma unroll
@@ -351,11 +375,11 @@ __global__ __launch_bounds__(CSR_NT) __attribute__((amdgpu_waves_per_eu(RPW > 1 
         }
         }   // pieces
         if (!is_w) {
-            red[wid * RPW + rslot][jl] = colsum;
+            red(wid * RPW + rslot, jl) = colsum;
             __syncthreads();
             if (tid < nj) {
                 double s = 0.0;
-                for (int w = 0; w < NW * RPW; ++w) s += red[w][tid];
+                for (int w = 0; w < NW * RPW; ++w) s += red(w, tid);
                 partial[(int64_t)blockIdx.x * sb + j0 + tid] = s;
             }
         }
