@@ -697,8 +697,8 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU; runs on more than one GPU are not part of this build",
-              file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (the row split "
+              "across GPUs is designed, not implemented)", file=sys.stderr)
         sys.exit(2)
     if args.copy_probe:
         copy_probe()
