@@ -41,7 +41,10 @@ __device__ __forceinline__ int xcd_remap(int bid, int total)
 // the map runs once per sigma group, every problem reduces its own beta, and
 // the Gram tiles are written once per group.  partial is then [p][group][sb]
 // and W is [g][sb][sb].
-template <int WM, int WN, int TM, int TN, int KIND, bool BATCH>
+// FULL: rows 16-byte aligned and n a multiple of BK, so every chunk is loaded
+// with unconditional 16-byte loads (no per-element bounds branches, which also
+// lets the compiler keep the next chunks' loads in flight across the stores).
+template <int WM, int WN, int TM, int TN, int KIND, bool BATCH, bool FULL>
 __global__ __launch_bounds__(64 * WM * WN) void kblock_f64_kernel(
     const double *__restrict__ A, int64_t lda, int64_t m, int64_t n,
     const int32_t *__restrict__ S, int32_t sb, const double *__restrict__ norms, KParams kp,
@@ -140,7 +143,7 @@ __global__ __launch_bounds__(64 * WM * WN) void kblock_f64_kernel(
             for (int i = 0; i < SEGA; ++i) {
                 const int seg = tid + i * NT;
                 const int64_t kk = k0 + 4 * (seg & 3);
-                if (aligned && kk + 4 <= n) {
+                if (FULL || (aligned && kk + 4 <= n)) {
                     const d2 *p = reinterpret_cast<const d2 *>(aptr[i] + k0);
                     d2 x = p[0], y = p[1];
                     ra[i][0] = x[0]; ra[i][1] = x[1]; ra[i][2] = y[0]; ra[i][3] = y[1];
@@ -153,7 +156,7 @@ __global__ __launch_bounds__(64 * WM * WN) void kblock_f64_kernel(
             for (int i = 0; i < SEGB; ++i) {
                 const int seg = tid + i * NT;
                 const int64_t kk = k0 + 4 * (seg & 3);
-                if (aligned && kk + 4 <= n) {
+                if (FULL || (aligned && kk + 4 <= n)) {
                     const d2 *p = reinterpret_cast<const d2 *>(bptr[i] + k0);
                     d2 x = p[0], y = p[1];
                     rb[i][0] = x[0]; rb[i][1] = x[1]; rb[i][2] = y[0]; rb[i][3] = y[1];
@@ -201,20 +204,43 @@ __global__ __launch_bounds__(64 * WM * WN) void kblock_f64_kernel(
             }
         };
 
-        load(0, ra0, rb0);
-        if (nK > 1) load(1, ra1, rb1);
-        store(0, ra0, rb0);
-        lds_barrier();
-        for (int64_t kc = 0; kc < nK; kc += 2) {
-            if (kc + 2 < nK) load(kc + 2, ra0, rb0);
-            compute(0);
-            if (kc + 1 < nK) store(1, ra1, rb1);
+        if constexpr (FULL) {
+            // Loads are unconditional (chunk indices clamped to the last chunk,
+            // which is then read again and ignored): a conditional load would
+            // make the compiler copy the stage registers around it and wait for
+            // every load in flight, including the chunk just issued.
+            const int64_t last = nK - 1;
+            load(0, ra0, rb0);
+            load(last < 1 ? last : 1, ra1, rb1);
+            store(0, ra0, rb0);
             lds_barrier();
-            if (kc + 1 >= nK) break;
-            if (kc + 3 < nK) load(kc + 3, ra1, rb1);
-            compute(1);
-            if (kc + 2 < nK) store(0, ra0, rb0);
+            for (int64_t kc = 0; kc < nK; kc += 2) {
+                load(kc + 2 < last ? kc + 2 : last, ra0, rb0);
+                compute(0);
+                if (kc + 1 < nK) store(1, ra1, rb1);
+                lds_barrier();
+                if (kc + 1 >= nK) break;
+                load(kc + 3 < last ? kc + 3 : last, ra1, rb1);
+                compute(1);
+                if (kc + 2 < nK) store(0, ra0, rb0);
+                lds_barrier();
+            }
+        } else {
+            load(0, ra0, rb0);
+            if (nK > 1) load(1, ra1, rb1);
+            store(0, ra0, rb0);
             lds_barrier();
+            for (int64_t kc = 0; kc < nK; kc += 2) {
+                if (kc + 2 < nK) load(kc + 2, ra0, rb0);
+                compute(0);
+                if (kc + 1 < nK) store(1, ra1, rb1);
+                lds_barrier();
+                if (kc + 1 >= nK) break;
+                if (kc + 3 < nK) load(kc + 3, ra1, rb1);
+                compute(1);
+                if (kc + 2 < nK) store(0, ra0, rb0);
+                lds_barrier();
+            }
         }
 
         // epilogue: item v of MFMA output lane l is row (l/16) + 4v, column l%16 of its block
@@ -469,20 +495,27 @@ hipError_t launch_cfg(const KBlockArgs &a, hipStream_t st)
     const int64_t n_n = (a.sb + BN - 1) / BN;
     const int64_t blocks = n_n * (groups + n_w);
     const int aligned = (A->ld % 2 == 0) && ((reinterpret_cast<uintptr_t>(A->values) & 15) == 0);
+    const bool full = aligned && A->n % BK == 0;
     dim3 grid((unsigned)blocks), block(64 * WM * WN);
-#define KDCD_LAUNCH(KIND)                                                                      \
-    KDCD_TIMED_LAUNCH((kblock_f64_kernel<WM, WN, TM, TN, KIND, BATCH>), grid, block, 0, st,    \
+#define KDCD_LAUNCH_F(KIND, FULL)                                                              \
+    KDCD_TIMED_LAUNCH((kblock_f64_kernel<WM, WN, TM, TN, KIND, BATCH, FULL>), grid, block, 0, st, \
                        A->values, A->ld, A->m, A->n, a.S, a.sb, a.norms, a.kp, a.beta,          \
                        a.beta_scale, a.partial, a.W, (int32_t)n_u, (int32_t)groups,            \
                        (int32_t)n_w, (int32_t)n_n, aligned, a.batch, BATCH ? nullptr : a.U,   \
                        a.stop, BATCH ? nullptr : a.pos, BATCH ? nullptr : a.posX, a.X,         \
                        a.prevS ? a.prev_sb : 0)
+#define KDCD_LAUNCH(KIND)                                                                      \
+    do {                                                                                        \
+        if (full) KDCD_LAUNCH_F(KIND, true);                                                    \
+        else KDCD_LAUNCH_F(KIND, false);                                                        \
+    } while (0)
     switch (a.kp.kind) {
     case KDCD_KERNEL_LINEAR: KDCD_LAUNCH(KDCD_KERNEL_LINEAR); break;
     case KDCD_KERNEL_POLY: KDCD_LAUNCH(KDCD_KERNEL_POLY); break;
     default: KDCD_LAUNCH(KDCD_KERNEL_RBF); break;
     }
 #undef KDCD_LAUNCH
+#undef KDCD_LAUNCH_F
     return hipGetLastError();
 }
 

@@ -145,12 +145,14 @@ __global__ __launch_bounds__(64 * WM * WN) void kblock_mixed_kernel(
 #pragma unroll
                 for (int i = 0; i < SEGA; ++i) {
                     const int seg = tid + i * NT;
-                    ra[h][i] = (s0 + (seg & 3) < nseg) ? src[aoff[i] + s0] : u4{0u, 0u, 0u, 0u};
+                    (void)seg;
+                    ra[h][i] = src[aoff[i] + s0];
                 }
 #pragma unroll
                 for (int i = 0; i < SEGB; ++i) {
                     const int seg = tid + i * NT;
-                    rb[h][i] = (s0 + (seg & 3) < nseg) ? src[boff[i] + s0] : u4{0u, 0u, 0u, 0u};
+                    (void)seg;
+                    rb[h][i] = src[boff[i] + s0];
                 }
             }
         };
@@ -196,17 +198,23 @@ __global__ __launch_bounds__(64 * WM * WN) void kblock_mixed_kernel(
                 }
         };
 
+        // The rounded copies are padded to whole chunks, so every chunk is
+        // loaded unconditionally; chunk indices past the end are clamped to the
+        // last chunk (read again, never stored), which keeps the compiler from
+        // copying the stage registers around conditional loads and waiting for
+        // every load in flight.
+        const int64_t last = nK - 1;
         load(0, ra0, rb0);
-        if (nK > 1) load(1, ra1, rb1);
+        load(last < 1 ? last : 1, ra1, rb1);
         store(0, ra0, rb0);
         lds_barrier();
         for (int64_t kc = 0; kc < nK; kc += 2) {
-            if (kc + 2 < nK) load(kc + 2, ra0, rb0);
+            load(kc + 2 < last ? kc + 2 : last, ra0, rb0);
             compute(0);
             if (kc + 1 < nK) store(1, ra1, rb1);
             lds_barrier();
             if (kc + 1 >= nK) break;
-            if (kc + 3 < nK) load(kc + 3, ra1, rb1);
+            load(kc + 3 < last ? kc + 3 : last, ra1, rb1);
             compute(1);
             if (kc + 2 < nK) store(0, ra0, rb0);
             lds_barrier();
