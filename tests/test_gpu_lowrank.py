@@ -199,3 +199,20 @@ def test_lowrank_tiny_rank_and_ragged(K, r):
     K.kdcd_lowrank_solve("krr", Phi_t, dev(y), 1e-2, b, s, H, idx_dev(idx_h), alpha)
     ref, _ = O.bdcd_krr(Phi_h, y, O.Kernel(O.LINEAR), 1e-2, b, H, idx_h, s=s)
     assert_parity(alpha.cpu().numpy(), ref, TOL, "alpha")
+
+
+def test_lowrank_c2_full_size_first_outer_iterations(K):
+    """The C2 recipe at full size (20000 x 512, RBF sigma = 1) on a rank-256
+    factor, s*b = 512 as the benchmark runs it: the factor and the first two
+    outer iterations of the low-rank K-RR solve against the oracle."""
+    d = inputs.dense_krr_c2()
+    m, r, b, s, H = 20000, 256, 8, 64, 128
+    L = inputs.landmarks(m, r, seed=1)
+    Phi_t = features(K, d["A"], (2, 1.0, 0.0, 1), L, 1e-8)
+    Phi_h = O.nystrom_features(d["A"], O.Kernel(O.RBF, sigma=1.0), L, 1e-8)
+    assert_parity(Phi_t.cpu().numpy(), Phi_h, 1e-9, "Phi")
+    idx_h = inputs.krr_indices(m, b, H, seed=0)
+    alpha = torch.zeros(m, dtype=torch.float64, device="cuda")
+    K.kdcd_lowrank_solve("krr", Phi_t, dev(d["y"]), 1e-3, b, s, H, idx_dev(idx_h), alpha)
+    ref, _ = O.bdcd_krr(Phi_h, d["y"], O.Kernel(O.LINEAR), 1e-3, b, H, idx_h, s=s)
+    assert_parity(alpha.cpu().numpy(), ref, TOL, "alpha")
