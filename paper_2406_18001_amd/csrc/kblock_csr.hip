@@ -215,12 +215,15 @@ __global__ __launch_bounds__(CSR_NT) __attribute__((amdgpu_waves_per_eu(RPW > 1 
     __shared__ uint32_t hfilt[CSR_FBITS / 32];
     __shared__ double hval[CSR_VMAX];
     __shared__ int32_t rowoff[LPR + 1];            // entry offsets of the chunk's sampled rows
-    // Per-wave scratch of SW doubles: the broadcast stages each position's
-    // entries here (value, and mask | offset << 32 when masks are 32-bit);
-    // the panel build's prefix sums and the cross-wave column sums use the
-    // same memory at times when no wave is broadcasting.
+    // Per-wave scratch of SW doubles.  SCATTER (at most 16 sampled rows per
+    // chunk): the rows' sums over their sampled rows, to which every lane adds
+    // its entries' products (LDS atomic adds; a wave's atomics on one address
+    // apply in lane order).  STAGE (32): the broadcast stages each position's
+    // entries here (value, and mask | offset << 32).  The panel build's prefix
+    // sums and the cross-wave column sums use the same memory at other times.
     constexpr int SW = 128;
-    constexpr bool STAGE = LPR <= 32;
+    constexpr bool SCATTER = LPR <= 16;              // few sampled rows per chunk
+    constexpr bool STAGE = LPR == 32;
     __shared__ double wbuf[NW * SW];
     int32_t *scan = reinterpret_cast<int32_t *>(wbuf);   // CSR_NT ints
     static_assert(CSR_NT * sizeof(int32_t) <= NW * SW * sizeof(double), "scan fits");
@@ -265,6 +268,13 @@ __global__ __launch_bounds__(CSR_NT) __attribute__((amdgpu_waves_per_eu(RPW > 1 
                                     hbase, hval, rowoff, scan, status);
         }
         const bool last = pc + 1 == npieces;
+        // SCATTER: the row's sums over its sampled rows live in this wave's
+        // scratch (the panel build above used the same memory for its scan)
+        double *rsum = wbuf + wid * SW + rslot * LPR;
+        if constexpr (SCATTER) {
+            rsum[jl] = 0.0;
+            wave_lds_sync();
+        }
         const int64_t nsteps = is_w ? 1 : (m + ROWS - 1) / ROWS;
         for (int64_t st = is_w ? 0 : blockIdx.x; st < nsteps; st += is_w ? 1 : n_row_groups) {
             const int64_t rix = (is_w ? (int64_t)wblk * ROWS : st * ROWS) + wid * RPW + rslot;
@@ -312,14 +322,28 @@ __global__ __launch_bounds__(CSR_NT) __attribute__((amdgpu_waves_per_eu(RPW > 1 
                             bs = hbase[h];
                         }
                     }
-                    // positions t whose entry hits the panel in some row of the wave
-                    // (a position that misses everywhere would add nothing)
-                    const uint64_t hits = __ballot(msk != 0);
-                    uint64_t pos = 0;
+                    if constexpr (SCATTER) {
+                        // every lane adds its entry's products into the row's LDS
+                        // sums, one sampled row (set bit) per step
+                        MaskT mm = msk;
+                        int k = 0;
+                        while (__ballot(mm != 0)) {
+                            if (mm) {
+                                const int j = __builtin_ctz((uint32_t)mm);
+                                mm &= mm - 1;
+                                atomicAdd(&rsum[j], a * hval[bs + k]);
+                                ++k;
+                            }
+                        }
+                    } else {
+                        // positions t whose entry hits the panel in some row of the wave
+                        // (a position that misses everywhere would add nothing)
+                        const uint64_t hits = __ballot(msk != 0);
+                        uint64_t pos = 0;
 #pragma unroll
-                    for (int g = 0; g < RPW; ++g) pos |= (hits >> (g * LPR));
-                    if constexpr (LPR < 64) pos &= (1ull << LPR) - 1;
-                    if constexpr (STAGE) {
+                        for (int g = 0; g < RPW; ++g) pos |= (hits >> (g * LPR));
+                        if constexpr (LPR < 64) pos &= (1ull << LPR) - 1;
+                        if constexpr (STAGE) {
                         double *sa = wbuf + wid * SW;
                         uint64_t *sp = reinterpret_cast<uint64_t *>(wbuf + wid * SW + 64);
                         wave_lds_sync();          // the previous position's reads are done
@@ -336,7 +360,7 @@ __global__ __launch_bounds__(CSR_NT) __attribute__((amdgpu_waves_per_eu(RPW > 1 
                             const int bt = (int)(pk >> 32);
                             if ((mt >> jl) & 1) acc += at * hval[bt + popc((MaskT)(mt & below))];
                         }
-                    } else {
+                        } else {
                         while (pos) {
                             const int t = __builtin_ctzll(pos);
                             pos &= pos - 1;
@@ -346,6 +370,7 @@ __global__ __launch_bounds__(CSR_NT) __attribute__((amdgpu_waves_per_eu(RPW > 1 
                             const int bt = __shfl(bs, src);
                             if ((mt >> jl) & 1) acc += at * hval[bt + popc((MaskT)(mt & below))];
                         }
+                        }
                     }
                 }
 #pragma unroll
@@ -353,6 +378,12 @@ __global__ __launch_bounds__(CSR_NT) __attribute__((amdgpu_waves_per_eu(RPW > 1 
                     cb[u] = nc[u];
                     vb[u] = nv[u];
                 }
+            }
+            if constexpr (SCATTER) {
+                wave_lds_sync();                  // every lane's additions are done
+                acc = rsum[jl];
+                rsum[jl] = 0.0;
+                wave_lds_sync();
             }
             if (rok && jok) {
                 if (npieces > 1) {

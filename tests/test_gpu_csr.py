@@ -150,3 +150,16 @@ def test_csr_rows_longer_than_panel(K, kk):
         r, W = K.kdcd_kernel_rhs(to_gpu(K, c), kk, idx_dev(S), dev(beta), want_W=True)
         assert_parity(r.cpu().numpy(), O.kernel_rhs(as_oracle(c), ok, S, beta), 1e-11, f"r {S[:3]}")
         assert_parity(W.cpu().numpy(), O.kernel_block(as_oracle(c), ok, S, S), 1e-12, f"W {S[:3]}")
+
+
+@pytest.mark.parametrize("sb", [4, 12, 32, 100])
+def test_csr_deterministic(K, c3_small, sb):
+    """The CSR product gives bitwise the same r and W on repeated calls."""
+    c = c3_small
+    S = idx_dev(inputs.ksvm_indices(c["m"], sb, seed=sb))
+    beta = dev(np.random.default_rng(sb).standard_normal(c["m"]))
+    A = to_gpu(K, c)
+    r0, W0 = K.kdcd_kernel_rhs(A, POLY13, S, beta, want_W=True)
+    for _ in range(3):
+        r1, W1 = K.kdcd_kernel_rhs(A, POLY13, S, beta, want_W=True)
+        assert torch.equal(r0, r1) and torch.equal(W0, W1)
