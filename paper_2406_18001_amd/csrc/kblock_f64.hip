@@ -44,8 +44,12 @@ __device__ __forceinline__ int xcd_remap(int bid, int total)
 // FULL: rows 16-byte aligned and n a multiple of BK, so every chunk is loaded
 // with unconditional 16-byte loads (no per-element bounds branches, which also
 // lets the compiler keep the next chunks' loads in flight across the stores).
+// The batched epilogue keeps one row of kernel values per sigma group live; left
+// to itself the compiler then settles on one wave per SIMD, so the batched
+// variants ask for two (they still fit without spilling).
 template <int WM, int WN, int TM, int TN, int KIND, bool BATCH, bool FULL>
-__global__ __launch_bounds__(64 * WM * WN) void kblock_f64_kernel(
+__global__ __launch_bounds__(64 * WM * WN) __attribute__((amdgpu_waves_per_eu(BATCH ? 2 : 1)))
+void kblock_f64_kernel(
     const double *__restrict__ A, int64_t lda, int64_t m, int64_t n,
     const int32_t *__restrict__ S, int32_t sb, const double *__restrict__ norms, KParams kp,
     const double *__restrict__ beta, const double *__restrict__ bscale,
