@@ -65,8 +65,11 @@ template <int CMP> constexpr int seg_elems() { return CMP == KDCD_F32 ? 4 : 8; }
 // BATCH: several problems share the product (see the FP64 kernel): the map
 // runs once per sigma group and every problem reduces its own beta;
 // partial is then [p][row group][sb].
+// Every variant asks for two waves per SIMD (all fit without spilling): left to
+// itself the compiler runs the batched and the 128 x 128 RBF variants at one.
 template <int CMP, int WM, int WN, int TM, int TN, int KIND, bool BATCH>
-__global__ __launch_bounds__(64 * WM * WN) void kblock_mixed_kernel(
+__global__ __launch_bounds__(64 * WM * WN) __attribute__((amdgpu_waves_per_eu(2)))
+void kblock_mixed_kernel(
     const u4 *__restrict__ Ahi, const u4 *__restrict__ Alo, int64_t ldseg, int64_t m,
     int64_t nseg, const float *__restrict__ normlow, const int32_t *__restrict__ S, int32_t sb,
     KParams kp, const double *__restrict__ beta, const double *__restrict__ bscale,
@@ -417,8 +420,13 @@ hipError_t launch_for(const KBlockArgs &a, hipStream_t st)
     const Cfg c = pick_cfg(a.sb);
     if (c.bn == 16) return launch_cfg<CMP, 4, 1, 2, 1, false>(a, st);
     if (c.bn == 32) return launch_cfg<CMP, 4, 1, 2, 2, false>(a, st);
-    if (c.bn == 64) return launch_cfg<CMP, 2, 2, 4, 2, false>(a, st);
-    return launch_cfg<CMP, 2, 2, 4, 4, false>(a, st);
+    if constexpr (CMP == KDCD_BF16X3) {
+        // three products per tile: the 128 x 128 tile would need one wave per SIMD
+        return launch_cfg<CMP, 2, 2, 4, 2, false>(a, st);
+    } else {
+        if (c.bn == 64) return launch_cfg<CMP, 2, 2, 4, 2, false>(a, st);
+        return launch_cfg<CMP, 2, 2, 4, 4, false>(a, st);
+    }
 }
 
 }  // namespace
