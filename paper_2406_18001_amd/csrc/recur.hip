@@ -25,6 +25,9 @@
 namespace kdcd {
 namespace {
 
+// A double in the constant address space: loads through it may be scalar.
+typedef const double __attribute__((address_space(4))) ConstF64;
+
 __device__ __forceinline__ int64_t clampi(int64_t v, int64_t lo, int64_t hi)
 {
     return v < lo ? lo : (v > hi ? hi : v);
@@ -196,11 +199,20 @@ __global__ __launch_bounds__(NT) void ksvm_recur_kernel(const KsvmRecurDesc D,
     }
 }
 
-// K-RR recurrence.  Elements are grouped in panels of PE = floor(64/b)*b
-// (whole blocks); panel q lives on lanes [0, PE) of wave q.  Inside a panel
-// the wave runs its blocks one after the other (values exchanged between
-// lanes with readlane, no workgroup barrier); then one barrier and every
-// later element folds in the panel's Delta values.  BMAX bounds b, NT the
+// K-RR recurrence (Algorithm 4's inner loop).  Elements are grouped in panels
+// of PE = floor(64/b)*b (whole blocks); panel q lives on lanes [0, PE) of wave
+// q.  With G[t][u] = W[t][u]/lambda + m [S_t = S_u] the block step for block j
+// of a panel is Delta_j = D_j^{-1} c_j, and every later element u of the panel
+// subtracts sum_q G[j_q][u] Delta_{j_q}.  Both are linear in c_j, so the
+// coefficients K[r][u] = (D_j^{-1})[u][r] (u in block j) or
+// sum_q G[j_q][u] (D_j^{-1})[q][r] (u later) are formed for the whole panel
+// before it starts, by the waves that do not own the running panel; the owner
+// then spends one b-term chain per block: x_u = sum_r K[r][u] c_{j_r}.  After
+// the panel, one barrier, and every later element folds in the panel's Delta
+// values.  Repeated coordinates (a coordinate sampled in several blocks) add
+// the m-term to G and their updates to the running sum of the coordinate; each
+// panel keeps the list of its elements whose coordinate comes again later, so
+// the folds visit only those for that term.  BMAX bounds b, NT the
 // thread count; BX > 0 fixes b = BX at compile time (fully unrolled block
 // loops), BX = 0 handles any b <= BMAX.
 template <int BMAX, int NT, int BX>
@@ -220,13 +232,20 @@ __global__ __launch_bounds__(NT) void krr_recur_kernel(const KrrRecurDesc D,
     double *__restrict__ trace = D.trace[pb];
     const double lambda = D.lambda[pb];
     constexpr int PF = NT > 512 ? 16 : ((BMAX >= 32 || BX == 0) ? 32 : 64);
-    __shared__ double Wd[2][64 * 64];
-    __shared__ double c_l[kMaxSB + 64];        // padded: entries past the last panel hold 0 / -1
-    __shared__ double d_l[kMaxSB + 64];
+    constexpr int NW = NT / 64;
+    constexpr int QN = BX > 0 ? BX : BMAX;
+    constexpr int RC = QN < 8 ? QN : 8;        // coefficient rows per work item
+    __shared__ double Kd[2][64 * 64];          // block-step coefficients of a panel, [row][lane]
+    __shared__ double d_l[kMaxSB + 64];        // padded: entries past the last panel hold 0 / -1
     __shared__ __align__(16) int32_t S_l[kMaxSB + 64];
     __shared__ int32_t hkeys[kHashSlots], hidx[kHashSlots];
+    __shared__ int32_t rep_l[NW * 64];         // panel q: rep_l[64 q, 64 q + rep_n[q]), ascending
+    __shared__ int32_t rep_n[NW];
     if (BX > 0) b = BX;
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    // wid through readfirstlane: the compiler then treats it (and what depends on it) as
+    // wave-uniform, so per-block coefficients and branches on the panel owner are scalar
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int sb = sk * b;
     const int PE = (64 / b) * b;
     const int npanels = (sb + PE - 1) / PE;
@@ -237,7 +256,6 @@ __global__ __launch_bounds__(NT) void krr_recur_kernel(const KrrRecurDesc D,
     const double inv_lambda = 1.0 / lambda;
     double c = act ? y[Sp] - mdbl * a0 - r[e] / lambda : 0.0;
     const int myblk = act ? e / b : sk;
-    const int ll = act ? e % b : 0;
     const int lblk = lane / b;                        // block index inside the panel
     for (int x = tid; x < kMaxSB + 64; x += NT) {   // every slot without an owner: S = -1, d = 0
         S_l[x] = -1;
@@ -245,42 +263,76 @@ __global__ __launch_bounds__(NT) void krr_recur_kernel(const KrrRecurDesc D,
     }
     lastocc_clear(hkeys, hidx, tid, NT);
     lds_barrier();
-    if (act) {
-        S_l[e] = (int32_t)Sp;
-        c_l[e] = c;
-    }
-    double dv[BMAX];
-#pragma unroll
-    for (int q = 0; q < BMAX; ++q)
-        dv[q] = (act && q < b) ? Dinv[((int64_t)myblk * b + ll) * b + q] : 0.0;
+    if (act) S_l[e] = (int32_t)Sp;
+    const int hslot = act ? lastocc_insert(hkeys, hidx, (int32_t)Sp, e) : 0;
 
-    // diagonal PE x PE block of panel q, stored with row stride 64
-    auto stage = [&](int q, double *dst, int rank, int count) {
+    // Coefficients of panel q into dst.  Work items are (block, chunk of RC rows);
+    // item i goes to the waves of rank i mod count, lane u computes column u.
+    auto build_k = [&](int q, double *dst, int rank, int count) {
         const int Q0 = q * PE;
-        constexpr int CH = 8;
-        for (int e0 = rank; e0 < 64 * 64; e0 += CH * count) {
-            double v[CH];
+        const int qlen = (sb - Q0) < PE ? (sb - Q0) : PE;
+        const int nrc = (b + RC - 1) / RC;
+        const int items = (qlen / b) * nrc;
+        const int u = lane;
+        const int32_t Su = S_l[Q0 + u];
+        for (int it = rank; it < items; it += count) {
+            const int bl = it / nrc, r0 = (it % nrc) * RC;
+            const int l0 = bl * b;
+            const int64_t blk = (Q0 + l0) / b;
+            const bool own = u >= l0 && u < l0 + b;
+            const bool lat = u >= l0 + b && u < qlen;
+            // every load at a clamped, valid address for every lane (no per-load
+            // branch), all issued before the first use
+            const int64_t ucol = Q0 + (u < qlen ? u : qlen - 1);
+            const int64_t urow = blk * b + (own ? u - l0 : 0);
+            double x[QN], dvo[RC];
 #pragma unroll
-            for (int cc = 0; cc < CH; ++cc) {
-                const int x = e0 + cc * count, t = x >> 6, u = x & 63;
-                v[cc] = (x < 64 * 64 && t < PE && u < PE && Q0 + t < sb && Q0 + u < sb)
-                            ? W[(int64_t)(Q0 + t) * sb + Q0 + u] : 0.0;
+            for (int t = 0; t < QN; ++t)
+                if (BX > 0 || t < b) x[t] = W[(int64_t)(Q0 + l0 + t) * sb + ucol];
+#pragma unroll
+            for (int rr = 0; rr < RC; ++rr)
+                if (r0 + rr < b) dvo[rr] = Dinv[urow * b + r0 + rr];
+#pragma unroll
+            for (int t = 0; t < QN; ++t) {
+                if (BX > 0 || t < b) {
+                    const double g = x[t] * inv_lambda + (S_l[Q0 + l0 + t] == Su ? mdbl : 0.0);
+                    x[t] = lat ? g : 0.0;
+                }
+            }
+            // D_j^{-1} is read-only during the launch and its addresses are uniform:
+            // through the constant address space its rows come in by scalar loads
+            const ConstF64 *Db = (const ConstF64 *)(Dinv + blk * b * b);
+            double kacc[RC];
+#pragma unroll
+            for (int rr = 0; rr < RC; ++rr) kacc[rr] = 0.0;
+#pragma unroll
+            for (int t = 0; t < QN; ++t) {
+                if (BX > 0 || t < b) {
+#pragma unroll
+                    for (int rr = 0; rr < RC; ++rr)
+                        if (r0 + rr < b) kacc[rr] += x[t] * Db[t * b + r0 + rr];
+                }
             }
 #pragma unroll
-            for (int cc = 0; cc < CH; ++cc) {
-                const int x = e0 + cc * count;
-                if (x < 64 * 64) dst[x] = v[cc];
-            }
+            for (int rr = 0; rr < RC; ++rr)
+                if (r0 + rr < b) dst[(l0 + r0 + rr) * 64 + u] = own ? dvo[rr] : kacc[rr];
         }
     };
-    stage(0, Wd[0], tid, NT);
     lds_barrier();
-    const int hslot = act ? lastocc_insert(hkeys, hidx, (int32_t)Sp, e) : 0;
     if (act) {
         const int q0 = myblk * b;
         for (int q = q0; q < q0 + b; ++q)
             if (q != e && S_l[q] == (int32_t)Sp) set_status(status, KDCD_ERR_INDEX_DUPLICATE);
     }
+    {   // elements of this wave's panel whose coordinate comes again later
+        const bool rl = act && hidx[hslot] != e;
+        const uint64_t bal = __ballot(rl);
+        const int below = __popcll(bal & ((1ull << lane) - 1ull));
+        if (rl) rep_l[wid * 64 + below] = e;
+        if (lane == 0) rep_n[wid] = __popcll(bal);
+    }
+    build_k(0, Kd[0], wid, NW);
+    lds_barrier();
 
     double delta = 0.0, dsum = 0.0;   // dsum: updates of earlier repeats of this coordinate, in order
     for (int p = 0; p < npanels; ++p) {
@@ -293,67 +345,48 @@ __global__ __launch_bounds__(NT) void krr_recur_kernel(const KrrRecurDesc D,
 #pragma unroll
             for (int t = 0; t < PF; ++t) wpre[t] = (t < plen) ? W[(int64_t)(P0 + t) * sb + e] : 0.0;
         }
-        if (wid != p && p + 1 < npanels) stage(p + 1, Wd[buf ^ 1], wid < p ? tid : tid - 64, NT - 64);
+        if (wid != p && p + 1 < npanels) build_k(p + 1, Kd[buf ^ 1], wid < p ? wid : wid - 1, NW - 1);
         if (wid == p) {
-            const double *wd = Wd[buf];
+            const double *kd = Kd[buf];
             const int nbl = plen / b;
-            constexpr int QN = BX > 0 ? BX : BMAX;
             for (int bl = 0; bl < nbl; ++bl) {
-                const int l0 = bl * b;                 // first lane of block bl
-                // coefficients of the fold-in, independent of the chain: fetched first
-                double coef[QN];
+                const int l0 = bl * b;
+                double kc[QN];
 #pragma unroll
-                for (int q = 0; q < QN; ++q) {
-                    if (BX > 0 || q < b) {
-                        const int32_t Sq = __builtin_amdgcn_readlane((int)Sp, l0 + q);
-                        coef[q] = (Sq == (int32_t)Sp ? mdbl : 0.0) + wd[(l0 + q) * 64 + lane] * inv_lambda;
-                    }
-                }
-                // Delta for block bl: lanes of the block combine the block's c values
-                double dl = 0.0;
+                for (int t = 0; t < QN; ++t)
+                    if (BX > 0 || t < b) kc[t] = kd[(l0 + t) * 64 + lane];
+                double x = 0.0;
 #pragma unroll
-                for (int q = 0; q < QN; ++q)
-                    if (BX > 0 || q < b) dl += dv[q] * readlane_d(c, l0 + q);
-                if (lblk == bl) delta = dl;
-                // every later lane of the panel subtracts (m [S_e = S_q] + W_qe / lambda) Delta_q
-                double acc = 0.0, dup_acc = 0.0;
-                bool any_dup = false;
-#pragma unroll
-                for (int q = 0; q < QN; ++q) {
-                    if (BX > 0 || q < b) {
-                        const double dq = readlane_d(dl, l0 + q);
-                        const bool dup = __builtin_amdgcn_readlane((int)Sp, l0 + q) == (int32_t)Sp;
-                        acc += coef[q] * dq;
-                        dup_acc += dup ? dq : 0.0;
-                        any_dup |= dup;
-                    }
-                }
-                if (act && lblk > bl) {
-                    c -= acc;
-                    if (any_dup) dsum += dup_acc;
-                }
+                for (int t = 0; t < QN; ++t)
+                    if (BX > 0 || t < b) x += kc[t] * readlane_d(c, l0 + t);
+                if (lblk == bl) delta = x;
+                if (act && lblk > bl) c -= x;
             }
             if (act) d_l[e] = delta;
         }
         lds_barrier();
+        const int nrep = rep_n[p];
+        if (wid == p && act) {
+            // repeats of this coordinate in the earlier blocks of the panel, in order
+            for (int k = 0; k < nrep; ++k) {
+                const int t = rep_l[p * 64 + k];
+                if (t < P0 + lblk * b && S_l[t] == (int32_t)Sp) dsum += d_l[t];
+            }
+        }
         if (later) {
-            // branch-free: wpre[t] and d_l[P0 + t] are 0 past the end of the panel
+            // wpre[t] and d_l[P0 + t] are 0 past the end of the panel
             double acc = 0.0;
 #pragma unroll
-            for (int t = 0; t < PF; ++t) {
-                const bool dup = S_l[P0 + t] == (int32_t)Sp;
-                const double dt = d_l[P0 + t];
-                acc += ((dup ? mdbl : 0.0) + wpre[t] * inv_lambda) * dt;
-                dsum += dup ? dt : 0.0;
+            for (int t = 0; t < PF; ++t) acc += wpre[t] * d_l[P0 + t];
+            for (int t = PF; t < plen; ++t) acc += W[(int64_t)(P0 + t) * sb + e] * d_l[P0 + t];
+            c -= acc * inv_lambda;
+            for (int k = 0; k < nrep; ++k) {          // repeats of this coordinate in the panel
+                const int t = rep_l[p * 64 + k];
+                if (S_l[t] == (int32_t)Sp) {
+                    c -= mdbl * d_l[t];
+                    dsum += d_l[t];
+                }
             }
-            for (int t = PF; t < plen; ++t) {
-                const bool dup = S_l[P0 + t] == (int32_t)Sp;
-                const double dt = d_l[P0 + t];
-                acc += ((dup ? mdbl : 0.0) + W[(int64_t)(P0 + t) * sb + e] * inv_lambda) * dt;
-                if (dup) dsum += dt;
-            }
-            c -= acc;
-            c_l[e] = c;
         }
     }
     // scatter: the last occurrence of a coordinate writes alpha_0 plus all of
