@@ -257,6 +257,12 @@ __global__ __launch_bounds__(NT) void krr_recur_kernel(const KrrRecurDesc D,
     double c = act ? y[Sp] - mdbl * a0 - r[e] / lambda : 0.0;
     const int myblk = act ? e / b : sk;
     const int lblk = lane / b;                        // block index inside the panel
+    constexpr bool PIPE = BX > 0 && BX <= 8 && NT <= 512;
+    constexpr int DVN = PIPE ? QN : 1;
+    double dv[DVN];                                   // PIPE: this element's row of D_j^{-1}
+#pragma unroll
+    for (int t = 0; t < DVN; ++t)
+        dv[t] = (PIPE && act) ? Dinv[((int64_t)myblk * b + e % b) * b + t] : 0.0;
     for (int x = tid; x < kMaxSB + 64; x += NT) {   // every slot without an owner: S = -1, d = 0
         S_l[x] = -1;
         d_l[x] = 0.0;
@@ -266,56 +272,88 @@ __global__ __launch_bounds__(NT) void krr_recur_kernel(const KrrRecurDesc D,
     if (act) S_l[e] = (int32_t)Sp;
     const int hslot = act ? lastocc_insert(hkeys, hidx, (int32_t)Sp, e) : 0;
 
-    // Coefficients of panel q into dst.  Work items are (block, chunk of RC rows);
-    // item i goes to the waves of rank i mod count, lane u computes column u.
-    auto build_k = [&](int q, double *dst, int rank, int count) {
+    // Coefficients of panel q: work items are (block, chunk of RC rows); lane u
+    // computes column u.  An item's loads are issued first (k_load) and turned
+    // into coefficients later (k_finish).  PIPE (b <= 8 fixed at compile time,
+    // 512 threads): the rows of a block's own lanes (its D_j^{-1} rows) are
+    // written by the owner wave when the panel starts, so only blocks with later
+    // lanes are items, and each wave loads its items of panel q + 2 while panel
+    // q runs: the coefficients of panel q + 1 are then formed from registers
+    // whose loads are long done.  Otherwise items also write the own rows and
+    // are loaded and finished in the panel before their use.
+    auto k_items = [&](int q) {
+        const int qlen = (sb - q * PE) < PE ? (sb - q * PE) : PE;
+        return (qlen / b - (PIPE ? 1 : 0)) * ((b + RC - 1) / RC);
+    };
+    auto k_load = [&](int q, int it, double (&x)[QN], double (&dvo)[RC]) {
         const int Q0 = q * PE;
         const int qlen = (sb - Q0) < PE ? (sb - Q0) : PE;
         const int nrc = (b + RC - 1) / RC;
-        const int items = (qlen / b) * nrc;
-        const int u = lane;
-        const int32_t Su = S_l[Q0 + u];
-        for (int it = rank; it < items; it += count) {
-            const int bl = it / nrc, r0 = (it % nrc) * RC;
-            const int l0 = bl * b;
-            const int64_t blk = (Q0 + l0) / b;
-            const bool own = u >= l0 && u < l0 + b;
-            const bool lat = u >= l0 + b && u < qlen;
-            // every load at a clamped, valid address for every lane (no per-load
-            // branch), all issued before the first use
-            const int64_t ucol = Q0 + (u < qlen ? u : qlen - 1);
-            const int64_t urow = blk * b + (own ? u - l0 : 0);
-            double x[QN], dvo[RC];
+        const int l0 = (it / nrc) * b;
+        // a clamped, valid column for every lane (no per-load branch); rows
+        // Q0 + l0 + t < Q0 + qlen as the block has later lanes
+        const int64_t ucol = Q0 + (lane < qlen ? lane : qlen - 1);
 #pragma unroll
-            for (int t = 0; t < QN; ++t)
-                if (BX > 0 || t < b) x[t] = W[(int64_t)(Q0 + l0 + t) * sb + ucol];
+        for (int t = 0; t < QN; ++t)
+            if (BX > 0 || t < b) x[t] = W[(int64_t)(Q0 + l0 + t) * sb + ucol];
+        if constexpr (!PIPE) {   // this lane's D_j^{-1} row, if the lane is in the block
+            const int r0 = (it % nrc) * RC;
+            const bool own = lane >= l0 && lane < l0 + b;
+            const int64_t urow = (Q0 + l0) + (own ? lane - l0 : 0);
 #pragma unroll
             for (int rr = 0; rr < RC; ++rr)
                 if (r0 + rr < b) dvo[rr] = Dinv[urow * b + r0 + rr];
+        }
+    };
+    auto k_finish = [&](int q, int it, double (&x)[QN], const double (&dvo)[RC], double *dst) {
+        const int Q0 = q * PE;
+        const int qlen = (sb - Q0) < PE ? (sb - Q0) : PE;
+        const int nrc = (b + RC - 1) / RC;
+        const int l0 = (it / nrc) * b, r0 = (it % nrc) * RC;
+        const int u = lane;
+        const int32_t Su = S_l[Q0 + u];
+        const bool lat = u >= l0 + b && u < qlen;
 #pragma unroll
-            for (int t = 0; t < QN; ++t) {
-                if (BX > 0 || t < b) {
-                    const double g = x[t] * inv_lambda + (S_l[Q0 + l0 + t] == Su ? mdbl : 0.0);
-                    x[t] = lat ? g : 0.0;
-                }
+        for (int t = 0; t < QN; ++t) {
+            if (BX > 0 || t < b) {
+                const double g = x[t] * inv_lambda + (S_l[Q0 + l0 + t] == Su ? mdbl : 0.0);
+                x[t] = lat ? g : 0.0;
             }
-            // D_j^{-1} is read-only during the launch and its addresses are uniform:
-            // through the constant address space its rows come in by scalar loads
-            const ConstF64 *Db = (const ConstF64 *)(Dinv + blk * b * b);
-            double kacc[RC];
+        }
+        // D_j^{-1} is read-only during the launch and its addresses are uniform:
+        // through the constant address space its rows come in by scalar loads
+        const ConstF64 *Db = (const ConstF64 *)(Dinv + (int64_t)(Q0 + l0) * b);
+        double kacc[RC];
 #pragma unroll
-            for (int rr = 0; rr < RC; ++rr) kacc[rr] = 0.0;
+        for (int rr = 0; rr < RC; ++rr) kacc[rr] = 0.0;
 #pragma unroll
-            for (int t = 0; t < QN; ++t) {
-                if (BX > 0 || t < b) {
+        for (int t = 0; t < QN; ++t) {
+            if (BX > 0 || t < b) {
 #pragma unroll
-                    for (int rr = 0; rr < RC; ++rr)
-                        if (r0 + rr < b) kacc[rr] += x[t] * Db[t * b + r0 + rr];
-                }
+                for (int rr = 0; rr < RC; ++rr)
+                    if (r0 + rr < b) kacc[rr] += x[t] * Db[t * b + r0 + rr];
             }
+        }
+        const bool own = u >= l0 && u < l0 + b;
 #pragma unroll
-            for (int rr = 0; rr < RC; ++rr)
-                if (r0 + rr < b) dst[(l0 + r0 + rr) * 64 + u] = own ? dvo[rr] : kacc[rr];
+        for (int rr = 0; rr < RC; ++rr) {
+            if (r0 + rr < b) {
+                if (!PIPE) dst[(l0 + r0 + rr) * 64 + u] = own ? dvo[rr] : kacc[rr];
+                else if (!own) dst[(l0 + r0 + rr) * 64 + u] = kacc[rr];   // own rows: the owner's
+            }
+        }
+    };
+    // items per wave held in registers between k_load and k_finish
+    constexpr int KI = PIPE ? ((64 / QN - 1) + NW - 2) / (NW - 1) : 1;
+    double xp[KI][PIPE ? QN : 1], dvp[PIPE ? RC : 1];
+    // the waves other than wave q - 1 form panel q's coefficients; rank among them
+    auto k_rank = [&](int q) { return wid < q - 1 ? wid : wid - 1; };
+    auto k_direct = [&](int q, double *dst, int rank, int count) {
+        const int items = k_items(q);
+        for (int it = rank; it < items; it += count) {
+            double x[QN], dvo[RC];
+            k_load(q, it, x, dvo);
+            k_finish(q, it, x, dvo, dst);
         }
     };
     lds_barrier();
@@ -331,7 +369,16 @@ __global__ __launch_bounds__(NT) void krr_recur_kernel(const KrrRecurDesc D,
         if (rl) rep_l[wid * 64 + below] = e;
         if (lane == 0) rep_n[wid] = __popcll(bal);
     }
-    build_k(0, Kd[0], wid, NW);
+    k_direct(0, Kd[0], wid, NW);
+    if constexpr (PIPE) {
+        if (wid != 0 && 1 < npanels) {
+#pragma unroll
+            for (int k = 0; k < KI; ++k) {
+                const int it = k_rank(1) + k * (NW - 1);
+                if (it < k_items(1)) k_load(1, it, xp[k], dvp);
+            }
+        }
+    }
     lds_barrier();
 
     double delta = 0.0, dsum = 0.0;   // dsum: updates of earlier repeats of this coordinate, in order
@@ -340,14 +387,44 @@ __global__ __launch_bounds__(NT) void krr_recur_kernel(const KrrRecurDesc D,
         const int plen = (sb - P0) < PE ? (sb - P0) : PE;
         const int buf = p & 1;
         const bool later = act && wid > p;
+        // the fold's W values: with PIPE issued after the coefficient work, so
+        // that its waits do not cover them
         double wpre[PF];
-        if (later) {
+        auto fold_loads = [&]() {
+            if (later) {
 #pragma unroll
-            for (int t = 0; t < PF; ++t) wpre[t] = (t < plen) ? W[(int64_t)(P0 + t) * sb + e] : 0.0;
+                for (int t = 0; t < PF; ++t)
+                    wpre[t] = (t < plen) ? W[(int64_t)(P0 + t) * sb + e] : 0.0;
+            }
+        };
+        if (!PIPE) fold_loads();
+        if (wid != p && p + 1 < npanels) {
+            if constexpr (PIPE) {
+#pragma unroll
+                for (int k = 0; k < KI; ++k) {
+                    const int it = k_rank(p + 1) + k * (NW - 1);
+                    if (it < k_items(p + 1)) k_finish(p + 1, it, xp[k], dvp, Kd[buf ^ 1]);
+                }
+            } else {
+                k_direct(p + 1, Kd[buf ^ 1], k_rank(p + 1), NW - 1);
+            }
         }
-        if (wid != p && p + 1 < npanels) build_k(p + 1, Kd[buf ^ 1], wid < p ? wid : wid - 1, NW - 1);
+        if constexpr (PIPE) {
+            if (wid != p + 1 && p + 2 < npanels) {
+#pragma unroll
+                for (int k = 0; k < KI; ++k) {
+                    const int it = k_rank(p + 2) + k * (NW - 1);
+                    if (it < k_items(p + 2)) k_load(p + 2, it, xp[k], dvp);
+                }
+            }
+        }
+        if (PIPE) fold_loads();
         if (wid == p) {
-            const double *kd = Kd[buf];
+            double *kd = Kd[buf];
+            if (PIPE && act) {   // this lane's row of its block's D_j^{-1}
+#pragma unroll
+                for (int t = 0; t < DVN; ++t) kd[(lblk * b + t) * 64 + lane] = dv[t];
+            }
             const int nbl = plen / b;
             for (int bl = 0; bl < nbl; ++bl) {
                 const int l0 = bl * b;

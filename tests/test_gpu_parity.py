@@ -136,9 +136,11 @@ def test_krr_c2_recipe_small(K, s):
 
 
 @pytest.mark.parametrize("b,s,H", [(1, 7, 50), (3, 5, 23), (5, 7, 50), (8, 128, 128), (16, 32, 70),
-                                   (16, 64, 64), (32, 16, 40), (32, 8, 33)])
+                                   (16, 64, 64), (32, 16, 40), (32, 8, 33), (1, 200, 430),
+                                   (2, 100, 250), (4, 64, 150), (8, 40, 90)])
 def test_krr_blocks_overlap_and_ragged(K, b, s, H):
-    """m = 97: blocks overlap heavily; b, s and H are ragged against every tile."""
+    """m = 97: blocks overlap heavily; b, s and H are ragged against every tile
+    (s*b up to 1024, several 64-element panels, a ragged last panel)."""
     d = inputs.dense_krr_c2(m=97, n=45, seed=6)
     idx = inputs.krr_indices(97, b, H, seed=4)
     _krr_case(K, d["A"], d["y"], kern(2, sigma=0.5), 1e-2, b, s, H, idx)
@@ -149,6 +151,14 @@ def test_krr_other_kernels(K, kk):
     d = inputs.dense_krr_c2(m=300, n=24, seed=2)
     idx = inputs.krr_indices(300, 4, 120, seed=3)
     _krr_case(K, d["A"], d["y"], kk, 1e-1, 4, 10, 120, idx)
+
+
+@pytest.mark.parametrize("b,s", [(1, 300), (2, 160), (4, 100), (8, 50)])
+def test_krr_panels_few_repeats(K, b, s):
+    """m = 5000: several 64-element panels, a few repeated coordinates per outer iteration."""
+    d = inputs.dense_krr_c2(m=5000, n=40, seed=8)
+    idx = inputs.krr_indices(5000, b, 2 * s, seed=5)
+    _krr_case(K, d["A"], d["y"], RBF1, 1e-3, b, s, 2 * s, idx)
 
 
 def test_krr_c2_full_size_first_outer_iteration(K):
