@@ -208,6 +208,14 @@ struct FinishDesc {
     double *Dinv[kMaxProblems];            // inverses of K-RR problem k, [sk][b][b]
     double inv_lambda[kMaxProblems];
     const int32_t *stop;    // non-null and set: the solve has converged, do nothing
+    // Gathered Gram of one problem (dup_S non-null): the product wrote one row
+    // per coordinate (row dup_pos[S_t]); rows of repeated coordinates are
+    // copied from it by extra blocks, and the inversions read such rows'
+    // diagonal entries from it
+    const int32_t *dup_S;   // S_k, [sb]
+    const int32_t *dup_pos; // row -> position table of S_k
+    double *dup_W;          // the Gram, [sb][sb]
+    int64_t m;
 };
 
 struct KsvmRecurDesc {
@@ -230,6 +238,12 @@ struct KrrRecurDesc {
     double *trace[kMaxProblems];
     double lambda[kMaxProblems];
     const int32_t *stop;
+    // One problem with a gathered Gram (pos non-null): after the scatter the
+    // launch clears the row -> position table for its block and marks S_next
+    // (sb_next entries; none after the last block) for the next product
+    int32_t *pos;
+    const int32_t *S_next;
+    int32_t sb_next;
 };
 
 // Convergence monitor state (device): stop word first, so that &stop can be

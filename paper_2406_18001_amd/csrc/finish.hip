@@ -85,9 +85,10 @@ __global__ void iota_i32_kernel(int32_t *p, int64_t count)
 constexpr int FIN_COLS = 16;    // columns per reduction workgroup
 constexpr int FIN_PARTS = 16;   // row-group partitions per column
 
-// Blocks [0, nprob * ceil(sb/16)) reduce r of every problem; the blocks after
-// that invert one diagonal block of one K-RR problem each (Gauss-Jordan
-// without pivoting, valid for SPD matrices).
+// Blocks [0, nprob * ceil(sb/16)) reduce r of every problem; the next nkrr * sk
+// invert one diagonal block of one K-RR problem each (Gauss-Jordan without
+// pivoting, valid for SPD matrices); with dup_S the last ceil(sb/4) copy the
+// Gram rows of repeated coordinates (one wave per row).
 __global__ __launch_bounds__(256) void finish_kernel(const FinishDesc d, int32_t sb, int32_t b,
                                                      int32_t sk, double mdbl, int32_t *status)
 {
@@ -114,15 +115,33 @@ __global__ __launch_bounds__(256) void finish_kernel(const FinishDesc d, int32_t
         return;
     }
     const int x = (int)blockIdx.x - n_red;
+    const int n_inv = d.nkrr * sk;
+    // row written for the coordinate of row t (t itself unless t repeats it)
+    auto src_row = [&](int64_t t) -> int64_t {
+        if (!d.dup_S) return t;
+        const int32_t p = d.dup_S[t];
+        if (p < 0 || p >= d.m) return t;
+        const int32_t w = d.dup_pos[p];
+        return (w >= 0 && w < sb) ? w : t;
+    };
+    if (x >= n_inv) {   // one wave per row
+        if (!d.dup_S) return;
+        const int lane = tid & 63;
+        const int64_t t = (int64_t)(x - n_inv) * 4 + (tid >> 6);
+        if (t >= sb) return;
+        const int64_t w = src_row(t);
+        if (w == t) return;
+        for (int64_t c = lane; c < sb; c += 64) d.dup_W[t * sb + c] = d.dup_W[w * sb + c];
+        return;
+    }
     const int k = x / sk, j = x % sk;
-    if (k >= d.nkrr) return;
     const double *W = d.W[k];
     const double inv_lambda = d.inv_lambda[k];
     const int bb = b * b;
     const int64_t base = (int64_t)j * b;
     for (int e = tid; e < bb; e += blockDim.x) {
         const int l = e / b, q = e % b;
-        sh[e] = W[(base + l) * sb + base + q] * inv_lambda + (l == q ? mdbl : 0.0);
+        sh[e] = W[src_row(base + l) * sb + base + q] * inv_lambda + (l == q ? mdbl : 0.0);
     }
     __syncthreads();
     bool bad = false;
@@ -202,7 +221,7 @@ hipError_t launch_finish(const FinishDesc &d, int32_t sb, int32_t b, int32_t sk,
                          int32_t *status, hipStream_t st)
 {
     const int per = (sb + FIN_COLS - 1) / FIN_COLS;
-    const int blocks = per * d.nprob + d.nkrr * sk;
+    const int blocks = per * d.nprob + d.nkrr * sk + (d.dup_S ? (sb + 3) / 4 : 0);
     KDCD_TIMED_LAUNCH(finish_kernel, dim3(blocks), dim3(256), 0, st, d, sb, b, sk, mdbl, status);
     return hipGetLastError();
 }

@@ -477,6 +477,14 @@ __global__ __launch_bounds__(NT) void krr_recur_kernel(const KrrRecurDesc D,
         }
         if (trace) trace[e] = delta;
     }
+    if (D.pos) {   // the next product's row -> position table: clear S_k, then mark S_next
+        if (act) D.pos[Sp] = -1;
+        __syncthreads();
+        for (int t = tid; t < D.sb_next; t += NT) {
+            const int32_t q = D.S_next[t];
+            if (q >= 0 && q < m) D.pos[q] = t;
+        }
+    }
 }
 
 }  // namespace

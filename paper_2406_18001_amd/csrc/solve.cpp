@@ -520,15 +520,19 @@ kdcd_status enqueue_solve(const SolveArgs &sa, const Layout &L, char *wsbase, St
         kb.prev_sb = kb.sb;
         kb.S = S;
         kb.sb = sb;
+        // K-RR with a gathered Gram: the finish launch copies the repeated rows
+        // and each recurrence prepares the row -> position table of the next
+        // block, so only the first block needs the separate update launch
+        const bool fused = !svm && kb.W && kb.pos && !kb.w_only;
         if (A->format == KDCD_DENSE && sa.opt.compute == KDCD_F64) {
             // the product kernel times itself (the row-position update and
             // the repeated-row copies of the gathered Gram are not timed)
-            KDCD_HIP_TRY(launch_kblock_f64_pre(kb, st));
+            if (k == 0 || !fused) KDCD_HIP_TRY(launch_kblock_f64_pre(kb, st));
             timer.arm(0);
             const hipError_t e = launch_kblock_f64_main(kb, st);
             timer.disarm();
             KDCD_HIP_TRY(e);
-            KDCD_HIP_TRY(launch_kblock_f64_post(kb, st));
+            if (!fused) KDCD_HIP_TRY(launch_kblock_f64_post(kb, st));
         } else {
             timer.begin(0, st);
             KDCD_HIP_TRY(launch_kblock(kb, st));
@@ -544,6 +548,12 @@ kdcd_status enqueue_solve(const SolveArgs &sa, const Layout &L, char *wsbase, St
         fd.Dinv[0] = Dinv;
         fd.inv_lambda[0] = svm ? 0.0 : 1.0 / sa.lambda;
         fd.stop = stop;
+        if (fused) {
+            fd.dup_S = S;
+            fd.dup_pos = kb.pos;
+            fd.dup_W = W;
+            fd.m = A->m;
+        }
         if (!product_only) timer.arm(1);
         {
             const hipError_t e = launch_finish(fd, sb, sa.b, sk, (double)A->m, status, st);
@@ -576,6 +586,13 @@ kdcd_status enqueue_solve(const SolveArgs &sa, const Layout &L, char *wsbase, St
             rd.trace[0] = tr;
             rd.lambda[0] = sa.lambda;
             rd.stop = stop;
+            if (fused) {
+                rd.pos = kb.pos;
+                if (k + 1 < n_outer) {
+                    rd.S_next = S + sb;
+                    rd.sb_next = (int32_t)std::min<int64_t>(sa.s, sa.H - done - sk) * sa.b;
+                }
+            }
             if (!product_only) timer.arm(2);
             const hipError_t e = launch_krr_recur(rd, 1, S, sa.b, sk, A->m, (double)A->m, status,
                                                   st);
