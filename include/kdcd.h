@@ -133,11 +133,15 @@ typedef struct {
  * timestamps in their dispatch (hipExtLaunchKernelGGL), and each timed
  * dispatch costs a few microseconds of device time, so a timed measurement
  * of whole-solve throughput times the product only.
+ * KDCD_FLAG_TIME_SAMPLE (with KDCD_FLAG_TIME_PRODUCT): only the product
+ * launches of outer iterations k with k % 8 == 0 are timed (kblock_launches
+ * counts them), which keeps the timing's device cost to one launch in eight.
  */
 enum {
     KDCD_FLAG_GRAPH = 1,
     KDCD_FLAG_OVERLAP = 2,
-    KDCD_FLAG_TIME_PRODUCT = 4
+    KDCD_FLAG_TIME_PRODUCT = 4,
+    KDCD_FLAG_TIME_SAMPLE = 8
 };
 
 typedef struct {

@@ -460,6 +460,7 @@ kdcd_status enqueue_solve(const SolveArgs &sa, const Layout &L, char *wsbase, St
 
     const bool svm = sa.problem == 0;
     const bool product_only = (sa.opt.flags & KDCD_FLAG_TIME_PRODUCT) != 0;
+    const bool sampled = product_only && (sa.opt.flags & KDCD_FLAG_TIME_SAMPLE) != 0;
     const double nu = svm ? (sa.opt.loss == 2 ? INFINITY : sa.C) : 0.0;
     const double omega = (svm && sa.opt.loss == 2) ? 1.0 / (2.0 * sa.C) : 0.0;
 
@@ -528,7 +529,7 @@ kdcd_status enqueue_solve(const SolveArgs &sa, const Layout &L, char *wsbase, St
             // the product kernel times itself (the row-position update and
             // the repeated-row copies of the gathered Gram are not timed)
             if (k == 0 || !fused) KDCD_HIP_TRY(launch_kblock_f64_pre(kb, st));
-            timer.arm(0);
+            if (!sampled || k % 8 == 0) timer.arm(0);
             const hipError_t e = launch_kblock_f64_main(kb, st);
             timer.disarm();
             KDCD_HIP_TRY(e);

@@ -48,3 +48,11 @@ def test_profile_product_only():
     assert p["kblock_launches"] == -(-H // s) and p["kblock_ms"] > 0.0
     assert p["finish_launches"] == 0 and p["recur_launches"] == 0
     assert p["kblock_ms"] <= p["total_ms"] * 1.001 + 1e-3
+    # one product launch in eight (outer iterations 0, 8, 16, ...)
+    a2 = torch.zeros(m, dtype=torch.float64, device="cuda")
+    q = K.kdcd_krr_solve(A, y, (2, 1.0, 0.0, 1), 1e-3, b, s, H, idx, a2, profile=True,
+                         flags=K.FLAG_TIME_PRODUCT | K.FLAG_TIME_SAMPLE)
+    assert torch.equal(a0, a2)
+    n_outer = -(-H // s)
+    assert q["kblock_launches"] == -(-n_outer // 8) and q["kblock_ms"] > 0.0
+    assert q["finish_launches"] == 0 and q["recur_launches"] == 0
