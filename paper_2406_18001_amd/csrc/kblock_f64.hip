@@ -46,9 +46,12 @@ __device__ __forceinline__ int xcd_remap(int bid, int total)
 // lets the compiler keep the next chunks' loads in flight across the stores).
 // The batched epilogue keeps one row of kernel values per sigma group live; left
 // to itself the compiler then settles on one wave per SIMD, so the batched
-// variants ask for two (they still fit without spilling).
-template <int WM, int WN, int TM, int TN, int KIND, bool BATCH, bool FULL>
-__global__ __launch_bounds__(64 * WM * WN) __attribute__((amdgpu_waves_per_eu(BATCH ? 2 : 1)))
+// variants ask for two (they still fit without spilling).  OCC > 0 asks for
+// OCC waves per SIMD (the 64 x 64 tile at three: three 4-wave workgroups per
+// CU, so that one's prologue and epilogue overlap the others' MFMA loops).
+template <int WM, int WN, int TM, int TN, int KIND, bool BATCH, bool FULL, int OCC>
+__global__ __launch_bounds__(64 * WM * WN)
+__attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : (BATCH ? 2 : 1))))
 void kblock_f64_kernel(
     const double *__restrict__ A, int64_t lda, int64_t m, int64_t n,
     const int32_t *__restrict__ S, int32_t sb, const double *__restrict__ norms, KParams kp,
@@ -487,7 +490,7 @@ struct Cfg {
 
 constexpr int64_t kMaxRowGroups = 1024;
 
-template <int WM, int WN, int TM, int TN, bool BATCH>
+template <int WM, int WN, int TM, int TN, bool BATCH, int OCC = 0>
 hipError_t launch_cfg(const KBlockArgs &a, hipStream_t st)
 {
     constexpr int BM = 16 * TM * WM, BN = 16 * TN * WN;
@@ -502,7 +505,7 @@ hipError_t launch_cfg(const KBlockArgs &a, hipStream_t st)
     const bool full = aligned && A->n % BK == 0;
     dim3 grid((unsigned)blocks), block(64 * WM * WN);
 #define KDCD_LAUNCH_F(KIND, FULL)                                                              \
-    KDCD_TIMED_LAUNCH((kblock_f64_kernel<WM, WN, TM, TN, KIND, BATCH, FULL>), grid, block, 0, st, \
+    KDCD_TIMED_LAUNCH((kblock_f64_kernel<WM, WN, TM, TN, KIND, BATCH, FULL, OCC>), grid, block, 0, st, \
                        A->values, A->ld, A->m, A->n, a.S, a.sb, a.norms, a.kp, a.beta,          \
                        a.beta_scale, a.partial, a.W, (int32_t)n_u, (int32_t)groups,            \
                        (int32_t)n_w, (int32_t)n_n, aligned, a.batch, BATCH ? nullptr : a.U,   \
@@ -546,6 +549,7 @@ constexpr F64Cfg kF64Cfgs[] = {
     {2, 2, 2, 4},   // 3: 64 x 128, 4 waves
     {2, 4, 2, 2},   // 4: 64 x 128, 8 waves
     {4, 2, 2, 2},   // 5: 128 x 64, 8 waves
+    {2, 2, 2, 2},   // 6: 64 x 64, 4 waves, built for three waves per SIMD
 };
 constexpr int kF64NumCfgs = sizeof(kF64Cfgs) / sizeof(kF64Cfgs[0]);
 
@@ -574,7 +578,7 @@ static int f64_default_id(int32_t sb)
     if (sb <= 16) return 0;
     if (sb <= 32) return 1;
     if (sb <= 64) return 2;
-    return 3;
+    return 6;
 }
 
 int f64_config_id(int64_t n, int32_t sb)
@@ -626,6 +630,7 @@ hipError_t launch_kblock_f64_main(const KBlockArgs &a, hipStream_t st)
     case 2: return launch_cfg<2, 2, 2, 2, false>(b, st);
     case 3: return launch_cfg<2, 2, 2, 4, false>(b, st);
     case 4: return launch_cfg<2, 4, 2, 2, false>(b, st);
+    case 6: return launch_cfg<2, 2, 2, 2, false, 3>(b, st);
     default: return launch_cfg<4, 2, 2, 2, false>(b, st);
     }
 }
