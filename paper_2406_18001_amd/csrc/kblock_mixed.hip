@@ -65,8 +65,9 @@ template <int CMP> constexpr int seg_elems() { return CMP == KDCD_F32 ? 4 : 8; }
 // BATCH: several problems share the product (see the FP64 kernel): the map
 // runs once per sigma group and every problem reduces its own beta;
 // partial is then [p][row group][sb].
-// Every variant asks for two waves per SIMD (all fit without spilling): left to
-// itself the compiler runs the batched and the 128 x 128 RBF variants at one.
+// Every variant asks for at least two waves per SIMD (all fit without
+// spilling; the 128 x 64 single-problem tile reaches three): left to itself the
+// compiler runs the batched variants at one.
 template <int CMP, int WM, int WN, int TM, int TN, int KIND, bool BATCH>
 __global__ __launch_bounds__(64 * WM * WN) __attribute__((amdgpu_waves_per_eu(2)))
 void kblock_mixed_kernel(
@@ -369,8 +370,7 @@ Cfg pick_cfg(int32_t sb)
 {
     if (sb <= 16) return {128, 16};
     if (sb <= 32) return {128, 32};
-    if (sb <= 64) return {128, 64};
-    return {128, 128};
+    return {128, 64};
 }
 
 template <int CMP, int WM, int WN, int TM, int TN, bool BATCH>
@@ -420,13 +420,9 @@ hipError_t launch_for(const KBlockArgs &a, hipStream_t st)
     const Cfg c = pick_cfg(a.sb);
     if (c.bn == 16) return launch_cfg<CMP, 4, 1, 2, 1, false>(a, st);
     if (c.bn == 32) return launch_cfg<CMP, 4, 1, 2, 2, false>(a, st);
-    if constexpr (CMP == KDCD_BF16X3) {
-        // three products per tile: the 128 x 128 tile would need one wave per SIMD
-        return launch_cfg<CMP, 2, 2, 4, 2, false>(a, st);
-    } else {
-        if (c.bn == 64) return launch_cfg<CMP, 2, 2, 4, 2, false>(a, st);
-        return launch_cfg<CMP, 2, 2, 4, 4, false>(a, st);
-    }
+    // wider blocks also take the 128 x 64 tile: it runs at three waves per
+    // SIMD (the 128 x 128 one at two, one for bf16x3), which measured faster
+    return launch_cfg<CMP, 2, 2, 4, 2, false>(a, st);
 }
 
 }  // namespace
