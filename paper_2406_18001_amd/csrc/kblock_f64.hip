@@ -47,9 +47,8 @@ __device__ __forceinline__ int xcd_remap(int bid, int total)
 // The batched epilogue keeps one row of kernel values per sigma group live; left
 // to itself the compiler then settles on one wave per SIMD, so the batched
 // variants ask for two (they still fit without spilling).  OCC > 0 asks for
-// OCC waves per SIMD (the 64 x 64 tile at three or four: three or four 4-wave
-// workgroups per CU, so that one's prologue and epilogue overlap the others'
-// MFMA loops).
+// OCC waves per SIMD (the 64 x 64 tile at three: three 4-wave workgroups per
+// CU, so that one's prologue and epilogue overlap the others' MFMA loops).
 template <int WM, int WN, int TM, int TN, int KIND, bool BATCH, bool FULL, int OCC>
 __global__ __launch_bounds__(64 * WM * WN)
 __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : (BATCH ? 2 : 1))))
@@ -551,7 +550,6 @@ constexpr F64Cfg kF64Cfgs[] = {
     {2, 4, 2, 2},   // 4: 64 x 128, 8 waves
     {4, 2, 2, 2},   // 5: 128 x 64, 8 waves
     {2, 2, 2, 2},   // 6: 64 x 64, 4 waves, built for three waves per SIMD
-    {2, 2, 2, 2},   // 7: 64 x 64, 4 waves, built for four waves per SIMD
 };
 constexpr int kF64NumCfgs = sizeof(kF64Cfgs) / sizeof(kF64Cfgs[0]);
 
@@ -633,7 +631,6 @@ hipError_t launch_kblock_f64_main(const KBlockArgs &a, hipStream_t st)
     case 3: return launch_cfg<2, 2, 2, 4, false>(b, st);
     case 4: return launch_cfg<2, 4, 2, 2, false>(b, st);
     case 6: return launch_cfg<2, 2, 2, 2, false, 3>(b, st);
-    case 7: return launch_cfg<2, 2, 2, 2, false, 4>(b, st);
     default: return launch_cfg<4, 2, 2, 2, false>(b, st);
     }
 }
