@@ -326,12 +326,29 @@ __global__ __launch_bounds__(NT) void krr_recur_kernel(const KrrRecurDesc D,
         double kacc[RC];
 #pragma unroll
         for (int rr = 0; rr < RC; ++rr) kacc[rr] = 0.0;
+        if constexpr (PIPE && QN == 8) {
+            // two halves of four columns: each half's 8 x 4 entries are fetched
+            // as one batch of scalar loads before its FMAs (two waits per item)
 #pragma unroll
-        for (int t = 0; t < QN; ++t) {
-            if (BX > 0 || t < b) {
+            for (int h = 0; h < 2; ++h) {
+                double dd[8][4];
 #pragma unroll
-                for (int rr = 0; rr < RC; ++rr)
-                    if (r0 + rr < b) kacc[rr] += x[t] * Db[t * b + r0 + rr];
+                for (int t = 0; t < 8; ++t)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) dd[t][c] = Db[t * 8 + h * 4 + c];
+#pragma unroll
+                for (int t = 0; t < 8; ++t)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) kacc[h * 4 + c] += x[t] * dd[t][c];
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < QN; ++t) {
+                if (BX > 0 || t < b) {
+#pragma unroll
+                    for (int rr = 0; rr < RC; ++rr)
+                        if (r0 + rr < b) kacc[rr] += x[t] * Db[t * b + r0 + rr];
+                }
             }
         }
         const bool own = u >= l0 && u < l0 + b;
