@@ -207,20 +207,28 @@ void kblock_mixed_kernel(
         // last chunk (read again, never stored), which keeps the compiler from
         // copying the stage registers around conditional loads and waiting for
         // every load in flight.
+        // Whole pairs of chunks in the loop and an odd last chunk after it: one
+        // loop exit, so the accumulators keep their registers across the
+        // back-edge (as in the FP64 kernel).
         const int64_t last = nK - 1;
         load(0, ra0, rb0);
         load(last < 1 ? last : 1, ra1, rb1);
         store(0, ra0, rb0);
         lds_barrier();
-        for (int64_t kc = 0; kc < nK; kc += 2) {
+        const int64_t npairs = nK / 2;
+        for (int64_t pk = 0; pk < npairs; ++pk) {
+            const int64_t kc = 2 * pk;
             load(kc + 2 < last ? kc + 2 : last, ra0, rb0);
             compute(0);
-            if (kc + 1 < nK) store(1, ra1, rb1);
+            store(1, ra1, rb1);              // chunk kc + 1 < nK
             lds_barrier();
-            if (kc + 1 >= nK) break;
             load(kc + 3 < last ? kc + 3 : last, ra1, rb1);
             compute(1);
             if (kc + 2 < nK) store(0, ra0, rb0);
+            lds_barrier();
+        }
+        if (nK & 1) {                        // chunk nK - 1, in buffer 0
+            compute(0);
             lds_barrier();
         }
 
