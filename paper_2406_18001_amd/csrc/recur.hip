@@ -414,7 +414,8 @@ __global__ __launch_bounds__(NT) void krr_recur_kernel(const KrrRecurDesc D,
                     wpre[t] = (t < plen) ? W[(int64_t)(P0 + t) * sb + e] : 0.0;
             }
         };
-        if (!PIPE) fold_loads();
+        // the next owner's fold loads go first (its fold is on the critical path)
+        if (!PIPE || wid == p + 1) fold_loads();
         if (wid != p && p + 1 < npanels) {
             if constexpr (PIPE) {
 #pragma unroll
@@ -435,7 +436,7 @@ __global__ __launch_bounds__(NT) void krr_recur_kernel(const KrrRecurDesc D,
                 }
             }
         }
-        if (PIPE) fold_loads();
+        if (PIPE && wid != p + 1) fold_loads();
         if (wid == p) {
             double *kd = Kd[buf];
             if (PIPE && act) {   // this lane's row of its block's D_j^{-1}
