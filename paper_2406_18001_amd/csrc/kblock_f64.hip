@@ -262,6 +262,24 @@ void kblock_f64_kernel(
         // epilogue: item v of MFMA output lane l is row (l/16) + 4v, column l%16 of its block
         if constexpr (BATCH) {
             const int ng = bd->ngroups, np = bd->nprob;
+            // beta (times its scale) of every problem for this tile's rows, staged
+            // once in the A operand buffers (free after the loop's last barrier)
+            // instead of one round of global loads per problem
+            static_assert(kMaxProblems * BM <= 2 * BM * BK, "staged beta must fit the A buffers");
+            double *bsh = &As[0][0];
+            if (!is_w) {
+                for (int x = tid; x < np * BM; x += NT) {
+                    const int p = x / BM;
+                    const int64_t grow = row0 + (x - p * BM);
+                    double bval = 0.0;
+                    if (grow < m) {
+                        bval = bd->beta[p][grow];
+                        if (bd->bscale[p]) bval *= bd->bscale[p][grow];
+                    }
+                    bsh[x] = bval;
+                }
+                __syncthreads();
+            }
             double na[TM][4];
 #pragma unroll
             for (int tm = 0; tm < TM; ++tm)
@@ -307,21 +325,12 @@ void kblock_f64_kernel(
                 }
                 for (int p = 0; p < np; ++p) {
                     if (bd->group[p] != g) continue;
-                    const double *bp = bd->beta[p];
-                    const double *sp = bd->bscale[p];
                     double bv[TM][4];
 #pragma unroll
                     for (int tm = 0; tm < TM; ++tm)
 #pragma unroll
-                        for (int v = 0; v < 4; ++v) {
-                            const int64_t grow = row0 + (wm * TM + tm) * 16 + (lane >> 4) + 4 * v;
-                            double x = 0.0;
-                            if (grow < m) {
-                                x = bp[grow];
-                                if (sp) x *= sp[grow];
-                            }
-                            bv[tm][v] = x;
-                        }
+                        for (int v = 0; v < 4; ++v)
+                            bv[tm][v] = bsh[p * BM + (wm * TM + tm) * 16 + (lane >> 4) + 4 * v];
 #pragma unroll
                     for (int tn = 0; tn < TN; ++tn) {
                         double acc_p = 0.0;
@@ -334,6 +343,7 @@ void kblock_f64_kernel(
                     }
                 }
             }
+            if (!is_w) __syncthreads();   // the staged beta is read before the next tile reuses As
         } else {
 #pragma unroll
             for (int tm = 0; tm < TM; ++tm) {
