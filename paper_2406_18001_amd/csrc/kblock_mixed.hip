@@ -235,6 +235,26 @@ void kblock_mixed_kernel(
         // epilogue: item v of lane l is row 4 (l/16) + v, column l%16 of its block
         if constexpr (BATCH) {
             const int ng = bd->ngroups, np = bd->nprob;
+            // beta (times its scale) of every problem for this tile's rows, staged
+            // once in the A operand buffers (free after the loop's last barrier)
+            // when they hold all problems (always for bf16x3, up to 16 problems
+            // otherwise); else one round of global loads per problem
+            constexpr int BSH_CAP = (int)(sizeof(As) / sizeof(double)) / BM;
+            double *bsh = reinterpret_cast<double *>(&As[0][0][0]);
+            const bool staged = np <= BSH_CAP;
+            if (staged) {
+                for (int x = tid; x < np * BM; x += NT) {
+                    const int p = x / BM;
+                    const int64_t grow = row0 + (x - p * BM);
+                    double bval = 0.0;
+                    if (grow < m) {
+                        bval = bd->beta[p][grow];
+                        if (bd->bscale[p]) bval *= bd->bscale[p][grow];
+                    }
+                    bsh[x] = bval;
+                }
+                __syncthreads();
+            }
             for (int g = 0; g < ng; ++g) {
                 KParams kg = kp;
                 kg.sigma = bd->sigma[g];
@@ -257,18 +277,26 @@ void kblock_mixed_kernel(
                     const double *bp = bd->beta[p];
                     const double *sp = bd->bscale[p];
                     double bv[TM][4];
+                    if (staged) {
 #pragma unroll
-                    for (int tm = 0; tm < TM; ++tm)
+                        for (int tm = 0; tm < TM; ++tm)
 #pragma unroll
-                        for (int v = 0; v < 4; ++v) {
-                            const int64_t grow = row0 + (wm * TM + tm) * 16 + 4 * (lane >> 4) + v;
-                            double x = 0.0;
-                            if (grow < m) {
-                                x = bp[grow];
-                                if (sp) x *= sp[grow];
+                            for (int v = 0; v < 4; ++v)
+                                bv[tm][v] = bsh[p * BM + (wm * TM + tm) * 16 + 4 * (lane >> 4) + v];
+                    } else {
+#pragma unroll
+                        for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) {
+                                const int64_t grow = row0 + (wm * TM + tm) * 16 + 4 * (lane >> 4) + v;
+                                double x = 0.0;
+                                if (grow < m) {
+                                    x = bp[grow];
+                                    if (sp) x *= sp[grow];
+                                }
+                                bv[tm][v] = x;
                             }
-                            bv[tm][v] = x;
-                        }
+                    }
 #pragma unroll
                     for (int tn = 0; tn < TN; ++tn) {
                         double acc_p = 0.0;
@@ -281,6 +309,7 @@ void kblock_mixed_kernel(
                     }
                 }
             }
+            if (staged) __syncthreads();   // the staged beta is read before the next tile reuses As
         } else {
 #pragma unroll
         for (int tm = 0; tm < TM; ++tm) {
