@@ -242,19 +242,25 @@ void kblock_f64_kernel(
                 lds_barrier();
             }
         } else {
+            // the same pair structure (one loop exit) with bounds-checked loads
             load(0, ra0, rb0);
             if (nK > 1) load(1, ra1, rb1);
             store(0, ra0, rb0);
             lds_barrier();
-            for (int64_t kc = 0; kc < nK; kc += 2) {
+            const int64_t npairs = nK / 2;
+            for (int64_t pk = 0; pk < npairs; ++pk) {
+                const int64_t kc = 2 * pk;
                 if (kc + 2 < nK) load(kc + 2, ra0, rb0);
                 compute(0);
-                if (kc + 1 < nK) store(1, ra1, rb1);
+                store(1, ra1, rb1);          // chunk kc + 1 < nK
                 lds_barrier();
-                if (kc + 1 >= nK) break;
                 if (kc + 3 < nK) load(kc + 3, ra1, rb1);
                 compute(1);
                 if (kc + 2 < nK) store(0, ra0, rb0);
+                lds_barrier();
+            }
+            if (nK & 1) {                    // chunk nK - 1, in buffer 0
+                compute(0);
                 lds_barrier();
             }
         }
