@@ -82,8 +82,8 @@ __global__ void iota_i32_kernel(int32_t *p, int64_t count)
     if (i < count) p[i] = (int32_t)i;
 }
 
-constexpr int FIN_COLS = 16;    // columns per reduction workgroup
-constexpr int FIN_PARTS = 16;   // row-group partitions per column
+constexpr int FIN_COLS = 8;     // columns per reduction workgroup
+constexpr int FIN_PARTS = 32;   // row-group partitions per column
 
 // Blocks [0, nprob * ceil(sb/16)) reduce r of every problem; the next nkrr * sk
 // invert one diagonal block of one K-RR problem each (Gauss-Jordan without
