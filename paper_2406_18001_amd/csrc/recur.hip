@@ -241,6 +241,7 @@ __global__ __launch_bounds__(NT) void krr_recur_kernel(const KrrRecurDesc D,
     __shared__ int32_t hkeys[kHashSlots], hidx[kHashSlots];
     __shared__ int32_t rep_l[NW * 64];         // panel q: rep_l[64 q, 64 q + rep_n[q]), ascending
     __shared__ int32_t rep_n[NW];
+    __shared__ double c_bc[QN];                // PIPE: c of the owner wave's running block
     if (BX > 0) b = BX;
     // wid through readfirstlane: the compiler then treats it (and what depends on it) as
     // wave-uniform, so per-block coefficients and branches on the panel owner are scalar
@@ -451,9 +452,20 @@ __global__ __launch_bounds__(NT) void krr_recur_kernel(const KrrRecurDesc D,
                 for (int t = 0; t < QN; ++t)
                     if (BX > 0 || t < b) kc[t] = kd[(l0 + t) * 64 + lane];
                 double x = 0.0;
+                if constexpr (PIPE) {
+                    // the block's lanes publish their c through LDS and every lane
+                    // reads the b values back: one LDS round trip is shorter than 2b
+                    // dependent lane reads
+                    if (lblk == bl) c_bc[lane - l0] = c;
+                    __builtin_amdgcn_wave_barrier();
 #pragma unroll
-                for (int t = 0; t < QN; ++t)
-                    if (BX > 0 || t < b) x += kc[t] * readlane_d(c, l0 + t);
+                    for (int t = 0; t < QN; ++t) x += kc[t] * c_bc[t];
+                    __builtin_amdgcn_wave_barrier();
+                } else {
+#pragma unroll
+                    for (int t = 0; t < QN; ++t)
+                        if (BX > 0 || t < b) x += kc[t] * readlane_d(c, l0 + t);
+                }
                 if (lblk == bl) delta = x;
                 if (act && lblk > bl) c -= x;
             }
