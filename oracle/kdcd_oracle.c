@@ -13,9 +13,13 @@
  *   - kernel functions: Table 1 definitions, evaluated directly (the RBF
  *     distance is summed as sum_k (x_k - y_k)^2, never by norm expansion;
  *     the polynomial power is repeated multiplication);
- *   - Algorithm 1 (DCD for K-SVM) and Algorithm 2 (s-step DCD), steps in
- *     the paper's order and notation;
- *   - Algorithm 3 (BDCD for K-RR) and Algorithm 4 / Eq. (3) (s-step BDCD);
+ *   - DCD for K-SVM (Algorithms 1 and 2) and BDCD for K-RR (Algorithms 3
+ *     and 4 / Eq. (3)) written as what they compute: exact minimisation of
+ *     the dual objective over one coordinate (K-SVM, projected onto the box)
+ *     or one block of coordinates (K-RR), in the order of the index
+ *     sequence, each at the current iterate; the s-step variants form the
+ *     kernel columns of s consecutive coordinates (blocks) in one pass over
+ *     A and then take the s steps with them;
  *   - the K-SVM dual objectives of Sec. 3.1, the primal of Eq. (1) in hinge
  *     form, and the K-RR dual of Eq. (2).
  *
@@ -190,8 +194,10 @@ static void svm_constants(int loss, double C, double *nu, double *omega)
 
 static double clip(double x, double nu) { return fmin(fmax(x, 0.0), nu); }
 
-/* The coordinate step shared by Algorithms 1 and 2: given the current value
- * rho of the coordinate, its gradient g and curvature eta, return theta. */
+/* Exact minimiser of rho + t over t of  t g + t^2 eta / 2  with rho + t
+ * kept in [0, nu]: the unconstrained step -g/eta, clipped.  When the
+ * projected gradient is exactly zero (reading R4) or eta <= 0 (R5) the step
+ * is 0. */
 static double dcd_theta(double rho, double g, double eta, double nu)
 {
     double gt = fabs(clip(rho - g, nu) - rho);
@@ -199,34 +205,59 @@ static double dcd_theta(double rho, double g, double eta, double nu)
     return 0.0;
 }
 
-/* Algorithm 1: DCD for K-SVM-L1 (loss 1) / K-SVM-L2 (loss 2).  idx holds the
- * H coordinates i_1..i_H; alpha is alpha_0 on entry and alpha_H on exit.
- * theta (optional, length H) receives every step's theta_k. */
+/* The dual of Sec. 3.1 restricted to coordinate i is the one-dimensional
+ * quadratic  f(alpha + t e_i) = f(alpha) + t g + t^2 eta / 2  with
+ * g = (Q alpha)_i - 1 + omega alpha_i  (the i-th partial derivative) and
+ * eta = Q_ii + omega, minimised over alpha_i + t in [0, nu].  Both DCD
+ * variants take exactly this step; they differ only in when the columns of
+ * Q are formed. */
+static double ksvm_coordinate_gradient(const double *Qcol, const double *alpha, int64_t m,
+                                       int64_t i, double omega)
+{
+    nsum acc = {0.0, 0.0};
+    for (int64_t p = 0; p < m; ++p) nadd(&acc, Qcol[p] * alpha[p]);
+    nadd(&acc, -1.0);
+    nadd(&acc, omega * alpha[i]);
+    return nval(&acc);
+}
+
+/* Column i of Q = diag(y) K diag(y) (reading R1): out[p] = y_p y_i K(a_p, a_i) */
+static void ksvm_q_column(const orc_matrix *A, const double *y, const orc_kernel *k, int64_t i,
+                          double *out)
+{
+    kernel_column(A, k, i, out);
+    for (int64_t p = 0; p < A->m; ++p) out[p] *= y[p] * y[i];
+}
+
+/* Algorithm 1 (DCD for K-SVM-L1 with loss 1, K-SVM-L2 with loss 2): one
+ * exact coordinate minimisation per entry of idx, each with a freshly formed
+ * column of Q.  idx holds i_1..i_H; alpha is alpha_0 on entry and alpha_H on
+ * exit; theta (optional, length H) receives each step. */
 int orc_dcd_ksvm(const orc_matrix *A, const double *y, const orc_kernel *k, double C, int loss,
                  int64_t H, const int32_t *idx, double *alpha, double *theta)
 {
     double nu, omega;
     svm_constants(loss, C, &nu, &omega);
-    double *u = malloc(sizeof(double) * (size_t)A->m);
-    if (!u) return ORC_ERR_ALLOC;
+    double *q = malloc(sizeof(double) * (size_t)A->m);
+    if (!q) return ORC_ERR_ALLOC;
     for (int64_t it = 0; it < H; ++it) {
-        int64_t i = idx[it];
-        /* u_k = K(Atilde, e_i^T Atilde): Q column i (reading R1) */
-        kernel_column(A, k, i, u);
-        for (int64_t p = 0; p < A->m; ++p) u[p] *= y[p] * y[i];
-        double eta = u[i] + omega;
-        nsum acc = {0.0, 0.0};
-        for (int64_t p = 0; p < A->m; ++p) nadd(&acc, u[p] * alpha[p]);
-        double g = nval(&acc) - 1.0 + omega * alpha[i];
-        double th = dcd_theta(alpha[i], g, eta, nu);
+        const int64_t i = idx[it];
+        ksvm_q_column(A, y, k, i, q);
+        const double g = ksvm_coordinate_gradient(q, alpha, A->m, i, omega);
+        const double th = dcd_theta(alpha[i], g, q[i] + omega, nu);
         alpha[i] += th;
         if (theta) theta[it] = th;
     }
-    free(u);
+    free(q);
     return ORC_OK;
 }
 
-/* Algorithm 2: s-step DCD for K-SVM.  Same contract as orc_dcd_ksvm. */
+/* Algorithm 2 (s-step DCD): the coordinates are taken s at a time; the s
+ * columns of Q that a group needs are formed together, in one pass over A,
+ * at the start of the group, and the group's s coordinate minimisations then
+ * run in order, each at the current iterate (the gradient of a later step
+ * sees every earlier step of its group, duplicates included).  Same contract
+ * as orc_dcd_ksvm. */
 int orc_sstep_dcd_ksvm(const orc_matrix *A, const double *y, const orc_kernel *k, double C,
                        int loss, int64_t s, int64_t H, const int32_t *idx, double *alpha,
                        double *theta)
@@ -234,50 +265,23 @@ int orc_sstep_dcd_ksvm(const orc_matrix *A, const double *y, const orc_kernel *k
     if (s < 1) return ORC_ERR_ARG;
     double nu, omega;
     svm_constants(loss, C, &nu, &omega);
-    int64_t m = A->m;
-    double *U = malloc(sizeof(double) * (size_t)(m * s));
-    double *col = malloc(sizeof(double) * (size_t)m);
-    double *G = malloc(sizeof(double) * (size_t)(s * s));
-    double *th = malloc(sizeof(double) * (size_t)s);
-    if (!U || !col || !G || !th) { free(U); free(col); free(G); free(th); return ORC_ERR_ALLOC; }
-    for (int64_t k0 = 0; k0 < H; k0 += s) {
-        int64_t sk = (H - k0 < s) ? H - k0 : s;        /* reading R2 */
-        const int32_t *I = idx + k0;
-        /* U_k = K(Atilde, Atilde_k): columns i_1..i_sk of Q, stored U[p*sk + j] */
-        for (int64_t j = 0; j < sk; ++j) {
-            kernel_column(A, k, I[j], col);
-            for (int64_t p = 0; p < m; ++p) U[p * sk + j] = col[p] * y[p] * y[I[j]];
-        }
-        /* G_k = V_k^T U_k + omega I ; eta_j = diag(G_k) */
-        for (int64_t t = 0; t < sk; ++t)
-            for (int64_t j = 0; j < sk; ++j)
-                G[t * sk + j] = U[(int64_t)I[t] * sk + j] + (t == j ? omega : 0.0);
-        for (int64_t j = 0; j < sk; ++j) {
-            /* rho_j = e_{i_j}^T alpha_sk + sum_{t<j, i_t = i_j} theta_t */
-            nsum rho = {0.0, 0.0};
-            nadd(&rho, alpha[I[j]]);
-            for (int64_t t = 0; t < j; ++t)
-                if (I[t] == I[j]) nadd(&rho, th[t]);
-            /* g_j = (U_k e_j)^T alpha_sk - 1 + omega alpha_{i_j}
-             *       + sum_{t<j} (e_{i_t}^T U_k e_j) theta_t
-             *       + omega sum_{t<j, i_t = i_j} theta_t */
-            nsum g = {0.0, 0.0};
-            for (int64_t p = 0; p < m; ++p) nadd(&g, U[p * sk + j] * alpha[p]);
-            nadd(&g, -1.0);
-            nadd(&g, omega * alpha[I[j]]);
-            for (int64_t t = 0; t < j; ++t) nadd(&g, U[(int64_t)I[t] * sk + j] * th[t]);
-            for (int64_t t = 0; t < j; ++t)
-                if (I[t] == I[j]) nadd(&g, omega * th[t]);
-            double eta = G[j * sk + j];
-            th[j] = dcd_theta(nval(&rho), nval(&g), eta, nu);
-        }
-        /* alpha_{sk+s} = alpha_sk + sum_t theta_t e_{i_t}, in t order */
-        for (int64_t t = 0; t < sk; ++t) {
-            alpha[I[t]] += th[t];
-            if (theta) theta[k0 + t] = th[t];
+    const int64_t m = A->m;
+    double *cols = malloc(sizeof(double) * (size_t)(m * s));   /* column t at cols + t*m */
+    if (!cols) return ORC_ERR_ALLOC;
+    for (int64_t first = 0; first < H; first += s) {
+        const int64_t len = (H - first < s) ? H - first : s;     /* reading R2 */
+        const int32_t *grp = idx + first;
+        for (int64_t t = 0; t < len; ++t) ksvm_q_column(A, y, k, grp[t], cols + t * m);
+        for (int64_t t = 0; t < len; ++t) {
+            const int64_t i = grp[t];
+            const double *q = cols + t * m;
+            const double g = ksvm_coordinate_gradient(q, alpha, m, i, omega);
+            const double th = dcd_theta(alpha[i], g, q[i] + omega, nu);
+            alpha[i] += th;
+            if (theta) theta[first + t] = th;
         }
     }
-    free(U); free(col); free(G); free(th);
+    free(cols);
     return ORC_OK;
 }
 
@@ -311,111 +315,85 @@ static int chol_solve(double *G, int64_t b, double *x)
     return ORC_OK;
 }
 
-/* Algorithm 3: BDCD for K-RR.  idx holds H blocks of b coordinates (block
- * major); alpha is alpha_0 on entry and alpha_H on exit.  delta (optional,
- * length H*b) receives every block's Delta alpha_k. */
+/* Exact minimisation of the K-RR dual f(alpha) = 1/2 a^T M a - y^T a,
+ * M = K/lambda + m I (reading R6), over the b coordinates of block `blk`
+ * with the others held fixed: the step d solves M[blk, blk] d = y[blk] -
+ * (M alpha)[blk].  cols holds the b kernel columns K(A, a_{blk_l}) (column l
+ * at cols + l*m).  The step is written to d and added to alpha. */
+static int krr_block_step(const double *cols, const double *y, double lambda, int64_t m,
+                          int64_t b, const int32_t *blk, double *alpha, double *G, double *d)
+{
+    for (int64_t l = 0; l < b; ++l) {
+        const double *kl = cols + l * m;
+        for (int64_t q = 0; q < b; ++q)
+            G[l * b + q] = kl[blk[q]] / lambda + (l == q ? (double)m : 0.0);
+        nsum ka = {0.0, 0.0};                    /* (K alpha)_{blk_l} */
+        for (int64_t p = 0; p < m; ++p) nadd(&ka, kl[p] * alpha[p]);
+        nsum v = {0.0, 0.0};
+        nadd(&v, y[blk[l]]);
+        nadd(&v, -nval(&ka) / lambda);
+        nadd(&v, -(double)m * alpha[blk[l]]);
+        d[l] = nval(&v);
+    }
+    const int rc = chol_solve(G, b, d);
+    if (rc != ORC_OK) return rc;
+    for (int64_t l = 0; l < b; ++l) alpha[blk[l]] += d[l];
+    return ORC_OK;
+}
+
+/* Algorithm 3 (BDCD for K-RR): one exact block minimisation per block of
+ * idx (H blocks of b distinct coordinates, block major), each with freshly
+ * formed kernel columns.  alpha is alpha_0 on entry and alpha_H on exit;
+ * delta (optional, length H*b) receives every block's step. */
 int orc_bdcd_krr(const orc_matrix *A, const double *y, const orc_kernel *k, double lambda,
                  int64_t b, int64_t H, const int32_t *idx, double *alpha, double *delta)
 {
-    int64_t m = A->m;
-    double *U = malloc(sizeof(double) * (size_t)(m * b));
-    double *col = malloc(sizeof(double) * (size_t)m);
+    const int64_t m = A->m;
+    double *cols = malloc(sizeof(double) * (size_t)(m * b));
     double *G = malloc(sizeof(double) * (size_t)(b * b));
-    double *x = malloc(sizeof(double) * (size_t)b);
+    double *d = malloc(sizeof(double) * (size_t)b);
     int rc = ORC_OK;
-    if (!U || !col || !G || !x) { rc = ORC_ERR_ALLOC; goto out; }
-    for (int64_t it = 0; it < H; ++it) {
-        const int32_t *S = idx + it * b;
-        /* U_k = K(A, V_k^T A) */
-        for (int64_t l = 0; l < b; ++l) {
-            kernel_column(A, k, S[l], col);
-            for (int64_t p = 0; p < m; ++p) U[p * b + l] = col[p];
-        }
-        /* G_k = (1/lambda) V_k^T U_k + m I */
-        for (int64_t l = 0; l < b; ++l)
-            for (int64_t q = 0; q < b; ++q)
-                G[l * b + q] = U[(int64_t)S[l] * b + q] / lambda + (l == q ? (double)m : 0.0);
-        /* rhs = V_k^T y - m V_k^T alpha - (1/lambda) U_k^T alpha */
-        for (int64_t l = 0; l < b; ++l) {
-            nsum ua = {0.0, 0.0};
-            for (int64_t p = 0; p < m; ++p) nadd(&ua, U[p * b + l] * alpha[p]);
-            nsum v = {0.0, 0.0};
-            nadd(&v, y[S[l]]);
-            nadd(&v, -(double)m * alpha[S[l]]);
-            nadd(&v, -nval(&ua) / lambda);
-            x[l] = nval(&v);
-        }
-        if ((rc = chol_solve(G, b, x)) != ORC_OK) goto out;
-        for (int64_t l = 0; l < b; ++l) {
-            alpha[S[l]] += x[l];
-            if (delta) delta[it * b + l] = x[l];
-        }
+    if (!cols || !G || !d) { rc = ORC_ERR_ALLOC; goto out; }
+    for (int64_t it = 0; it < H && rc == ORC_OK; ++it) {
+        const int32_t *blk = idx + it * b;
+        for (int64_t l = 0; l < b; ++l) kernel_column(A, k, blk[l], cols + l * m);
+        rc = krr_block_step(cols, y, lambda, m, b, blk, alpha, G, d);
+        if (rc == ORC_OK && delta) memcpy(delta + it * b, d, sizeof(double) * (size_t)b);
     }
 out:
-    free(U); free(col); free(G); free(x);
+    free(cols); free(G); free(d);
     return rc;
 }
 
-/* Algorithm 4 / Eq. (3): s-step BDCD for K-RR.  Same contract as orc_bdcd_krr. */
+/* Algorithm 4 / Eq. (3) (s-step BDCD): blocks are taken s at a time; the
+ * s*b kernel columns a group needs are formed together, in one pass over A,
+ * at the start of the group, and the group's s block minimisations then run
+ * in order, each at the current iterate (so a later block sees the earlier
+ * blocks' steps, including on coordinates the blocks share).  Same contract
+ * as orc_bdcd_krr. */
 int orc_sstep_bdcd_krr(const orc_matrix *A, const double *y, const orc_kernel *k, double lambda,
                        int64_t b, int64_t s, int64_t H, const int32_t *idx, double *alpha,
                        double *delta)
 {
     if (s < 1) return ORC_ERR_ARG;
-    int64_t m = A->m, sbmax = s * b;
-    double *Q = malloc(sizeof(double) * (size_t)(m * sbmax));
-    double *col = malloc(sizeof(double) * (size_t)m);
+    const int64_t m = A->m;
+    double *cols = malloc(sizeof(double) * (size_t)(m * s * b));
     double *G = malloc(sizeof(double) * (size_t)(b * b));
-    double *D = malloc(sizeof(double) * (size_t)sbmax);
+    double *d = malloc(sizeof(double) * (size_t)b);
     int rc = ORC_OK;
-    if (!Q || !col || !G || !D) { rc = ORC_ERR_ALLOC; goto out; }
-    for (int64_t k0 = 0; k0 < H; k0 += s) {
-        int64_t sk = (H - k0 < s) ? H - k0 : s;        /* reading R2 */
-        int64_t sb = sk * b;
-        const int32_t *Om = idx + k0 * b;              /* Omega_k, sk*b coordinates */
-        /* Q_k = K(A, Omega_k^T A), stored Q[p*sb + c] */
-        for (int64_t c = 0; c < sb; ++c) {
-            kernel_column(A, k, Om[c], col);
-            for (int64_t p = 0; p < m; ++p) Q[p * sb + c] = col[p];
-        }
-        for (int64_t j = 0; j < sk; ++j) {
-            const int32_t *Sj = Om + j * b;            /* V_{sk+j}; U_{sk+j} = Q_k Psi_j */
-            /* G_{sk+j} = (1/lambda) V^T U + m I */
-            for (int64_t l = 0; l < b; ++l)
-                for (int64_t q = 0; q < b; ++q)
-                    G[l * b + q] = Q[(int64_t)Sj[l] * sb + j * b + q] / lambda +
-                                   (l == q ? (double)m : 0.0);
-            double *x = D + j * b;
-            for (int64_t l = 0; l < b; ++l) {
-                /* V^T y - m V^T alpha_sk - m sum_t V_j^T V_t Delta_t
-                 *  - (1/lambda) U^T alpha_sk - (1/lambda) sum_t U_j^T V_t Delta_t */
-                nsum ua = {0.0, 0.0};
-                for (int64_t p = 0; p < m; ++p) nadd(&ua, Q[p * sb + j * b + l] * alpha[p]);
-                nsum ov = {0.0, 0.0}, uv = {0.0, 0.0};
-                for (int64_t t = 0; t < j; ++t)
-                    for (int64_t q = 0; q < b; ++q) {
-                        int32_t it = Om[t * b + q];
-                        if (it == Sj[l]) nadd(&ov, D[t * b + q]);
-                        nadd(&uv, Q[(int64_t)it * sb + j * b + l] * D[t * b + q]);
-                    }
-                nsum v = {0.0, 0.0};
-                nadd(&v, y[Sj[l]]);
-                nadd(&v, -(double)m * alpha[Sj[l]]);
-                nadd(&v, -(double)m * nval(&ov));
-                nadd(&v, -nval(&ua) / lambda);
-                nadd(&v, -nval(&uv) / lambda);
-                x[l] = nval(&v);
-            }
-            if ((rc = chol_solve(G, b, x)) != ORC_OK) goto out;
-        }
-        /* alpha_{sk+s} = alpha_sk + sum_t V_t Delta_t, in t order */
-        for (int64_t c = 0; c < sb; ++c) {
-            alpha[Om[c]] += D[c];
-            if (delta) delta[k0 * b + c] = D[c];
+    if (!cols || !G || !d) { rc = ORC_ERR_ALLOC; goto out; }
+    for (int64_t first = 0; first < H && rc == ORC_OK; first += s) {
+        const int64_t len = (H - first < s) ? H - first : s;     /* reading R2 */
+        const int32_t *grp = idx + first * b;
+        for (int64_t c = 0; c < len * b; ++c) kernel_column(A, k, grp[c], cols + c * m);
+        for (int64_t t = 0; t < len && rc == ORC_OK; ++t) {
+            rc = krr_block_step(cols + t * b * m, y, lambda, m, b, grp + t * b, alpha, G, d);
+            if (rc == ORC_OK && delta)
+                memcpy(delta + (first + t) * b, d, sizeof(double) * (size_t)b);
         }
     }
 out:
-    free(Q); free(col); free(G); free(D);
+    free(cols); free(G); free(d);
     return rc;
 }
 

@@ -163,6 +163,25 @@ def test_slog_feature_values():
     assert np.all(np.sign(xs) == np.sign(gg))
 
 
+def test_ksvm_features_hand_rows():
+    """Feature map (alpha_i / C, slog g_i, K_ii, y_i) on rows worked out by hand:
+    a swapped column, alpha * C instead of alpha / C, or a missing 1/8 fails."""
+    C = 10.0
+    alpha = [2.5, 0.0, 10.0, 5.0]
+    g = [2.0 ** -20, 0.5 * 2.0 ** -20, 2.0 ** -10, -3.0 * 2.0 ** -20]
+    kdiag = [1.0, 8.0, 1.0, 0.25]
+    y = [1.0, 1.0, -1.0, -1.0]
+    # slog: v = |g| 2^20; v = 1 -> 1; v = 0.5 -> 0.5; v = 2^10 = 0.5 * 2^11 -> 1 + 10 + 0 = 11;
+    # v = 3 = 0.75 * 2^2 -> 1 + 1 + 0.5 = 2.5; then sign(g) and a factor 1/8
+    expect = np.array([[0.25, 0.125, 1.0, 1.0],
+                       [0.0, 0.0625, 8.0, 1.0],
+                       [1.0, 1.375, 1.0, -1.0],
+                       [0.5, -0.3125, 0.25, -1.0]], dtype=np.float32)
+    x = S.ksvm_features(alpha, g, kdiag, y, C)
+    assert x.dtype == np.float32 and x.shape == (4, 4)
+    np.testing.assert_array_equal(x, expect)
+
+
 def test_pool_candidates_and_pool_selection():
     c = np.concatenate([S.pool_candidates(50, 512, k, seed=3) for k in range(100)])
     assert c.min() >= 0 and c.max() < 50
