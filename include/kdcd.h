@@ -118,14 +118,6 @@ typedef struct {
  * serialised by one lock.  With a profile, only total_ms is reported.
  */
 /*
- * KDCD_FLAG_OVERLAP (dense FP64 kdcd_ksvm_solve / kdcd_krr_solve, not with
- * the monitor or graph replay): the recurrence of each outer iteration runs
- * on a second stream of the device next to the next kernel-block product,
- * which leaves out the rows the recurrence is changing; a small correction
- * adds them afterwards (same result up to the order of the sums).  Two
- * cross-stream event waits per outer iteration are on its critical path.
- */
-/*
  * KDCD_FLAG_TIME_PRODUCT (with a profile; dense FP64 kdcd_ksvm_solve /
  * kdcd_krr_solve on the serial loop): only the kernel-block product is timed
  * (kblock_ms, kblock_launches and total_ms from its first start to its last
@@ -137,9 +129,9 @@ typedef struct {
  * launches of outer iterations k with k % 8 == 0 are timed (kblock_launches
  * counts them), which keeps the timing's device cost to one launch in eight.
  */
+/* Any other bit of flags is refused with KDCD_ERR_INVALID_ARG. */
 enum {
     KDCD_FLAG_GRAPH = 1,
-    KDCD_FLAG_OVERLAP = 2,
     KDCD_FLAG_TIME_PRODUCT = 4,
     KDCD_FLAG_TIME_SAMPLE = 8
 };

@@ -165,22 +165,19 @@ struct KBlockArgs {
     int32_t *pos;
     const int32_t *prevS;
     int32_t prev_sb;
-    // dense F64 only, lookahead (requires pos): rows of prevS are left out of
-    // the reduction (a concurrent recurrence is updating their beta) and their
-    // kernel rows go to X[t][j] = K(a_{prevS_t}, a_{S_j}) instead, t the first
-    // position of the row in prevS (posX[p], or INT32_MAX when p is not in
-    // prevS; the launch clears the entries of prev2S and marks prevS).
-    int32_t *posX;
-    const int32_t *prev2S;
-    int32_t prev2_sb;
-    double *X;
     // CSR only: m + s*b doubles of scratch for sampled rows longer than the
     // LDS panel (their dot products are summed over pieces); null refuses them
     double *carry;
+    // dense single-problem FP64 product: tile configuration, resolved once by
+    // the caller together with the row-group count the finish pass sums
+    // (-1: looked up in the tuning table at launch)
+    int32_t cfg = -1;
 };
 
 // Launchers (return hipError_t of the launch).
-int64_t kblock_f64_row_groups(int64_t m, int64_t n, int32_t sb, bool batch = false);
+// Row groups of a dense FP64 launch with configuration cfg (single problem;
+// cfg < 0: the tuning table's choice for (n, sb)) or of a batched launch.
+int64_t kblock_f64_row_groups(int cfg, int64_t m, int64_t n, int32_t sb, bool batch = false);
 // Tile configurations of the FP64 product and the process-wide tuning table.
 int f64_config_count();
 void f64_config_shape(int id, int *bm, int *bn, int *waves);
@@ -268,11 +265,6 @@ hipError_t launch_rho_init(const double *Ka, const double *y, const double *alph
                            double inv_lambda, double mdbl, int64_t m, double *rho, hipStream_t st);
 
 // r[j] += sum over the first occurrences t in prevS of X[t][j] * beta(prevS_t),
-// beta = alpha (o bscale): the rows a lookahead launch left out.
-hipError_t launch_lookahead_fix(const double *X, const int32_t *prevS, int32_t xsb,
-                                const double *alpha, const double *bscale, double *r, int32_t sb,
-                                hipStream_t st);
-
 hipError_t launch_finish(const FinishDesc &d, int32_t sb, int32_t b, int32_t sk, double mdbl,
                          int32_t *status, hipStream_t st);
 hipError_t launch_ksvm_recur(const KsvmRecurDesc &d, int32_t nprob, const int32_t *S, int32_t sb,

@@ -59,8 +59,7 @@ void kblock_f64_kernel(
     double *__restrict__ partial, double *__restrict__ W, int32_t n_u_tiles,
     int32_t n_row_groups, int32_t n_w_tiles, int32_t n_tiles_n, int32_t aligned,
     const BatchDesc *__restrict__ bd, double *__restrict__ U, const int32_t *__restrict__ stop,
-    const int32_t *__restrict__ pos, const int32_t *__restrict__ posX, double *__restrict__ X,
-    int32_t xsb)
+    const int32_t *__restrict__ pos)
 {
     if (stop && *stop) return;   // the solve has converged
     constexpr int NT = 64 * WM * WN;
@@ -359,15 +358,8 @@ void kblock_f64_kernel(
                     const int64_t grow = row0 + lrow;
                     if (!is_w) {
                         if (grow < m) {
-                            // a row of the previous block (lookahead): its beta is being
-                            // updated concurrently, so it goes to X instead of the sums
-                            const int32_t xrow = posX ? posX[grow] : INT32_MAX;
-                            const bool held = xrow < xsb;
-                            double bval = 0.0;
-                            if (!held) {
-                                bval = beta[grow];
-                                if (bscale) bval *= bscale[grow];
-                            }
+                            double bval = beta[grow];
+                            if (bscale) bval *= bscale[grow];
                             const double na = (KIND == KDCD_KERNEL_RBF) ? norms[grow] : 0.0;
                             const int32_t wrow = pos ? pos[grow] : -1;   // row of W, if sampled
 #pragma unroll
@@ -376,8 +368,7 @@ void kblock_f64_kernel(
                                     const double kv = kernel_map<KIND>(acc[tm][tn][v], na, nb[tn],
                                                                        grow == Sc[tn], kp);
                                     const int64_t gcol = col0 + (wn * TN + tn) * 16 + (lane & 15);
-                                    if (held) X[(int64_t)xrow * sb + gcol] = kv;
-                                    else colsum[tn] += bval * kv;
+                                    colsum[tn] += bval * kv;
                                     if (U) U[gcol * m + grow] = kv;
                                     if (wrow >= 0 && wrow < sb) W[(int64_t)wrow * sb + gcol] = kv;
                                 }
@@ -427,16 +418,11 @@ void kblock_f64_kernel(
 }
 
 // pos[] upkeep: clear the previous block's entries, then mark the new one
-// (one workgroup, so the clears are ordered before the marks).  With posX
-// (lookahead) also clear prev2S's entries and mark the first position of
-// every row of prevS.
+// (one workgroup, so the clears are ordered before the marks).
 __global__ __launch_bounds__(1024) void pos_set_kernel(int32_t *__restrict__ pos, int64_t m,
                                                        const int32_t *__restrict__ prevS,
                                                        int32_t prev_sb,
                                                        const int32_t *__restrict__ S, int32_t sb,
-                                                       int32_t *__restrict__ posX,
-                                                       const int32_t *__restrict__ prev2S,
-                                                       int32_t prev2_sb,
                                                        const int32_t *__restrict__ stop)
 {
     if (stop && *stop) return;
@@ -444,21 +430,11 @@ __global__ __launch_bounds__(1024) void pos_set_kernel(int32_t *__restrict__ pos
         const int32_t p = prevS[t];
         if (p >= 0 && p < m) pos[p] = -1;
     }
-    if (posX)
-        for (int t = threadIdx.x; t < prev2_sb; t += blockDim.x) {
-            const int32_t p = prev2S[t];
-            if (p >= 0 && p < m) posX[p] = INT32_MAX;
-        }
     __syncthreads();
     for (int t = threadIdx.x; t < sb; t += blockDim.x) {
         const int32_t p = S[t];
         if (p >= 0 && p < m) pos[p] = t;
     }
-    if (posX)
-        for (int t = threadIdx.x; t < prev_sb; t += blockDim.x) {
-            const int32_t p = prevS[t];
-            if (p >= 0 && p < m) atomicMin(&posX[p], t);
-        }
 }
 
 // Rows of W for repeated indices: row t copies the row written for S_t.
@@ -475,38 +451,6 @@ __global__ __launch_bounds__(256) void w_dup_kernel(double *__restrict__ W, int6
     if (r == t || r < 0) return;
     for (int j = threadIdx.x; j < sb; j += blockDim.x)
         W[(int64_t)t * sb + j] = W[(int64_t)r * sb + j];
-}
-
-// r[j] += sum_{t first occurrence in prevS} X[t][j] beta(prevS_t), t ascending.
-__global__ __launch_bounds__(256) void lookahead_fix_kernel(const double *__restrict__ X,
-                                                            const int32_t *__restrict__ prevS,
-                                                            int32_t xsb,
-                                                            const double *__restrict__ alpha,
-                                                            const double *__restrict__ bscale,
-                                                            double *__restrict__ r, int32_t sb)
-{
-    __shared__ int32_t Sl[kMaxSB];
-    __shared__ double bv[kMaxSB];
-    for (int t = threadIdx.x; t < xsb; t += blockDim.x) Sl[t] = prevS[t];
-    __syncthreads();
-    for (int t = threadIdx.x; t < xsb; t += blockDim.x) {
-        const int32_t p = Sl[t];
-        bool first = true;
-        for (int q = 0; q < t && first; ++q) first = Sl[q] != p;
-        double b = 0.0;
-        if (first) {
-            b = alpha[p];
-            if (bscale) b *= bscale[p];
-        }
-        bv[t] = b;                    // 0 for repeats: each row counts once
-    }
-    __syncthreads();
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= sb) return;
-    double acc = 0.0;
-    for (int t = 0; t < xsb; ++t)
-        if (bv[t] != 0.0) acc = fma(X[(int64_t)t * sb + j], bv[t], acc);
-    r[j] += acc;
 }
 
 struct Cfg {
@@ -534,8 +478,7 @@ hipError_t launch_cfg(const KBlockArgs &a, hipStream_t st)
                        A->values, A->ld, A->m, A->n, a.S, a.sb, a.norms, a.kp, a.beta,          \
                        a.beta_scale, a.partial, a.W, (int32_t)n_u, (int32_t)groups,            \
                        (int32_t)n_w, (int32_t)n_n, aligned, a.batch, BATCH ? nullptr : a.U,   \
-                       a.stop, BATCH ? nullptr : a.pos, BATCH ? nullptr : a.posX, a.X,         \
-                       a.prevS ? a.prev_sb : 0)
+                       a.stop, BATCH ? nullptr : a.pos)
 #define KDCD_LAUNCH(KIND)                                                                      \
     do {                                                                                        \
         if (full) KDCD_LAUNCH_F(KIND, true);                                                    \
@@ -580,15 +523,6 @@ constexpr int kF64NumCfgs = sizeof(kF64Cfgs) / sizeof(kF64Cfgs[0]);
 
 int f64_config_count() { return kF64NumCfgs; }
 
-hipError_t launch_lookahead_fix(const double *X, const int32_t *prevS, int32_t xsb,
-                                const double *alpha, const double *bscale, double *r, int32_t sb,
-                                hipStream_t st)
-{
-    hipLaunchKernelGGL(lookahead_fix_kernel, dim3((unsigned)((sb + 255) / 256)), dim3(256), 0, st,
-                       X, prevS, xsb, alpha, bscale, r, sb);
-    return hipGetLastError();
-}
-
 void f64_config_shape(int id, int *bm, int *bn, int *waves)
 {
     const F64Cfg &c = kF64Cfgs[id];
@@ -612,14 +546,14 @@ int f64_config_id(int64_t n, int32_t sb)
     return (id >= 0 && id < kF64NumCfgs) ? id : f64_default_id(sb);
 }
 
-int64_t kblock_f64_row_groups(int64_t m, int64_t n, int32_t sb, bool batch)
+int64_t kblock_f64_row_groups(int cfg, int64_t m, int64_t n, int32_t sb, bool batch)
 {
     int bm;
     if (batch) {
         bm = pick_cfg_batch(sb).bm;
     } else {
         int bn, w;
-        f64_config_shape(f64_config_id(n, sb), &bm, &bn, &w);
+        f64_config_shape(cfg >= 0 && cfg < kF64NumCfgs ? cfg : f64_config_id(n, sb), &bm, &bn, &w);
     }
     const int64_t n_u = (m + bm - 1) / bm;
     return n_u < kMaxRowGroups ? n_u : kMaxRowGroups;
@@ -631,8 +565,7 @@ hipError_t launch_kblock_f64_pre(const KBlockArgs &a, hipStream_t st)
 {
     if (a.batch || !(a.W && a.pos && !a.w_only)) return hipSuccess;
     hipLaunchKernelGGL(pos_set_kernel, dim3(1), dim3(1024), 0, st, a.pos, a.A->m, a.prevS,
-                       a.prevS ? a.prev_sb : 0, a.S, a.sb, a.posX, a.prev2S,
-                       a.prev2S ? a.prev2_sb : 0, a.stop);
+                       a.prevS ? a.prev_sb : 0, a.S, a.sb, a.stop);
     return hipGetLastError();
 }
 
@@ -645,11 +578,8 @@ hipError_t launch_kblock_f64_main(const KBlockArgs &a, hipStream_t st)
         return launch_cfg<2, 2, 2, 2, true>(a, st);
     }
     KBlockArgs b = a;
-    if (!(a.W && a.pos && !a.w_only)) {
-        b.pos = nullptr;
-        b.posX = nullptr;
-    }
-    switch (f64_config_id(a.A->n, a.sb)) {
+    if (!(a.W && a.pos && !a.w_only)) b.pos = nullptr;
+    switch (a.cfg >= 0 && a.cfg < kF64NumCfgs ? a.cfg : f64_config_id(a.A->n, a.sb)) {
     case 0: return launch_cfg<4, 1, 2, 1, false>(b, st);
     case 1: return launch_cfg<4, 1, 2, 2, false>(b, st);
     case 2: return launch_cfg<2, 2, 2, 2, false>(b, st);

@@ -90,11 +90,20 @@ kdcd_status check_compute(const kdcd_matrix *A, int32_t compute)
     return KDCD_OK;
 }
 
-int64_t row_groups(const kdcd_matrix *A, int32_t sb, int32_t compute, bool batch = false)
+// The product's tile configuration is looked up once (into kb.cfg) and the
+// finish pass sums the row groups of that same configuration, so a change of
+// the tuning table between the two cannot pair a launch with the wrong count.
+// Uses kb.A, kb.sb and kb.compute; returns the row-group count.
+int64_t bind_config(KBlockArgs &kb, bool batch = false)
 {
-    if (A->format == KDCD_CSR) return kblock_csr_row_groups(A->m, sb);
-    if (compute == KDCD_F64) return kblock_f64_row_groups(A->m, A->n, sb, batch);
-    return kblock_mixed_row_groups(A->m, sb, batch);
+    const kdcd_matrix *A = kb.A;
+    kb.cfg = -1;
+    if (A->format == KDCD_CSR) return kblock_csr_row_groups(A->m, kb.sb);
+    if (kb.compute == KDCD_F64) {
+        if (!batch) kb.cfg = f64_config_id(A->n, kb.sb);
+        return kblock_f64_row_groups(kb.cfg, A->m, A->n, kb.sb, batch);
+    }
+    return kblock_mixed_row_groups(A->m, kb.sb, batch);
 }
 
 // One kernel-block pass.  Mixed precisions produce the U-part only; their
@@ -117,25 +126,11 @@ size_t lowp_elem_bytes(int32_t compute) { return compute == KDCD_F32 ? 4 : 2; }
 struct Layout {
     size_t status, norms, partial, r, W, Dinv, iota, hi, lo, normlow, pos, carry, total;
     int64_t ldlow;
-    // lookahead (0 when off): second partial and W buffers, two cross blocks,
-    // the previous-block row table
-    size_t la_partial, la_W, la_X0, la_X1, la_posX;
     // convergence monitor (0 when off): state, partial sums, maintained
     // gradient / residual (m), stored kernel block (s*b x m), updates (s*b),
     // scratch m-vector
     size_t mon, mon_part, mon_v, mon_U, mon_th, mon_tmp;
 };
-
-void add_lookahead(Layout &L, int64_t m, int64_t sbmax)
-{
-    size_t off = L.total;
-    L.la_partial = off; off += align256(sizeof(double) * (size_t)(kMaxGroups * sbmax));
-    L.la_W = off; off += align256(sizeof(double) * (size_t)(sbmax * sbmax));
-    L.la_X0 = off; off += align256(sizeof(double) * (size_t)(sbmax * sbmax));
-    L.la_X1 = off; off += align256(sizeof(double) * (size_t)(sbmax * sbmax));
-    L.la_posX = off; off += align256(sizeof(int32_t) * (size_t)m);
-    L.total = off;
-}
 
 void add_monitor(Layout &L, int64_t m, int64_t sbmax)
 {
@@ -525,6 +520,7 @@ kdcd_status enqueue_solve(const SolveArgs &sa, const Layout &L, char *wsbase, St
         // and each recurrence prepares the row -> position table of the next
         // block, so only the first block needs the separate update launch
         const bool fused = !svm && kb.W && kb.pos && !kb.w_only;
+        const int64_t groups = bind_config(kb);
         if (A->format == KDCD_DENSE && sa.opt.compute == KDCD_F64) {
             // the product kernel times itself (the row-position update and
             // the repeated-row copies of the gathered Gram are not timed)
@@ -542,7 +538,7 @@ kdcd_status enqueue_solve(const SolveArgs &sa, const Layout &L, char *wsbase, St
         FinishDesc fd{};
         fd.nprob = 1;
         fd.nkrr = svm ? 0 : 1;
-        fd.groups = (int32_t)row_groups(A, sb, sa.opt.compute);
+        fd.groups = (int32_t)groups;
         fd.partial[0] = partial;
         fd.r[0] = r;
         fd.W[0] = W;
@@ -630,192 +626,6 @@ kdcd_status enqueue_solve(const SolveArgs &sa, const Layout &L, char *wsbase, St
                                         sizeof(double) * (size_t)A->m, hipMemcpyDeviceToDevice,
                                         st));
     }
-    return KDCD_OK;
-}
-
-// ------------------------------------------------------------ lookahead
-// KDCD_FLAG_OVERLAP: dense FP64 single-problem solves overlap the recurrence
-// of outer iteration k (on a second stream) with the kernel-block product of
-// iteration k+1 (on the caller's stream).  The product of k+1 reads beta everywhere except the
-// rows of S_k, which the running recurrence is changing; those rows' kernel
-// values go to a cross block X = K(A_{S_k}, A_{S_{k+1}}), and once the
-// recurrence is done a small kernel adds X^T beta(S_k) (each row once) to
-// r_{k+1}.  Partials, W and X are double-buffered; events order the streams:
-//   caller stream: [wait F(k)] pos -> product(k+1) -> W duplicates -> event P(k+1)
-//   second stream: [wait P(k+1)] finish(k+1) -> correction -> event F(k+1) -> recur(k+1)
-// The product of k+1 needs recur(k-1) (the last writer of the rows it reads
-// and of the buffers it reuses), which F(k) implies, but not recur(k): the
-// one-workgroup recurrence runs next to the product.
-
-hipStream_t aux_stream()
-{
-    static std::mutex mu;
-    static hipStream_t streams[64] = {};
-    int dev = -1;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
-    std::lock_guard<std::mutex> lk(mu);
-    if (!streams[dev] && hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking) != hipSuccess)
-        return nullptr;
-    return streams[dev];
-}
-
-struct EventRing {
-    static constexpr int N = 4;
-    hipEvent_t ev[N] = {};
-    bool ok = true;
-    EventRing()
-    {
-        for (auto &e : ev)
-            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) ok = false;
-    }
-    ~EventRing()
-    {
-        for (auto &e : ev)
-            if (e) (void)hipEventDestroy(e);
-    }
-    hipEvent_t operator[](int64_t k) const { return ev[k % N]; }
-};
-
-// Events of a lookahead solve; they outlive the enqueue (destroyed after the
-// caller has synchronised).
-struct LookaheadEvents {
-    EventRing P, R, F;
-    hipEvent_t start = nullptr;
-    bool ok = false;
-    LookaheadEvents()
-    {
-        ok = P.ok && R.ok && F.ok && hipEventCreateWithFlags(&start, hipEventDisableTiming) == hipSuccess;
-    }
-    ~LookaheadEvents()
-    {
-        if (start) (void)hipEventDestroy(start);
-    }
-};
-
-kdcd_status enqueue_solve_lookahead(const SolveArgs &sa, const Layout &L, char *wsbase,
-                                    StageTimer &timer, hipStream_t aux, LookaheadEvents &E)
-{
-    const kdcd_matrix *A = sa.A;
-    const hipStream_t st = sa.st;
-    Workspace ws;
-    ws.base = wsbase;
-    int32_t *status = ws.at<int32_t>(L.status);
-    double *norms = ws.at<double>(L.norms);
-    double *part[2] = {ws.at<double>(L.partial), ws.at<double>(L.la_partial)};
-    double *Wb[2] = {ws.at<double>(L.W), ws.at<double>(L.la_W)};
-    double *Xb[2] = {ws.at<double>(L.la_X0), ws.at<double>(L.la_X1)};
-    double *r = ws.at<double>(L.r);
-    double *Dinv = sa.problem == 1 ? ws.at<double>(L.Dinv) : nullptr;
-    const bool svm = sa.problem == 0;
-    const double nu = svm ? (sa.opt.loss == 2 ? INFINITY : sa.C) : 0.0;
-    const double omega = (svm && sa.opt.loss == 2) ? 1.0 / (2.0 * sa.C) : 0.0;
-    if (!E.ok) return KDCD_ERR_HIP;
-    const EventRing &evP = E.P, &evR = E.R, &evF = E.F;
-    hipEvent_t start = E.start;
-
-    KDCD_HIP_TRY(launch_fill_i32(status, 0, 1, st));
-    KDCD_HIP_TRY(launch_validate(sa.idx, sa.H * sa.b, A->m, sa.y, sa.alpha, A->m, sa.problem, nu,
-                                 status, st));
-    if (sa.kernel->kind == KDCD_KERNEL_RBF) KDCD_HIP_TRY(launch_norms(A, norms, st));
-    KBlockArgs kb{};
-    kb.A = A;
-    kb.norms = norms;
-    kb.kp = to_params(sa.kernel);
-    kb.beta = sa.alpha;
-    kb.beta_scale = svm ? sa.y : nullptr;
-    kb.status = status;
-    kb.compute = KDCD_F64;
-    kb.pos = ws.at<int32_t>(L.pos);
-    kb.posX = ws.at<int32_t>(L.la_posX);
-    KDCD_HIP_TRY(launch_fill_i32(kb.pos, -1, A->m, st));
-    KDCD_HIP_TRY(launch_fill_i32(kb.posX, INT32_MAX, A->m, st));
-    KDCD_HIP_TRY(hipEventRecord(start, st));
-    KDCD_HIP_TRY(hipStreamWaitEvent(aux, start, 0));      // the second stream starts after set-up
-
-    const int64_t n_outer = (sa.H + sa.s - 1) / sa.s;
-    int64_t snap = 0;
-    const int32_t *S_prev = nullptr, *S_prev2 = nullptr;
-    int32_t sb_prev = 0, sb_prev2 = 0;
-    for (int64_t k = 0; k < n_outer; ++k) {
-        const int64_t done = k * sa.s;
-        const int32_t sk = (int32_t)std::min<int64_t>(sa.s, sa.H - done);
-        const int32_t sb = sk * sa.b;
-        const int32_t *S = sa.idx + done * sa.b;
-        const int q = (int)(k & 1);
-        // product k on the caller's stream, once finish(k-1) and its correction
-        // are done (so that those short many-workgroup kernels are not starved
-        // behind the product); it then runs next to recur(k-1)
-        if (k >= 1) KDCD_HIP_TRY(hipStreamWaitEvent(st, evF[k - 1], 0));
-        kb.S = S;
-        kb.sb = sb;
-        kb.prevS = S_prev;
-        kb.prev_sb = sb_prev;
-        kb.prev2S = S_prev2;
-        kb.prev2_sb = sb_prev2;
-        kb.partial = part[q];
-        kb.W = Wb[q];
-        kb.X = Xb[q];
-        timer.begin(0, st);
-        KDCD_HIP_TRY(launch_kblock(kb, st));
-        timer.end(0, st);
-        KDCD_HIP_TRY(hipEventRecord(evP[k], st));
-        // finish, correction and recurrence k on the second stream
-        KDCD_HIP_TRY(hipStreamWaitEvent(aux, evP[k], 0));
-        timer.begin(1, aux);
-        FinishDesc fd{};
-        fd.nprob = 1;
-        fd.nkrr = svm ? 0 : 1;
-        fd.groups = (int32_t)row_groups(A, sb, KDCD_F64);
-        fd.partial[0] = part[q];
-        fd.r[0] = r;
-        fd.W[0] = Wb[q];
-        fd.Dinv[0] = Dinv;
-        fd.inv_lambda[0] = svm ? 0.0 : 1.0 / sa.lambda;
-        KDCD_HIP_TRY(launch_finish(fd, sb, sa.b, sk, (double)A->m, status, aux));
-        if (S_prev)
-            KDCD_HIP_TRY(launch_lookahead_fix(Xb[q], S_prev, sb_prev, sa.alpha,
-                                              svm ? sa.y : nullptr, r, sb, aux));
-        KDCD_HIP_TRY(hipEventRecord(evF[k], aux));
-        timer.end(1, aux);
-        timer.begin(2, aux);
-        double *tr = sa.opt.trace ? sa.opt.trace + done * sa.b : nullptr;
-        if (svm) {
-            KsvmRecurDesc kd{};
-            kd.r[0] = r;
-            kd.W[0] = Wb[q];
-            kd.y[0] = sa.y;
-            kd.alpha[0] = sa.alpha;
-            kd.trace[0] = tr;
-            kd.nu[0] = nu;
-            kd.omega[0] = omega;
-            KDCD_HIP_TRY(launch_ksvm_recur(kd, 1, S, sb, A->m, status, aux));
-        } else {
-            KrrRecurDesc rd{};
-            rd.r[0] = r;
-            rd.W[0] = Wb[q];
-            rd.Dinv[0] = Dinv;
-            rd.y[0] = sa.y;
-            rd.alpha[0] = sa.alpha;
-            rd.trace[0] = tr;
-            rd.lambda[0] = sa.lambda;
-            KDCD_HIP_TRY(launch_krr_recur(rd, 1, S, sa.b, sk, A->m, (double)A->m, status, aux));
-        }
-        timer.end(2, aux);
-        if (sa.opt.snapshot_every > 0 && sa.opt.snapshots &&
-            ((k + 1) % sa.opt.snapshot_every == 0 || k + 1 == n_outer)) {
-            KDCD_HIP_TRY(hipMemcpyAsync(sa.opt.snapshots + snap * A->m, sa.alpha,
-                                        sizeof(double) * (size_t)A->m, hipMemcpyDeviceToDevice,
-                                        aux));
-            ++snap;
-        }
-        KDCD_HIP_TRY(hipEventRecord(evR[k], aux));
-        S_prev2 = S_prev;
-        sb_prev2 = sb_prev;
-        S_prev = S;
-        sb_prev = sb;
-    }
-    // join: the caller's stream waits for the last recurrence
-    KDCD_HIP_TRY(hipStreamWaitEvent(st, evR[n_outer - 1], 0));
     return KDCD_OK;
 }
 
@@ -983,11 +793,6 @@ kdcd_status run_solve(const SolveArgs &sa)
     if (rc != KDCD_OK) return rc;
     Layout L = make_layout(sa.problem, sa.A, sa.kernel, sa.b, sa.s, sa.opt.compute);
     if (sa.opt.monitor_every > 0) add_monitor(L, sa.A->m, (int64_t)sa.s * sa.b);
-    const int64_t n_outer = (sa.H + sa.s - 1) / sa.s;
-    const bool lookahead = (sa.opt.flags & KDCD_FLAG_OVERLAP) && sa.A->format == KDCD_DENSE &&
-                           sa.opt.compute == KDCD_F64 && sa.opt.monitor_every == 0 &&
-                           n_outer >= 2 && !(sa.opt.flags & KDCD_FLAG_GRAPH);
-    if (lookahead) add_lookahead(L, sa.A->m, (int64_t)sa.s * sa.b);
     if (sa.opt.flags & KDCD_FLAG_GRAPH) {
         KeyBuilder kb;
         kb.add('S');
@@ -1010,17 +815,9 @@ kdcd_status run_solve(const SolveArgs &sa)
     if ((rc = acquire(ws, L, &sa.opt, sa.st)) != KDCD_OK) return rc;
     StageTimer timer;
     timer.on = sa.opt.profile != nullptr;
-    hipStream_t aux = lookahead ? aux_stream() : nullptr;
-    std::unique_ptr<LookaheadEvents> events;   // destroyed after the status read below
-    if (lookahead && aux) {
-        events.reset(new LookaheadEvents());
-        rc = enqueue_solve_lookahead(sa, L, ws.base, timer, aux, *events);
-    } else {
-        rc = enqueue_solve(sa, L, ws.base, timer);
-    }
+    rc = enqueue_solve(sa, L, ws.base, timer);
     if (rc != KDCD_OK) {
         (void)hipStreamSynchronize(sa.st);
-        if (aux) (void)hipStreamSynchronize(aux);
         return rc;
     }
     rc = read_status(ws.at<int32_t>(L.status), sa.st);
@@ -1044,6 +841,8 @@ kdcd_status common_checks(const kdcd_matrix *A, const double *y, const kdcd_kern
         if ((rc = check_compute(A, opt->compute)) != KDCD_OK) return rc;
         if (opt->snapshot_every < 0) return KDCD_ERR_INVALID_ARG;
         if (opt->snapshot_every > 0 && !opt->snapshots) return KDCD_ERR_INVALID_ARG;
+        if (opt->flags & ~(KDCD_FLAG_GRAPH | KDCD_FLAG_TIME_PRODUCT | KDCD_FLAG_TIME_SAMPLE))
+            return KDCD_ERR_INVALID_ARG;
     }
     if ((int64_t)s * b > kMaxSB) return KDCD_ERR_UNSUPPORTED;
     return KDCD_OK;
@@ -1215,9 +1014,9 @@ kdcd_status kdcd_batch_solve(const kdcd_matrix *A, const kdcd_kernel *kernel, in
         const int32_t sk = (int32_t)std::min<int64_t>(s, H - done);
         const int32_t sb = sk * b;
         const int32_t *S = idx + done * b;
-        const int32_t groups = (int32_t)row_groups(A, sb, o.compute, true);
         kb.S = S;
         kb.sb = sb;
+        const int32_t groups = (int32_t)bind_config(kb, true);
         timer.begin(0, st);
         KDCD_HIP_TRY(launch_kblock(kb, st));
         timer.end(0, st);
@@ -1461,13 +1260,14 @@ kdcd_status kdcd_ksvm_solve_sampled(const kdcd_matrix *A, const double *y,
         kb.prev_sb = kb.sb;
         kb.S = S;
         kb.sb = sk;
+        const int64_t groups = bind_config(kb);
         timer.begin(0, st);
         KDCD_HIP_TRY(launch_kblock(kb, st));
         timer.end(0, st);
         timer.begin(1, st);
         FinishDesc fd{};
         fd.nprob = 1;
-        fd.groups = (int32_t)row_groups(A, sk, KDCD_F64);
+        fd.groups = (int32_t)groups;
         fd.partial[0] = partial;
         fd.r[0] = r;
         fd.stop = stop;
@@ -1551,7 +1351,6 @@ kdcd_status kdcd_autotune(const kdcd_matrix *A, const kdcd_kernel *kernel, int32
         kb.prevS = S;                      // every launch re-marks the same block
         kb.prev_sb = sb;
     }
-    const int prev = tune_lookup(compute, A->n, sb);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return KDCD_ERR_HIP;
     // three interleaved rounds; a configuration's time is its fastest round
@@ -1560,7 +1359,7 @@ kdcd_status kdcd_autotune(const kdcd_matrix *A, const kdcd_kernel *kernel, int32
     rc = KDCD_OK;
     for (int round = 0; round < 3 && rc == KDCD_OK; ++round) {
         for (int id = 0; id < ncfg && rc == KDCD_OK; ++id) {
-            tune_store(compute, A->n, sb, id);
+            kb.cfg = id;                   // timed by id; the table changes only at the end
             float ms = 0.f;
             if (launch_kblock(kb, st) != hipSuccess || hipEventRecord(e0, st) != hipSuccess) {
                 rc = KDCD_ERR_HIP;
@@ -1587,8 +1386,8 @@ kdcd_status kdcd_autotune(const kdcd_matrix *A, const kdcd_kernel *kernel, int32
         }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    tune_store(compute, A->n, sb, rc == KDCD_OK ? best : prev);
     if (rc != KDCD_OK) return rc;
+    tune_store(compute, A->n, sb, best);
     if ((rc = read_status(ws.at<int32_t>(L.status), st)) != KDCD_OK) return rc;
     if (best_id) *best_id = best;
     if (best_us) *best_us = best_t;
@@ -1635,10 +1434,11 @@ kdcd_status kdcd_kernel_rhs(const kdcd_matrix *A, const kdcd_kernel *kernel, con
     if (A->format == KDCD_CSR) base.carry = ws.at<double>(L.carry);
     KBlockArgs kb;
     if ((rc = prepare_lowp(base, L, ws, st, kb)) != KDCD_OK) return rc;
+    const int64_t groups = bind_config(kb);
     KDCD_HIP_TRY(launch_kblock(kb, st));
     FinishDesc fd{};
     fd.nprob = 1;
-    fd.groups = (int32_t)row_groups(A, sb, compute);
+    fd.groups = (int32_t)groups;
     fd.partial[0] = partial;
     fd.r[0] = r;
     KDCD_HIP_TRY(launch_finish(fd, sb, 1, 0, 0.0, status, st));
@@ -1681,10 +1481,11 @@ static kdcd_status kernel_matvec(const kdcd_matrix *A, const kdcd_kernel *kernel
         a.status = status;
         a.compute = KDCD_F64;
         if (A->format == KDCD_CSR) a.carry = ws.at<double>(L.carry);
+        const int64_t groups = bind_config(a);
         KDCD_HIP_TRY(launch_kblock(a, st));
         FinishDesc fd{};
         fd.nprob = 1;
-        fd.groups = (int32_t)row_groups(A, sb, KDCD_F64);
+        fd.groups = (int32_t)groups;
         fd.partial[0] = partial;
         fd.r[0] = r;
         KDCD_HIP_TRY(launch_finish(fd, sb, 1, 0, 0.0, status, st));

@@ -30,7 +30,6 @@ KERNEL_LINEAR, KERNEL_POLY, KERNEL_RBF = 0, 1, 2
 DENSE, CSR_FORMAT = 0, 1
 COMPUTE = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3, "bf16x3": 4}
 FLAG_GRAPH = 1
-FLAG_OVERLAP = 2
 FLAG_TIME_PRODUCT = 4
 FLAG_TIME_SAMPLE = 8
 

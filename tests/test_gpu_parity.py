@@ -200,10 +200,8 @@ def test_determinism_and_resume(K):
     K.kdcd_krr_solve(A, y, RBF1, 1e-3, 8, 16, 48, I, a)
     K.kdcd_krr_solve(A, y, RBF1, 1e-3, 8, 16, 48, idx_dev(idx[48 * 8:]), a)
     assert torch.equal(a, one)
-    a = torch.zeros(1500, dtype=torch.float64, device="cuda")
-    K.kdcd_krr_solve(A, y, RBF1, 1e-3, 8, 16, 48, I, a, flags=K.FLAG_OVERLAP)
-    K.kdcd_krr_solve(A, y, RBF1, 1e-3, 8, 16, 48, idx_dev(idx[48 * 8:]), a, flags=K.FLAG_OVERLAP)
-    assert_parity(a.cpu().numpy(), runs[0], 1e-12, "resumed, overlapped")
+    with pytest.raises(K.KdcdError):         # an unknown flag bit is refused
+        K.kdcd_krr_solve(A, y, RBF1, 1e-3, 8, 16, 48, I, a, flags=2)
 
 
 def test_snapshots(K):

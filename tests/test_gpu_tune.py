@@ -67,3 +67,39 @@ def test_autotune_records_its_choice(K):
         print(f"autotune 8000x256 sb=256: config {best} {K.kdcd_tune_configs('f64')[best]} {us:.1f} us")
     finally:
         K.kdcd_tune_set("f64", 256, 256, -1)
+
+
+def test_table_changes_during_solves(K):
+    """Each launch resolves its tile configuration once and the finish pass sums
+    that configuration's row groups: a second thread flipping the table between
+    a 128-row and a 64-row tile while launches run leaves every result exact."""
+    import threading
+    m, n, sb = 3000, 128, 128
+    rng = np.random.default_rng(11)
+    A = rng.standard_normal((m, n)) / np.sqrt(n)
+    S = rng.integers(0, m, size=sb).astype(np.int32)
+    beta = rng.standard_normal(m)
+    r_ref = O.kernel_rhs(A, O.Kernel(O.RBF, sigma=1.0), S, beta)
+    shapes = K.kdcd_tune_configs("f64")
+    ids = [i for i, (bm, _, _) in enumerate(shapes) if bm == 128][:1] + \
+          [i for i, (bm, _, _) in enumerate(shapes) if bm == 64][:1]
+    assert len(ids) == 2
+    done = threading.Event()
+
+    def flip():
+        k = 0
+        while not done.is_set():
+            K.kdcd_tune_set("f64", n, sb, ids[k % 2])
+            k += 1
+
+    t = threading.Thread(target=flip)
+    Ad, Sd, bd = dev(A), idx_dev(S), dev(beta)
+    t.start()
+    try:
+        for _ in range(20):
+            r = K.kdcd_kernel_rhs(Ad, (2, 1.0, 0.0, 1), Sd, bd)
+            assert_parity(r.cpu().numpy(), r_ref, 1e-11, "r while the table changes")
+    finally:
+        done.set()
+        t.join()
+        K.kdcd_tune_set("f64", n, sb, -1)
