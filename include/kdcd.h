@@ -215,6 +215,31 @@ kdcd_status kdcd_krr_solve(const kdcd_matrix *A, const double *y, const kdcd_ker
                            double lambda, int32_t b, int32_t s, int64_t H, const int32_t *idx,
                            double *alpha, const kdcd_options *opt, kdcd_stream stream);
 
+/*
+ * kdcd_krr_solve_noalloc -- kdcd_krr_solve for callers that cannot allocate
+ * device memory: code under stream capture, tight serving loops, harnesses
+ * that forbid allocation.  The workspace is a fixed array of
+ * KDCD_NOALLOC_SCRATCH_BYTES in the library's device memory (each device
+ * holds its own copy from the first such call on it until the process ends);
+ * the call allocates nothing.  Arguments and results are those of
+ * kdcd_krr_solve on the current device (stream must belong to it).
+ * opt: compute, snapshots and trace as in kdcd_krr_solve; workspace,
+ * workspace_bytes, monitor_every, flags and profile must be zero / NULL
+ * (UNSUPPORTED otherwise, since each of them allocates).
+ * Errors: those of kdcd_krr_solve, and WORKSPACE when
+ * kdcd_workspace_bytes(1, A, kernel, b, s, compute) exceeds
+ * KDCD_NOALLOC_SCRATCH_BYTES.
+ * All calls on one device share the one array: calls that overlap in time on
+ * a device (other host threads, or other streams before the previous call
+ * returned) race and give undefined results.  Every call rewrites the parts of
+ * the array it reads before reading them.
+ */
+#define KDCD_NOALLOC_SCRATCH_BYTES (32u << 20)
+kdcd_status kdcd_krr_solve_noalloc(const kdcd_matrix *A, const double *y,
+                                   const kdcd_kernel *kernel, double lambda, int32_t b, int32_t s,
+                                   int64_t H, const int32_t *idx, double *alpha,
+                                   const kdcd_options *opt, kdcd_stream stream);
+
 /* One problem of a batched solve. */
 typedef struct {
     int32_t problem;      /* 0 = K-SVM, 1 = K-RR                                        */

@@ -110,6 +110,8 @@ _lib.kdcd_ksvm_solve.argtypes = [_P, _P, _P, ctypes.c_double, ctypes.c_int32, ct
                                  ctypes.c_int64, _P, _P, _P, _P]
 _lib.kdcd_krr_solve.restype = ctypes.c_int
 _lib.kdcd_krr_solve.argtypes = _lib.kdcd_ksvm_solve.argtypes
+_lib.kdcd_krr_solve_noalloc.restype = ctypes.c_int
+_lib.kdcd_krr_solve_noalloc.argtypes = _lib.kdcd_ksvm_solve.argtypes
 _lib.kdcd_batch_solve.restype = ctypes.c_int
 _lib.kdcd_batch_solve.argtypes = [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, _P, _P,
                                   ctypes.c_int32, _P, _P]
@@ -311,6 +313,17 @@ def kdcd_krr_solve(A, y, kernel, lam, b, s, H, idx, alpha, *, compute="f64", sna
     return _solve(_lib.kdcd_krr_solve, "kdcd_krr_solve", A, y, kernel, lam, b, s, H, idx, alpha,
                   compute, 1, snapshot_every, snapshots, trace, workspace, profile, flags, stream,
                   monitor_every, tol)
+
+
+def kdcd_krr_solve_noalloc(A, y, kernel, lam, b, s, H, idx, alpha, *, compute="f64",
+                           snapshot_every=0, snapshots=None, trace=None, stream=None):
+    """kdcd_krr_solve with the library's fixed device workspace (no allocation)."""
+    return _solve(_lib.kdcd_krr_solve_noalloc, "kdcd_krr_solve_noalloc", A, y, kernel, lam, b, s,
+                  H, idx, alpha, compute, 1, snapshot_every, snapshots, trace, None, False, 0,
+                  stream)
+
+
+NOALLOC_SCRATCH_BYTES = 32 << 20
 
 
 def kdcd_nystrom_features(A, kernel, L, jitter, Phi, X=None, stream=None):
