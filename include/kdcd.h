@@ -463,11 +463,14 @@ kdcd_status kdcd_ksvm_solve_sampled(const kdcd_matrix *A, const double *y,
                                     const kdcd_options *opt, kdcd_stream stream);
 
 /* ---------------------------------------------------------------------------
- * Tuning of the kernel-block product.  The tile configuration of the FP64
- * product is chosen per (compute, n, sb) from a process-wide table, else by a
- * built-in rule.  Entries come from kdcd_autotune (which times every
- * configuration on the caller's matrix) or kdcd_tune_set, and can be saved to
- * and loaded from a text file.  Table updates must not overlap solves.
+ * Tuning of the kernel-block products.  The tile configuration of the FP64
+ * product and of the single-problem BF16 / F16 / BF16X3 product is chosen per
+ * (compute, n, sb) from a process-wide table, else by a built-in rule.
+ * Entries come from kdcd_autotune (which times every configuration on the
+ * caller's matrix) or kdcd_tune_set, and can be saved to and loaded from a
+ * text file.  A launch reads the table once and its finish pass uses the same
+ * configuration, so the table may change while solves run (they then take
+ * the old or the new entry).
  * ------------------------------------------------------------------------- */
 /* Number of configurations for `compute` (0 if not tunable); fills up to
  * `max` entries of bm, bn (tile rows x columns) and waves per workgroup
@@ -479,7 +482,8 @@ kdcd_status kdcd_tune_set(int32_t compute, int64_t n, int32_t sb, int32_t id);
 int32_t kdcd_tune_get(int32_t compute, int64_t n, int32_t sb);
 /* Time every configuration on A with sb sampled rows (evenly strided),
  * three rounds of `reps` launches each (a configuration counts with its
- * fastest round), record the fastest for (compute, A->n, sb).
+ * fastest round), record the fastest for (compute, A->n, sb).  The
+ * low-precision products are timed without the FP64 Gram launch.
  * best_id / best_us (host, may be NULL) receive the winner and its mean
  * launch time.  Dense A only.  Synchronises `stream`. */
 kdcd_status kdcd_autotune(const kdcd_matrix *A, const kdcd_kernel *kernel, int32_t sb,

@@ -184,7 +184,14 @@ void f64_config_shape(int id, int *bm, int *bn, int *waves);
 int f64_config_id(int64_t n, int32_t sb);
 int tune_lookup(int32_t compute, int64_t n, int32_t sb);   // -1: no entry
 void tune_store(int32_t compute, int64_t n, int32_t sb, int id);   // id < 0 removes
-int64_t kblock_mixed_row_groups(int64_t m, int32_t sb, bool batch = false);
+int64_t kblock_mixed_row_groups(int64_t m, int32_t sb, int32_t compute, bool batch = false);
+// Single-problem bf16 / fp16 / bf16x3 product (32 x 32 x 16 MFMA tiles) and
+// its tile configurations (tuning table entries under the compute id).
+int lowp_config_count();
+void lowp_config_shape(int id, int *bm, int *bn, int *waves);
+int lowp_config_id(int32_t compute, int64_t n, int32_t sb);
+int64_t kblock_lowp_row_groups(int cfg, int64_t m);
+hipError_t launch_kblock_lowp(const KBlockArgs &a, hipStream_t st);
 hipError_t launch_kblock_f64(const KBlockArgs &a, hipStream_t st);
 // launch_kblock_f64 = pre (row positions of the gathered Gram) + main (the
 // product) + post (repeated Gram rows); pre and post do nothing outside the

@@ -464,8 +464,9 @@ hipError_t launch_for(const KBlockArgs &a, hipStream_t st)
 
 }  // namespace
 
-int64_t kblock_mixed_row_groups(int64_t m, int32_t sb, bool batch)
+int64_t kblock_mixed_row_groups(int64_t m, int32_t sb, int32_t compute, bool batch)
 {
+    (void)compute;   // single-problem bf16 / fp16 / bf16x3 launches use the lowp product
     const Cfg c = batch ? pick_cfg_batch(sb) : pick_cfg(sb);
     const int64_t n_u = (m + c.bm - 1) / c.bm;
     return n_u < kMaxRowGroups ? n_u : kMaxRowGroups;
@@ -473,6 +474,7 @@ int64_t kblock_mixed_row_groups(int64_t m, int32_t sb, bool batch)
 
 hipError_t launch_kblock_mixed(const KBlockArgs &a, hipStream_t st)
 {
+    if (!a.batch && a.compute != KDCD_F32) return launch_kblock_lowp(a, st);
     switch (a.compute) {
     case KDCD_F32: return launch_for<KDCD_F32>(a, st);
     case KDCD_BF16: return launch_for<KDCD_BF16>(a, st);

@@ -103,7 +103,11 @@ int64_t bind_config(KBlockArgs &kb, bool batch = false)
         if (!batch) kb.cfg = f64_config_id(A->n, kb.sb);
         return kblock_f64_row_groups(kb.cfg, A->m, A->n, kb.sb, batch);
     }
-    return kblock_mixed_row_groups(A->m, kb.sb, batch);
+    if (!batch && kb.compute != KDCD_F32) {
+        kb.cfg = lowp_config_id(kb.compute, A->n, kb.sb);
+        return kblock_lowp_row_groups(kb.cfg, A->m);
+    }
+    return kblock_mixed_row_groups(A->m, kb.sb, kb.compute, batch);
 }
 
 // One kernel-block pass.  Mixed precisions produce the U-part only; their
@@ -163,7 +167,7 @@ Layout make_layout(int32_t problem, const kdcd_matrix *A, const kdcd_kernel *ker
     L.ldlow = 0;
     L.hi = L.lo = L.normlow = off;
     if (compute != KDCD_F64) {
-        L.ldlow = (A->n + 31) / 32 * 32;   // pad K to whole MFMA chunks
+        L.ldlow = (A->n + 63) / 64 * 64;   // pad K to whole stages of every product tile
         const size_t bytes = align256(lowp_elem_bytes(compute) * (size_t)(A->m * L.ldlow));
         L.hi = off; off += bytes;
         L.lo = off; off += (compute == KDCD_BF16X3) ? bytes : 0;
@@ -1319,10 +1323,12 @@ kdcd_status kdcd_autotune(const kdcd_matrix *A, const kdcd_kernel *kernel, int32
     kdcd_status rc = check_matrix(A);
     if (rc != KDCD_OK) return rc;
     if ((rc = check_kernel(kernel)) != KDCD_OK) return rc;
-    if (compute != KDCD_F64 || A->format != KDCD_DENSE) return KDCD_ERR_UNSUPPORTED;
+    if (A->format != KDCD_DENSE) return KDCD_ERR_UNSUPPORTED;
+    const int ncfg = kdcd_tune_configs(compute, nullptr, nullptr, nullptr, 0);
+    if (ncfg == 0) return KDCD_ERR_UNSUPPORTED;
     if (sb < 1 || sb > kMaxSB || sb > A->m || reps < 1) return KDCD_ERR_INVALID_ARG;
     const hipStream_t st = (hipStream_t)stream;
-    Layout L = make_layout(0, A, kernel, 1, sb, KDCD_F64);
+    Layout L = make_layout(0, A, kernel, 1, sb, compute);
     const size_t o_S = L.total;
     L.total += align256(sizeof(int32_t) * (size_t)sb);
     Workspace ws;
@@ -1342,10 +1348,16 @@ kdcd_status kdcd_autotune(const kdcd_matrix *A, const kdcd_kernel *kernel, int32
     kb.kp = to_params(kernel);
     kb.beta = norms;                 // any finite m-vector
     kb.partial = ws.at<double>(L.partial);
-    kb.W = ws.at<double>(L.W);
     kb.status = ws.at<int32_t>(L.status);
-    kb.compute = KDCD_F64;
-    if (sb >= kGatherMinSB) {              // W from the U rows, as in the solves
+    kb.compute = compute;
+    // the low-precision products are timed alone (their Gram comes from the
+    // FP64 kernel whatever the configuration)
+    kb.W = compute == KDCD_F64 ? ws.at<double>(L.W) : nullptr;
+    if (compute != KDCD_F64) {
+        KBlockArgs low;
+        if ((rc = prepare_lowp(kb, L, ws, st, low)) != KDCD_OK) return rc;
+        kb = low;
+    } else if (sb >= kGatherMinSB) {       // W from the U rows, as in the solves
         kb.pos = ws.at<int32_t>(L.pos);
         KDCD_HIP_TRY(launch_fill_i32(kb.pos, -1, A->m, st));
         kb.prevS = S;                      // every launch re-marks the same block
@@ -1354,7 +1366,6 @@ kdcd_status kdcd_autotune(const kdcd_matrix *A, const kdcd_kernel *kernel, int32
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return KDCD_ERR_HIP;
     // three interleaved rounds; a configuration's time is its fastest round
-    const int ncfg = f64_config_count();
     std::vector<double> tmin((size_t)ncfg, 0.0);
     rc = KDCD_OK;
     for (int round = 0; round < 3 && rc == KDCD_OK; ++round) {

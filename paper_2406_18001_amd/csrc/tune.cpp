@@ -1,7 +1,8 @@
-// Process-wide tuning table of the kernel-block product: the tile
-// configuration chosen per (compute, n, sb), filled by kdcd_autotune or
-// kdcd_tune_set, saved to and loaded from a plain text file
-// ("compute n sb id" per line).
+// Process-wide tuning table of the kernel-block products: the tile
+// configuration chosen per (compute, n, sb) -- the FP64 product's, or the
+// single-problem bf16 / fp16 / bf16x3 product's -- filled by kdcd_autotune or
+// kdcd_tune_set, saved to and loaded from a plain text file ("compute n sb id"
+// per line).
 #include <cstdio>
 #include <map>
 #include <mutex>
@@ -46,15 +47,29 @@ void tune_store(int32_t compute, int64_t n, int32_t sb, int id)
 
 using namespace kdcd;
 
+namespace {
+
+// Number of tile configurations of the product computed in `compute` (0: not tunable).
+int config_count(int32_t compute)
+{
+    switch (compute) {
+    case KDCD_F64: return f64_config_count();
+    case KDCD_BF16: case KDCD_F16: case KDCD_BF16X3: return lowp_config_count();
+    default: return 0;
+    }
+}
+
+}  // namespace
+
 extern "C" {
 
 int32_t kdcd_tune_configs(int32_t compute, int32_t *bm, int32_t *bn, int32_t *waves, int32_t max)
 {
-    if (compute != KDCD_F64) return 0;
-    const int n = f64_config_count();
+    const int n = config_count(compute);
     for (int i = 0; i < n && i < max; ++i) {
         int a, b, w;
-        f64_config_shape(i, &a, &b, &w);
+        if (compute == KDCD_F64) f64_config_shape(i, &a, &b, &w);
+        else lowp_config_shape(i, &a, &b, &w);
         if (bm) bm[i] = a;
         if (bn) bn[i] = b;
         if (waves) waves[i] = w;
@@ -64,16 +79,17 @@ int32_t kdcd_tune_configs(int32_t compute, int32_t *bm, int32_t *bn, int32_t *wa
 
 kdcd_status kdcd_tune_set(int32_t compute, int64_t n, int32_t sb, int32_t id)
 {
-    if (compute != KDCD_F64) return KDCD_ERR_UNSUPPORTED;
-    if (n < 1 || sb < 1 || sb > kMaxSB || id >= f64_config_count()) return KDCD_ERR_INVALID_ARG;
+    const int nc = config_count(compute);
+    if (nc == 0) return KDCD_ERR_UNSUPPORTED;
+    if (n < 1 || sb < 1 || sb > kMaxSB || id >= nc) return KDCD_ERR_INVALID_ARG;
     tune_store(compute, n, sb, id < 0 ? -1 : id);
     return KDCD_OK;
 }
 
 int32_t kdcd_tune_get(int32_t compute, int64_t n, int32_t sb)
 {
-    if (compute != KDCD_F64 || n < 1 || sb < 1 || sb > kMaxSB) return -1;
-    return f64_config_id(n, sb);
+    if (config_count(compute) == 0 || n < 1 || sb < 1 || sb > kMaxSB) return -1;
+    return compute == KDCD_F64 ? f64_config_id(n, sb) : lowp_config_id(compute, n, sb);
 }
 
 kdcd_status kdcd_tune_save(const char *path)
@@ -101,8 +117,8 @@ kdcd_status kdcd_tune_load(const char *path)
     while (true) {
         const int got = std::fscanf(f, "%d %lld %d %d", &c, &n, &sb, &id);
         if (got == EOF) break;
-        if (got != 4 || c != KDCD_F64 || n < 1 || sb < 1 || sb > kMaxSB || id < 0 ||
-            id >= f64_config_count()) {
+        if (got != 4 || config_count(c) == 0 || n < 1 || sb < 1 || sb > kMaxSB || id < 0 ||
+            id >= config_count(c)) {
             rc = KDCD_ERR_INVALID_ARG;
             break;
         }

@@ -92,7 +92,19 @@ def test_tuning_table_host_side(tmp_path):
     bm, bn, w = (ctypes.c_int32 * n)(), (ctypes.c_int32 * n)(), (ctypes.c_int32 * n)()
     assert lib.kdcd_tune_configs(0, bm, bn, w, n) == n
     assert all(bm[i] % 16 == 0 and bn[i] % 16 == 0 and w[i] in (4, 8) for i in range(n))
-    assert lib.kdcd_tune_configs(2, None, None, None, 0) == 0          # bf16: not tunable
+    nl = lib.kdcd_tune_configs(2, None, None, None, 0)                 # bf16: its own table
+    assert nl >= 2 and lib.kdcd_tune_configs(4, None, None, None, 0) == nl   # bf16x3 shares it
+    assert lib.kdcd_tune_configs(1, None, None, None, 0) == 0          # f32: not tunable
+    bl, nlb, wl = (ctypes.c_int32 * nl)(), (ctypes.c_int32 * nl)(), (ctypes.c_int32 * nl)()
+    assert lib.kdcd_tune_configs(2, bl, nlb, wl, nl) == nl
+    assert all(bl[i] % 64 == 0 and nlb[i] % 64 == 0 and wl[i] == 4 for i in range(nl))
+    dl = lib.kdcd_tune_get(2, 1024, 512)
+    assert 0 <= dl < nl
+    assert lib.kdcd_tune_set(2, 1024, 512, (dl + 1) % nl) == 0
+    assert lib.kdcd_tune_get(2, 1024, 512) == (dl + 1) % nl
+    assert lib.kdcd_tune_get(3, 1024, 512) == dl                       # f16 is keyed apart
+    assert lib.kdcd_tune_set(2, 1024, 512, -1) == 0
+    assert lib.kdcd_tune_get(2, 1024, 512) == dl
     default = lib.kdcd_tune_get(0, 777, 96)
     assert 0 <= default < n
     other = (default + 1) % n
@@ -105,7 +117,7 @@ def test_tuning_table_host_side(tmp_path):
     assert lib.kdcd_tune_load(path.encode()) == 0
     assert lib.kdcd_tune_get(0, 777, 96) == other
     assert lib.kdcd_tune_set(0, 777, 96, n) == -1                      # unknown id
-    assert lib.kdcd_tune_set(2, 777, 96, 0) == -2
+    assert lib.kdcd_tune_set(1, 777, 96, 0) == -2                      # f32: not tunable
     bad = tmp_path / "bad.txt"
     bad.write_text("0 10 10 99\n")
     assert lib.kdcd_tune_load(str(bad).encode()) == -1

@@ -141,7 +141,11 @@ def test_mixed_precision_batch_matches_single_mixed(K, c4, compute):
     for i, (lam, sig) in enumerate(sweep):
         a1 = zeros(m)
         K.kdcd_krr_solve(A, y, (2, sig, 0.0, 1), lam, b, s, H, idx, a1, compute=compute)
-        assert_parity(probs[i].alpha.cpu().numpy(), a1.cpu().numpy(), 1e-9, f"{compute} {i}")
+        # f32 runs the same product in both; the single-problem bf16 / bf16x3
+        # product uses the 32 x 32 x 16 MFMA shape and the batched one the
+        # 16 x 16 x 32 shape, which round the FP32 sums differently
+        tol = 1e-9 if compute == "f32" else 5e-5
+        assert_parity(probs[i].alpha.cpu().numpy(), a1.cpu().numpy(), tol, f"{compute} {i}")
 
 
 def test_full_batch_limits(K, c4):

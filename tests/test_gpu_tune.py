@@ -103,3 +103,30 @@ def test_table_changes_during_solves(K):
         done.set()
         t.join()
         K.kdcd_tune_set("f64", n, sb, -1)
+
+
+LOWP_TOL = {"bf16": 1.5e-2, "f16": 2e-3, "bf16x3": 1e-5}
+
+
+@pytest.mark.parametrize("m,n,sb", [(1000, 100, 7), (2500, 513, 128), (1200, 96, 1024),
+                                    (140000, 32, 300)])
+@pytest.mark.parametrize("kk", [(2, 0.9, 0.0, 1), (1, 0.0, 1.0, 3), (0, 0.0, 0.0, 1)])
+def test_every_lowp_config_within_bounds(K, m, n, sb, kk):
+    """Every tile configuration of the bf16 / fp16 / bf16x3 product, forced
+    through the table, within the precision's error bound of the FP64 oracle
+    (m = 140000 walks several row tiles per workgroup in every configuration)."""
+    rng = np.random.default_rng(m + sb + 1)
+    A = rng.standard_normal((m, n)) / np.sqrt(n)
+    S = rng.integers(0, m, size=sb).astype(np.int32)
+    beta = rng.standard_normal(m)
+    ok = O.Kernel(kk[0], sigma=kk[1], c=kk[2], degree=kk[3])
+    r_ref = O.kernel_rhs(A, ok, S, beta)
+    Ad, Sd, bd = dev(A), idx_dev(S), dev(beta)
+    for compute, tol in LOWP_TOL.items():
+        try:
+            for cid in range(len(K.kdcd_tune_configs(compute))):
+                K.kdcd_tune_set(compute, n, sb, cid)
+                r = K.kdcd_kernel_rhs(Ad, kk, Sd, bd, compute=compute)
+                assert_parity(r.cpu().numpy(), r_ref, tol, f"{compute} config {cid}")
+        finally:
+            K.kdcd_tune_set(compute, n, sb, -1)
