@@ -50,13 +50,21 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the built-in tile rule instead of timing the configurations")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the oracle sample")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c4-sweep", "c5s-sampler", "c2-nystrom", "news20-krr", "c3-csr"],
+    ap.add_argument("--workload", default="c2",
+                    choices=["c2", "c4-mixed", "c4-sweep", "c5s-sampler", "c2-nystrom", "news20-krr",
+                             "c3-csr", "peaks"],
                     help="c2: the headline line; c4-sweep: batched (lambda, sigma) sweep and "
                          "one-vs-rest K-SVMs against sequential solves; c5s-sampler: learned "
                          "against uniform coordinate sampling; c2-nystrom: the C2 K-RR on "
                          "Nystrom factors of several ranks; news20-krr: sparse K-RR with RBF "
                          "on news20-shaped rows, s-step against s = 1; c3-csr: the sparse "
-                         "K-SVM of the C3 recipe, s-step against s = 1")
+                         "K-SVM of the C3 recipe, s-step against s = 1; c4-mixed: the "
+                         "single-problem bf16 / fp16 / bf16x3 product on C4 and time to 1e-6 "
+                         "per precision; peaks: measured MFMA / HBM peaks")
+    ap.add_argument("--computes", default="bf16,f16,bf16x3,f64",
+                    help="c4-mixed: precisions to measure")
+    ap.add_argument("--c4-outer-max", type=int, default=6000,
+                    help="c4-mixed: outer iterations searched for the 1e-6 target")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy 4 times (byte-counter calibration)")
     return ap.parse_args()
@@ -74,6 +82,8 @@ def copy_probe():
 
 
 PROFILE_F64 = os.path.join(ROOT, "profiles", "kblock_f64_krr_c2_s64.txt")
+PROFILE_LOWP = os.path.join(ROOT, "profiles", "kblock_lowp_krr_c4_bf16.txt")
+KBLOCK_LOWP_SRC = os.path.join(ROOT, "paper_2406_18001_amd", "csrc", "kblock_lowp.hip")
 KBLOCK_F64_SRC = os.path.join(ROOT, "paper_2406_18001_amd", "csrc", "kblock_f64.hip")
 
 
@@ -324,6 +334,227 @@ def bench_c4_sweep(args):
         "time_to_rel_obj_err_1e-6_krr8": conv,
     }
     print(json.dumps(out), flush=True)
+
+
+PEAK_LOWP = 2516.6         # TFLOP/s, MI355X dense bf16 / fp16 MFMA
+PEAK_F32 = 157.3           # TFLOP/s, MI355X dense FP32 (matrix)
+
+
+def krr_bound(K, A, y, kern, lam, alpha):
+    """Certified relative objective error of K-RR at alpha, evaluated in FP64 on
+    the device: f - f* <= ||y - M a||^2 / (2 m) because lambda_min(M) >= m."""
+    m = A.shape[0]
+    ev = K.kdcd_krr_eval(A, y, kern, lam, alpha)
+    bound = 0.5 * ev["residual_norm"] ** 2 / m
+    return bound / max(abs(ev["objective"]) - bound, 1e-300)
+
+
+def first_outer_to_target(K, A, y, kern, lam, b, s, idx_long, compute, k_max, coarse=64,
+                          target=1e-6):
+    """Smallest k <= k_max (outer iterations from alpha = 0) whose iterate has a
+    certified relative objective error <= target, found with granularity 1:
+    snapshots every `coarse` outer iterations bisected with FP64 evaluations,
+    then the bracket re-run from its start with a snapshot after every outer
+    iteration and bisected again.  Returns (k or None, bound at k, evaluations)."""
+    import torch
+    m = A.shape[0]
+    sbk = s * b
+    rows = -(-k_max // coarse)
+    snaps = torch.zeros(rows, m, dtype=torch.float64, device="cuda")
+    a = torch.zeros(m, dtype=torch.float64, device="cuda")
+    K.kdcd_krr_solve(A, y, kern, lam, b, s, k_max * s, idx_long[:k_max * sbk], a, compute=compute,
+                     snapshot_every=coarse, snapshots=snaps)
+    evals = [0]
+
+    def ok(alpha):
+        evals[0] += 1
+        r = krr_bound(K, A, y, kern, lam, alpha)
+        return r <= target, r
+
+    hit, last_r = ok(snaps[rows - 1])
+    if not hit:
+        return None, last_r, evals[0]
+    lo, hi = -1, rows - 1              # snapshot index: lo fails (or is alpha = 0), hi passes
+    while hi - lo > 1:
+        mid = (lo + hi) // 2
+        if ok(snaps[mid])[0]:
+            hi = mid
+        else:
+            lo = mid
+    k0 = (lo + 1) * coarse             # outer iterations done at the last failing snapshot
+    k1 = min((hi + 1) * coarse, k_max)
+    start = snaps[lo].clone() if lo >= 0 else torch.zeros(m, dtype=torch.float64, device="cuda")
+    n = k1 - k0
+    fine = torch.zeros(n, m, dtype=torch.float64, device="cuda")
+    K.kdcd_krr_solve(A, y, kern, lam, b, s, n * s, idx_long[k0 * sbk:k1 * sbk], start,
+                     compute=compute, snapshot_every=1, snapshots=fine)
+    lo, hi = -1, n - 1
+    while hi - lo > 1:
+        mid = (lo + hi) // 2
+        if ok(fine[mid])[0]:
+            hi = mid
+        else:
+            lo = mid
+    _, r = ok(fine[hi])
+    return k0 + hi + 1, r, evals[0]
+
+
+def bench_c4_mixed(args):
+    """G1 on C4 (200000 x 1024 rows N(0, I)/sqrt(1024), K-RR targets as C2, RBF
+    sigma = 1, lambda = 1e-3, b = 16, s = 32, s*b = 512): the single-problem
+    kernel-block product in bf16, fp16 and bf16x3 (FP32 accumulation) against
+    FP64, each at its autotuned tile, timed in its own dispatches over the
+    product launches of timed solves; then, for every precision, the first outer
+    iteration whose iterate has a certified FP64 relative objective error of
+    1e-6 (granularity 1) and the wall time of one solve of exactly that many
+    outer iterations (the FP64 solve also once with the on-device monitor)."""
+    import torch
+
+    from paper_2406_18001_amd import inputs
+    from paper_2406_18001_amd import kdcd as K
+    m, n, b, s, lam, sig = 200000, 1024, 16, 32, 1e-3, 1.0
+    sb = s * b
+    d = inputs.dense_c4(m=m, n=n)
+    A = torch.tensor(d["A"], device="cuda")
+    y = torch.tensor(d["y"], device="cuda")
+    kern = (2, sig, 0.0, 1)
+    computes = args.computes.split(",")
+    n_out = 8
+    I = torch.tensor(inputs.krr_indices(m, b, n_out * s, seed=0), device="cuda")
+    fl_launch = 2 * m * n * sb
+    peaks = {"f64": PEAK_F64, "f32": PEAK_F32, "bf16": PEAK_LOWP, "f16": PEAK_LOWP,
+             "bf16x3": PEAK_LOWP}
+    log("c4-mixed: inputs ready")
+    prod = {}
+    for comp in computes:
+        tile = None
+        if K.kdcd_tune_configs(comp) and not args.no_autotune:
+            cid, us = K.kdcd_autotune(A, kern, sb, compute=comp, reps=5)
+            tile = {"config": cid, "tile": list(K.kdcd_tune_configs(comp)[cid]),
+                    "autotune_us": round(us, 2)}
+        a = torch.zeros(m, dtype=torch.float64, device="cuda")
+        K.kdcd_krr_solve(A, y, kern, lam, b, s, n_out * s, I, a, compute=comp)
+        torch.cuda.synchronize()
+        kb_ms, launches, wall = 0.0, 0, 0.0
+        reps = max(1, args.steps // 4)
+        for _ in range(reps):
+            a.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            p = K.kdcd_krr_solve(A, y, kern, lam, b, s, n_out * s, I, a, compute=comp,
+                                 profile=True, flags=K.FLAG_TIME_PRODUCT)
+            torch.cuda.synchronize()
+            wall += time.perf_counter() - t0
+            kb_ms += p["kblock_ms"]
+            launches += p["kblock_launches"]
+        us = kb_ms / launches * 1e3
+        tf = fl_launch / (us * 1e-6) / 1e12
+        e = {"product_us": round(us, 2), "TFLOP/s": round(tf, 2), "peak": peaks[comp],
+             "frac": round(tf / peaks[comp], 4), "launches": launches,
+             "ms_per_outer_iteration_solve": round(wall / reps / n_out * 1e3, 4)}
+        if comp == "bf16x3":
+            e["issued_TFLOP/s"] = round(3 * tf, 2)
+            e["issued_frac"] = round(3 * tf / peaks[comp], 4)
+        if tile:
+            e["tile"] = tile
+        prod[comp] = e
+        log(f"c4-mixed: {comp} product {us:.1f} us, {tf:.1f} TFLOP/s ({tf / peaks[comp]:.3f})")
+
+    conv = {}
+    if not args.no_convergence:
+        k_max = args.c4_outer_max
+        idx_long = torch.tensor(inputs.krr_indices(m, b, k_max * s, seed=1), device="cuda")
+        Hl = k_max * s
+        a = torch.zeros(m, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = K.kdcd_krr_solve(A, y, kern, lam, b, s, Hl, idx_long, a, monitor_every=16, tol=1e-6)
+        torch.cuda.synchronize()
+        conv["f64_monitored"] = {"outer_iterations": info["outer_done"],
+                                 "seconds": round(time.perf_counter() - t0, 4),
+                                 "rel_obj_err_bound": info["rel_err"],
+                                 "note": "one solve that stops itself on the device (the "
+                                         "monitor stores the FP64 kernel block)"}
+        log(f"c4-mixed: f64 monitored {conv['f64_monitored']}")
+        for comp in computes:
+            k, r, nev = first_outer_to_target(K, A, y, kern, lam, b, s, idx_long, comp, k_max)
+            if k is None:
+                conv[comp] = {"outer_iterations": None, "rel_obj_err_bound": r,
+                              "note": f"not reached within {k_max} outer iterations"}
+                log(f"c4-mixed: {comp} not reached ({r:.3e})")
+                continue
+            best = None
+            for _ in range(2):
+                a.zero_()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                K.kdcd_krr_solve(A, y, kern, lam, b, s, k * s, idx_long[:k * sb], a, compute=comp)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                best = dt if best is None else min(best, dt)
+            conv[comp] = {"outer_iterations": k, "seconds": round(best, 4),
+                          "rel_obj_err_bound": r, "evaluations": nev,
+                          "note": "wall time of one solve of exactly this many outer iterations "
+                                  "(the first to reach the target, FP64-certified)"}
+            log(f"c4-mixed: {comp} reaches 1e-6 after {k} outer iterations, {best:.3f} s")
+    bf = prod.get("bf16", next(iter(prod.values())))
+    lead = "bf16" if "bf16" in prod else computes[0]
+    out = {
+        "metric": METRIC,
+        "value": bf["TFLOP/s"],
+        "unit": "TFLOP/s",
+        "n_gpus": 1, "steps": max(1, args.steps // 4), "warmup": 1,
+        "ms_per_step": round(bf["ms_per_outer_iteration_solve"] * n_out, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": lead,
+        "data": "synthetic",
+        "config": {"workload": f"C4: K-RR s-step BDCD, dense A {m}x{n} rows N(0,I)/sqrt(n), RBF "
+                               f"sigma={sig}, lambda={lam}, b={b}, s={s} (s*b={sb}); one step = "
+                               f"{n_out} outer iterations", "m": m, "n": n, "b": b, "s": s,
+                   "compute": lead},
+        "roofline": {"bound": "mfma", "achieved": bf["TFLOP/s"], "peak": bf["peak"],
+                     "unit": "TFLOP/s", "frac": bf["frac"],
+                     "traffic": (profiled_traffic(PROFILE_LOWP, KBLOCK_LOWP_SRC)
+                                 if lead == "bf16" else None),
+                     "kernel": "kblock_lowp_kernel", "avg_launch_us": bf["product_us"]},
+        "products": prod,
+    }
+    if conv:
+        out["time_to_rel_obj_err_1e-6"] = conv
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        idx1 = inputs.krr_indices(m, b, s, seed=0)
+        t0 = time.perf_counter()
+        O.bdcd_krr(d["A"], d["y"], O.Kernel(O.RBF, sigma=sig), lam, b, s, idx1, s=s)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(fl_launch / dt / 1e12, 6), "unit": "TFLOP/s",
+                               "cores": O.threads(), "kind": "oracle",
+                               "sample": f"one outer iteration of the same solve (s*b={sb}), "
+                                         f"{dt:.2f} s, FP64 oracle"}
+    print(json.dumps(out), flush=True)
+
+
+def bench_peaks(args):
+    """Measured MFMA and HBM peaks of this MI355X with the microbenchmark
+    library: MFMA throughput per instruction shape at 1, 2 and 4 waves per SIMD
+    (independent accumulator chains, no memory traffic), and a read-only and a
+    copy stream over 2 GiB / 1 GiB."""
+    import ctypes
+
+    import torch
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2406_18001_amd", "libkdcd_peak.so"))
+    lib.kdcd_peak_mfma.restype = ctypes.c_double
+    lib.kdcd_peak_mfma.argtypes = [ctypes.c_int, ctypes.c_int]
+    lib.kdcd_peak_stream.restype = ctypes.c_double
+    lib.kdcd_peak_stream.argtypes = [ctypes.c_int, ctypes.c_int64]
+    torch.zeros(1, device="cuda")
+    res = {}
+    for shape, name, pub in [(0, "f64_16x16x4", PEAK_F64), (1, "bf16_16x16x32", PEAK_LOWP),
+                             (2, "bf16_32x32x16", PEAK_LOWP), (3, "f16_16x16x32", PEAK_LOWP)]:
+        best = max(lib.kdcd_peak_mfma(shape, w) for w in (1, 2, 4))
+        res[name] = {"TFLOP/s": round(best, 1), "published": pub, "frac": round(best / pub, 3)}
+    res["hbm_read_GB/s"] = round(lib.kdcd_peak_stream(0, 2 << 30), 1)
+    res["hbm_copy_GB/s"] = round(lib.kdcd_peak_stream(1, 1 << 30), 1)
+    print(json.dumps({"metric": "measured MFMA / HBM peaks", "peaks": res}), flush=True)
 
 
 def bench_c5s_sampler(args):
@@ -708,6 +939,12 @@ def main():
         return
     if args.workload == "c4-sweep":
         bench_c4_sweep(args)
+        return
+    if args.workload == "c4-mixed":
+        bench_c4_mixed(args)
+        return
+    if args.workload == "peaks":
+        bench_peaks(args)
         return
     if args.workload == "c5s-sampler":
         bench_c5s_sampler(args)

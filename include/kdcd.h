@@ -118,8 +118,9 @@ typedef struct {
  * serialised by one lock.  With a profile, only total_ms is reported.
  */
 /*
- * KDCD_FLAG_TIME_PRODUCT (with a profile; dense FP64 kdcd_ksvm_solve /
- * kdcd_krr_solve on the serial loop): only the kernel-block product is timed
+ * KDCD_FLAG_TIME_PRODUCT (with a profile; dense kdcd_ksvm_solve /
+ * kdcd_krr_solve, any compute): only the kernel-block product is timed (for
+ * low-precision computes the product launch alone, not the FP64 Gram launch)
  * (kblock_ms, kblock_launches and total_ms from its first start to its last
  * end; the other stages report 0).  Stage kernels record their own
  * timestamps in their dispatch (hipExtLaunchKernelGGL), and each timed

@@ -44,6 +44,21 @@ def _compile(src: str) -> str:
     return obj
 
 
+PEAK_SRC = os.path.join(PKG, "peak", "peak.hip")
+PEAK_LIB = os.path.join(PKG, "libkdcd_peak.so")
+
+
+def build_peak() -> str:
+    """The MFMA / HBM peak microbenchmarks (a library of their own)."""
+    tmp = PEAK_LIB + ".tmp"
+    cmd = [HIPCC, *FLAGS, "-shared", PEAK_SRC, "-o", tmp]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"hipcc failed for {PEAK_SRC}:\n{res.stderr}")
+    os.replace(tmp, PEAK_LIB)
+    return PEAK_LIB
+
+
 def build_library(jobs: int | None = None) -> str:
     os.makedirs(BUILD, exist_ok=True)
     srcs = sources()
@@ -61,3 +76,4 @@ def build_library(jobs: int | None = None) -> str:
 
 if __name__ == "__main__":
     print(build_library())
+    print(build_peak())

@@ -423,7 +423,7 @@ hipError_t launch_cfg(const KBlockArgs &a, hipStream_t st)
     const int64_t nseg = (A->n * esz + 15) / 16;
     dim3 grid((unsigned)(n_n * groups)), block(64 * WM * WN);
 #define KDCD_LAUNCH(KIND)                                                                       \
-    hipLaunchKernelGGL((kblock_mixed_kernel<CMP, WM, WN, TM, TN, KIND, BATCH>), grid, block, 0, st, \
+    KDCD_TIMED_LAUNCH((kblock_mixed_kernel<CMP, WM, WN, TM, TN, KIND, BATCH>), grid, block, 0, st,  \
                        static_cast<const u4 *>(a.Alow), static_cast<const u4 *>(a.Alow2), ldseg, \
                        A->m, nseg, a.normlow, a.S, a.sb, a.kp, a.beta, a.beta_scale, a.partial, \
                        (int32_t)n_u, (int32_t)groups, (int32_t)n_n, a.batch)

@@ -121,6 +121,7 @@ hipError_t launch_kblock(const KBlockArgs &a, hipStream_t st)
     KBlockArgs w = a;
     w.compute = KDCD_F64;
     w.w_only = 1;
+    w.cfg = -1;          // the FP64 table's choice (a.cfg names a low-precision tile)
     return launch_kblock_f64(w, st);
 }
 
@@ -534,6 +535,18 @@ kdcd_status enqueue_solve(const SolveArgs &sa, const Layout &L, char *wsbase, St
             timer.disarm();
             KDCD_HIP_TRY(e);
             if (!fused) KDCD_HIP_TRY(launch_kblock_f64_post(kb, st));
+        } else if (product_only && A->format == KDCD_DENSE) {
+            // low-precision product timed in its own dispatch; the FP64 Gram
+            // launch after it is not timed
+            if (!sampled || k % 8 == 0) timer.arm(0);
+            const hipError_t e = launch_kblock_mixed(kb, st);
+            timer.disarm();
+            KDCD_HIP_TRY(e);
+            KBlockArgs w = kb;
+            w.compute = KDCD_F64;
+            w.w_only = 1;
+            w.cfg = -1;
+            KDCD_HIP_TRY(launch_kblock_f64(w, st));
         } else {
             timer.begin(0, st);
             KDCD_HIP_TRY(launch_kblock(kb, st));
