@@ -310,6 +310,17 @@ kdcd_status kdcd_ksvm_eval(const kdcd_matrix *A, const double *y, const kdcd_ker
 kdcd_status kdcd_krr_eval(const kdcd_matrix *A, const double *y, const kdcd_kernel *kernel,
                           double lambda, const double *alpha, double *out, kdcd_stream stream);
 
+/*
+ * kdcd_batch_eval -- kdcd_krr_eval / kdcd_ksvm_eval of every problem of a
+ * batch (descriptors as in kdcd_batch_solve), with one shared FP64 kernel
+ * pass over A for all problems (measurement only; m^2 kernel evaluations per
+ * sigma group).  out (host, 4 doubles per problem): K-RR {f, ||y - M a||, 0,
+ * 0}; K-SVM {f, P, gap, max |projected gradient|}.  Synchronises `stream`.
+ */
+kdcd_status kdcd_batch_eval(const kdcd_matrix *A, const kdcd_kernel *kernel,
+                            const kdcd_batch_problem *problems, int32_t n_problems, double *out,
+                            kdcd_stream stream);
+
 /* ---------------------------------------------------------------------------
  * Low-rank kernel blocks.  The conclusion proposes approximating the sampled
  * kernel matrix (for instance by the Nystrom method) to cut the cost of the
@@ -473,6 +484,9 @@ kdcd_status kdcd_ksvm_solve_sampled(const kdcd_matrix *A, const double *y,
  * configuration, so the table may change while solves run (they then take
  * the old or the new entry).
  * ------------------------------------------------------------------------- */
+/* compute + KDCD_TUNE_BATCH addresses the table of the batched product
+ * (kdcd_batch_solve) computed in `compute`, in every kdcd_tune_* call. */
+#define KDCD_TUNE_BATCH 16
 /* Number of configurations for `compute` (0 if not tunable); fills up to
  * `max` entries of bm, bn (tile rows x columns) and waves per workgroup
  * (each array may be NULL). */
@@ -490,6 +504,16 @@ int32_t kdcd_tune_get(int32_t compute, int64_t n, int32_t sb);
 kdcd_status kdcd_autotune(const kdcd_matrix *A, const kdcd_kernel *kernel, int32_t sb,
                           int32_t compute, int32_t reps, int32_t *best_id, double *best_us,
                           kdcd_stream stream);
+/* kdcd_autotune for the batched product of kdcd_batch_solve on these problems
+ * (their alpha arrays are read, not changed; sigma groups as in the solve):
+ * every configuration of compute + KDCD_TUNE_BATCH is timed with sb evenly
+ * strided sampled rows, the product and its Gram included, and the fastest is
+ * recorded for (compute + KDCD_TUNE_BATCH, A->n, sb).  Dense A only.
+ * Synchronises `stream`. */
+kdcd_status kdcd_autotune_batch(const kdcd_matrix *A, const kdcd_kernel *kernel, int32_t sb,
+                                const kdcd_batch_problem *problems, int32_t n_problems,
+                                int32_t compute, int32_t reps, int32_t *best_id, double *best_us,
+                                kdcd_stream stream);
 kdcd_status kdcd_tune_save(const char *path);
 kdcd_status kdcd_tune_load(const char *path);
 

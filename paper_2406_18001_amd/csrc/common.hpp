@@ -184,7 +184,15 @@ void f64_config_shape(int id, int *bm, int *bn, int *waves);
 int f64_config_id(int64_t n, int32_t sb);
 int tune_lookup(int32_t compute, int64_t n, int32_t sb);   // -1: no entry
 void tune_store(int32_t compute, int64_t n, int32_t sb, int id);   // id < 0 removes
-int64_t kblock_mixed_row_groups(int64_t m, int32_t sb, int32_t compute, bool batch = false);
+int64_t kblock_mixed_row_groups(int cfg, int64_t m, int64_t n, int32_t sb, int32_t compute,
+                                bool batch);
+// Tile configurations of the batched products, tuned under compute + KDCD_TUNE_BATCH.
+int f64_batch_config_count();
+void f64_batch_config_shape(int id, int *bm, int *bn, int *waves);
+int f64_batch_config_id(int64_t n, int32_t sb);
+int mixed_batch_config_count();
+void mixed_batch_config_shape(int id, int *bm, int *bn, int *waves);
+int mixed_batch_config_id(int32_t compute, int64_t n, int32_t sb);
 // Single-problem bf16 / fp16 / bf16x3 product (32 x 32 x 16 MFMA tiles) and
 // its tile configurations (tuning table entries under the compute id).
 int lowp_config_count();

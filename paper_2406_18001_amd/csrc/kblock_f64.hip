@@ -496,20 +496,30 @@ hipError_t launch_cfg(const KBlockArgs &a, hipStream_t st)
 
 }  // namespace
 
-// Batched launches use a 64 x 64 tile: the mapped values of every sigma group
-// stay in registers while the problems of the group are reduced.
-Cfg pick_cfg_batch(int32_t sb)
+// Configurations of the batched launch (WM, WN, TM, TN): the mapped values of
+// every sigma group stay in registers while the problems of the group are
+// reduced, so the tiles stay small.
+struct F64Cfg {
+    int wm, wn, tm, tn;
+};
+constexpr F64Cfg kF64BatchCfgs[] = {
+    {4, 1, 2, 1},   // 0: 128 x 16, 4 waves
+    {4, 1, 2, 2},   // 1: 128 x 32, 4 waves
+    {2, 2, 2, 2},   // 2: 64 x 64, 4 waves
+    {4, 2, 2, 2},   // 3: 128 x 64, 8 waves
+    {2, 2, 2, 1},   // 4: 64 x 32, 4 waves
+};
+constexpr int kF64BatchNumCfgs = sizeof(kF64BatchCfgs) / sizeof(kF64BatchCfgs[0]);
+
+int f64_batch_default_id(int32_t sb)
 {
-    if (sb <= 16) return {128, 16};
-    if (sb <= 32) return {128, 32};
-    return {64, 64};
+    if (sb <= 16) return 0;
+    if (sb <= 32) return 1;
+    return 2;
 }
 
 // Configurations of the single-problem launch: (WM, WN, TM, TN).  The 8-wave
 // shapes keep the 64 x 128 / 128 x 64 tile at two waves per SIMD.
-struct F64Cfg {
-    int wm, wn, tm, tn;
-};
 constexpr F64Cfg kF64Cfgs[] = {
     {4, 1, 2, 1},   // 0: 128 x 16, 4 waves
     {4, 1, 2, 2},   // 1: 128 x 32, 4 waves
@@ -546,11 +556,29 @@ int f64_config_id(int64_t n, int32_t sb)
     return (id >= 0 && id < kF64NumCfgs) ? id : f64_default_id(sb);
 }
 
+int f64_batch_config_count() { return kF64BatchNumCfgs; }
+
+void f64_batch_config_shape(int id, int *bm, int *bn, int *waves)
+{
+    const F64Cfg &c = kF64BatchCfgs[id >= 0 && id < kF64BatchNumCfgs ? id : 2];
+    *bm = 16 * c.tm * c.wm;
+    *bn = 16 * c.tn * c.wn;
+    *waves = c.wm * c.wn;
+}
+
+int f64_batch_config_id(int64_t n, int32_t sb)
+{
+    const int id = tune_lookup(KDCD_F64 + KDCD_TUNE_BATCH, n, sb);
+    return (id >= 0 && id < kF64BatchNumCfgs) ? id : f64_batch_default_id(sb);
+}
+
 int64_t kblock_f64_row_groups(int cfg, int64_t m, int64_t n, int32_t sb, bool batch)
 {
     int bm;
     if (batch) {
-        bm = pick_cfg_batch(sb).bm;
+        int bn, w;
+        f64_batch_config_shape(cfg >= 0 && cfg < kF64BatchNumCfgs ? cfg : f64_batch_config_id(n, sb),
+                               &bm, &bn, &w);
     } else {
         int bn, w;
         f64_config_shape(cfg >= 0 && cfg < kF64NumCfgs ? cfg : f64_config_id(n, sb), &bm, &bn, &w);
@@ -572,10 +600,13 @@ hipError_t launch_kblock_f64_pre(const KBlockArgs &a, hipStream_t st)
 hipError_t launch_kblock_f64_main(const KBlockArgs &a, hipStream_t st)
 {
     if (a.batch) {
-        const Cfg c = pick_cfg_batch(a.sb);
-        if (c.bn == 16) return launch_cfg<4, 1, 2, 1, true>(a, st);
-        if (c.bn == 32) return launch_cfg<4, 1, 2, 2, true>(a, st);
-        return launch_cfg<2, 2, 2, 2, true>(a, st);
+        switch (a.cfg >= 0 && a.cfg < kF64BatchNumCfgs ? a.cfg : f64_batch_config_id(a.A->n, a.sb)) {
+        case 0: return launch_cfg<4, 1, 2, 1, true>(a, st);
+        case 1: return launch_cfg<4, 1, 2, 2, true>(a, st);
+        case 3: return launch_cfg<4, 2, 2, 2, true>(a, st);
+        case 4: return launch_cfg<2, 2, 2, 1, true>(a, st);
+        default: return launch_cfg<2, 2, 2, 2, true>(a, st);
+        }
     }
     KBlockArgs b = a;
     if (!(a.W && a.pos && !a.w_only)) b.pos = nullptr;

@@ -437,22 +437,38 @@ hipError_t launch_cfg(const KBlockArgs &a, hipStream_t st)
 }
 
 // Batched launches use at most a 128 x 64 tile (mapped values of a sigma group
-// stay in registers while its problems are reduced).
-Cfg pick_cfg_batch(int32_t sb)
+// stay in registers while its problems are reduced): (WM, WN, TM, TN).
+struct MixedCfg {
+    int wm, wn, tm, tn;
+};
+constexpr MixedCfg kMixedBatchCfgs[] = {
+    {4, 1, 2, 1},   // 0: 128 x 16
+    {4, 1, 2, 2},   // 1: 128 x 32
+    {2, 2, 4, 2},   // 2: 128 x 64
+    {2, 2, 2, 2},   // 3: 64 x 64
+};
+constexpr int kMixedBatchNumCfgs = sizeof(kMixedBatchCfgs) / sizeof(kMixedBatchCfgs[0]);
+
+int mixed_batch_default_id(int32_t sb)
 {
-    if (sb <= 16) return {128, 16};
-    if (sb <= 32) return {128, 32};
-    return {128, 64};
+    if (sb <= 16) return 0;
+    if (sb <= 32) return 1;
+    return 2;
 }
+
+int mixed_batch_valid(int id) { return id >= 0 && id < kMixedBatchNumCfgs; }
 
 template <int CMP>
 hipError_t launch_for(const KBlockArgs &a, hipStream_t st)
 {
     if (a.batch) {
-        const Cfg c = pick_cfg_batch(a.sb);
-        if (c.bn == 16) return launch_cfg<CMP, 4, 1, 2, 1, true>(a, st);
-        if (c.bn == 32) return launch_cfg<CMP, 4, 1, 2, 2, true>(a, st);
-        return launch_cfg<CMP, 2, 2, 4, 2, true>(a, st);
+        switch (mixed_batch_valid(a.cfg) ? a.cfg
+                                         : mixed_batch_config_id(a.compute, a.A->n, a.sb)) {
+        case 0: return launch_cfg<CMP, 4, 1, 2, 1, true>(a, st);
+        case 1: return launch_cfg<CMP, 4, 1, 2, 2, true>(a, st);
+        case 3: return launch_cfg<CMP, 2, 2, 2, 2, true>(a, st);
+        default: return launch_cfg<CMP, 2, 2, 4, 2, true>(a, st);
+        }
     }
     const Cfg c = pick_cfg(a.sb);
     if (c.bn == 16) return launch_cfg<CMP, 4, 1, 2, 1, false>(a, st);
@@ -464,11 +480,35 @@ hipError_t launch_for(const KBlockArgs &a, hipStream_t st)
 
 }  // namespace
 
-int64_t kblock_mixed_row_groups(int64_t m, int32_t sb, int32_t compute, bool batch)
+int mixed_batch_config_count() { return kMixedBatchNumCfgs; }
+
+void mixed_batch_config_shape(int id, int *bm, int *bn, int *waves)
 {
-    (void)compute;   // single-problem bf16 / fp16 / bf16x3 launches use the lowp product
-    const Cfg c = batch ? pick_cfg_batch(sb) : pick_cfg(sb);
-    const int64_t n_u = (m + c.bm - 1) / c.bm;
+    const MixedCfg &c = kMixedBatchCfgs[mixed_batch_valid(id) ? id : 2];
+    *bm = 16 * c.tm * c.wm;
+    *bn = 16 * c.tn * c.wn;
+    *waves = c.wm * c.wn;
+}
+
+int mixed_batch_config_id(int32_t compute, int64_t n, int32_t sb)
+{
+    const int id = tune_lookup(compute + KDCD_TUNE_BATCH, n, sb);
+    return mixed_batch_valid(id) ? id : mixed_batch_default_id(sb);
+}
+
+// Row groups of the launches of this file: the batched product (configuration
+// cfg, or the table's choice when cfg < 0) and the single-problem FP32 product.
+int64_t kblock_mixed_row_groups(int cfg, int64_t m, int64_t n, int32_t sb, int32_t compute,
+                                bool batch)
+{
+    int bm = pick_cfg(sb).bm;
+    if (batch) {
+        int bn, w;
+        mixed_batch_config_shape(mixed_batch_valid(cfg) ? cfg
+                                                        : mixed_batch_config_id(compute, n, sb),
+                                 &bm, &bn, &w);
+    }
+    const int64_t n_u = (m + bm - 1) / bm;
     return n_u < kMaxRowGroups ? n_u : kMaxRowGroups;
 }
 

@@ -100,14 +100,15 @@ int64_t bind_config(KBlockArgs &kb, bool batch = false)
     kb.cfg = -1;
     if (A->format == KDCD_CSR) return kblock_csr_row_groups(A->m, kb.sb);
     if (kb.compute == KDCD_F64) {
-        if (!batch) kb.cfg = f64_config_id(A->n, kb.sb);
+        kb.cfg = batch ? f64_batch_config_id(A->n, kb.sb) : f64_config_id(A->n, kb.sb);
         return kblock_f64_row_groups(kb.cfg, A->m, A->n, kb.sb, batch);
     }
     if (!batch && kb.compute != KDCD_F32) {
         kb.cfg = lowp_config_id(kb.compute, A->n, kb.sb);
         return kblock_lowp_row_groups(kb.cfg, A->m);
     }
-    return kblock_mixed_row_groups(A->m, kb.sb, kb.compute, batch);
+    if (batch) kb.cfg = mixed_batch_config_id(kb.compute, A->n, kb.sb);
+    return kblock_mixed_row_groups(kb.cfg, A->m, A->n, kb.sb, kb.compute, batch);
 }
 
 // One kernel-block pass.  Mixed precisions produce the U-part only; their
@@ -376,6 +377,47 @@ static kdcd_status kernel_matvec(const kdcd_matrix *A, const kdcd_kernel *kernel
                                  hipStream_t st);
 
 namespace {
+
+// Sigma groups and problem lists of a batch (shared by the solve and the tuner).
+kdcd_status describe_batch(const kdcd_kernel *kernel, const kdcd_batch_problem *problems,
+                           int32_t n_problems, BatchDesc &bd, std::vector<int> &krr,
+                           std::vector<int> &svm)
+{
+    const bool rbf = kernel->kind == KDCD_KERNEL_RBF;
+    kdcd_status rc = KDCD_OK;
+    bd = BatchDesc{};
+    bd.nprob = n_problems;
+    for (int p = 0; p < n_problems; ++p) {
+        const kdcd_batch_problem &q = problems[p];
+        kdcd_kernel kp = *kernel;
+        kp.sigma = q.sigma;
+        if ((rc = check_kernel(&kp)) != KDCD_OK) return rc;
+        if (!q.y || !q.alpha || !finite_pos(q.param)) return KDCD_ERR_INVALID_ARG;
+        if (q.problem == 1) {
+            krr.push_back(p);
+        } else if (q.problem == 0) {
+            if (q.loss != 0 && q.loss != 1 && q.loss != 2) return KDCD_ERR_INVALID_ARG;
+            svm.push_back(p);
+        } else {
+            return KDCD_ERR_INVALID_ARG;
+        }
+        int g = 0;
+        if (rbf) {
+            while (g < bd.ngroups && bd.sigma[g] != q.sigma) ++g;
+            if (g == bd.ngroups) {
+                if (bd.ngroups == kMaxSigmas) return KDCD_ERR_UNSUPPORTED;
+                bd.sigma[bd.ngroups++] = q.sigma;
+            }
+        } else {
+            bd.ngroups = 1;
+            bd.sigma[0] = kernel->sigma;
+        }
+        bd.group[p] = g;
+        bd.beta[p] = q.alpha;
+        bd.bscale[p] = q.problem == 0 ? q.y : nullptr;
+    }
+    return KDCD_OK;
+}
 
 // The maintained dual vector at the start: K-SVM g = Q a0 - 1 + omega a0,
 // K-RR rho = y - M a0; the kernel product only runs for a nonzero a0 (one
@@ -931,41 +973,12 @@ kdcd_status kdcd_batch_solve(const kdcd_matrix *A, const kdcd_kernel *kernel, in
     if ((rc = check_compute(A, o.compute)) != KDCD_OK) return rc;
     if (A->format != KDCD_DENSE) return KDCD_ERR_UNSUPPORTED;
     if (o.snapshot_every != 0 || o.trace) return KDCD_ERR_INVALID_ARG;   // per problem instead
-    const bool rbf = kernel->kind == KDCD_KERNEL_RBF;
 
     // sigma groups and problem lists
     BatchDesc bd{};
-    bd.nprob = n_problems;
     std::vector<int> krr, svm;
-    for (int p = 0; p < n_problems; ++p) {
-        const kdcd_batch_problem &q = problems[p];
-        kdcd_kernel kp = *kernel;
-        kp.sigma = q.sigma;
-        if ((rc = check_kernel(&kp)) != KDCD_OK) return rc;
-        if (!q.y || !q.alpha || !finite_pos(q.param)) return KDCD_ERR_INVALID_ARG;
-        if (q.problem == 1) {
-            krr.push_back(p);
-        } else if (q.problem == 0) {
-            if (q.loss != 0 && q.loss != 1 && q.loss != 2) return KDCD_ERR_INVALID_ARG;
-            svm.push_back(p);
-        } else {
-            return KDCD_ERR_INVALID_ARG;
-        }
-        int g = 0;
-        if (rbf) {
-            while (g < bd.ngroups && bd.sigma[g] != q.sigma) ++g;
-            if (g == bd.ngroups) {
-                if (bd.ngroups == kMaxSigmas) return KDCD_ERR_UNSUPPORTED;
-                bd.sigma[bd.ngroups++] = q.sigma;
-            }
-        } else {
-            bd.ngroups = 1;
-            bd.sigma[0] = kernel->sigma;
-        }
-        bd.group[p] = g;
-        bd.beta[p] = q.alpha;
-        bd.bscale[p] = q.problem == 0 ? q.y : nullptr;
-    }
+    if ((rc = describe_batch(kernel, problems, n_problems, bd, krr, svm)) != KDCD_OK) return rc;
+    const bool rbf = kernel->kind == KDCD_KERNEL_RBF;
     if (!krr.empty()) {
         if (b > kMaxB) return KDCD_ERR_UNSUPPORTED;
         const int nt = krr_recur_threads(b, s);
@@ -1418,6 +1431,102 @@ kdcd_status kdcd_autotune(const kdcd_matrix *A, const kdcd_kernel *kernel, int32
     return KDCD_OK;
 }
 
+kdcd_status kdcd_autotune_batch(const kdcd_matrix *A, const kdcd_kernel *kernel, int32_t sb,
+                                const kdcd_batch_problem *problems, int32_t n_problems,
+                                int32_t compute, int32_t reps, int32_t *best_id, double *best_us,
+                                kdcd_stream stream)
+{
+    kdcd_status rc = check_matrix(A);
+    if (rc != KDCD_OK) return rc;
+    if (!kernel || kernel->kind < KDCD_KERNEL_LINEAR || kernel->kind > KDCD_KERNEL_RBF)
+        return KDCD_ERR_INVALID_ARG;
+    if (A->format != KDCD_DENSE) return KDCD_ERR_UNSUPPORTED;
+    if ((rc = check_compute(A, compute)) != KDCD_OK) return rc;
+    if (!problems || n_problems < 1 || sb < 1 || sb > A->m || reps < 1)
+        return KDCD_ERR_INVALID_ARG;
+    if (n_problems > kMaxProblems || sb > kMaxSB) return KDCD_ERR_UNSUPPORTED;
+    const int32_t key = compute + KDCD_TUNE_BATCH;
+    const int ncfg = kdcd_tune_configs(key, nullptr, nullptr, nullptr, 0);
+    if (ncfg == 0) return KDCD_ERR_UNSUPPORTED;
+    BatchDesc bd{};
+    std::vector<int> krr, svm;
+    if ((rc = describe_batch(kernel, problems, n_problems, bd, krr, svm)) != KDCD_OK) return rc;
+    const hipStream_t st = (hipStream_t)stream;
+    Layout L = make_layout(0, A, kernel, 1, sb, compute);
+    size_t off = L.total;
+    const size_t o_bd = off; off += align256(sizeof(BatchDesc));
+    const int64_t max_groups = std::min<int64_t>(kMaxGroups, (A->m + 63) / 64);
+    const size_t o_part = off; off += align256(sizeof(double) * (size_t)(n_problems * max_groups * sb));
+    const size_t o_W = off; off += align256(sizeof(double) * (size_t)(bd.ngroups * sb * sb));
+    const size_t o_S = off; off += align256(sizeof(int32_t) * (size_t)sb);
+    L.total = off;
+    Workspace ws;
+    if ((rc = acquire(ws, L, nullptr, st)) != KDCD_OK) return rc;
+    int32_t *S = ws.at<int32_t>(o_S);
+    std::vector<int32_t> hS((size_t)sb);
+    for (int32_t j = 0; j < sb; ++j) hS[(size_t)j] = (int32_t)(((int64_t)j * A->m) / sb);
+    KDCD_HIP_TRY(hipMemcpyAsync(S, hS.data(), sizeof(int32_t) * (size_t)sb, hipMemcpyHostToDevice, st));
+    KDCD_HIP_TRY(hipMemcpyAsync(ws.at<BatchDesc>(o_bd), &bd, sizeof(BatchDesc),
+                                hipMemcpyHostToDevice, st));
+    KDCD_HIP_TRY(hipStreamSynchronize(st));          // bd and hS are host locals
+    double *norms = ws.at<double>(L.norms);
+    KDCD_HIP_TRY(launch_fill_i32(ws.at<int32_t>(L.status), 0, 1, st));
+    if (kernel->kind == KDCD_KERNEL_RBF) KDCD_HIP_TRY(launch_norms(A, norms, st));
+    KBlockArgs kb{};
+    kb.A = A;
+    kb.S = S;
+    kb.sb = sb;
+    kb.norms = norms;
+    kb.kp = to_params(kernel);
+    kb.beta = problems[0].alpha;
+    kb.partial = ws.at<double>(o_part);
+    kb.W = ws.at<double>(o_W);
+    kb.status = ws.at<int32_t>(L.status);
+    kb.compute = compute;
+    kb.batch = ws.at<BatchDesc>(o_bd);
+    KBlockArgs low;
+    if ((rc = prepare_lowp(kb, L, ws, st, low)) != KDCD_OK) return rc;
+    kb = low;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return KDCD_ERR_HIP;
+    std::vector<double> tmin((size_t)ncfg, 0.0);
+    for (int round = 0; round < 3 && rc == KDCD_OK; ++round) {
+        for (int id = 0; id < ncfg && rc == KDCD_OK; ++id) {
+            kb.cfg = id;
+            float ms = 0.f;
+            if (launch_kblock(kb, st) != hipSuccess || hipEventRecord(e0, st) != hipSuccess) {
+                rc = KDCD_ERR_HIP;
+                break;
+            }
+            for (int r = 0; r < reps && rc == KDCD_OK; ++r)
+                if (launch_kblock(kb, st) != hipSuccess) rc = KDCD_ERR_HIP;
+            if (rc != KDCD_OK || hipEventRecord(e1, st) != hipSuccess ||
+                hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                rc = KDCD_ERR_HIP;
+                break;
+            }
+            const double t = 1e3 * (double)ms / reps;
+            if (round == 0 || t < tmin[(size_t)id]) tmin[(size_t)id] = t;
+        }
+    }
+    int best = -1;
+    double best_t = 0.0;
+    for (int id = 0; id < ncfg; ++id)
+        if (best < 0 || tmin[(size_t)id] < best_t) {
+            best = id;
+            best_t = tmin[(size_t)id];
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != KDCD_OK) return rc;
+    if ((rc = read_status(ws.at<int32_t>(L.status), st)) != KDCD_OK) return rc;
+    tune_store(key, A->n, sb, best);
+    if (best_id) *best_id = best;
+    if (best_us) *best_us = best_t;
+    return KDCD_OK;
+}
+
 kdcd_status kdcd_kernel_rhs(const kdcd_matrix *A, const kdcd_kernel *kernel, const int32_t *S,
                             int32_t sb, const double *beta, const double *beta_scale, double *r,
                             double *W, int32_t compute, kdcd_stream stream)
@@ -1571,6 +1680,125 @@ kdcd_status kdcd_ksvm_eval(const kdcd_matrix *A, const double *y, const kdcd_ker
     out[1] = P;
     out[2] = P + f;
     out[3] = kkt;
+    return KDCD_OK;
+}
+
+kdcd_status kdcd_batch_eval(const kdcd_matrix *A, const kdcd_kernel *kernel,
+                            const kdcd_batch_problem *problems, int32_t n_problems, double *out,
+                            kdcd_stream stream)
+{
+    kdcd_status rc = check_matrix(A);
+    if (rc != KDCD_OK) return rc;
+    if (!kernel || kernel->kind < KDCD_KERNEL_LINEAR || kernel->kind > KDCD_KERNEL_RBF)
+        return KDCD_ERR_INVALID_ARG;
+    if (!problems || !out || n_problems < 1) return KDCD_ERR_INVALID_ARG;
+    if (n_problems > kMaxProblems) return KDCD_ERR_UNSUPPORTED;
+    if (A->format != KDCD_DENSE) return KDCD_ERR_UNSUPPORTED;
+    BatchDesc bd{};
+    std::vector<int> krr, svm;
+    if ((rc = describe_batch(kernel, problems, n_problems, bd, krr, svm)) != KDCD_OK) return rc;
+    const hipStream_t st = (hipStream_t)stream;
+    const int64_t m = A->m;
+    const int32_t chunk = kMaxSB;
+    Layout L = make_layout(2, A, kernel, 1, chunk, KDCD_F64);
+    size_t off = L.total;
+    const size_t o_bd = off; off += align256(sizeof(BatchDesc));
+    const int64_t max_groups = std::min<int64_t>(kMaxGroups, (m + 63) / 64);
+    const size_t o_part = off; off += align256(sizeof(double) * (size_t)(n_problems * max_groups * chunk));
+    const size_t o_r = off; off += align256(sizeof(double) * (size_t)(n_problems * chunk));
+    L.total = off;
+    Workspace ws;
+    if ((rc = acquire(ws, L, nullptr, st)) != KDCD_OK) return rc;
+    int32_t *status = ws.at<int32_t>(L.status);
+    double *norms = ws.at<double>(L.norms);
+    double *partial = ws.at<double>(o_part);
+    double *r = ws.at<double>(o_r);
+    int32_t *iota = ws.at<int32_t>(L.iota);
+    BatchDesc *dbd = ws.at<BatchDesc>(o_bd);
+    KDCD_HIP_TRY(hipMemcpyAsync(dbd, &bd, sizeof(BatchDesc), hipMemcpyHostToDevice, st));
+    KDCD_HIP_TRY(launch_fill_i32(status, 0, 1, st));
+    KDCD_HIP_TRY(launch_iota_i32(iota, m, st));
+    if (kernel->kind == KDCD_KERNEL_RBF) KDCD_HIP_TRY(launch_norms(A, norms, st));
+    // (K_p beta_p) for every problem: K_p is its sigma group's kernel, beta_p =
+    // alpha_p (K-RR) or y_p o alpha_p (K-SVM); row chunks of the symmetric K
+    std::vector<double> Kb((size_t)(n_problems * m), 0.0);
+    std::vector<double> hr((size_t)(n_problems * chunk));
+    for (int64_t c0 = 0; c0 < m; c0 += chunk) {
+        const int32_t sb = (int32_t)std::min<int64_t>(chunk, m - c0);
+        KBlockArgs a{};
+        a.A = A;
+        a.S = iota + c0;
+        a.sb = sb;
+        a.norms = norms;
+        a.kp = to_params(kernel);
+        a.beta = problems[0].alpha;
+        a.partial = partial;
+        a.W = nullptr;
+        a.status = status;
+        a.compute = KDCD_F64;
+        a.batch = dbd;
+        const int64_t groups = bind_config(a, true);
+        KDCD_HIP_TRY(launch_kblock(a, st));
+        FinishDesc fd{};
+        fd.nprob = n_problems;
+        fd.groups = (int32_t)groups;
+        for (int p = 0; p < n_problems; ++p) {
+            fd.partial[p] = partial + (int64_t)p * groups * sb;
+            fd.r[p] = r + (int64_t)p * sb;
+        }
+        KDCD_HIP_TRY(launch_finish(fd, sb, 1, 0, 0.0, status, st));
+        KDCD_HIP_TRY(hipMemcpyAsync(hr.data(), r, sizeof(double) * (size_t)(n_problems * sb),
+                                    hipMemcpyDeviceToHost, st));
+        KDCD_HIP_TRY(hipStreamSynchronize(st));
+        for (int p = 0; p < n_problems; ++p)
+            std::copy(hr.begin() + (int64_t)p * sb, hr.begin() + (int64_t)(p + 1) * sb,
+                      Kb.begin() + (int64_t)p * m + c0);
+    }
+    if ((rc = read_status(status, st)) != KDCD_OK) return rc;
+    for (int p = 0; p < n_problems; ++p) {
+        const kdcd_batch_problem &q = problems[p];
+        std::vector<double> hy, ha;
+        copy_to_host(hy, q.y, m, st);
+        copy_to_host(ha, q.alpha, m, st);
+        const double *kb = Kb.data() + (int64_t)p * m;
+        double *o = out + 4 * p;
+        if (q.problem == 1) {
+            long double aMa = 0, ya = 0, rr = 0;
+            for (int64_t i = 0; i < m; ++i) {
+                const double Ma = kb[i] / q.param + (double)m * ha[i];
+                aMa += (long double)ha[i] * Ma;
+                ya += (long double)hy[i] * ha[i];
+                const double res = hy[i] - Ma;
+                rr += (long double)res * res;
+            }
+            o[0] = (double)(0.5L * aMa - ya);
+            o[1] = std::sqrt((double)rr);
+            o[2] = o[3] = 0.0;
+        } else {
+            const int loss = q.loss == 2 ? 2 : 1;
+            const double C = q.param;
+            const double nu = loss == 2 ? INFINITY : C, omega = loss == 2 ? 1.0 / (2.0 * C) : 0.0;
+            long double aQa = 0, sa = 0, sa2 = 0, hinge = 0;
+            double kkt = 0.0;
+            for (int64_t i = 0; i < m; ++i) {
+                const double Qa = hy[i] * kb[i];
+                aQa += (long double)ha[i] * Qa;
+                sa += ha[i];
+                sa2 += (long double)ha[i] * ha[i];
+                const double xi = std::max(0.0, 1.0 - Qa);
+                hinge += loss == 2 ? (long double)xi * xi : xi;
+                const double g = Qa - 1.0 + omega * ha[i];
+                const double pg = ha[i] <= 0.0 ? std::min(0.0, g) : (ha[i] >= nu ? std::max(0.0, g) : g);
+                kkt = std::max(kkt, std::fabs(pg));
+            }
+            const double f = (double)(0.5L * aQa - sa + (loss == 2 ? sa2 / (4.0L * C) : 0.0L));
+            const double P = (double)(0.5L * aQa + (long double)C * hinge);
+            o[0] = f;
+            o[1] = P;
+            o[2] = P + f;
+            o[3] = kkt;
+        }
+    }
     return KDCD_OK;
 }
 

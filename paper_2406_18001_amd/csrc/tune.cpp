@@ -49,14 +49,27 @@ using namespace kdcd;
 
 namespace {
 
-// Number of tile configurations of the product computed in `compute` (0: not tunable).
+// Number of tile configurations of the product computed in `compute` (0: not
+// tunable); compute + KDCD_TUNE_BATCH names the batched product.
 int config_count(int32_t compute)
 {
     switch (compute) {
     case KDCD_F64: return f64_config_count();
     case KDCD_BF16: case KDCD_F16: case KDCD_BF16X3: return lowp_config_count();
+    case KDCD_F64 + KDCD_TUNE_BATCH: return f64_batch_config_count();
+    case KDCD_F32 + KDCD_TUNE_BATCH: case KDCD_BF16 + KDCD_TUNE_BATCH:
+    case KDCD_F16 + KDCD_TUNE_BATCH: case KDCD_BF16X3 + KDCD_TUNE_BATCH:
+        return mixed_batch_config_count();
     default: return 0;
     }
+}
+
+void config_shape(int32_t compute, int id, int *bm, int *bn, int *w)
+{
+    if (compute == KDCD_F64) f64_config_shape(id, bm, bn, w);
+    else if (compute == KDCD_F64 + KDCD_TUNE_BATCH) f64_batch_config_shape(id, bm, bn, w);
+    else if (compute >= KDCD_TUNE_BATCH) mixed_batch_config_shape(id, bm, bn, w);
+    else lowp_config_shape(id, bm, bn, w);
 }
 
 }  // namespace
@@ -68,8 +81,7 @@ int32_t kdcd_tune_configs(int32_t compute, int32_t *bm, int32_t *bn, int32_t *wa
     const int n = config_count(compute);
     for (int i = 0; i < n && i < max; ++i) {
         int a, b, w;
-        if (compute == KDCD_F64) f64_config_shape(i, &a, &b, &w);
-        else lowp_config_shape(i, &a, &b, &w);
+        config_shape(compute, i, &a, &b, &w);
         if (bm) bm[i] = a;
         if (bn) bn[i] = b;
         if (waves) waves[i] = w;
@@ -89,7 +101,10 @@ kdcd_status kdcd_tune_set(int32_t compute, int64_t n, int32_t sb, int32_t id)
 int32_t kdcd_tune_get(int32_t compute, int64_t n, int32_t sb)
 {
     if (config_count(compute) == 0 || n < 1 || sb < 1 || sb > kMaxSB) return -1;
-    return compute == KDCD_F64 ? f64_config_id(n, sb) : lowp_config_id(compute, n, sb);
+    if (compute == KDCD_F64) return f64_config_id(n, sb);
+    if (compute == KDCD_F64 + KDCD_TUNE_BATCH) return f64_batch_config_id(n, sb);
+    if (compute >= KDCD_TUNE_BATCH) return mixed_batch_config_id(compute - KDCD_TUNE_BATCH, n, sb);
+    return lowp_config_id(compute, n, sb);
 }
 
 kdcd_status kdcd_tune_save(const char *path)

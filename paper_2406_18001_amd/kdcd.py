@@ -149,6 +149,11 @@ _lib.kdcd_tune_get.restype = ctypes.c_int32
 _lib.kdcd_tune_get.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32]
 _lib.kdcd_autotune.restype = ctypes.c_int
 _lib.kdcd_autotune.argtypes = [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P, _P]
+_lib.kdcd_batch_eval.restype = ctypes.c_int
+_lib.kdcd_batch_eval.argtypes = [_P, _P, _P, ctypes.c_int32, _P, _P]
+_lib.kdcd_autotune_batch.restype = ctypes.c_int
+_lib.kdcd_autotune_batch.argtypes = [_P, _P, ctypes.c_int32, _P, ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.c_int32, _P, _P, _P]
 _lib.kdcd_tune_save.restype = ctypes.c_int
 _lib.kdcd_tune_save.argtypes = [ctypes.c_char_p]
 _lib.kdcd_tune_load.restype = ctypes.c_int
@@ -390,6 +395,20 @@ def kdcd_batch_solve(A, kernel, b, s, H, idx, problems, *, compute="f64", worksp
     kdcd_ksvm_solve(..., 1, s*b, H*b, ...) over the same idx."""
     mat, m, _ = _matrix(A)
     _dev(idx, torch.int32, int(H) * int(b), "idx")
+    arr = _batch_array(problems, m, H, b)
+    opt, prof = _options(compute, 1, 0, None, None, workspace, profile, flags, m, 0, 0)
+    kern = _kernel(kernel)
+    st = _lib.kdcd_batch_solve(ctypes.byref(mat), ctypes.byref(kern), int(b), int(s), int(H),
+                               idx.data_ptr(), arr, len(problems), ctypes.byref(opt),
+                               _stream(stream))
+    if st != 0:
+        raise KdcdError(st, "kdcd_batch_solve")
+    if prof is not None:
+        return {f: getattr(prof, f) for f, _ in _Profile._fields_}
+    return None
+
+
+def _batch_array(problems, m, H, b):
     arr = (_BatchProblem * max(len(problems), 1))()
     for i, q in enumerate(problems):
         q = q if isinstance(q, BatchProblem) else BatchProblem(**q)
@@ -403,16 +422,7 @@ def kdcd_batch_solve(A, kernel, b, s, H, idx, problems, *, compute="f64", worksp
         arr[i].alpha = _dev(q.alpha, torch.float64, m, f"problems[{i}].alpha")
         arr[i].trace = (None if q.trace is None else
                         _dev(q.trace, torch.float64, int(H) * int(b), f"problems[{i}].trace"))
-    opt, prof = _options(compute, 1, 0, None, None, workspace, profile, flags, m, 0, 0)
-    kern = _kernel(kernel)
-    st = _lib.kdcd_batch_solve(ctypes.byref(mat), ctypes.byref(kern), int(b), int(s), int(H),
-                               idx.data_ptr(), arr, len(problems), ctypes.byref(opt),
-                               _stream(stream))
-    if st != 0:
-        raise KdcdError(st, "kdcd_batch_solve")
-    if prof is not None:
-        return {f: getattr(prof, f) for f, _ in _Profile._fields_}
-    return None
+    return arr
 
 
 def kdcd_kernel_rhs(A, kernel, S, beta, beta_scale=None, *, want_W=False, compute="f64",
@@ -627,6 +637,42 @@ def kdcd_autotune(A, kernel, sb, compute="f64", reps=10, stream=None):
                               int(reps), ctypes.byref(best), ctypes.byref(us), _stream(stream)),
            "kdcd_autotune")
     return best.value, us.value
+
+
+def kdcd_autotune_batch(A, kernel, sb, problems, compute="f64", reps=5, stream=None):
+    """Time every batched-product configuration on these problems; returns
+    (best id, mean launch us), recorded under compute + TUNE_BATCH."""
+    mat, m, _ = _matrix(A)
+    arr = _batch_array(problems, m, 0, 1)
+    best = ctypes.c_int32(-1)
+    us = ctypes.c_double(0.0)
+    _check(_lib.kdcd_autotune_batch(ctypes.byref(mat), ctypes.byref(_kernel(kernel)), int(sb), arr,
+                                    len(problems), _compute_id(compute), int(reps),
+                                    ctypes.byref(best), ctypes.byref(us), _stream(stream)),
+           "kdcd_autotune_batch")
+    return best.value, us.value
+
+
+TUNE_BATCH = 16
+
+
+def kdcd_batch_eval(A, kernel, problems, stream=None) -> list:
+    """FP64 objectives of every problem of a batch in one shared kernel pass:
+    K-RR {objective, residual_norm}, K-SVM {dual, primal, gap, kkt}."""
+    mat, m, _ = _matrix(A)
+    arr = _batch_array(problems, m, 0, 1)
+    out = (ctypes.c_double * (4 * len(problems)))()
+    _check(_lib.kdcd_batch_eval(ctypes.byref(mat), ctypes.byref(_kernel(kernel)), arr,
+                                len(problems), out, _stream(stream)), "kdcd_batch_eval")
+    res = []
+    for i, q in enumerate(problems):
+        kind = q.problem if isinstance(q, BatchProblem) else q["problem"]
+        o = out[4 * i:4 * i + 4]
+        if kind == "krr":
+            res.append({"objective": o[0], "residual_norm": o[1]})
+        else:
+            res.append({"dual": o[0], "primal": o[1], "gap": o[2], "kkt": o[3]})
+    return res
 
 
 def kdcd_tune_save(path):

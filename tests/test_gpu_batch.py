@@ -198,3 +198,34 @@ def test_batch_errors(K, c4):
     with pytest.raises(K.KdcdError) as e:
         K.kdcd_batch_solve(A, kern, 4, 2, 8, bad, [K.BatchProblem("krr", 1e-3, 1.0, y, zeros(m))])
     assert e.value.status == -3
+
+
+def test_batch_eval_matches_single_evals_and_oracle(K, c4):
+    """kdcd_batch_eval: every problem's objectives equal kdcd_krr_eval /
+    kdcd_ksvm_eval on its own, and the oracle's, at random feasible points."""
+    m = c4["A"].shape[0]
+    A, y = dev(c4["A"]), dev(c4["y"])
+    rng = np.random.default_rng(3)
+    probs, refs = [], []
+    for lam, sig in [(1e-3, 0.5), (1e-2, 1.0)]:
+        a = rng.standard_normal(m) * 1e-3
+        probs.append(K.BatchProblem("krr", lam, sig, y, dev(a)))
+        refs.append(O.krr_eval(c4["A"], c4["y"], O.Kernel(O.RBF, sigma=sig), lam, a))
+    for c, (C, loss, sig) in enumerate([(1.0, 1, 1.0), (2.0, 2, 0.5)]):
+        a = rng.uniform(0.0, C, m) if loss == 1 else rng.uniform(0.0, 1.0, m)
+        yc = c4["Y_ovr"][c]
+        probs.append(K.BatchProblem("ksvm", C, sig, dev(yc), dev(a), loss=loss))
+        refs.append(O.ksvm_eval(c4["A"], yc, O.Kernel(O.RBF, sigma=sig), C, a, loss=loss))
+    got = K.kdcd_batch_eval(A, (2, 1.0, 0.0, 1), probs)
+    for q, g, ref in zip(probs, got, refs):
+        kp = (2, q.sigma, 0.0, 1)
+        if q.problem == "krr":
+            one = K.kdcd_krr_eval(A, q.y, kp, q.param, q.alpha)
+            assert abs(g["objective"] - one["objective"]) <= 1e-12 * abs(one["objective"])
+            assert abs(g["residual_norm"] - one["residual_norm"]) <= 1e-12 * one["residual_norm"]
+        else:
+            one = K.kdcd_ksvm_eval(A, q.y, kp, q.param, q.alpha, loss=q.loss)
+            for key in ("dual", "primal", "gap"):
+                assert abs(g[key] - one[key]) <= 1e-11 * max(abs(one[key]), 1.0), key
+        key = "objective" if q.problem == "krr" else "dual"
+        assert abs(g[key] - ref[key]) <= 1e-10 * abs(ref[key])

@@ -130,3 +130,47 @@ def test_every_lowp_config_within_bounds(K, m, n, sb, kk):
                 assert_parity(r.cpu().numpy(), r_ref, tol, f"{compute} config {cid}")
         finally:
             K.kdcd_tune_set(compute, n, sb, -1)
+
+
+@pytest.mark.parametrize("compute,tol", [("f64", 1e-9), ("bf16x3", 1e-4), ("f32", 1e-4)])
+def test_every_batch_config(K, compute, tol):
+    """Every tile configuration of the batched product, forced through the table
+    (compute + TUNE_BATCH), against the FP64 oracle run problem by problem
+    (three sigma groups, K-RR and K-SVM problems, a ragged last outer iteration);
+    the batched autotuner records its choice."""
+    d = inputs.dense_c4(m=1800, n=96, n_classes=2, seed=13)
+    m, b, s, H = 1800, 8, 16, 40           # 2 full outer iterations and one of 8 blocks
+    idx_h = inputs.krr_indices(m, b, H, seed=4)
+    I = idx_dev(idx_h)
+    A, y = dev(d["A"]), dev(d["y"])
+    specs = [("krr", 1e-3, 0.5), ("krr", 1e-3, 1.0), ("ksvm", 1.0, 1.0), ("krr", 1e-2, 2.0)]
+    key = K.COMPUTE[compute] + K.TUNE_BATCH
+    refs = []
+    for kind, par, sig in specs:
+        if kind == "krr":
+            refs.append(O.bdcd_krr(d["A"], d["y"], O.Kernel(O.RBF, sigma=sig), par, b, H, idx_h, s=s)[0])
+        else:
+            refs.append(O.dcd_ksvm(d["A"], d["Y_ovr"][0], O.Kernel(O.RBF, sigma=sig), par, H * b,
+                                   idx_h, s=s * b)[0])
+
+    def problems():
+        return [K.BatchProblem(kind, par, sig, y if kind == "krr" else dev(d["Y_ovr"][0]),
+                               torch.zeros(m, dtype=torch.float64, device="cuda"))
+                for kind, par, sig in specs]
+
+    n_cfg = len(K.kdcd_tune_configs(key))
+    assert n_cfg >= 3
+    try:
+        for cid in range(n_cfg):
+            for sb in (s * b, 8 * b):
+                K.kdcd_tune_set(key, 96, sb, cid)
+            probs = problems()
+            K.kdcd_batch_solve(A, (2, 1.0, 0.0, 1), b, s, H, I, probs, compute=compute)
+            for p, ref in zip(probs, refs):
+                assert_parity(p.alpha.cpu().numpy(), ref, tol, f"{compute} batch config {cid}")
+        best, us = K.kdcd_autotune_batch(A, (2, 1.0, 0.0, 1), s * b, problems(), compute=compute)
+        assert 0 <= best < n_cfg and us > 0
+        assert K.kdcd_tune_get(key, 96, s * b) == best
+    finally:
+        for sb in (s * b, 8 * b):
+            K.kdcd_tune_set(key, 96, sb, -1)
