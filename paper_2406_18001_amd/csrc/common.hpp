@@ -168,6 +168,9 @@ struct KBlockArgs {
     // CSR only: m + s*b doubles of scratch for sampled rows longer than the
     // LDS panel (their dot products are summed over pieces); null refuses them
     double *carry;
+    // CSR only: the dense-head panel (kblock_csr_panel_bytes(n) bytes, prepared
+    // once with launch_csr_panel_init); null keeps the broadcast kernels
+    void *csr_panel = nullptr;
     // dense single-problem FP64 product: tile configuration, resolved once by
     // the caller together with the row-group count the finish pass sums
     // (-1: looked up in the tuning table at launch)
@@ -184,6 +187,8 @@ void f64_config_shape(int id, int *bm, int *bn, int *waves);
 int f64_config_id(int64_t n, int32_t sb);
 int tune_lookup(int32_t compute, int64_t n, int32_t sb);   // -1: no entry
 void tune_store(int32_t compute, int64_t n, int32_t sb, int id);   // id < 0 removes
+size_t kblock_csr_panel_bytes(int64_t n);
+hipError_t launch_csr_panel_init(const kdcd_matrix *A, void *panel, hipStream_t st);
 int64_t kblock_mixed_row_groups(int cfg, int64_t m, int64_t n, int32_t sb, int32_t compute,
                                 bool batch);
 // Tile configurations of the batched products, tuned under compute + KDCD_TUNE_BATCH.

@@ -101,7 +101,7 @@ constexpr int csr_nbatch() { return KIND == KDCD_KERNEL_RBF ? 2 : (RPW == 8 ? 3 
 // is then hashed in pieces of CSR_VMAX consecutive entries (piece >= 0: the
 // panel holds entries [piece * CSR_VMAX, ...) of row j0 only).  Called by
 // every thread of the workgroup; ends with a barrier.
-template <class MaskT, int LPR>
+template <class MaskT, int LPR, int NT = CSR_NT>
 __device__ int build_panel(int j0, int piece, const int64_t *__restrict__ row_ptr,
                            const int32_t *__restrict__ col_idx, const double *__restrict__ val,
                            int64_t m, int64_t nnz, const int32_t *__restrict__ S, int32_t sb,
@@ -124,25 +124,46 @@ __device__ int build_panel(int j0, int piece, const int64_t *__restrict__ row_pt
             rowoff[1] = tot;
         }
     } else {
-        if (tid == 0) rowoff[0] = 0;
-        while (j1 < sb && j1 - j0 < LPR) {
-            const int64_t r = clampi(S[j1], 0, m - 1);
-            const int len = (int)(rp(r + 1) - rp(r));
-            if (tot + len > CSR_VMAX) break;
-            tot += len;
-            ++j1;
-            if (tid == 0) rowoff[j1 - j0] = tot;
+        // the lengths of sampled rows j0 .. j0 + LPR - 1 are loaded in parallel by
+        // the first wave; the chunk takes the longest prefix that fits the panel
+        static_assert(LPR <= 64, "one wave covers the chunk");
+        if (tid < 64) {
+            const int lane = tid;
+            const bool ok = lane < LPR && j0 + lane < sb;
+            int len = 0;
+            if (ok) {
+                const int64_t r = clampi(S[j0 + lane], 0, m - 1);
+                len = (int)(rp(r + 1) - rp(r));
+            }
+            int incl = len;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int up = __shfl_up(incl, o, 64);
+                if (lane >= o) incl += up;
+            }
+            // incl is nondecreasing and ok a prefix, so the rows that fit form a prefix
+            const int nrows = __popcll(__ballot(ok && incl <= CSR_VMAX));
+            if (lane < nrows) rowoff[lane + 1] = incl;
+            if (lane == 0) {
+                rowoff[0] = 0;
+                scan[0] = nrows;
+            }
         }
-        if (j1 == j0) return -2;          // one sampled row alone exceeds the panel
+        __syncthreads();
+        const int nrows = scan[0];
+        __syncthreads();                  // scan[] is reused below
+        if (nrows == 0) return -2;        // one sampled row alone exceeds the panel
+        j1 = j0 + nrows;
+        tot = rowoff[nrows];
     }
-    for (int x = tid; x < CSR_HS; x += CSR_NT) {
+    for (int x = tid; x < CSR_HS; x += NT) {
         hkey[x] = -1;
         hmask[x] = 0;
     }
-    for (int x = tid; x < CSR_FBITS / 32; x += CSR_NT) hfilt[x] = 0u;
+    for (int x = tid; x < CSR_FBITS / 32; x += NT) hfilt[x] = 0u;
     __syncthreads();
     // 1. insert every stored entry's column, mark which sampled row holds it
-    for (int f = tid; f < tot; f += CSR_NT) {
+    for (int f = tid; f < tot; f += NT) {
         int jj = 0;
         while (rowoff[jj + 1] <= f) ++jj;
         const int64_t r = clampi(S[j0 + jj], 0, m - 1);
@@ -160,13 +181,13 @@ __device__ int build_panel(int j0, int piece, const int64_t *__restrict__ row_pt
     }
     __syncthreads();
     // 2. offsets of each column's values: exclusive scan of popcounts over the slots
-    constexpr int PER = CSR_HS / CSR_NT;
+    constexpr int PER = CSR_HS / NT;
     int cnt = 0;
 #pragma unroll
     for (int q = 0; q < PER; ++q) cnt += popc(hmask[tid * PER + q]);
     scan[tid] = cnt;
     __syncthreads();
-    for (int off = 1; off < CSR_NT; off <<= 1) {   // Hillis-Steele inclusive scan
+    for (int off = 1; off < NT; off <<= 1) {   // Hillis-Steele inclusive scan
         const int v = tid >= off ? scan[tid - off] : 0;
         __syncthreads();
         scan[tid] += v;
@@ -180,7 +201,7 @@ __device__ int build_panel(int j0, int piece, const int64_t *__restrict__ row_pt
     }
     __syncthreads();
     // 3. place the values, in sampled-row order inside each column
-    for (int f = tid; f < tot; f += CSR_NT) {
+    for (int f = tid; f < tot; f += NT) {
         int jj = 0;
         while (rowoff[jj + 1] <= f) ++jj;
         const int64_t r = clampi(S[j0 + jj], 0, m - 1);
@@ -201,7 +222,8 @@ __global__ __launch_bounds__(CSR_NT) __attribute__((amdgpu_waves_per_eu(RPW > 1 
     const double *__restrict__ val, int64_t m, int64_t nnz, const int32_t *__restrict__ S,
     int32_t sb, const double *__restrict__ norms, KParams kp, const double *__restrict__ beta,
     const double *__restrict__ bscale, double *__restrict__ partial, double *__restrict__ W,
-    int32_t n_row_groups, double *__restrict__ carry, int32_t *status)
+    int32_t n_row_groups, double *__restrict__ carry, int32_t *status, int32_t jbeg,
+    int32_t jend, const int32_t *__restrict__ gate)
 {
     constexpr int LPR = 64 / RPW;                  // lanes per row = sampled rows per chunk
     constexpr int NW = CSR_NT / 64;
@@ -237,8 +259,9 @@ __global__ __launch_bounds__(CSR_NT) __attribute__((amdgpu_waves_per_eu(RPW > 1 
     const int wblk = (int)blockIdx.x - n_row_groups;   // W-part: sampled rows [wblk*ROWS, +ROWS)
     auto rp = [&](int64_t r) { return clampi(row_ptr[clampi(r, 0, m)], 0, nnz); };
 
-    for (int j0 = 0; j0 < sb;) {
-        int j1 = build_panel<MaskT, LPR>(j0, -1, row_ptr, col_idx, val, m, nnz, S, sb, hkey, hfilt,
+    if (gate && *gate == 0) return;   // the dense-head pass handled this chunk
+    for (int j0 = jbeg; j0 < jend;) {
+        int j1 = build_panel<MaskT, LPR>(j0, -1, row_ptr, col_idx, val, m, nnz, S, jend, hkey, hfilt,
                                           hmask, hbase, hval, rowoff, scan, status);
         int npieces = 1;
         if (j1 == -2) {                  // a sampled row longer than the panel: in pieces
@@ -264,7 +287,7 @@ __global__ __launch_bounds__(CSR_NT) __attribute__((amdgpu_waves_per_eu(RPW > 1 
             // carry[] (data rows of the U-part at [row], sampled rows of the
             // Gram part at [m + t]) before the map
             __syncthreads();             // every wave is done with the previous piece
-            build_panel<MaskT, LPR>(j0, pc, row_ptr, col_idx, val, m, nnz, S, sb, hkey, hfilt, hmask,
+            build_panel<MaskT, LPR>(j0, pc, row_ptr, col_idx, val, m, nnz, S, jend, hkey, hfilt, hmask,
                                     hbase, hval, rowoff, scan, status);
         }
         const bool last = pc + 1 == npieces;
@@ -431,7 +454,8 @@ __global__ __launch_bounds__(CSR_NT) __attribute__((amdgpu_waves_per_eu(4))) voi
     const double *__restrict__ val, int64_t m, int64_t nnz, const int32_t *__restrict__ S,
     int32_t sb, const double *__restrict__ norms, KParams kp, const double *__restrict__ beta,
     const double *__restrict__ bscale, double *__restrict__ partial, double *__restrict__ W,
-    int32_t n_row_groups, double *__restrict__ carry, int32_t *status)
+    int32_t n_row_groups, double *__restrict__ carry, int32_t *status, int32_t jbeg,
+    int32_t jend, const int32_t *__restrict__ gate)
 {
     constexpr int NW = CSR_NT / 64;
     constexpr int NB = KIND == KDCD_KERNEL_RBF ? 2 : 4;   // entries per lane per batch
@@ -451,8 +475,9 @@ __global__ __launch_bounds__(CSR_NT) __attribute__((amdgpu_waves_per_eu(4))) voi
     const int wblk = (int)blockIdx.x - n_row_groups;   // W-part: sampled rows [wblk*NW, +NW)
     auto rp = [&](int64_t r) { return clampi(row_ptr[clampi(r, 0, m)], 0, nnz); };
 
-    for (int j0 = 0; j0 < sb;) {
-        int j1 = build_panel<MaskT, WJ>(j0, -1, row_ptr, col_idx, val, m, nnz, S, sb, hkey, hfilt,
+    if (gate && *gate == 0) return;
+    for (int j0 = jbeg; j0 < jend;) {
+        int j1 = build_panel<MaskT, WJ>(j0, -1, row_ptr, col_idx, val, m, nnz, S, jend, hkey, hfilt,
                                         hmask, hbase, hval, rowoff, scan, status);
         int npieces = 1;
         if (j1 == -2) {                  // a sampled row longer than the panel: in pieces
@@ -473,7 +498,7 @@ __global__ __launch_bounds__(CSR_NT) __attribute__((amdgpu_waves_per_eu(4))) voi
         for (int pc = 0; pc < npieces; ++pc) {
         if (npieces > 1) {               // dot products summed over the pieces in carry[]
             __syncthreads();
-            build_panel<MaskT, WJ>(j0, pc, row_ptr, col_idx, val, m, nnz, S, sb, hkey, hfilt, hmask,
+            build_panel<MaskT, WJ>(j0, pc, row_ptr, col_idx, val, m, nnz, S, jend, hkey, hfilt, hmask,
                                    hbase, hval, rowoff, scan, status);
         }
         const bool last = pc + 1 == npieces;
@@ -565,6 +590,433 @@ __global__ __launch_bounds__(CSR_NT) __attribute__((amdgpu_waves_per_eu(4))) voi
     }
 }
 
+// ---------------------------------------------------------------- dense head
+// Chunks of up to 32 sampled rows, short data rows.  The panel's most shared
+// columns -- those stored by at least t* of the chunk's sampled rows, t* the
+// smallest count that keeps them <= HD_HEAD -- carry most of the multiply-adds
+// (on the C3 workload the 50-odd columns stored by four or more of the 32
+// sampled rows carry over nine tenths).  For them a dense HD_HEAD x 32 block
+// Bh of the sampled rows' values is kept; every wave scatters the head entries
+// of 16 data rows into a dense 16 x HD_HEAD tile X in LDS and forms X Bh^T on
+// v_mfma_f64_16x16x4.  Entries in the other panel columns (a few sampled rows
+// each) are added to per-row sums Pt in LDS with atomics.  Each wave owns its
+// rows' X and Pt, and one wave's atomics apply in lane and instruction order,
+// so every sum has a fixed order.
+//
+// The panel is built once per chunk by csr_panel_build_kernel (one workgroup)
+// into workspace memory: a column map over all n columns (EMPTY, a head
+// position | HD_HEADBIT, or a tail slot), the tail slots' row masks, value
+// offsets and values, and Bh.  The map is cleared column by column by the next
+// build (the list of the chunk's columns is kept), so it is filled once per
+// workspace.  A chunk of more than HD_CAP stored entries is left to the
+// broadcast kernel (the build raises a flag that gates both passes).
+constexpr int HD_NT = 256;                 // 4 waves
+constexpr int HD_NJ = 32;                  // sampled rows per chunk
+constexpr int HD_HEAD = 64;                // largest dense head
+constexpr int HD_RB = 16;                  // data rows per wave block (one MFMA row block)
+constexpr int HD_XLD = HD_HEAD + 1;        // padded row of X (rows land in different banks)
+constexpr int HD_MAXGROUPS = 512;
+constexpr int HD_CAP = 32768;              // stored entries of one chunk
+constexpr int HD_BUILD_NT = 1024;
+constexpr int32_t HD_EMPTY = INT32_MAX;
+constexpr int32_t HD_HEADBIT = 0x40000000;
+
+struct PanelMeta {
+    int32_t prev;        // columns set by the last build (cleared by the next)
+    int32_t nh;          // head columns
+    int32_t fallback;    // 1: the chunk exceeds HD_CAP, the broadcast kernel runs it
+    int32_t pad;
+};
+
+struct PanelPtrs {
+    PanelMeta *meta;
+    int32_t *colmap;     // n
+    int32_t *clist;      // HD_CAP columns of the last build
+    uint32_t *tmask;     // HD_CAP slots: row mask
+    int32_t *tbase;      // HD_CAP slots: offset of the slot's values (tail), head position (head)
+    double *tval;        // HD_CAP values
+    double *Bh;          // HD_HEAD x HD_NJ
+};
+
+__host__ __device__ inline size_t hd_al(size_t x) { return (x + 255) & ~size_t(255); }
+
+__host__ __device__ inline PanelPtrs panel_ptrs(void *base, int64_t n)
+{
+    char *p = static_cast<char *>(base);
+    PanelPtrs q;
+    q.meta = reinterpret_cast<PanelMeta *>(p); p += 256;
+    q.colmap = reinterpret_cast<int32_t *>(p); p += hd_al(sizeof(int32_t) * (size_t)n);
+    q.clist = reinterpret_cast<int32_t *>(p); p += hd_al(sizeof(int32_t) * HD_CAP);
+    q.tmask = reinterpret_cast<uint32_t *>(p); p += hd_al(sizeof(uint32_t) * HD_CAP);
+    q.tbase = reinterpret_cast<int32_t *>(p); p += hd_al(sizeof(int32_t) * HD_CAP);
+    q.tval = reinterpret_cast<double *>(p); p += hd_al(sizeof(double) * HD_CAP);
+    q.Bh = reinterpret_cast<double *>(p);
+    return q;
+}
+
+inline size_t panel_bytes(int64_t n)
+{
+    return 256 + hd_al(sizeof(int32_t) * (size_t)n) + 3 * hd_al(sizeof(int32_t) * HD_CAP) +
+           hd_al(sizeof(double) * HD_CAP) + hd_al(sizeof(double) * HD_HEAD * HD_NJ);
+}
+
+__global__ __launch_bounds__(256) void csr_panel_init_kernel(void *base, int64_t n)
+{
+    const PanelPtrs q = panel_ptrs(base, n);
+    for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < n; c += (int64_t)gridDim.x * 256)
+        q.colmap[c] = HD_EMPTY;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *q.meta = PanelMeta{0, 0, 0, 0};
+}
+
+// Block-wide exclusive scan of one int per thread (HD_BUILD_NT threads);
+// returns the thread's offset, total in *tot.
+__device__ int block_scan(int v, int32_t *sh, int *tot)
+{
+    const int tid = threadIdx.x;
+    sh[tid] = v;
+    __syncthreads();
+    for (int off = 1; off < HD_BUILD_NT; off <<= 1) {
+        const int u = tid >= off ? sh[tid - off] : 0;
+        __syncthreads();
+        sh[tid] += u;
+        __syncthreads();
+    }
+    const int incl = sh[tid];
+    *tot = sh[HD_BUILD_NT - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+// The panel of sampled rows S[0 .. nj) (nj <= HD_NJ), one workgroup.
+__global__ __launch_bounds__(HD_BUILD_NT) void csr_panel_build_kernel(
+    const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx,
+    const double *__restrict__ val, int64_t m, int64_t nnz, const int32_t *__restrict__ S,
+    int32_t nj, int64_t n, void *base)
+{
+    const PanelPtrs q = panel_ptrs(base, n);
+    __shared__ int32_t rowoff[HD_NJ + 1];
+    __shared__ int64_t rowbeg[HD_NJ];
+    __shared__ int32_t sh[HD_BUILD_NT];
+    __shared__ int32_t hist[HD_NJ + 2];
+    __shared__ int32_t info[4];
+    const int tid = threadIdx.x;
+    auto rp = [&](int64_t r) { return clampi(row_ptr[clampi(r, 0, m)], 0, nnz); };
+    // 1. clear the previous chunk's columns; entry ranges of the sampled rows
+    const int prev = q.meta->prev;
+    for (int i = tid; i < prev; i += HD_BUILD_NT) {
+        const int32_t c = q.clist[i];
+        if (c >= 0 && c < n) q.colmap[c] = HD_EMPTY;
+    }
+    if (tid < 64) {
+        int len = 0;
+        int64_t b0 = 0;
+        if (tid < nj) {
+            const int64_t r = clampi(S[tid], 0, m - 1);
+            b0 = rp(r);
+            len = (int)(rp(r + 1) - b0);
+        }
+        int incl = len;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int up = __shfl_up(incl, o, 64);
+            if (tid >= o) incl += up;
+        }
+        if (tid < nj) {
+            rowoff[tid + 1] = incl;
+            rowbeg[tid] = b0;
+        }
+        if (tid == 0) rowoff[0] = 0;
+    }
+    if (tid < HD_NJ + 2) hist[tid] = 0;
+    __threadfence();
+    __syncthreads();
+    const int total = rowoff[nj];
+    if (total > HD_CAP) {
+        if (tid == 0) *q.meta = PanelMeta{0, 0, 1, 0};
+        return;
+    }
+    auto entry = [&](int f, int &jj) {
+        jj = 0;
+        while (jj + 1 < nj && rowoff[jj + 1] <= f) ++jj;
+        return clampi(rowbeg[jj] + (f - rowoff[jj]), 0, nnz - 1);
+    };
+    // 2. every column's first entry (entries in chunk order)
+    for (int f = tid; f < total; f += HD_BUILD_NT) {
+        int jj;
+        const int32_t c = col_idx[entry(f, jj)];
+        if (c >= 0 && c < n) atomicMin(&q.colmap[c], f);
+    }
+    __threadfence();
+    __syncthreads();
+    // 3. the first entry of a column numbers it: slots in entry order
+    int nslots = 0;
+    for (int f0 = 0; f0 < total; f0 += HD_BUILD_NT) {
+        const int f = f0 + tid;
+        int jj = 0;
+        int32_t c = -1;
+        bool own = false;
+        if (f < total) {
+            c = col_idx[entry(f, jj)];
+            own = c >= 0 && c < n && q.colmap[c] == f;
+        }
+        int cnt;
+        const int slot = nslots + block_scan(own ? 1 : 0, sh, &cnt);
+        if (own) {
+            q.clist[slot] = c;
+            q.tmask[slot] = 0u;
+        }
+        nslots += cnt;
+    }
+    __threadfence();
+    __syncthreads();
+    for (int s = tid; s < nslots; s += HD_BUILD_NT) q.colmap[q.clist[s]] = -1 - s;   // column -> slot
+    __threadfence();
+    __syncthreads();
+    // 4. row masks of the slots, counts
+    for (int f = tid; f < total; f += HD_BUILD_NT) {
+        int jj;
+        const int32_t c = col_idx[entry(f, jj)];
+        if (c >= 0 && c < n) atomicOr(&q.tmask[-1 - q.colmap[c]], 1u << jj);
+    }
+    __threadfence();
+    __syncthreads();
+    for (int s = tid; s < nslots; s += HD_BUILD_NT) atomicAdd(&hist[__popc(q.tmask[s])], 1);
+    __syncthreads();
+    if (tid == 0) {
+        int t = HD_NJ + 1, acc = 0;
+        while (t > 1 && acc + hist[t - 1] <= HD_HEAD) acc += hist[--t];
+        info[0] = t;          // columns stored by >= t sampled rows form the head
+    }
+    for (int x = tid; x < HD_HEAD * HD_NJ; x += HD_BUILD_NT) q.Bh[x] = 0.0;
+    __syncthreads();
+    const int tstar = info[0];
+    // 5. head positions and tail value offsets, both in slot order
+    int nh = 0, nv = 0;
+    for (int s0 = 0; s0 < nslots; s0 += HD_BUILD_NT) {
+        const int s = s0 + tid;
+        const uint32_t msk = s < nslots ? q.tmask[s] : 0u;
+        const bool head = s < nslots && __popc(msk) >= tstar;
+        int ch, cv;
+        const int ph = nh + block_scan(head ? 1 : 0, sh, &ch);
+        const int pv = nv + block_scan((s < nslots && !head) ? __popc(msk) : 0, sh, &cv);
+        if (s < nslots) q.tbase[s] = head ? -1 - ph : pv;   // < 0 marks a head slot
+        nh += ch;
+        nv += cv;
+    }
+    __threadfence();
+    __syncthreads();
+    // 6. values: dense head block, tail values in sampled-row order per column
+    for (int f = tid; f < total; f += HD_BUILD_NT) {
+        int jj;
+        const int64_t e = entry(f, jj);
+        const int32_t c = col_idx[e];
+        if (c < 0 || c >= n) continue;        // a malformed matrix (its check reports it)
+        const int32_t s = -1 - q.colmap[c];
+        const int32_t tb = q.tbase[s];
+        if (tb < 0)
+            q.Bh[(-1 - tb) * HD_NJ + jj] = val[e];
+        else
+            q.tval[tb + __popc(q.tmask[s] & ((1u << jj) - 1u))] = val[e];
+    }
+    __threadfence();
+    __syncthreads();
+    // 7. final column map: head position | HD_HEADBIT, or the tail slot
+    for (int s = tid; s < nslots; s += HD_BUILD_NT) {
+        const int32_t tb = q.tbase[s];
+        q.colmap[q.clist[s]] = tb < 0 ? (HD_HEADBIT | (-1 - tb)) : s;
+    }
+    if (tid == 0) *q.meta = PanelMeta{nslots, nh, 0, 0};
+}
+
+template <int KIND>
+__global__ __launch_bounds__(HD_NT) __attribute__((amdgpu_waves_per_eu(3))) void kblock_csr_head_kernel(
+    const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx,
+    const double *__restrict__ val, int64_t m, int64_t nnz, int64_t n,
+    const int32_t *__restrict__ S, int32_t sb, int32_t j0, int32_t nj,
+    const double *__restrict__ norms, KParams kp, const double *__restrict__ beta,
+    const double *__restrict__ bscale, double *__restrict__ partial, double *__restrict__ W,
+    int32_t n_row_groups, const void *__restrict__ pbase)
+{
+    constexpr int NW = HD_NT / 64;
+    const PanelPtrs q = panel_ptrs(const_cast<void *>(pbase), n);
+    if (q.meta->fallback) return;
+    __shared__ double X[NW][HD_RB][HD_XLD];
+    __shared__ double Pt[NW][HD_RB][HD_NJ];
+    __shared__ int32_t woff[NW][HD_RB + 1];     // entry offsets of a block's rows
+    __shared__ int64_t wbeg[NW][HD_RB];         // first entry of each row of the block
+    __shared__ double red[NW][HD_NJ];
+
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const bool is_w = (int)blockIdx.x >= n_row_groups;
+    if (is_w && W == nullptr) return;
+    const int wblk = (int)blockIdx.x - n_row_groups;   // W-part: sampled rows [wblk*64, +64)
+    auto rp = [&](int64_t r) { return clampi(row_ptr[clampi(r, 0, m)], 0, nnz); };
+    const int li = lane & 15, lk = lane >> 4;          // MFMA operand row / k slot
+    const int nks = (q.meta->nh + 3) / 4;              // MFMA k-steps over the head
+
+    // this lane's part of Bh (B operand of every k-step), in registers
+    double bh[HD_HEAD / 4][2];
+#pragma unroll
+    for (int ks = 0; ks < HD_HEAD / 4; ++ks)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) bh[ks][c] = q.Bh[(4 * ks + lk) * HD_NJ + c * 16 + li];
+    int64_t Sj[2];
+    double nb[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const int jj = c * 16 + li;
+        Sj[c] = clampi(S[j0 + (jj < nj ? jj : 0)], 0, m - 1);
+        nb[c] = (KIND == KDCD_KERNEL_RBF) ? norms[Sj[c]] : 0.0;
+    }
+    double colsum[2] = {0.0, 0.0};
+
+    const int64_t nblk = is_w ? (sb + HD_RB - 1) / HD_RB : (m + HD_RB - 1) / HD_RB;
+    const int64_t b_first = is_w ? (int64_t)wblk * NW + wid : (int64_t)blockIdx.x * NW + wid;
+    const int64_t b_end = is_w ? min(nblk, (int64_t)(wblk + 1) * NW) : nblk;
+    const int64_t b_step = is_w ? NW : (int64_t)n_row_groups * NW;
+    // entry range of row lane (< HD_RB) of block blk
+    auto rowinfo = [&](int64_t blk, int64_t &b0, int32_t &len) {
+        b0 = 0;
+        len = 0;
+        if (lane < HD_RB && blk < b_end) {
+            const int64_t rix = blk * HD_RB + lane;
+            const bool rok = is_w ? rix < sb : rix < m;
+            const int64_t row = is_w ? clampi(S[clampi(rix, 0, sb - 1)], 0, m - 1) : rix;
+            if (rok) {
+                b0 = rp(row);
+                len = (int32_t)(rp(row + 1) - b0);
+            }
+        }
+    };
+    int64_t nb0;
+    int32_t nlen;
+    rowinfo(b_first, nb0, nlen);
+    for (int64_t blk = b_first; blk < b_end; blk += b_step) {
+        // rows of the block, their entry ranges (the next block's are loaded now,
+        // in flight while this one is processed) and the zeroed tiles
+        const int64_t b0 = nb0;
+        const int32_t len = nlen;
+        rowinfo(blk + b_step, nb0, nlen);
+        int32_t incl = len;                   // inclusive scan over lanes 0..15
+#pragma unroll
+        for (int o = 1; o < HD_RB; o <<= 1) {
+            const int32_t up = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += up;
+        }
+        if (lane < HD_RB) {
+            wbeg[wid][lane] = b0;
+            woff[wid][lane + 1] = incl;
+        }
+        if (lane == 0) woff[wid][0] = 0;
+        for (int x = lane; x < HD_RB * HD_XLD; x += 64) (&X[wid][0][0])[x] = 0.0;
+        for (int x = lane; x < HD_RB * HD_NJ; x += 64) (&Pt[wid][0][0])[x] = 0.0;
+        wave_lds_sync();
+        const int total = woff[wid][HD_RB];
+        // this lane's output rows (t = l/16 + 4 v): beta and norms, loaded ahead
+        double bvv[4], nav[4];
+        int64_t rowv[4];
+        bool rokv[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t rix = blk * HD_RB + lk + 4 * v;
+            rokv[v] = is_w ? rix < sb : rix < m;
+            rowv[v] = is_w ? clampi(S[clampi(rix, 0, sb - 1)], 0, m - 1) : clampi(rix, 0, m - 1);
+            double bv = 0.0;
+            if (!is_w && rokv[v]) {
+                bv = beta[rowv[v]];
+                if (bscale) bv *= bscale[rowv[v]];
+            }
+            bvv[v] = bv;
+            nav[v] = (KIND == KDCD_KERNEL_RBF && rokv[v]) ? norms[rowv[v]] : 0.0;
+        }
+        // entries: position f of the block's concatenated rows, its row by search;
+        // HD_EPL entries per lane loaded together, then their columns looked up
+        constexpr int HD_EPL = 8;
+        for (int base = 0; base < total; base += 64 * HD_EPL) {
+            int32_t cu[HD_EPL], tu[HD_EPL], mu[HD_EPL];
+            double vu[HD_EPL];
+#pragma unroll
+            for (int u = 0; u < HD_EPL; ++u) {
+                const int f = base + lane + 64 * u;
+                int t = 0;
+#pragma unroll
+                for (int step = 8; step >= 1; step >>= 1)
+                    if (woff[wid][t + step] <= f) t += step;
+                const int64_t e = clampi(wbeg[wid][t] + (f - woff[wid][t]), 0, nnz - 1);
+                tu[u] = t;
+                cu[u] = f < total ? col_idx[e] : -1;
+                vu[u] = f < total ? val[e] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < HD_EPL; ++u)
+                mu[u] = (cu[u] >= 0 && cu[u] < n) ? q.colmap[cu[u]] : HD_EMPTY;
+#pragma unroll
+            for (int u = 0; u < HD_EPL; ++u) {
+                const int32_t code = mu[u];
+                if (code == HD_EMPTY) continue;
+                const int t = tu[u];
+                if (code & HD_HEADBIT) {
+                    X[wid][t][code & (HD_HEADBIT - 1)] = vu[u];
+                } else {
+                    uint32_t msk = q.tmask[code];
+                    const int bs = q.tbase[code];
+                    int k = 0;
+                    while (msk) {
+                        const int j = __builtin_ctz(msk);
+                        msk &= msk - 1;
+                        atomicAdd(&Pt[wid][t][j], vu[u] * q.tval[bs + k]);
+                        ++k;
+                    }
+                }
+            }
+        }
+        wave_lds_sync();
+        // head product on MFMA: P = X Bh^T, two 16 x 16 blocks of sampled rows
+        d4 acc[2] = {d4{0.0, 0.0, 0.0, 0.0}, d4{0.0, 0.0, 0.0, 0.0}};
+#pragma unroll
+        for (int ks = 0; ks < HD_HEAD / 4; ++ks) {
+            if (ks < nks) {                           // uniform
+                const double a = X[wid][li][4 * ks + lk];
+#pragma unroll
+                for (int c = 0; c < 2; ++c)
+                    acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bh[ks][c], acc[c], 0, 0, 0);
+            }
+        }
+        // item v of lane l: row l/16 + 4 v of the block, column l%16 of block c
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int t = lk + 4 * v;
+            const int64_t rix = blk * HD_RB + t;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const int jj = c * 16 + li;
+                if (!rokv[v] || jj >= nj) continue;
+                const double pv = acc[c][v] + Pt[wid][t][jj];
+                const double kv = kernel_map<KIND>(pv, nav[v], nb[c], rowv[v] == Sj[c], kp);
+                if (is_w) W[rix * sb + j0 + jj] = kv;
+                else colsum[c] += bvv[v] * kv;
+            }
+        }
+        wave_lds_sync();          // the block's X / Pt reads are done
+    }
+    if (!is_w) {
+        // lanes l, l ^ 16, l ^ 32, l ^ 48 hold the same column: lanes -> waves -> group
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            double v = colsum[c];
+            v += __shfl_xor(v, 16);
+            v += __shfl_xor(v, 32);
+            if (lane < 16) red[wid][c * 16 + lane] = v;
+        }
+        __syncthreads();
+        if (tid < nj) {
+            double t = 0.0;
+            for (int w = 0; w < NW; ++w) t += red[w][tid];
+            partial[(int64_t)blockIdx.x * sb + j0 + tid] = t;
+        }
+    }
+}
+
 int64_t groups_for(int64_t m)
 {
     const int64_t steps = (m + 15) / 16;
@@ -572,12 +1024,6 @@ int64_t groups_for(int64_t m)
 }
 
 }  // namespace
-
-int64_t kblock_csr_row_groups(int64_t m, int32_t sb)
-{
-    (void)sb;
-    return groups_for(m);
-}
 
 // Lanes per row (LPR = 64 / RPW): no more than the sampled rows need, and
 // few enough that a chunk of LPR average-length sampled rows fits the panel
@@ -590,20 +1036,103 @@ int csr_rows_per_wave(const kdcd_matrix *A, int32_t sb)
     return 64 / lpr;
 }
 
+// Kernel choice: long rows (average >= kCsrWaveMinAvg at <= 8 sampled rows per
+// chunk) -> one wave per row; more than 16 sampled rows -> the dense-head
+// kernel; otherwise the broadcast / scatter kernel.
+enum CsrPath { CSR_BROADCAST, CSR_WAVE, CSR_HEAD };
+CsrPath csr_path(const kdcd_matrix *A, int32_t sb)
+{
+    const int rpw = csr_rows_per_wave(A, sb);
+    if (rpw == 8 && (double)A->nnz >= kCsrWaveMinAvg * (double)A->m) return CSR_WAVE;
+    return sb > 16 ? CSR_HEAD : CSR_BROADCAST;
+}
+
+int64_t kblock_csr_row_groups(const kdcd_matrix *A, int32_t sb)
+{
+    if (csr_path(A, sb) == CSR_HEAD) {
+        const int64_t steps = (A->m + 63) / 64;          // 4 waves x 16 rows per step
+        return steps < HD_MAXGROUPS ? steps : HD_MAXGROUPS;
+    }
+    return groups_for(A->m);
+}
+
+size_t kblock_csr_panel_bytes(int64_t n) { return panel_bytes(n); }
+
+hipError_t launch_csr_panel_init(const kdcd_matrix *A, void *panel, hipStream_t st)
+{
+    const int64_t blocks = std::min<int64_t>((A->n + 255) / 256, 4096);
+    hipLaunchKernelGGL(csr_panel_init_kernel, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256),
+                       0, st, panel, A->n);
+    return hipGetLastError();
+}
+
 hipError_t launch_kblock_csr(const KBlockArgs &a, hipStream_t st)
 {
     const kdcd_matrix *A = a.A;
     const int rpw = csr_rows_per_wave(A, a.sb);
+    const CsrPath path = csr_path(A, a.sb);
+    if (path == CSR_HEAD && a.csr_panel) {
+        // per chunk of HD_NJ sampled rows: panel build, dense-head pass, and the
+        // broadcast kernel gated on the build's fallback flag
+        const int64_t groups = kblock_csr_row_groups(A, a.sb);
+        const int64_t n_w = a.W ? (a.sb + 63) / 64 : 0;
+        const PanelPtrs q = panel_ptrs(a.csr_panel, A->n);
+        const int64_t rows_per_wg_b = (CSR_NT / 64) * rpw;
+        const int64_t n_w_b = a.W ? (a.sb + rows_per_wg_b - 1) / rows_per_wg_b : 0;
+        ArmedEvents armed = armed_events();          // the timer covers the whole chunk loop
+        armed_events() = ArmedEvents{nullptr, nullptr};
+        for (int32_t j0 = 0; j0 < a.sb; j0 += HD_NJ) {
+            const int32_t nj = std::min<int32_t>(HD_NJ, a.sb - j0);
+            const bool first = j0 == 0, lastc = j0 + HD_NJ >= a.sb;
+            if (first && armed.start) (void)hipEventRecord(armed.start, st);
+            hipLaunchKernelGGL(csr_panel_build_kernel, dim3(1), dim3(HD_BUILD_NT), 0, st, A->row_ptr,
+                               A->col_idx, A->values, A->m, A->nnz, a.S + j0, nj, A->n, a.csr_panel);
+            dim3 grid((unsigned)(groups + n_w)), block(HD_NT);
+#define KDCD_CSR_HEAD(KIND)                                                                    \
+    hipLaunchKernelGGL((kblock_csr_head_kernel<KIND>), grid, block, 0, st, A->row_ptr,          \
+                       A->col_idx, A->values, A->m, A->nnz, A->n, a.S, a.sb, j0, nj, a.norms,  \
+                       a.kp, a.beta, a.beta_scale, a.partial, a.W, (int32_t)groups, a.csr_panel)
+            switch (a.kp.kind) {
+            case KDCD_KERNEL_LINEAR: KDCD_CSR_HEAD(KDCD_KERNEL_LINEAR); break;
+            case KDCD_KERNEL_POLY: KDCD_CSR_HEAD(KDCD_KERNEL_POLY); break;
+            default: KDCD_CSR_HEAD(KDCD_KERNEL_RBF); break;
+            }
+#undef KDCD_CSR_HEAD
+            dim3 gridb((unsigned)(groups + n_w_b)), blockb(CSR_NT);
+#define KDCD_CSR_FB(RPW, KIND)                                                                  \
+    hipLaunchKernelGGL((kblock_csr_kernel<RPW, KIND>), gridb, blockb, 0, st, A->row_ptr,          \
+                       A->col_idx, A->values, A->m, A->nnz, a.S, a.sb, a.norms, a.kp, a.beta,    \
+                       a.beta_scale, a.partial, a.W, (int32_t)groups, a.carry, a.status, j0,     \
+                       j0 + nj, &q.meta->fallback)
+#define KDCD_CSR_FB_KIND(RPW)                                                                   \
+    switch (a.kp.kind) {                                                                        \
+    case KDCD_KERNEL_LINEAR: KDCD_CSR_FB(RPW, KDCD_KERNEL_LINEAR); break;                       \
+    case KDCD_KERNEL_POLY: KDCD_CSR_FB(RPW, KDCD_KERNEL_POLY); break;                           \
+    default: KDCD_CSR_FB(RPW, KDCD_KERNEL_RBF); break;                                          \
+    }
+            switch (rpw) {
+            case 1: KDCD_CSR_FB_KIND(1) break;
+            case 2: KDCD_CSR_FB_KIND(2) break;
+            case 4: KDCD_CSR_FB_KIND(4) break;
+            default: KDCD_CSR_FB_KIND(8) break;
+            }
+#undef KDCD_CSR_FB_KIND
+#undef KDCD_CSR_FB
+            if (lastc && armed.stop) (void)hipEventRecord(armed.stop, st);
+        }
+        return hipGetLastError();
+    }
     // long rows: one wave per data row and per-lane sums (chunks of <= 8 rows)
-    const bool wave = rpw == 8 && (double)A->nnz >= kCsrWaveMinAvg * (double)A->m;
+    const bool wave = path == CSR_WAVE;
+    const int64_t groups = kblock_csr_row_groups(A, a.sb);
     const int rows_per_wg = (CSR_NT / 64) * (wave ? 1 : rpw);
-    const int64_t groups = groups_for(A->m);
     const int64_t n_w = a.W ? (a.sb + rows_per_wg - 1) / rows_per_wg : 0;
     dim3 grid((unsigned)(groups + n_w)), block(CSR_NT);
 #define KDCD_CSR(RPW, KIND)                                                                   \
-    hipLaunchKernelGGL((kblock_csr_kernel<RPW, KIND>), grid, block, 0, st, A->row_ptr,         \
+    KDCD_TIMED_LAUNCH((kblock_csr_kernel<RPW, KIND>), grid, block, 0, st, A->row_ptr,          \
                        A->col_idx, A->values, A->m, A->nnz, a.S, a.sb, a.norms, a.kp, a.beta,  \
-                       a.beta_scale, a.partial, a.W, (int32_t)groups, a.carry, a.status)
+                       a.beta_scale, a.partial, a.W, (int32_t)groups, a.carry, a.status, 0, a.sb, \
+                       nullptr)
 #define KDCD_CSR_KIND(RPW)                                                                    \
     switch (a.kp.kind) {                                                                      \
     case KDCD_KERNEL_LINEAR: KDCD_CSR(RPW, KDCD_KERNEL_LINEAR); break;                        \
@@ -613,19 +1142,22 @@ hipError_t launch_kblock_csr(const KBlockArgs &a, hipStream_t st)
     if (wave) {
         switch (a.kp.kind) {
         case KDCD_KERNEL_LINEAR:
-            hipLaunchKernelGGL((kblock_csr_wave_kernel<KDCD_KERNEL_LINEAR>), grid, block, 0, st,
+            KDCD_TIMED_LAUNCH((kblock_csr_wave_kernel<KDCD_KERNEL_LINEAR>), grid, block, 0, st,
                                A->row_ptr, A->col_idx, A->values, A->m, A->nnz, a.S, a.sb, a.norms,
-                               a.kp, a.beta, a.beta_scale, a.partial, a.W, (int32_t)groups, a.carry, a.status);
+                               a.kp, a.beta, a.beta_scale, a.partial, a.W, (int32_t)groups, a.carry, a.status,
+                               0, a.sb, nullptr);
             break;
         case KDCD_KERNEL_POLY:
-            hipLaunchKernelGGL((kblock_csr_wave_kernel<KDCD_KERNEL_POLY>), grid, block, 0, st,
+            KDCD_TIMED_LAUNCH((kblock_csr_wave_kernel<KDCD_KERNEL_POLY>), grid, block, 0, st,
                                A->row_ptr, A->col_idx, A->values, A->m, A->nnz, a.S, a.sb, a.norms,
-                               a.kp, a.beta, a.beta_scale, a.partial, a.W, (int32_t)groups, a.carry, a.status);
+                               a.kp, a.beta, a.beta_scale, a.partial, a.W, (int32_t)groups, a.carry, a.status,
+                               0, a.sb, nullptr);
             break;
         default:
-            hipLaunchKernelGGL((kblock_csr_wave_kernel<KDCD_KERNEL_RBF>), grid, block, 0, st,
+            KDCD_TIMED_LAUNCH((kblock_csr_wave_kernel<KDCD_KERNEL_RBF>), grid, block, 0, st,
                                A->row_ptr, A->col_idx, A->values, A->m, A->nnz, a.S, a.sb, a.norms,
-                               a.kp, a.beta, a.beta_scale, a.partial, a.W, (int32_t)groups, a.carry, a.status);
+                               a.kp, a.beta, a.beta_scale, a.partial, a.W, (int32_t)groups, a.carry, a.status,
+                               0, a.sb, nullptr);
             break;
         }
         return hipGetLastError();

@@ -127,8 +127,10 @@ def test_csr_errors(K):
 @pytest.mark.parametrize("kk", [POLY13, (2, 0.5, 0.0, 1)])
 def test_csr_rows_longer_than_panel(K, kk):
     """Sampled rows with more stored entries than the LDS panel holds (3072)
-    are hashed in pieces and their dot products summed before the map: r and
-    W against the oracle, with the long rows alone and among short ones."""
+    are hashed in pieces and their dot products summed before the map, and
+    chunks of sampled rows too large for the dense-head panel fall back to the
+    broadcast kernel: r and W against the oracle, with the long rows alone and
+    among short ones."""
     m, n = 300, 20000
     rng = np.random.default_rng(4)
     lens = [4000, 7000, 3073] + list(rng.integers(0, 60, m - 3))   # some rows empty
@@ -145,7 +147,10 @@ def test_csr_rows_longer_than_panel(K, kk):
     beta = rng.standard_normal(m)
     empty = [i for i in range(3, m) if lens[i] == 0][:2]
     assert empty
-    for S in ([0], [1, 5], [3, 0, 7, 1, 2], list(range(10, 50)) + [1], empty + [2, 4]):
+    # the sixth set's first 32 rows store more entries than one panel chunk
+    # takes (the broadcast kernel runs that chunk), its last three fewer
+    for S in ([0], [1, 5], [3, 0, 7, 1, 2], list(range(10, 50)) + [1], empty + [2, 4],
+              [0, 1, 2] * 6 + list(range(3, 20))):
         S = np.asarray(S, dtype=np.int32)
         r, W = K.kdcd_kernel_rhs(to_gpu(K, c), kk, idx_dev(S), dev(beta), want_W=True)
         assert_parity(r.cpu().numpy(), O.kernel_rhs(as_oracle(c), ok, S, beta), 1e-11, f"r {S[:3]}")
