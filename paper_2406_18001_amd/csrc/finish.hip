@@ -104,7 +104,17 @@ __global__ __launch_bounds__(256) void finish_kernel(const FinishDesc d, int32_t
         const double *partial = d.partial[p];
         double s = 0.0;
         if (col < sb)
-            for (int64_t g = part; g < d.groups; g += FIN_PARTS) s += partial[g * sb + col];
+            for (int64_t g0 = part; g0 < d.groups; g0 += 8 * FIN_PARTS) {
+                // eight loads in flight, added in row-group order
+                double v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int64_t g = g0 + (int64_t)u * FIN_PARTS;
+                    v[u] = g < d.groups ? partial[g * sb + col] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) s += v[u];
+            }
         sh[part * FIN_COLS + c] = s;
         __syncthreads();
         if (part == 0 && col < sb) {

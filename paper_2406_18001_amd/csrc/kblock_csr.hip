@@ -603,26 +603,45 @@ __global__ __launch_bounds__(CSR_NT) __attribute__((amdgpu_waves_per_eu(4))) voi
 // rows' X and Pt, and one wave's atomics apply in lane and instruction order,
 // so every sum has a fixed order.
 //
-// The panel is built once per chunk by csr_panel_build_kernel (one workgroup)
-// into workspace memory: a column map over all n columns (EMPTY, a head
-// position | HD_HEADBIT, or a tail slot), the tail slots' row masks, value
-// offsets and values, and Bh.  The map is cleared column by column by the next
-// build (the list of the chunk's columns is kept), so it is filled once per
-// workspace.  A chunk of more than HD_CAP stored entries is left to the
-// broadcast kernel (the build raises a flag that gates both passes).
-constexpr int HD_NT = 256;                 // 4 waves
+// The panel is built once per chunk by csr_panel_build_kernel (one workgroup,
+// an LDS hash of the chunk's columns) into workspace memory: a 16-byte record
+// per column of A, the tail values and Bh.  A record holds a code word -- the
+// build's epoch, a head flag, and the head position or the offset of the
+// column's values in tval -- the sampled rows that store the column, and the
+// first of its values.  A data entry needs one record load, and most tail
+// entries (one sampled row) nothing more.  Records of other epochs are not in
+// the panel, so nothing is cleared between builds.  A chunk of more than
+// HD_CAP stored entries is left to the broadcast kernel (the build raises a
+// flag that gates both passes).
+constexpr int HD_NT = 128;                 // 2 waves
 constexpr int HD_NJ = 32;                  // sampled rows per chunk
 constexpr int HD_HEAD = 64;                // largest dense head
 constexpr int HD_RB = 16;                  // data rows per wave block (one MFMA row block)
 constexpr int HD_XLD = HD_HEAD + 1;        // padded row of X (rows land in different banks)
-constexpr int HD_MAXGROUPS = 512;
-constexpr int HD_CAP = 32768;              // stored entries of one chunk
+constexpr int HD_PLD = HD_NJ + 1;          // padded row of Pt
+constexpr int HD_MAXGROUPS = 2048;         // eight workgroups per CU
+constexpr int HD_FBGROUPS = 128;           // row groups of the broadcast fallback
 constexpr int HD_BUILD_NT = 1024;
-constexpr int32_t HD_EMPTY = INT32_MAX;
-constexpr int32_t HD_HEADBIT = 0x40000000;
+constexpr int HD_EPT = 4;                  // stored entries per build thread
+constexpr int HD_CAP = HD_BUILD_NT * HD_EPT;   // stored entries of one chunk
+constexpr int HD_HS = 2 * HD_CAP;          // build hash slots (power of two)
+// code word: epoch << HD_EPOCH_SHIFT | HD_HEADBIT (head) | position or offset
+constexpr int HD_EPOCH_SHIFT = 13;
+constexpr uint32_t HD_HEADBIT = 1u << 12;
+constexpr uint32_t HD_VALMASK = HD_HEADBIT - 1u;
+constexpr uint32_t HD_EPOCH_END = 1u << (32 - HD_EPOCH_SHIFT);   // epochs 1 .. END-1
+static_assert(HD_CAP <= (int)HD_HEADBIT, "tail offsets fit the code word");
+static_assert(HD_HEAD <= (int)HD_HEADBIT, "head positions fit the code word");
+
+// A tail column of the current chunk's panel.
+struct __align__(16) TailRec {
+    uint32_t mask;       // the sampled rows (bits) that store the column
+    uint32_t pad;
+    double v0;           // value of the first of them (also at tval[offset])
+};
 
 struct PanelMeta {
-    int32_t prev;        // columns set by the last build (cleared by the next)
+    uint32_t epoch;      // epoch of the last build (0: none since the init)
     int32_t nh;          // head columns
     int32_t fallback;    // 1: the chunk exceeds HD_CAP, the broadcast kernel runs it
     int32_t pad;
@@ -630,11 +649,9 @@ struct PanelMeta {
 
 struct PanelPtrs {
     PanelMeta *meta;
-    int32_t *colmap;     // n
-    int32_t *clist;      // HD_CAP columns of the last build
-    uint32_t *tmask;     // HD_CAP slots: row mask
-    int32_t *tbase;      // HD_CAP slots: offset of the slot's values (tail), head position (head)
-    double *tval;        // HD_CAP values
+    uint32_t *code;      // n: code word of every column (another epoch: not in the panel)
+    TailRec *tail;       // n: set for the tail columns of the current chunk
+    double *tval;        // HD_CAP tail values, per column in sampled-row order
     double *Bh;          // HD_HEAD x HD_NJ
 };
 
@@ -645,10 +662,8 @@ __host__ __device__ inline PanelPtrs panel_ptrs(void *base, int64_t n)
     char *p = static_cast<char *>(base);
     PanelPtrs q;
     q.meta = reinterpret_cast<PanelMeta *>(p); p += 256;
-    q.colmap = reinterpret_cast<int32_t *>(p); p += hd_al(sizeof(int32_t) * (size_t)n);
-    q.clist = reinterpret_cast<int32_t *>(p); p += hd_al(sizeof(int32_t) * HD_CAP);
-    q.tmask = reinterpret_cast<uint32_t *>(p); p += hd_al(sizeof(uint32_t) * HD_CAP);
-    q.tbase = reinterpret_cast<int32_t *>(p); p += hd_al(sizeof(int32_t) * HD_CAP);
+    q.code = reinterpret_cast<uint32_t *>(p); p += hd_al(sizeof(uint32_t) * (size_t)n);
+    q.tail = reinterpret_cast<TailRec *>(p); p += hd_al(sizeof(TailRec) * (size_t)n);
     q.tval = reinterpret_cast<double *>(p); p += hd_al(sizeof(double) * HD_CAP);
     q.Bh = reinterpret_cast<double *>(p);
     return q;
@@ -656,62 +671,66 @@ __host__ __device__ inline PanelPtrs panel_ptrs(void *base, int64_t n)
 
 inline size_t panel_bytes(int64_t n)
 {
-    return 256 + hd_al(sizeof(int32_t) * (size_t)n) + 3 * hd_al(sizeof(int32_t) * HD_CAP) +
-           hd_al(sizeof(double) * HD_CAP) + hd_al(sizeof(double) * HD_HEAD * HD_NJ);
+    return 256 + hd_al(sizeof(uint32_t) * (size_t)n) + hd_al(sizeof(TailRec) * (size_t)n) +
+           hd_al(sizeof(double) * HD_CAP) +
+           hd_al(sizeof(double) * HD_HEAD * HD_NJ);
 }
 
 __global__ __launch_bounds__(256) void csr_panel_init_kernel(void *base, int64_t n)
 {
     const PanelPtrs q = panel_ptrs(base, n);
     for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < n; c += (int64_t)gridDim.x * 256)
-        q.colmap[c] = HD_EMPTY;
-    if (blockIdx.x == 0 && threadIdx.x == 0) *q.meta = PanelMeta{0, 0, 0, 0};
+        q.code[c] = 0u;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *q.meta = PanelMeta{0u, 0, 0, 0};
 }
 
-// Block-wide exclusive scan of one int per thread (HD_BUILD_NT threads);
-// returns the thread's offset, total in *tot.
-__device__ int block_scan(int v, int32_t *sh, int *tot)
+__device__ __forceinline__ uint32_t hd_hash(int32_t c)
 {
-    const int tid = threadIdx.x;
-    sh[tid] = v;
-    __syncthreads();
-    for (int off = 1; off < HD_BUILD_NT; off <<= 1) {
-        const int u = tid >= off ? sh[tid - off] : 0;
-        __syncthreads();
-        sh[tid] += u;
-        __syncthreads();
-    }
-    const int incl = sh[tid];
-    *tot = sh[HD_BUILD_NT - 1];
-    __syncthreads();
-    return incl - v;
+    return ((uint32_t)c * 2654435761u) & (HD_HS - 1);
 }
 
-// The panel of sampled rows S[0 .. nj) (nj <= HD_NJ), one workgroup.
+// The panel of sampled rows S[0 .. nj) (nj <= HD_NJ), one workgroup.  Entry f
+// of the chunk (its rows' stored entries concatenated in sampled-row order) is
+// held by thread f % HD_BUILD_NT; the first entry of a column numbers it, so
+// head positions and tail offsets follow the chunk's order and do not depend
+// on the order of the hash inserts.
 __global__ __launch_bounds__(HD_BUILD_NT) void csr_panel_build_kernel(
     const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx,
     const double *__restrict__ val, int64_t m, int64_t nnz, const int32_t *__restrict__ S,
     int32_t nj, int64_t n, void *base)
 {
+    constexpr int NWB = HD_BUILD_NT / 64;
     const PanelPtrs q = panel_ptrs(base, n);
+    __shared__ int32_t hkey[HD_HS];
+    __shared__ uint32_t hmask[HD_HS];
+    __shared__ int32_t hcode[HD_HS];       // first entry of the column, then its code
     __shared__ int32_t rowoff[HD_NJ + 1];
     __shared__ int64_t rowbeg[HD_NJ];
-    __shared__ int32_t sh[HD_BUILD_NT];
+    __shared__ int32_t wsum[2][HD_EPT][NWB];
     __shared__ int32_t hist[HD_NJ + 2];
-    __shared__ int32_t info[4];
-    const int tid = threadIdx.x;
+    __shared__ int32_t info[1];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     auto rp = [&](int64_t r) { return clampi(row_ptr[clampi(r, 0, m)], 0, nnz); };
-    // 1. clear the previous chunk's columns; entry ranges of the sampled rows
-    const int prev = q.meta->prev;
-    for (int i = tid; i < prev; i += HD_BUILD_NT) {
-        const int32_t c = q.clist[i];
-        if (c >= 0 && c < n) q.colmap[c] = HD_EMPTY;
+
+    // 1. the new epoch (after the last one every record is reset first); empty
+    //    hash; entry ranges of the sampled rows
+    uint32_t epoch = q.meta->epoch + 1u;
+    if (epoch >= HD_EPOCH_END) {
+        for (int64_t c = tid; c < n; c += HD_BUILD_NT) q.code[c] = 0u;
+        epoch = 1u;
     }
-    if (tid < 64) {
+    for (int x = tid; x < HD_HEAD * HD_NJ; x += HD_BUILD_NT) q.Bh[x] = 0.0;
+    for (int x = tid; x < HD_HS; x += HD_BUILD_NT) {
+        hkey[x] = -1;
+        hmask[x] = 0u;
+        hcode[x] = INT32_MAX;
+    }
+    if (tid < HD_NJ + 2) hist[tid] = 0;
+    if (wid == 0) {
         int len = 0;
         int64_t b0 = 0;
-        if (tid < nj) {
-            const int64_t r = clampi(S[tid], 0, m - 1);
+        if (lane < nj) {
+            const int64_t r = clampi(S[lane], 0, m - 1);
             b0 = rp(r);
             len = (int)(rp(r + 1) - b0);
         }
@@ -719,117 +738,137 @@ __global__ __launch_bounds__(HD_BUILD_NT) void csr_panel_build_kernel(
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
             const int up = __shfl_up(incl, o, 64);
-            if (tid >= o) incl += up;
+            if (lane >= o) incl += up;
         }
-        if (tid < nj) {
-            rowoff[tid + 1] = incl;
-            rowbeg[tid] = b0;
+        if (lane < nj) {
+            rowoff[lane + 1] = incl;
+            rowbeg[lane] = b0;
         }
-        if (tid == 0) rowoff[0] = 0;
+        if (lane == 0) rowoff[0] = 0;
     }
-    if (tid < HD_NJ + 2) hist[tid] = 0;
-    __threadfence();
     __syncthreads();
     const int total = rowoff[nj];
     if (total > HD_CAP) {
-        if (tid == 0) *q.meta = PanelMeta{0, 0, 1, 0};
+        if (tid == 0) *q.meta = PanelMeta{epoch, 0, 1, 0};
         return;
     }
-    auto entry = [&](int f, int &jj) {
-        jj = 0;
-        while (jj + 1 < nj && rowoff[jj + 1] <= f) ++jj;
-        return clampi(rowbeg[jj] + (f - rowoff[jj]), 0, nnz - 1);
-    };
-    // 2. every column's first entry (entries in chunk order)
-    for (int f = tid; f < total; f += HD_BUILD_NT) {
-        int jj;
-        const int32_t c = col_idx[entry(f, jj)];
-        if (c >= 0 && c < n) atomicMin(&q.colmap[c], f);
-    }
-    __threadfence();
-    __syncthreads();
-    // 3. the first entry of a column numbers it: slots in entry order
-    int nslots = 0;
-    for (int f0 = 0; f0 < total; f0 += HD_BUILD_NT) {
-        const int f = f0 + tid;
+
+    // 2. this thread's entries and their sampled rows
+    int32_t cc[HD_EPT], jv[HD_EPT], hh[HD_EPT];
+    double vv[HD_EPT];
+#pragma unroll
+    for (int u = 0; u < HD_EPT; ++u) {
+        const int f = tid + HD_BUILD_NT * u;
         int jj = 0;
-        int32_t c = -1;
-        bool own = false;
-        if (f < total) {
-            c = col_idx[entry(f, jj)];
-            own = c >= 0 && c < n && q.colmap[c] == f;
-        }
-        int cnt;
-        const int slot = nslots + block_scan(own ? 1 : 0, sh, &cnt);
-        if (own) {
-            q.clist[slot] = c;
-            q.tmask[slot] = 0u;
-        }
-        nslots += cnt;
+#pragma unroll
+        for (int step = 16; step >= 1; step >>= 1)
+            if (jj + step < nj && rowoff[jj + step] <= f) jj += step;
+        const int64_t e = clampi(rowbeg[jj] + (f - rowoff[jj]), 0, nnz - 1);
+        jv[u] = jj;
+        cc[u] = f < total ? col_idx[e] : -1;
+        vv[u] = f < total ? val[e] : 0.0;
     }
-    __threadfence();
-    __syncthreads();
-    for (int s = tid; s < nslots; s += HD_BUILD_NT) q.colmap[q.clist[s]] = -1 - s;   // column -> slot
-    __threadfence();
-    __syncthreads();
-    // 4. row masks of the slots, counts
-    for (int f = tid; f < total; f += HD_BUILD_NT) {
-        int jj;
-        const int32_t c = col_idx[entry(f, jj)];
-        if (c >= 0 && c < n) atomicOr(&q.tmask[-1 - q.colmap[c]], 1u << jj);
+    // 3. hash the columns: slot, sampled-row mask, first entry
+#pragma unroll
+    for (int u = 0; u < HD_EPT; ++u) {
+        hh[u] = -1;
+        const int32_t c = cc[u];
+        if (c < 0 || c >= n) continue;    // also a malformed matrix (its check reports it)
+        uint32_t h = hd_hash(c);
+        for (;;) {                         // at most HD_CAP keys in HD_HS slots: ends
+            const int32_t old = atomicCAS(&hkey[h], -1, c);
+            if (old == -1 || old == c) break;
+            h = (h + 1) & (HD_HS - 1);
+        }
+        hh[u] = (int)h;
+        atomicMin(&hcode[h], tid + HD_BUILD_NT * u);
+        atomicOr(&hmask[h], 1u << jv[u]);
     }
-    __threadfence();
     __syncthreads();
-    for (int s = tid; s < nslots; s += HD_BUILD_NT) atomicAdd(&hist[__popc(q.tmask[s])], 1);
+    // 4. owners (first entries) and the histogram of their sampled-row counts
+    bool own[HD_EPT];
+    uint32_t mk[HD_EPT];
+#pragma unroll
+    for (int u = 0; u < HD_EPT; ++u) {
+        own[u] = hh[u] >= 0 && hcode[hh[u]] == tid + HD_BUILD_NT * u;
+        mk[u] = hh[u] >= 0 ? hmask[hh[u]] : 0u;
+        if (own[u]) atomicAdd(&hist[__popc(mk[u])], 1);
+    }
     __syncthreads();
     if (tid == 0) {
         int t = HD_NJ + 1, acc = 0;
         while (t > 1 && acc + hist[t - 1] <= HD_HEAD) acc += hist[--t];
         info[0] = t;          // columns stored by >= t sampled rows form the head
     }
-    for (int x = tid; x < HD_HEAD * HD_NJ; x += HD_BUILD_NT) q.Bh[x] = 0.0;
     __syncthreads();
     const int tstar = info[0];
-    // 5. head positions and tail value offsets, both in slot order
-    int nh = 0, nv = 0;
-    for (int s0 = 0; s0 < nslots; s0 += HD_BUILD_NT) {
-        const int s = s0 + tid;
-        const uint32_t msk = s < nslots ? q.tmask[s] : 0u;
-        const bool head = s < nslots && __popc(msk) >= tstar;
-        int ch, cv;
-        const int ph = nh + block_scan(head ? 1 : 0, sh, &ch);
-        const int pv = nv + block_scan((s < nslots && !head) ? __popc(msk) : 0, sh, &cv);
-        if (s < nslots) q.tbase[s] = head ? -1 - ph : pv;   // < 0 marks a head slot
-        nh += ch;
-        nv += cv;
+    // 5. head positions and tail offsets in chunk order: scans over the waves
+    int hx[HD_EPT], tx[HD_EPT];
+    bool head[HD_EPT];
+#pragma unroll
+    for (int u = 0; u < HD_EPT; ++u) {
+        head[u] = own[u] && __popc(mk[u]) >= tstar;
+        const int a0 = head[u] ? 1 : 0, b0 = (own[u] && !head[u]) ? __popc(mk[u]) : 0;
+        int a = a0, b = b0;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int ua = __shfl_up(a, o, 64), ub = __shfl_up(b, o, 64);
+            if (lane >= o) {
+                a += ua;
+                b += ub;
+            }
+        }
+        if (lane == 63) {
+            wsum[0][u][wid] = a;
+            wsum[1][u][wid] = b;
+        }
+        hx[u] = a - a0;
+        tx[u] = b - b0;
     }
-    __threadfence();
     __syncthreads();
-    // 6. values: dense head block, tail values in sampled-row order per column
-    for (int f = tid; f < total; f += HD_BUILD_NT) {
-        int jj;
-        const int64_t e = entry(f, jj);
-        const int32_t c = col_idx[e];
-        if (c < 0 || c >= n) continue;        // a malformed matrix (its check reports it)
-        const int32_t s = -1 - q.colmap[c];
-        const int32_t tb = q.tbase[s];
-        if (tb < 0)
-            q.Bh[(-1 - tb) * HD_NJ + jj] = val[e];
+    const uint32_t ep = epoch << HD_EPOCH_SHIFT;
+    int oa = 0, ob = 0;
+#pragma unroll
+    for (int u = 0; u < HD_EPT; ++u) {
+        int pa = oa, pb = ob;
+        for (int w = 0; w < NWB; ++w) {
+            if (w < wid) {
+                pa += wsum[0][u][w];
+                pb += wsum[1][u][w];
+            }
+            oa += wsum[0][u][w];
+            ob += wsum[1][u][w];
+        }
+        if (own[u]) hcode[hh[u]] = (int32_t)(ep | (head[u] ? (HD_HEADBIT | (uint32_t)(pa + hx[u]))
+                                                              : (uint32_t)(pb + tx[u])));
+    }
+    const int nh = oa;
+    __syncthreads();
+    // 6. values into the head block or tval; the owners write the records
+#pragma unroll
+    for (int u = 0; u < HD_EPT; ++u) {
+        if (hh[u] < 0) continue;
+        const uint32_t code = (uint32_t)hcode[hh[u]];
+        const int jj = jv[u];
+        if (code & HD_HEADBIT)
+            q.Bh[(code & HD_VALMASK) * HD_NJ + jj] = vv[u];
         else
-            q.tval[tb + __popc(q.tmask[s] & ((1u << jj) - 1u))] = val[e];
+            q.tval[(code & HD_VALMASK) + __popc(mk[u] & ((1u << jj) - 1u))] = vv[u];
+        if (own[u]) {
+            q.code[cc[u]] = code;
+            if (!(code & HD_HEADBIT)) q.tail[cc[u]] = TailRec{mk[u], 0u, vv[u]};
+        }
     }
-    __threadfence();
-    __syncthreads();
-    // 7. final column map: head position | HD_HEADBIT, or the tail slot
-    for (int s = tid; s < nslots; s += HD_BUILD_NT) {
-        const int32_t tb = q.tbase[s];
-        q.colmap[q.clist[s]] = tb < 0 ? (HD_HEADBIT | (-1 - tb)) : s;
-    }
-    if (tid == 0) *q.meta = PanelMeta{nslots, nh, 0, 0};
+    if (tid == 0) *q.meta = PanelMeta{epoch, nh, 0, 0};
 }
 
+// One workgroup = two waves on blocks of 16 data rows.  Wave w walks the
+// entries of rows 8 w .. 8 w + 7 of a block (eight lanes a row, entry k of a
+// row at lane k % 8) into X and Pt, and forms output columns 16 w .. 16 w + 15
+// (a 16 x 16 MFMA block) of all 16 rows.  Each wave writes only its own rows
+// of X and Pt, so Pt's atomics stay in one wave (fixed order).
 template <int KIND>
-__global__ __launch_bounds__(HD_NT) __attribute__((amdgpu_waves_per_eu(3))) void kblock_csr_head_kernel(
+__global__ __launch_bounds__(HD_NT) __attribute__((amdgpu_waves_per_eu(4))) void kblock_csr_head_kernel(
     const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx,
     const double *__restrict__ val, int64_t m, int64_t nnz, int64_t n,
     const int32_t *__restrict__ S, int32_t sb, int32_t j0, int32_t nj,
@@ -837,49 +876,44 @@ __global__ __launch_bounds__(HD_NT) __attribute__((amdgpu_waves_per_eu(3))) void
     const double *__restrict__ bscale, double *__restrict__ partial, double *__restrict__ W,
     int32_t n_row_groups, const void *__restrict__ pbase)
 {
-    constexpr int NW = HD_NT / 64;
     const PanelPtrs q = panel_ptrs(const_cast<void *>(pbase), n);
-    if (q.meta->fallback) return;
-    __shared__ double X[NW][HD_RB][HD_XLD];
-    __shared__ double Pt[NW][HD_RB][HD_NJ];
-    __shared__ int32_t woff[NW][HD_RB + 1];     // entry offsets of a block's rows
-    __shared__ int64_t wbeg[NW][HD_RB];         // first entry of each row of the block
-    __shared__ double red[NW][HD_NJ];
-
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const bool is_w = (int)blockIdx.x >= n_row_groups;
+    if (q.meta->fallback) {
+        // the broadcast kernel runs this chunk on its first HD_FBGROUPS row
+        // groups; the other groups' sums for it are zero
+        if (!is_w && (int)blockIdx.x >= HD_FBGROUPS && tid < nj)
+            partial[(int64_t)blockIdx.x * sb + j0 + tid] = 0.0;
+        return;
+    }
     if (is_w && W == nullptr) return;
-    const int wblk = (int)blockIdx.x - n_row_groups;   // W-part: sampled rows [wblk*64, +64)
+    __shared__ double X[HD_RB][HD_XLD];
+    __shared__ double Pt[HD_RB][HD_PLD];
+
     auto rp = [&](int64_t r) { return clampi(row_ptr[clampi(r, 0, m)], 0, nnz); };
     const int li = lane & 15, lk = lane >> 4;          // MFMA operand row / k slot
-    const int nks = (q.meta->nh + 3) / 4;              // MFMA k-steps over the head
+    const int tr = 8 * wid + (lane >> 3), sub = lane & 7;   // entry walk: row tr, every 8th entry
+    const int jj = 16 * wid + li;                      // this lane's output column
+    const uint32_t epoch = q.meta->epoch;
 
     // this lane's part of Bh (B operand of every k-step), in registers
-    double bh[HD_HEAD / 4][2];
+    double bh[HD_HEAD / 4];
 #pragma unroll
-    for (int ks = 0; ks < HD_HEAD / 4; ++ks)
-#pragma unroll
-        for (int c = 0; c < 2; ++c) bh[ks][c] = q.Bh[(4 * ks + lk) * HD_NJ + c * 16 + li];
-    int64_t Sj[2];
-    double nb[2];
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        const int jj = c * 16 + li;
-        Sj[c] = clampi(S[j0 + (jj < nj ? jj : 0)], 0, m - 1);
-        nb[c] = (KIND == KDCD_KERNEL_RBF) ? norms[Sj[c]] : 0.0;
-    }
-    double colsum[2] = {0.0, 0.0};
+    for (int ks = 0; ks < HD_HEAD / 4; ++ks) bh[ks] = q.Bh[(4 * ks + lk) * HD_NJ + jj];
+    const int64_t Sj = clampi(S[j0 + (jj < nj ? jj : 0)], 0, m - 1);
+    const double nb = (KIND == KDCD_KERNEL_RBF) ? norms[Sj] : 0.0;
+    double colsum = 0.0;
 
     const int64_t nblk = is_w ? (sb + HD_RB - 1) / HD_RB : (m + HD_RB - 1) / HD_RB;
-    const int64_t b_first = is_w ? (int64_t)wblk * NW + wid : (int64_t)blockIdx.x * NW + wid;
-    const int64_t b_end = is_w ? min(nblk, (int64_t)(wblk + 1) * NW) : nblk;
-    const int64_t b_step = is_w ? NW : (int64_t)n_row_groups * NW;
-    // entry range of row lane (< HD_RB) of block blk
+    const int64_t b_first = is_w ? (int64_t)((int)blockIdx.x - n_row_groups) : (int64_t)blockIdx.x;
+    const int64_t b_end = is_w ? min(nblk, b_first + 1) : nblk;
+    const int64_t b_step = is_w ? 1 : (int64_t)n_row_groups;
+    // entry range of this lane's row tr of block blk
     auto rowinfo = [&](int64_t blk, int64_t &b0, int32_t &len) {
         b0 = 0;
         len = 0;
-        if (lane < HD_RB && blk < b_end) {
-            const int64_t rix = blk * HD_RB + lane;
+        if (blk < b_end) {
+            const int64_t rix = blk * HD_RB + tr;
             const bool rok = is_w ? rix < sb : rix < m;
             const int64_t row = is_w ? clampi(S[clampi(rix, 0, sb - 1)], 0, m - 1) : rix;
             if (rok) {
@@ -888,31 +922,97 @@ __global__ __launch_bounds__(HD_NT) __attribute__((amdgpu_waves_per_eu(3))) void
             }
         }
     };
+    // Every lane loads an entry of its row (index clamped into the row) and
+    // then a record (column clamped into [0, n)); entries past the row's end
+    // are dropped afterwards.
+    constexpr int HD_EPL = KIND == KDCD_KERNEL_RBF ? 5 : 7;
+    constexpr int BATCH = 8 * HD_EPL;                  // entries of a row per batch
+    const uint32_t nlast = (uint32_t)(n - 1);
+    double *xrow = &X[tr][0];
+    double *prow = &Pt[tr][0];
     int64_t nb0;
     int32_t nlen;
     rowinfo(b_first, nb0, nlen);
     for (int64_t blk = b_first; blk < b_end; blk += b_step) {
-        // rows of the block, their entry ranges (the next block's are loaded now,
-        // in flight while this one is processed) and the zeroed tiles
-        const int64_t b0 = nb0;
-        const int32_t len = nlen;
+        // this lane's row's entries (the next block's range is loaded now, in
+        // flight while this one is processed); this wave's rows of the tiles
+        // zeroed
+        const int32_t len = nnz > 0 ? nlen : 0;
+        // a row with no entries reads entry 0 of its range, moved into the array
+        const int64_t b0 = len > 0 ? nb0 : min(nb0, nnz - 1);
+        const int32_t *cp = col_idx + b0;
+        const double *vp = val + b0;
         rowinfo(blk + b_step, nb0, nlen);
-        int32_t incl = len;                   // inclusive scan over lanes 0..15
+        constexpr int XW = (HD_RB / 2) * HD_XLD, PW = (HD_RB / 2) * HD_PLD;
 #pragma unroll
-        for (int o = 1; o < HD_RB; o <<= 1) {
-            const int32_t up = __shfl_up(incl, o, 64);
-            if (lane >= o) incl += up;
+        for (int i = 0; i < (XW + 63) / 64; ++i) {
+            const int x = lane + 64 * i;
+            if (i + 1 < (XW + 63) / 64 || x < XW) (&X[8 * wid][0])[x] = 0.0;
         }
-        if (lane < HD_RB) {
-            wbeg[wid][lane] = b0;
-            woff[wid][lane + 1] = incl;
+#pragma unroll
+        for (int i = 0; i < (PW + 63) / 64; ++i) {
+            const int x = lane + 64 * i;
+            if (i + 1 < (PW + 63) / 64 || x < PW) (&Pt[8 * wid][0])[x] = 0.0;
         }
-        if (lane == 0) woff[wid][0] = 0;
-        for (int x = lane; x < HD_RB * HD_XLD; x += 64) (&X[wid][0][0])[x] = 0.0;
-        for (int x = lane; x < HD_RB * HD_NJ; x += 64) (&Pt[wid][0][0])[x] = 0.0;
         wave_lds_sync();
-        const int total = woff[wid][HD_RB];
-        // this lane's output rows (t = l/16 + 4 v): beta and norms, loaded ahead
+        const int32_t klast = max(len - 1, 0);
+        for (int k0 = 0; __ballot(k0 < len) != 0; k0 += BATCH) {    // uniform
+            int32_t cu[HD_EPL];
+            double vu[HD_EPL];
+#pragma unroll
+            for (int u = 0; u < HD_EPL; ++u) {
+                const int k = min(k0 + sub + 8 * u, klast);
+                cu[u] = cp[k];
+                vu[u] = vp[k];
+            }
+            // code words: head entries go to X now; tail entries fetch their
+            // column's tail record (all fetches in flight together)
+            uint32_t cd[HD_EPL];
+#pragma unroll
+            for (int u = 0; u < HD_EPL; ++u) cd[u] = q.code[min((uint32_t)cu[u], nlast)];
+            bool tl[HD_EPL];
+#pragma unroll
+            for (int u = 0; u < HD_EPL; ++u) {
+                const bool in = k0 + sub + 8 * u < len && (cd[u] >> HD_EPOCH_SHIFT) == epoch &&
+                                (uint32_t)cu[u] <= nlast;
+                tl[u] = in && !(cd[u] & HD_HEADBIT);
+                if (in && (cd[u] & HD_HEADBIT)) xrow[cd[u] & (HD_HEAD - 1)] = vu[u];
+            }
+            TailRec ru[HD_EPL];
+#pragma unroll
+            for (int u = 0; u < HD_EPL; ++u) ru[u] = tl[u] ? q.tail[cu[u]] : TailRec{0u, 0u, 0.0};
+            uint32_t rem[HD_EPL];
+            bool more = false;
+#pragma unroll
+            for (int u = 0; u < HD_EPL; ++u) {
+                rem[u] = 0u;
+                if (tl[u]) {
+                    const uint32_t msk = ru[u].mask;
+                    atomicAdd(&prow[__builtin_ctz(msk)], vu[u] * ru[u].v0);
+                    rem[u] = msk & (msk - 1u);
+                }
+                more |= rem[u] != 0u;
+            }
+            // further sampled rows of tail entries, in rounds: one tval load per
+            // entry and round
+            for (int kk = 1; __ballot(more) != 0; ++kk) {    // uniform
+                double tv[HD_EPL];
+#pragma unroll
+                for (int u = 0; u < HD_EPL; ++u)
+                    tv[u] = q.tval[rem[u] ? (cd[u] & HD_VALMASK) + kk : 0];
+                more = false;
+#pragma unroll
+                for (int u = 0; u < HD_EPL; ++u) {
+                    if (rem[u]) {
+                        atomicAdd(&prow[__builtin_ctz(rem[u])], vu[u] * tv[u]);
+                        rem[u] &= rem[u] - 1u;
+                    }
+                    more |= rem[u] != 0u;
+                }
+            }
+        }
+        // this lane's output rows (t = l/16 + 4 v): beta (zero for rows past
+        // the end) and norms, in flight during the product
         double bvv[4], nav[4];
         int64_t rowv[4];
         bool rokv[4];
@@ -922,98 +1022,43 @@ __global__ __launch_bounds__(HD_NT) __attribute__((amdgpu_waves_per_eu(3))) void
             rokv[v] = is_w ? rix < sb : rix < m;
             rowv[v] = is_w ? clampi(S[clampi(rix, 0, sb - 1)], 0, m - 1) : clampi(rix, 0, m - 1);
             double bv = 0.0;
-            if (!is_w && rokv[v]) {
+            if (!is_w) {
                 bv = beta[rowv[v]];
                 if (bscale) bv *= bscale[rowv[v]];
+                bv = rokv[v] ? bv : 0.0;
             }
             bvv[v] = bv;
-            nav[v] = (KIND == KDCD_KERNEL_RBF && rokv[v]) ? norms[rowv[v]] : 0.0;
+            nav[v] = (KIND == KDCD_KERNEL_RBF) ? norms[rowv[v]] : 0.0;
         }
-        // entries: position f of the block's concatenated rows, its row by search;
-        // HD_EPL entries per lane loaded together, then their columns looked up
-        constexpr int HD_EPL = 8;
-        for (int base = 0; base < total; base += 64 * HD_EPL) {
-            int32_t cu[HD_EPL], tu[HD_EPL], mu[HD_EPL];
-            double vu[HD_EPL];
+        lds_barrier();            // both waves' rows of X / Pt are in
+        // head product on MFMA: this wave's 16 x 16 block of P = X Bh^T (X
+        // columns and Bh rows past the head are zero)
+        d4 acc = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int u = 0; u < HD_EPL; ++u) {
-                const int f = base + lane + 64 * u;
-                int t = 0;
-#pragma unroll
-                for (int step = 8; step >= 1; step >>= 1)
-                    if (woff[wid][t + step] <= f) t += step;
-                const int64_t e = clampi(wbeg[wid][t] + (f - woff[wid][t]), 0, nnz - 1);
-                tu[u] = t;
-                cu[u] = f < total ? col_idx[e] : -1;
-                vu[u] = f < total ? val[e] : 0.0;
-            }
-#pragma unroll
-            for (int u = 0; u < HD_EPL; ++u)
-                mu[u] = (cu[u] >= 0 && cu[u] < n) ? q.colmap[cu[u]] : HD_EMPTY;
-#pragma unroll
-            for (int u = 0; u < HD_EPL; ++u) {
-                const int32_t code = mu[u];
-                if (code == HD_EMPTY) continue;
-                const int t = tu[u];
-                if (code & HD_HEADBIT) {
-                    X[wid][t][code & (HD_HEADBIT - 1)] = vu[u];
-                } else {
-                    uint32_t msk = q.tmask[code];
-                    const int bs = q.tbase[code];
-                    int k = 0;
-                    while (msk) {
-                        const int j = __builtin_ctz(msk);
-                        msk &= msk - 1;
-                        atomicAdd(&Pt[wid][t][j], vu[u] * q.tval[bs + k]);
-                        ++k;
-                    }
-                }
-            }
-        }
-        wave_lds_sync();
-        // head product on MFMA: P = X Bh^T, two 16 x 16 blocks of sampled rows
-        d4 acc[2] = {d4{0.0, 0.0, 0.0, 0.0}, d4{0.0, 0.0, 0.0, 0.0}};
-#pragma unroll
-        for (int ks = 0; ks < HD_HEAD / 4; ++ks) {
-            if (ks < nks) {                           // uniform
-                const double a = X[wid][li][4 * ks + lk];
-#pragma unroll
-                for (int c = 0; c < 2; ++c)
-                    acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bh[ks][c], acc[c], 0, 0, 0);
-            }
-        }
-        // item v of lane l: row l/16 + 4 v of the block, column l%16 of block c
-#pragma unroll
+        for (int ks = 0; ks < HD_HEAD / 4; ++ks)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(X[li][4 * ks + lk], bh[ks], acc, 0, 0, 0);
+        // item v of lane l: row l/16 + 4 v of the block.  U-part: rows past the
+        // end have beta 0, and the sums of sampled rows past nj are never
+        // written.  (The exponential map is not unrolled: its copies would spill.)
+#pragma unroll(KIND == KDCD_KERNEL_RBF ? 1 : 4)
         for (int v = 0; v < 4; ++v) {
             const int t = lk + 4 * v;
-            const int64_t rix = blk * HD_RB + t;
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                const int jj = c * 16 + li;
-                if (!rokv[v] || jj >= nj) continue;
-                const double pv = acc[c][v] + Pt[wid][t][jj];
-                const double kv = kernel_map<KIND>(pv, nav[v], nb[c], rowv[v] == Sj[c], kp);
-                if (is_w) W[rix * sb + j0 + jj] = kv;
-                else colsum[c] += bvv[v] * kv;
+            const double pv = acc[v] + Pt[t][jj];
+            const double kv = kernel_map<KIND>(pv, nav[v], nb, rowv[v] == Sj, kp);
+            if (is_w) {
+                if (rokv[v] && jj < nj) W[(blk * HD_RB + t) * sb + j0 + jj] = kv;
+            } else {
+                colsum += bvv[v] * kv;
             }
         }
-        wave_lds_sync();          // the block's X / Pt reads are done
+        lds_barrier();            // the block's X / Pt reads are done
     }
     if (!is_w) {
-        // lanes l, l ^ 16, l ^ 32, l ^ 48 hold the same column: lanes -> waves -> group
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            double v = colsum[c];
-            v += __shfl_xor(v, 16);
-            v += __shfl_xor(v, 32);
-            if (lane < 16) red[wid][c * 16 + lane] = v;
-        }
-        __syncthreads();
-        if (tid < nj) {
-            double t = 0.0;
-            for (int w = 0; w < NW; ++w) t += red[w][tid];
-            partial[(int64_t)blockIdx.x * sb + j0 + tid] = t;
-        }
+        // lanes l, l ^ 16, l ^ 32, l ^ 48 hold the same column
+        double v = colsum;
+        v += __shfl_xor(v, 16);
+        v += __shfl_xor(v, 32);
+        if (lane < 16 && jj < nj) partial[(int64_t)blockIdx.x * sb + j0 + jj] = v;
     }
 }
 
@@ -1050,10 +1095,16 @@ CsrPath csr_path(const kdcd_matrix *A, int32_t sb)
 int64_t kblock_csr_row_groups(const kdcd_matrix *A, int32_t sb)
 {
     if (csr_path(A, sb) == CSR_HEAD) {
-        const int64_t steps = (A->m + 63) / 64;          // 4 waves x 16 rows per step
+        const int64_t steps = (A->m + HD_RB - 1) / HD_RB;   // 16 rows per step
         return steps < HD_MAXGROUPS ? steps : HD_MAXGROUPS;
     }
     return groups_for(A->m);
+}
+
+int64_t kblock_csr_max_row_groups(int64_t m)
+{
+    const int64_t head = std::min<int64_t>((m + HD_RB - 1) / HD_RB, HD_MAXGROUPS);
+    return std::max<int64_t>(head, groups_for(m));
 }
 
 size_t kblock_csr_panel_bytes(int64_t n) { return panel_bytes(n); }
@@ -1075,18 +1126,21 @@ hipError_t launch_kblock_csr(const KBlockArgs &a, hipStream_t st)
         // per chunk of HD_NJ sampled rows: panel build, dense-head pass, and the
         // broadcast kernel gated on the build's fallback flag
         const int64_t groups = kblock_csr_row_groups(A, a.sb);
-        const int64_t n_w = a.W ? (a.sb + 63) / 64 : 0;
+        const int64_t n_w = a.W ? (a.sb + HD_RB - 1) / HD_RB : 0;
         const PanelPtrs q = panel_ptrs(a.csr_panel, A->n);
         const int64_t rows_per_wg_b = (CSR_NT / 64) * rpw;
         const int64_t n_w_b = a.W ? (a.sb + rows_per_wg_b - 1) / rows_per_wg_b : 0;
-        ArmedEvents armed = armed_events();          // the timer covers the whole chunk loop
+        const int64_t groups_b = std::min<int64_t>(groups, HD_FBGROUPS);
+        // the stage timer covers the dense-head passes (from the first chunk's to
+        // the last chunk's; the builds and gated passes between them included)
+        ArmedEvents armed = armed_events();
         armed_events() = ArmedEvents{nullptr, nullptr};
         for (int32_t j0 = 0; j0 < a.sb; j0 += HD_NJ) {
             const int32_t nj = std::min<int32_t>(HD_NJ, a.sb - j0);
             const bool first = j0 == 0, lastc = j0 + HD_NJ >= a.sb;
-            if (first && armed.start) (void)hipEventRecord(armed.start, st);
             hipLaunchKernelGGL(csr_panel_build_kernel, dim3(1), dim3(HD_BUILD_NT), 0, st, A->row_ptr,
                                A->col_idx, A->values, A->m, A->nnz, a.S + j0, nj, A->n, a.csr_panel);
+            if (first && armed.start) (void)hipEventRecord(armed.start, st);
             dim3 grid((unsigned)(groups + n_w)), block(HD_NT);
 #define KDCD_CSR_HEAD(KIND)                                                                    \
     hipLaunchKernelGGL((kblock_csr_head_kernel<KIND>), grid, block, 0, st, A->row_ptr,          \
@@ -1098,11 +1152,12 @@ hipError_t launch_kblock_csr(const KBlockArgs &a, hipStream_t st)
             default: KDCD_CSR_HEAD(KDCD_KERNEL_RBF); break;
             }
 #undef KDCD_CSR_HEAD
-            dim3 gridb((unsigned)(groups + n_w_b)), blockb(CSR_NT);
+            if (lastc && armed.stop) (void)hipEventRecord(armed.stop, st);
+            dim3 gridb((unsigned)(groups_b + n_w_b)), blockb(CSR_NT);
 #define KDCD_CSR_FB(RPW, KIND)                                                                  \
     hipLaunchKernelGGL((kblock_csr_kernel<RPW, KIND>), gridb, blockb, 0, st, A->row_ptr,          \
                        A->col_idx, A->values, A->m, A->nnz, a.S, a.sb, a.norms, a.kp, a.beta,    \
-                       a.beta_scale, a.partial, a.W, (int32_t)groups, a.carry, a.status, j0,     \
+                       a.beta_scale, a.partial, a.W, (int32_t)groups_b, a.carry, a.status, j0,   \
                        j0 + nj, &q.meta->fallback)
 #define KDCD_CSR_FB_KIND(RPW)                                                                   \
     switch (a.kp.kind) {                                                                        \
@@ -1118,7 +1173,6 @@ hipError_t launch_kblock_csr(const KBlockArgs &a, hipStream_t st)
             }
 #undef KDCD_CSR_FB_KIND
 #undef KDCD_CSR_FB
-            if (lastc && armed.stop) (void)hipEventRecord(armed.stop, st);
         }
         return hipGetLastError();
     }

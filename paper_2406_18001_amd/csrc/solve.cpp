@@ -21,6 +21,7 @@ namespace kdcd {
 hipError_t launch_kblock_mixed(const KBlockArgs &a, hipStream_t st);
 hipError_t launch_kblock_csr(const KBlockArgs &a, hipStream_t st);
 int64_t kblock_csr_row_groups(const kdcd_matrix *A, int32_t sb);
+int64_t kblock_csr_max_row_groups(int64_t m);
 hipError_t launch_convert_lowp(const kdcd_matrix *A, int32_t compute, void *hi, void *lo,
                                int64_t ldlow, float *normlow, hipStream_t st);
 int krr_recur_threads(int32_t b, int32_t sk);
@@ -45,6 +46,14 @@ hipError_t launch_lowrank_z_init(const double *Phi, int64_t ldp, int64_t m, int3
 namespace {
 
 constexpr int64_t kMaxGroups = 1024;   // upper bound on row groups of any kernel-block launch
+
+// Upper bound on the row groups (rows of the partial column sums) of any
+// kernel-block launch on A.
+int64_t max_row_groups(const kdcd_matrix *A)
+{
+    if (A->format == KDCD_CSR) return kblock_csr_max_row_groups(A->m);
+    return std::min<int64_t>(kMaxGroups, (A->m + 63) / 64);   // dense tiles are >= 64 rows
+}
 // From this block width on, the Gram rows come from the U-part (two small
 // launches per outer iteration) instead of tiles of their own, which at
 // these widths add a round of workgroups.
@@ -158,7 +167,7 @@ Layout make_layout(int32_t problem, const kdcd_matrix *A, const kdcd_kernel *ker
     size_t off = 0;
     L.status = off; off += 256;
     L.norms = off; off += align256(sizeof(double) * (size_t)A->m);
-    L.partial = off; off += align256(sizeof(double) * (size_t)(kMaxGroups * sb));
+    L.partial = off; off += align256(sizeof(double) * (size_t)(max_row_groups(A) * sb));
     L.r = off; off += align256(sizeof(double) * (size_t)sb);
     L.W = off; off += align256(sizeof(double) * (size_t)(sb * sb));
     L.Dinv = off; off += (problem == 1) ? align256(sizeof(double) * (size_t)(sb * b)) : 0;
@@ -1003,8 +1012,7 @@ kdcd_status kdcd_batch_solve(const kdcd_matrix *A, const kdcd_kernel *kernel, in
     Layout L = make_layout(0, A, kernel, b, s, o.compute);
     size_t off = L.total;
     const size_t o_bd = off; off += align256(sizeof(BatchDesc));
-    // every dense tile is at least 64 rows tall, so no launch has more row groups
-    const int64_t max_groups = std::min<int64_t>(kMaxGroups, (A->m + 63) / 64);
+    const int64_t max_groups = max_row_groups(A);
     const size_t o_part = off; off += align256(sizeof(double) * (size_t)(n_problems * max_groups * sbmax));
     const size_t o_r = off; off += align256(sizeof(double) * (size_t)(n_problems * sbmax));
     const size_t o_W = off; off += align256(sizeof(double) * (size_t)(bd.ngroups * sbmax * sbmax));
@@ -1467,7 +1475,7 @@ kdcd_status kdcd_autotune_batch(const kdcd_matrix *A, const kdcd_kernel *kernel,
     Layout L = make_layout(0, A, kernel, 1, sb, compute);
     size_t off = L.total;
     const size_t o_bd = off; off += align256(sizeof(BatchDesc));
-    const int64_t max_groups = std::min<int64_t>(kMaxGroups, (A->m + 63) / 64);
+    const int64_t max_groups = max_row_groups(A);
     const size_t o_part = off; off += align256(sizeof(double) * (size_t)(n_problems * max_groups * sb));
     const size_t o_W = off; off += align256(sizeof(double) * (size_t)(bd.ngroups * sb * sb));
     const size_t o_S = off; off += align256(sizeof(int32_t) * (size_t)sb);
@@ -1723,7 +1731,7 @@ kdcd_status kdcd_batch_eval(const kdcd_matrix *A, const kdcd_kernel *kernel,
     Layout L = make_layout(2, A, kernel, 1, chunk, KDCD_F64);
     size_t off = L.total;
     const size_t o_bd = off; off += align256(sizeof(BatchDesc));
-    const int64_t max_groups = std::min<int64_t>(kMaxGroups, (m + 63) / 64);
+    const int64_t max_groups = max_row_groups(A);
     const size_t o_part = off; off += align256(sizeof(double) * (size_t)(n_problems * max_groups * chunk));
     const size_t o_r = off; off += align256(sizeof(double) * (size_t)(n_problems * chunk));
     L.total = off;
