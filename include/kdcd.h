@@ -152,11 +152,17 @@ typedef struct {
     double tol;              /* monitor: stop once the certified relative error <= tol      */
     int64_t *outer_done;     /* host or NULL: outer iterations performed                    */
     double *rel_err;         /* host or NULL: last certified relative objective error       */
+    double *monitor_log;     /* device or NULL: monitor_log_len records of 4 doubles        */
+    int64_t monitor_log_len;
 } kdcd_options;
 
 /*
  * Convergence monitor (monitor_every > 0; kdcd_ksvm_solve / kdcd_krr_solve on
- * dense A in FP64, and kdcd_ksvm_solve_sampled; not with KDCD_FLAG_GRAPH).
+ * dense A in FP64, BF16, FP16 or BF16X3, on CSR A in FP64, and
+ * kdcd_ksvm_solve_sampled; not with KDCD_FLAG_GRAPH, not in FP32).  With a
+ * low-precision compute the gradient is carried with the kernel values the
+ * product computed, so the bound certifies the problem with those values (the
+ * exact problem's objective differs by the kernel's rounding).
  * The solve keeps the full dual gradient current on the device (K-SVM:
  * g = Q alpha - 1 + omega alpha; K-RR: the residual y - M alpha, M =
  * K/lambda + m I) from the kernel block it already computes, and every
@@ -173,6 +179,10 @@ typedef struct {
  * kdcd_workspace_bytes).
  * Costs per outer iteration: m*s*b*8 bytes written and read (the stored
  * kernel block) plus the O(m) evaluation.
+ * monitor_log (optional): evaluation i writes record i (i < monitor_log_len)
+ * = {outer iterations done, certified relative error, objective f, seconds
+ * since the solve's first launch by the device's wall clock}; records past
+ * the last evaluation are left as they were.
  */
 
 /*

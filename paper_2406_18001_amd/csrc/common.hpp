@@ -271,7 +271,15 @@ struct MonitorState {
     int64_t outer_done;   // outer iterations done at the last evaluation
     double rel;           // last certified relative objective error
     double f;             // last objective value
+    uint64_t t0;          // device wall clock at the set-up
+    double tick;          // seconds per wall-clock tick
+    double *log;          // optional records {outer, rel, f, seconds} per evaluation
+    int64_t log_len;
+    int64_t nlog;         // evaluations so far
 };
+
+// Set-up after the state is zero-filled: start clock and the optional log.
+hipError_t launch_monitor_start(MonitorState *mon, double *log, int64_t log_len, hipStream_t st);
 
 hipError_t launch_dual_update(const double *U, int64_t m, int32_t sb, const int32_t *S,
                               const double *theta, const double *vscale, double uscale,

@@ -223,7 +223,7 @@ __global__ __launch_bounds__(CSR_NT) __attribute__((amdgpu_waves_per_eu(RPW > 1 
     int32_t sb, const double *__restrict__ norms, KParams kp, const double *__restrict__ beta,
     const double *__restrict__ bscale, double *__restrict__ partial, double *__restrict__ W,
     int32_t n_row_groups, double *__restrict__ carry, int32_t *status, int32_t jbeg,
-    int32_t jend, const int32_t *__restrict__ gate)
+    int32_t jend, const int32_t *__restrict__ gate, double *__restrict__ U)
 {
     constexpr int LPR = 64 / RPW;                  // lanes per row = sampled rows per chunk
     constexpr int NW = CSR_NT / 64;
@@ -423,6 +423,7 @@ __global__ __launch_bounds__(CSR_NT) __attribute__((amdgpu_waves_per_eu(RPW > 1 
                         double bv = beta[row];
                         if (bscale) bv *= bscale[row];
                         colsum += bv * kv;
+                        if (U) U[(int64_t)(j0 + jl) * m + row] = kv;
                     }
                 }
             }
@@ -455,7 +456,7 @@ __global__ __launch_bounds__(CSR_NT) __attribute__((amdgpu_waves_per_eu(4))) voi
     int32_t sb, const double *__restrict__ norms, KParams kp, const double *__restrict__ beta,
     const double *__restrict__ bscale, double *__restrict__ partial, double *__restrict__ W,
     int32_t n_row_groups, double *__restrict__ carry, int32_t *status, int32_t jbeg,
-    int32_t jend, const int32_t *__restrict__ gate)
+    int32_t jend, const int32_t *__restrict__ gate, double *__restrict__ U)
 {
     constexpr int NW = CSR_NT / 64;
     constexpr int NB = KIND == KDCD_KERNEL_RBF ? 2 : 4;   // entries per lane per batch
@@ -571,6 +572,7 @@ __global__ __launch_bounds__(CSR_NT) __attribute__((amdgpu_waves_per_eu(4))) voi
                         double bv = beta[row];
                         if (bscale) bv *= bscale[row];
                         colsum += bv * kv;
+                        if (U) U[(int64_t)(j0 + lane) * m + row] = kv;
                     }
                 }
             }
@@ -874,7 +876,7 @@ __global__ __launch_bounds__(HD_NT) __attribute__((amdgpu_waves_per_eu(4))) void
     const int32_t *__restrict__ S, int32_t sb, int32_t j0, int32_t nj,
     const double *__restrict__ norms, KParams kp, const double *__restrict__ beta,
     const double *__restrict__ bscale, double *__restrict__ partial, double *__restrict__ W,
-    int32_t n_row_groups, const void *__restrict__ pbase)
+    int32_t n_row_groups, const void *__restrict__ pbase, double *__restrict__ U)
 {
     const PanelPtrs q = panel_ptrs(const_cast<void *>(pbase), n);
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -1049,6 +1051,7 @@ __global__ __launch_bounds__(HD_NT) __attribute__((amdgpu_waves_per_eu(4))) void
                 if (rokv[v] && jj < nj) W[(blk * HD_RB + t) * sb + j0 + jj] = kv;
             } else {
                 colsum += bvv[v] * kv;
+                if (U && rokv[v] && jj < nj) U[(int64_t)(j0 + jj) * m + rowv[v]] = kv;
             }
         }
         lds_barrier();            // the block's X / Pt reads are done
@@ -1145,7 +1148,7 @@ hipError_t launch_kblock_csr(const KBlockArgs &a, hipStream_t st)
 #define KDCD_CSR_HEAD(KIND)                                                                    \
     hipLaunchKernelGGL((kblock_csr_head_kernel<KIND>), grid, block, 0, st, A->row_ptr,          \
                        A->col_idx, A->values, A->m, A->nnz, A->n, a.S, a.sb, j0, nj, a.norms,  \
-                       a.kp, a.beta, a.beta_scale, a.partial, a.W, (int32_t)groups, a.csr_panel)
+                       a.kp, a.beta, a.beta_scale, a.partial, a.W, (int32_t)groups, a.csr_panel, a.U)
             switch (a.kp.kind) {
             case KDCD_KERNEL_LINEAR: KDCD_CSR_HEAD(KDCD_KERNEL_LINEAR); break;
             case KDCD_KERNEL_POLY: KDCD_CSR_HEAD(KDCD_KERNEL_POLY); break;
@@ -1158,7 +1161,7 @@ hipError_t launch_kblock_csr(const KBlockArgs &a, hipStream_t st)
     hipLaunchKernelGGL((kblock_csr_kernel<RPW, KIND>), gridb, blockb, 0, st, A->row_ptr,          \
                        A->col_idx, A->values, A->m, A->nnz, a.S, a.sb, a.norms, a.kp, a.beta,    \
                        a.beta_scale, a.partial, a.W, (int32_t)groups_b, a.carry, a.status, j0,   \
-                       j0 + nj, &q.meta->fallback)
+                       j0 + nj, &q.meta->fallback, a.U)
 #define KDCD_CSR_FB_KIND(RPW)                                                                   \
     switch (a.kp.kind) {                                                                        \
     case KDCD_KERNEL_LINEAR: KDCD_CSR_FB(RPW, KDCD_KERNEL_LINEAR); break;                       \
@@ -1186,7 +1189,7 @@ hipError_t launch_kblock_csr(const KBlockArgs &a, hipStream_t st)
     KDCD_TIMED_LAUNCH((kblock_csr_kernel<RPW, KIND>), grid, block, 0, st, A->row_ptr,          \
                        A->col_idx, A->values, A->m, A->nnz, a.S, a.sb, a.norms, a.kp, a.beta,  \
                        a.beta_scale, a.partial, a.W, (int32_t)groups, a.carry, a.status, 0, a.sb, \
-                       nullptr)
+                       nullptr, a.U)
 #define KDCD_CSR_KIND(RPW)                                                                    \
     switch (a.kp.kind) {                                                                      \
     case KDCD_KERNEL_LINEAR: KDCD_CSR(RPW, KDCD_KERNEL_LINEAR); break;                        \
@@ -1199,19 +1202,19 @@ hipError_t launch_kblock_csr(const KBlockArgs &a, hipStream_t st)
             KDCD_TIMED_LAUNCH((kblock_csr_wave_kernel<KDCD_KERNEL_LINEAR>), grid, block, 0, st,
                                A->row_ptr, A->col_idx, A->values, A->m, A->nnz, a.S, a.sb, a.norms,
                                a.kp, a.beta, a.beta_scale, a.partial, a.W, (int32_t)groups, a.carry, a.status,
-                               0, a.sb, nullptr);
+                               0, a.sb, nullptr, a.U);
             break;
         case KDCD_KERNEL_POLY:
             KDCD_TIMED_LAUNCH((kblock_csr_wave_kernel<KDCD_KERNEL_POLY>), grid, block, 0, st,
                                A->row_ptr, A->col_idx, A->values, A->m, A->nnz, a.S, a.sb, a.norms,
                                a.kp, a.beta, a.beta_scale, a.partial, a.W, (int32_t)groups, a.carry, a.status,
-                               0, a.sb, nullptr);
+                               0, a.sb, nullptr, a.U);
             break;
         default:
             KDCD_TIMED_LAUNCH((kblock_csr_wave_kernel<KDCD_KERNEL_RBF>), grid, block, 0, st,
                                A->row_ptr, A->col_idx, A->values, A->m, A->nnz, a.S, a.sb, a.norms,
                                a.kp, a.beta, a.beta_scale, a.partial, a.W, (int32_t)groups, a.carry, a.status,
-                               0, a.sb, nullptr);
+                               0, a.sb, nullptr, a.U);
             break;
         }
         return hipGetLastError();

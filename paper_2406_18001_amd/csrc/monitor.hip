@@ -117,7 +117,25 @@ __global__ __launch_bounds__(64) void monitor_final_kernel(int32_t problem, int6
     mon->rel = rel;
     mon->f = f;
     mon->outer_done = outer;
+    const int64_t i = mon->nlog;
+    if (mon->log && i < mon->log_len) {
+        double *r = mon->log + 4 * i;
+        r[0] = (double)outer;
+        r[1] = rel;
+        r[2] = f;
+        r[3] = (double)(wall_clock64() - mon->t0) * mon->tick;
+    }
+    mon->nlog = i + 1;
     if (rel <= tol) mon->stop = 1;
+}
+
+__global__ void monitor_start_kernel(MonitorState *mon, double *log, int64_t log_len, double tick)
+{
+    if (threadIdx.x != 0) return;
+    mon->log = log;
+    mon->log_len = log ? log_len : 0;
+    mon->tick = tick;
+    mon->t0 = wall_clock64();
 }
 
 // rho = y - Ka / lambda - m a   (Ka = K alpha_0, null when alpha_0 = 0)
@@ -152,6 +170,17 @@ hipError_t launch_dual_update(const double *U, int64_t m, int32_t sb, const int3
 }
 
 size_t monitor_partial_bytes() { return sizeof(double) * 4 * MON_BLOCKS; }
+
+hipError_t launch_monitor_start(MonitorState *mon, double *log, int64_t log_len, hipStream_t st)
+{
+    int dev = 0, khz = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+    if (e != hipSuccess) return e;
+    const double tick = khz > 0 ? 1e-3 / (double)khz : 0.0;
+    hipLaunchKernelGGL(monitor_start_kernel, dim3(1), dim3(64), 0, st, mon, log, log_len, tick);
+    return hipGetLastError();
+}
 
 hipError_t launch_monitor(int32_t problem, int64_t m, const double *alpha, const double *y,
                           const double *v, double omega, int32_t loss, double C, double tol,

@@ -132,6 +132,7 @@ hipError_t launch_kblock(const KBlockArgs &a, hipStream_t st)
     w.compute = KDCD_F64;
     w.w_only = 1;
     w.cfg = -1;          // the FP64 table's choice (a.cfg names a low-precision tile)
+    w.U = nullptr;       // the stored kernel block is the low-precision product's
     return launch_kblock_f64(w, st);
 }
 
@@ -554,6 +555,7 @@ kdcd_status enqueue_solve(const SolveArgs &sa, const Layout &L, char *wsbase, St
     if (monitor) {
         KDCD_HIP_TRY(launch_fill_i32(reinterpret_cast<int32_t *>(mon),
                                      0, (int64_t)(sizeof(MonitorState) / 4), st));
+        KDCD_HIP_TRY(launch_monitor_start(mon, sa.opt.monitor_log, sa.opt.monitor_log_len, st));
         rc = init_dual_vector(sa.problem, A, sa.kernel, sa.y, sa.alpha, omega, sa.lambda, dual,
                               ws.at<double>(L.mon_tmp), &mon->pad, st);
         if (rc != KDCD_OK) return rc;
@@ -862,7 +864,12 @@ kdcd_status check_monitor(const kdcd_matrix *A, const kdcd_options &o)
     if (o.monitor_every < 0) return KDCD_ERR_INVALID_ARG;
     if (o.monitor_every == 0) return KDCD_OK;
     if (!(o.tol >= 0.0) || !std::isfinite(o.tol)) return KDCD_ERR_INVALID_ARG;
-    if (A->format != KDCD_DENSE || o.compute != KDCD_F64 || (o.flags & KDCD_FLAG_GRAPH))
+    if (o.monitor_log_len < 0 || (o.monitor_log_len > 0 && !o.monitor_log))
+        return KDCD_ERR_INVALID_ARG;
+    if (o.flags & KDCD_FLAG_GRAPH) return KDCD_ERR_UNSUPPORTED;
+    // the U store of the product: FP64 (dense or CSR) and the single-problem
+    // low-precision products; not the FP32 product
+    if (A->format == KDCD_CSR ? o.compute != KDCD_F64 : o.compute == KDCD_F32)
         return KDCD_ERR_UNSUPPORTED;
     return KDCD_OK;
 }
@@ -1234,6 +1241,7 @@ kdcd_status kdcd_ksvm_solve_sampled(const kdcd_matrix *A, const double *y,
     const int32_t *stop = monitor ? &mon->stop : nullptr;
     KDCD_HIP_TRY(launch_fill_i32(reinterpret_cast<int32_t *>(mon), 0,
                                  (int64_t)(sizeof(MonitorState) / 4), st));
+    KDCD_HIP_TRY(launch_monitor_start(mon, o.monitor_log, o.monitor_log_len, st));
 
     KDCD_HIP_TRY(launch_fill_i32(status, 0, 1, st));
     KDCD_HIP_TRY(launch_fill_i32(flag, 0, 1, st));

@@ -101,7 +101,8 @@ class _Options(ctypes.Structure):
                 ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
                 ("profile", ctypes.c_void_p), ("monitor_every", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("tol", ctypes.c_double),
-                ("outer_done", ctypes.c_void_p), ("rel_err", ctypes.c_void_p)]
+                ("outer_done", ctypes.c_void_p), ("rel_err", ctypes.c_void_p),
+                ("monitor_log", ctypes.c_void_p), ("monitor_log_len", ctypes.c_int64)]
 
 
 _P = ctypes.c_void_p
@@ -239,9 +240,12 @@ def _stream(stream) -> int:
 
 
 class _MonitorOut:
-    def __init__(self):
+    def __init__(self, n_outer=0, every=0, log=False):
         self.outer = ctypes.c_int64(-1)
         self.rel = ctypes.c_double(float("nan"))
+        # one record per evaluation: every `every` outer iterations and after the last
+        self.log = (torch.full((n_outer // max(every, 1) + 2, 4), float("nan"), dtype=torch.float64,
+                               device="cuda") if log else None)
 
 
 def _options(compute, loss, snapshot_every, snapshots, trace, workspace, profile, flags,
@@ -252,6 +256,9 @@ def _options(compute, loss, snapshot_every, snapshots, trace, workspace, profile
     if mon is not None:
         o.outer_done = ctypes.cast(ctypes.pointer(mon.outer), ctypes.c_void_p)
         o.rel_err = ctypes.cast(ctypes.pointer(mon.rel), ctypes.c_void_p)
+        if mon.log is not None:
+            o.monitor_log = mon.log.data_ptr()
+            o.monitor_log_len = mon.log.shape[0]
     o.compute = COMPUTE[compute] if isinstance(compute, str) else int(compute)
     o.loss = int(loss)
     o.snapshot_every = int(snapshot_every)
@@ -279,17 +286,21 @@ def _result(prof, mon):
     if mon is not None:
         out["outer_done"] = mon.outer.value
         out["rel_err"] = mon.rel.value
+        if mon.log is not None:
+            # (outer iterations done, certified relative error, objective, seconds)
+            out["log"] = [tuple(r) for r in mon.log.cpu().tolist() if r[0] == r[0]]
     return out
 
 
 def _solve(fn, name, A, y, kernel, param, b, s, H, idx, alpha, compute, loss, snapshot_every,
-           snapshots, trace, workspace, profile, flags, stream, monitor_every=0, tol=0.0):
+           snapshots, trace, workspace, profile, flags, stream, monitor_every=0, tol=0.0,
+           monitor_log=False):
     mat, m, _ = _matrix(A)
     _dev(y, torch.float64, m, "y")
     _dev(alpha, torch.float64, m, "alpha")
     _dev(idx, torch.int32, int(H) * int(b), "idx")
     n_outer = -(-int(H) // max(int(s), 1))
-    mon = _MonitorOut() if monitor_every else None
+    mon = _MonitorOut(n_outer, int(monitor_every), monitor_log) if monitor_every else None
     opt, prof = _options(compute, loss, snapshot_every, snapshots, trace, workspace, profile,
                          flags, m, n_outer, int(H) * int(b), monitor_every, tol, mon)
     kern = _kernel(kernel)
@@ -302,22 +313,23 @@ def _solve(fn, name, A, y, kernel, param, b, s, H, idx, alpha, compute, loss, sn
 
 def kdcd_ksvm_solve(A, y, kernel, C, b, s, H, idx, alpha, *, compute="f64", loss=1,
                     snapshot_every=0, snapshots=None, trace=None, workspace=None, profile=False,
-                    flags=0, stream=None, monitor_every=0, tol=0.0):
+                    flags=0, stream=None, monitor_every=0, tol=0.0, monitor_log=False):
     """s-step DCD for K-SVM (Algorithm 2); alpha is updated in place.
     Returns a dict with the stage timings (profile=True) and the monitor's
-    outer_done / rel_err (monitor_every > 0), else None."""
+    outer_done / rel_err (monitor_every > 0; with monitor_log=True also its
+    records as "log"), else None."""
     return _solve(_lib.kdcd_ksvm_solve, "kdcd_ksvm_solve", A, y, kernel, C, b, s, H, idx, alpha,
                   compute, loss, snapshot_every, snapshots, trace, workspace, profile, flags,
-                  stream, monitor_every, tol)
+                  stream, monitor_every, tol, monitor_log)
 
 
 def kdcd_krr_solve(A, y, kernel, lam, b, s, H, idx, alpha, *, compute="f64", snapshot_every=0,
                    snapshots=None, trace=None, workspace=None, profile=False, flags=0,
-                   stream=None, monitor_every=0, tol=0.0):
+                   stream=None, monitor_every=0, tol=0.0, monitor_log=False):
     """s-step BDCD for K-RR (Algorithm 4); alpha is updated in place."""
     return _solve(_lib.kdcd_krr_solve, "kdcd_krr_solve", A, y, kernel, lam, b, s, H, idx, alpha,
                   compute, 1, snapshot_every, snapshots, trace, workspace, profile, flags, stream,
-                  monitor_every, tol)
+                  monitor_every, tol, monitor_log)
 
 
 def kdcd_krr_solve_noalloc(A, y, kernel, lam, b, s, H, idx, alpha, *, compute="f64",
@@ -571,7 +583,8 @@ def kdcd_sampler_select(keys: torch.Tensor, s: int, epsilon: float, seed: int, o
 def kdcd_ksvm_solve_sampled(A, y, kernel, C, s, H, alpha, *, model=None, epsilon=0.0, tau=1.0,
                             seed=0, pool=0, idx_out=None, features_out=None, grad_out=None, loss=1,
                             trace=None, snapshot_every=0, snapshots=None, workspace=None,
-                            profile=False, flags=0, stream=None, monitor_every=0, tol=0.0):
+                            profile=False, flags=0, stream=None, monitor_every=0, tol=0.0,
+                            monitor_log=False):
     """Algorithm 2 (b = 1) with the coordinates drawn on the device by
     `model` (a Sampler; None draws uniformly).  Returns (idx_out, profile or
     None); alpha is updated in place."""
@@ -593,7 +606,7 @@ def kdcd_ksvm_solve_sampled(A, y, kernel, C, s, H, alpha, *, model=None, epsilon
     if grad_out is not None:
         smp.grad_out = _dev(grad_out, torch.float64, m, "grad_out")
     n_outer = -(-H // max(int(s), 1))
-    mon = _MonitorOut() if monitor_every else None
+    mon = _MonitorOut(n_outer, int(monitor_every), monitor_log) if monitor_every else None
     opt, prof = _options("f64", loss, snapshot_every, snapshots, trace, workspace, profile, flags,
                          m, n_outer, H, monitor_every, tol, mon)
     kern = _kernel(kernel)

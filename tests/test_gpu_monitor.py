@@ -129,15 +129,94 @@ def test_monitor_errors(K):
         K.kdcd_krr_solve(*args, monitor_every=2, tol=-1.0)
     assert e.value.status == -1
     with pytest.raises(K.KdcdError) as e:
-        K.kdcd_krr_solve(*args, monitor_every=2, tol=1e-6, compute="bf16")
+        K.kdcd_krr_solve(*args, monitor_every=2, tol=1e-6, compute="f32")
     assert e.value.status == -2
     with pytest.raises(K.KdcdError) as e:
         K.kdcd_krr_solve(*args, monitor_every=2, tol=1e-6, flags=K.FLAG_GRAPH)
     assert e.value.status == -2
-    c = inputs.csr_ksvm_c3(m=300, n=100, nnz_per_row=5, seed=1)
-    A = K.CSR(torch.as_tensor(c["row_ptr"]).cuda(), torch.as_tensor(c["col_idx"]).cuda(),
-              torch.as_tensor(c["val"]).cuda(), 300, 100)
-    with pytest.raises(K.KdcdError) as e:
-        K.kdcd_ksvm_solve(A, dev(c["y"]), (1, 0.0, 1.0, 3), 1.0, 1, 4, 8,
-                          idx_dev(np.arange(8, dtype=np.int32)), a, monitor_every=2, tol=1e-6)
-    assert e.value.status == -2
+
+
+def csr_of(K, c):
+    return K.CSR(torch.as_tensor(c["row_ptr"]).cuda(), torch.as_tensor(c["col_idx"]).cuda(),
+                 torch.as_tensor(c["val"]).cuda(), c["m"], c["n"])
+
+
+@pytest.mark.parametrize("s", [8, 32])
+def test_csr_ksvm_monitor_value_and_early_stop(K, s):
+    """CSR K-SVM (C3 recipe, small): s = 8 runs the broadcast product, s = 32
+    the dense-head product; the certified gap against the oracle's at the
+    final iterate, and an early stop against a plain solve."""
+    c = inputs.csr_ksvm_c3(m=2000, n=1500, nnz_per_row=20, seed=41)
+    m, C = c["m"], 1.0
+    kern, okern = (1, 0.0, 1.0, 3), O.Kernel(O.POLY, c=1.0, degree=3)
+    A, oA = csr_of(K, c), (c["row_ptr"], c["col_idx"], c["val"], c["m"], c["n"])
+    H = 4 * m
+    idx = inputs.ksvm_indices(m, H, seed=6)
+    a = torch.zeros(m, dtype=torch.float64, device="cuda")
+    H2 = 2 * m
+    info = K.kdcd_ksvm_solve(A, dev(c["y"]), kern, C, 1, s, H2, idx_dev(idx[:H2]), a,
+                             monitor_every=5, tol=0.0, monitor_log=True)
+    ev = O.ksvm_eval(oA, c["y"], okern, C, a.cpu().numpy())
+    ref = ev["gap"] / abs(ev["dual"])
+    assert abs(info["rel_err"] - ref) <= 1e-7 * ref + 1e-12, (info["rel_err"], ref)
+    log = info["log"]
+    n_outer = -(-H2 // s)
+    assert [int(r[0]) for r in log] == list(range(5, n_outer + 1, 5)) + (
+        [n_outer] if n_outer % 5 else [])
+    assert log[-1][1] == info["rel_err"]
+    assert all(t1 > t0 for (_, _, _, t0), (_, _, _, t1) in zip(log, log[1:]))
+    # stop at the bound the logged run certified half-way (same iterates)
+    j = len(log) // 2
+    a = torch.zeros(m, dtype=torch.float64, device="cuda")
+    info = K.kdcd_ksvm_solve(A, dev(c["y"]), kern, C, 1, s, H, idx_dev(idx), a,
+                             monitor_every=5, tol=log[j][1])
+    k = info["outer_done"]
+    assert 0 < k <= int(log[j][0]) and k % 5 == 0 and info["rel_err"] <= log[j][1]
+    plain = torch.zeros(m, dtype=torch.float64, device="cuda")
+    K.kdcd_ksvm_solve(A, dev(c["y"]), kern, C, 1, s, k * s, idx_dev(idx[:k * s]), plain)
+    assert torch.equal(a, plain)
+
+
+def test_csr_krr_monitor_value(K):
+    """CSR K-RR with the RBF kernel (b = 4, s = 8: the dense-head product):
+    the certified bound against the oracle's residual at the final iterate."""
+    c = inputs.csr_ksvm_c3(m=1500, n=1200, nnz_per_row=15, seed=43)
+    m, b, s, lam = c["m"], 4, 8, 1e-2
+    y = np.random.default_rng(2).standard_normal(m)
+    A, oA = csr_of(K, c), (c["row_ptr"], c["col_idx"], c["val"], c["m"], c["n"])
+    H = 40 * s + 3
+    idx = inputs.krr_indices(m, b, H, seed=8)
+    a = torch.zeros(m, dtype=torch.float64, device="cuda")
+    info = K.kdcd_krr_solve(A, dev(y), (2, 0.5, 0.0, 1), lam, b, s, H, idx_dev(idx), a,
+                            monitor_every=7, tol=0.0)
+    ev = O.krr_eval(oA, y, O.Kernel(O.RBF, sigma=0.5), lam, a.cpu().numpy())
+    ref = krr_rel(ev, m)
+    assert abs(info["rel_err"] - ref) <= 1e-7 * ref
+
+
+@pytest.mark.parametrize("compute,tol", [("bf16x3", 1e-4), ("bf16", 5e-2), ("f16", 5e-2)])
+def test_lowp_monitor(K, compute, tol):
+    """Low-precision K-RR products store their kernel block for the monitor:
+    the certified bound follows the exact problem's (oracle) within the
+    kernel's rounding, and an early stop matches a plain solve."""
+    d = inputs.dense_krr_c2(m=2000, n=64, seed=8)
+    m, b, s, H = 2000, 8, 16, 16 * 20
+    idx = inputs.krr_indices(m, b, H, seed=3)
+    kern = (2, 1.0, 0.0, 1)
+    a = torch.zeros(m, dtype=torch.float64, device="cuda")
+    info = K.kdcd_krr_solve(dev(d["A"]), dev(d["y"]), kern, 1e-3, b, s, H, idx_dev(idx), a,
+                            compute=compute, monitor_every=4, tol=0.0, monitor_log=True)
+    ev = O.krr_eval(d["A"], d["y"], O.Kernel(O.RBF, sigma=1.0), 1e-3, a.cpu().numpy())
+    ref = krr_rel(ev, m)
+    assert abs(info["rel_err"] - ref) <= tol * ref, (info["rel_err"], ref)
+    assert len(info["log"]) == H // s // 4 and info["log"][-1][1] == info["rel_err"]
+    stop_at = info["log"][2][1] * 1.0000001      # reached at the third evaluation
+    a = torch.zeros(m, dtype=torch.float64, device="cuda")
+    info = K.kdcd_krr_solve(dev(d["A"]), dev(d["y"]), kern, 1e-3, b, s, H, idx_dev(idx), a,
+                            compute=compute, monitor_every=4, tol=stop_at)
+    k = info["outer_done"]
+    assert k <= 12 and k % 4 == 0 and info["rel_err"] <= stop_at, k
+    plain = torch.zeros(m, dtype=torch.float64, device="cuda")
+    K.kdcd_krr_solve(dev(d["A"]), dev(d["y"]), kern, 1e-3, b, s, k * s, idx_dev(idx[:k * s * b]),
+                     plain, compute=compute)
+    assert torch.equal(a, plain)
