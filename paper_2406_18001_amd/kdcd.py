@@ -244,8 +244,15 @@ class _MonitorOut:
         self.outer = ctypes.c_int64(-1)
         self.rel = ctypes.c_double(float("nan"))
         # one record per evaluation: every `every` outer iterations and after the last
-        self.log = (torch.full((n_outer // max(every, 1) + 2, 4), float("nan"), dtype=torch.float64,
-                               device="cuda") if log else None)
+        # (log may also be the caller's (records, 4) float64 device tensor)
+        if isinstance(log, torch.Tensor):
+            _dev(log, torch.float64, None, "monitor_log")
+            if log.dim() != 2 or log.shape[1] != 4:
+                raise ValueError("monitor_log must be a (records, 4) tensor")
+            self.log = log
+        else:
+            self.log = (torch.full((n_outer // max(every, 1) + 2, 4), float("nan"),
+                                   dtype=torch.float64, device="cuda") if log else None)
 
 
 def _options(compute, loss, snapshot_every, snapshots, trace, workspace, profile, flags,
