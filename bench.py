@@ -51,9 +51,10 @@ def parse():
                     help="use the built-in tile rule instead of timing the configurations")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the oracle sample")
     ap.add_argument("--workload", default="c2",
-                    choices=["c2", "c4-mixed", "c4-sweep", "c5s-sampler", "c2-nystrom", "news20-krr",
-                             "c3-csr", "peaks"],
-                    help="c2: the headline line; c4-sweep: batched (lambda, sigma) sweep and "
+                    choices=["c2", "c1", "c4-mixed", "c4-sweep", "c5s-sampler", "c2-nystrom",
+                             "news20-krr", "c3-csr", "peaks"],
+                    help="c2: the headline line; c1: K-SVM DCD on C1 at s = 1 and 8; "
+                         "c4-sweep: batched (lambda, sigma) sweep and "
                          "one-vs-rest K-SVMs against sequential solves; c5s-sampler: learned "
                          "against uniform coordinate sampling; c2-nystrom: the C2 K-RR on "
                          "Nystrom factors of several ranks; news20-krr: sparse K-RR with RBF "
@@ -127,15 +128,31 @@ def block_flops(h_blocks, s, b, m, n, every=1):
     return total
 
 
+def host_cpu():
+    """The host CPU's model name and logical CPU count (from /proc/cpuinfo)."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count()}
+
+
 def cpu_baseline(d, idx, s, target_s):
     """Time the FP64 oracle (s-step BDCD) on the first outer iterations of the
-    same solve; grow the sample until it lasts about target_s seconds."""
+    same solve; grow the sample until it lasts about target_s seconds.  Beside
+    it: the classical oracle (s = 1) on the same block updates (the CPU
+    analogue of the s-step speedup), and the s-step oracle on one thread over
+    one outer iteration at s = 8."""
     from oracle import oracle as O
     kern = O.Kernel(O.RBF, sigma=SIGMA)
 
-    def run(outer):
+    def run(outer, s_run=s):
         t0 = time.perf_counter()
-        O.bdcd_krr(d["A"], d["y"], kern, LAM, B, outer * s, idx, s=s)
+        O.bdcd_krr(d["A"], d["y"], kern, LAM, B, outer * s, idx, s=s_run)
         return time.perf_counter() - t0
 
     outer, dt = 1, run(1)
@@ -144,10 +161,23 @@ def cpu_baseline(d, idx, s, target_s):
         dt = run(outer)
     hb = outer * s
     fl = block_flops(hb, s, B, M, N)
-    return {"value": fl / dt / 1e12, "unit": "TFLOP/s", "cores": O.threads(), "kind": "oracle",
+    dt1 = run(outer, 1)
+    cores = O.threads()
+    O.set_threads(1)
+    t0 = time.perf_counter()
+    O.bdcd_krr(d["A"], d["y"], kern, LAM, B, 8, idx, s=8)
+    dt_one = time.perf_counter() - t0
+    O.set_threads(cores)
+    return {"value": fl / dt / 1e12, "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
             "sample": f"first {outer} outer iteration(s) = {hb} block updates of the same solve "
                       f"(s={s}, b={B}), {dt:.2f} s, FP64 oracle with OpenMP over rows",
-            "seconds": dt}
+            "seconds": dt,
+            "classical_s1": {"seconds": round(dt1, 3), "speedup_of_s_step": round(dt1 / dt, 3),
+                             "sample": f"the same {hb} block updates with s = 1"},
+            "one_thread": {"value": block_flops(8, 8, B, M, N) / dt_one / 1e12, "unit": "TFLOP/s",
+                           "seconds": round(dt_one, 3),
+                           "sample": "one outer iteration at s = 8 (8 block updates), one thread"},
+            "host": host_cpu()}
 
 
 def krr_outer_to_target(K, A, y, kern, lam, b, s, idx_long, compute, every=8, target=1e-6,
@@ -975,6 +1005,54 @@ def bench_news20_krr(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_c1(args):
+    """The C1 recipe (dense 2000 x 64 N(0,1), K-SVM-L1 with RBF sigma = 1,
+    C = 1, b = 1, H = 500 coordinate updates): wall time of the whole solve
+    and time per outer iteration at s = 1 and s = 8 (median of repeated
+    solves after a warm-up)."""
+    import statistics
+
+    import torch
+
+    from paper_2406_18001_amd import inputs
+    from paper_2406_18001_amd import kdcd as K
+    m, n, H, C = 2000, 64, 500, 1.0
+    d = inputs.dense_ksvm_c1(m=m, n=n)
+    A = torch.tensor(d["A"], device="cuda")
+    y = torch.tensor(d["y"], device="cuda")
+    idx = torch.tensor(inputs.ksvm_indices(m, H, seed=0), device="cuda")
+    kern = (2, 1.0, 0.0, 1)
+    reps = max(5, args.steps)
+    runs = []
+    for s in (1, 8):
+        a = torch.zeros(m, dtype=torch.float64, device="cuda")
+        for _ in range(2):                                  # warm-up
+            a.zero_()
+            K.kdcd_ksvm_solve(A, y, kern, C, 1, s, H, idx, a)
+        ts = []
+        for _ in range(reps):
+            a.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            K.kdcd_ksvm_solve(A, y, kern, C, 1, s, H, idx, a)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        t = statistics.median(ts)
+        n_outer = -(-H // s)
+        e = {"s": s, "solve_ms": round(t * 1e3, 3), "us_per_outer_iteration": round(t / n_outer * 1e6, 2),
+             "updates_per_s": round(H / t, 1), "outer_iterations": n_outer}
+        log(f"c1 {e}")
+        runs.append(e)
+    out = {"metric": "K-SVM DCD on C1: microseconds per outer iteration", "value": runs[-1]["us_per_outer_iteration"],
+           "unit": "us/outer iteration", "n_gpus": 1, "steps": reps, "warmup": 2,
+           "ms_per_step": runs[-1]["solve_ms"], "higher_is_better": False, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"C1: dense A {m}x{n} N(0,1), y = sign(A w) with 5% flips, "
+                                  f"K-SVM-L1 RBF sigma=1, C={C}, b=1, s in (1, 8), H={H}"},
+           "runs": runs, "speedup_s8_vs_s1": round(runs[0]["solve_ms"] / runs[1]["solve_ms"], 3)}
+    print(json.dumps(out), flush=True)
+
+
 def bench_c3_csr(args):
     """The C3 recipe (CSR 100000 x 50000, 50 stored entries per row, Zipf(1.1)
     columns, polynomial kernel (x.y + 1)^3, K-SVM-L1, C = 1): wall time of
@@ -1062,6 +1140,9 @@ def main():
         sys.exit(2)
     if args.copy_probe:
         copy_probe()
+        return
+    if args.workload == "c1":
+        bench_c1(args)
         return
     if args.workload == "c4-sweep":
         bench_c4_sweep(args)

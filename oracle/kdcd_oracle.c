@@ -94,6 +94,16 @@ int orc_threads(void)
 #endif
 }
 
+/* Threads of the later calls (timing only: results do not depend on it). */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------ kernel function -- */
 
 /* Table 1: a_p . a_q  (compensated sum over the features) */

@@ -60,11 +60,17 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        build()
-        L = ctypes.CDLL(LIB)
+        # KDCD_ORACLE_LIBRARY: a prebuilt variant of the same source (for
+        # example the AddressSanitizer build), loaded as is
+        path = os.environ.get("KDCD_ORACLE_LIBRARY")
+        if not path:
+            build()
+            path = LIB
+        L = ctypes.CDLL(path)
         P = ctypes.c_void_p
         i64, i32, dbl = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
         L.orc_threads.restype = ctypes.c_int
+        L.orc_set_threads.argtypes = [ctypes.c_int]
         L.orc_kernel_eval.restype = dbl
         L.orc_kernel_eval.argtypes = [P, P, i64, i64]
         L.orc_kernel_block.argtypes = [P, P, P, i64, P, i64, P]
@@ -84,6 +90,11 @@ def lib():
 
 def threads() -> int:
     return int(lib().orc_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of later oracle calls (for timing; results do not depend on it)."""
+    lib().orc_set_threads(int(n))
 
 
 class _Args:

@@ -74,6 +74,61 @@ def build_library(jobs: int | None = None) -> str:
     return LIB
 
 
+ASAN_DIR = os.path.join(BUILD, "asan")
+ASAN_RUNTIME = "libclang_rt.asan-x86_64.so"
+
+
+def asan_runtime() -> str:
+    """The clang AddressSanitizer runtime that the host code below links against."""
+    found = sorted(glob.glob(os.path.join(os.path.dirname(HIPCC), "..", "llvm", "lib", "clang", "*",
+                                          "lib", "linux", ASAN_RUNTIME)))
+    if not found:
+        raise RuntimeError("clang AddressSanitizer runtime not found")
+    return os.path.realpath(found[-1])
+
+
+def build_asan() -> tuple[str, str]:
+    """CPU-side AddressSanitizer build: the library's host code (device code
+    is compiled as usual) and the C oracle, both with clang's runtime, into
+    _build/asan/.  Run the CPU suite against them with
+
+      LD_PRELOAD=<asan_runtime()> ASAN_OPTIONS=detect_leaks=0 \
+      KDCD_LIBRARY=_build/asan/libkdcd.so KDCD_ORACLE_LIBRARY=_build/asan/liboracle.so \
+      python -m pytest tests -m "not gpu"
+    """
+    os.makedirs(ASAN_DIR, exist_ok=True)
+    san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fno-omit-frame-pointer",
+           "-Xarch_host", "-g"]
+
+    def comp(src):
+        obj = os.path.join(ASAN_DIR, os.path.basename(src) + ".o")
+        res = subprocess.run([HIPCC, *FLAGS, *san, "-c", src, "-o", obj], capture_output=True, text=True)
+        if res.returncode != 0:
+            raise RuntimeError(f"hipcc (asan) failed for {src}:\n{res.stderr}")
+        return obj
+
+    with cf.ThreadPoolExecutor(max_workers=8) as ex:
+        objs = list(ex.map(comp, sources()))
+    lib = os.path.join(ASAN_DIR, "libkdcd.so")
+    res = subprocess.run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-fsanitize=address",
+                          "-shared-libasan", *objs, "-o", lib], capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"asan link failed:\n{res.stderr}")
+    clang = os.path.join(os.path.dirname(HIPCC), "..", "llvm", "bin", "clang")
+    orc = os.path.join(ASAN_DIR, "liboracle.so")
+    res = subprocess.run([clang, "-std=c11", "-O1", "-g", "-fno-omit-frame-pointer", "-ffp-contract=off",
+                          "-fno-fast-math", "-fopenmp", "-fsanitize=address,undefined",
+                          "-fno-sanitize-recover=undefined", "-shared-libasan", "-fPIC", "-shared",
+                          os.path.join(ROOT, "oracle", "kdcd_oracle.c"), "-o", orc, "-lm"],
+                         capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"oracle asan build failed:\n{res.stderr}")
+    return lib, orc
+
+
 if __name__ == "__main__":
-    print(build_library())
-    print(build_peak())
+    if "--asan" in sys.argv:
+        print(*build_asan(), asan_runtime())
+    else:
+        print(build_library())
+        print(build_peak())

@@ -19,7 +19,7 @@ from typing import NamedTuple, Optional
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libkdcd.so")
+LIB_PATH = os.environ.get("KDCD_LIBRARY") or os.path.join(_HERE, "libkdcd.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"kdcd HIP library not built: {LIB_PATH} is missing "

@@ -212,19 +212,22 @@ def test_learned_sampled_solve_replays_and_selects_exactly(K):
 
 
 def test_trained_sampler_beats_uniform(K):
-    """Train on the features and realised |theta| of uniform runs, then run
-    the learned draw for the same number of updates: its dual objective is
-    lower (K-SVM-L1 on the C5 recipe at reduced size, sigma = 2/n)."""
+    """Train on the features and realised |theta| of a uniform run on one
+    instance of the C5 recipe (reduced size, sigma = 2/n), then run the learned
+    draw on another instance for as many updates as the uniform draw: its dual
+    objective is lower."""
     m, n, C, s = 4000, 64, 10.0, 64
     d = inputs.dense_ksvm_c5(m=m, n=n, seed=23)
     A, y = dev(d["A"]), dev(d["y"])
     kern = (2, 2.0 / n, 0.0, 1)
-    H = 3 * m
-    alpha = torch.zeros(m, dtype=torch.float64, device="cuda")
+    mt, nt = 3000, 128                                  # the training instance
+    dt = inputs.dense_ksvm_c5(m=mt, n=nt, seed=24)
+    H = 3 * mt
+    alpha = torch.zeros(mt, dtype=torch.float64, device="cuda")
     feats = torch.zeros(4 * H, dtype=torch.float32, device="cuda")
     trace = torch.zeros(H, dtype=torch.float64, device="cuda")
-    K.kdcd_ksvm_solve_sampled(A, y, kern, C, s, H, alpha, seed=100, features_out=feats,
-                              trace=trace)
+    K.kdcd_ksvm_solve_sampled(dev(dt["A"]), dev(dt["y"]), (2, 2.0 / nt, 0.0, 1), C, s, H, alpha,
+                              seed=100, features_out=feats, trace=trace)
     x = feats.view(H, 4)
     t = torch.log(1e-7 + trace.abs() / C).float()
     smp = K.Sampler(1)
