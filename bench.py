@@ -1295,6 +1295,25 @@ def main():
         conv["f64_monitored"] = {"outer_iterations": info["outer_done"], "seconds": round(dt, 5),
                                  "rel_obj_err_bound": info["rel_err"],
                                  "note": "wall time of one solve that stops itself on the device"}
+        # bf16x3 with the monitor: its bound certifies the problem with the
+        # product's rounded kernel values
+        for rep in range(2):
+            alpha.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = K.kdcd_krr_solve(A, y, kern, LAM, B, s, Hl, idx_long, alpha, compute="bf16x3",
+                                    monitor_every=8, tol=1e-6)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        ev = K.kdcd_krr_eval(A, y, kern, LAM, alpha)
+        bound = 0.5 * ev["residual_norm"] ** 2 / M
+        conv["bf16x3_monitored"] = {
+            "outer_iterations": info["outer_done"], "seconds": round(dt, 5),
+            "rel_obj_err_bound": info["rel_err"],
+            "rel_obj_err_bound_fp64": bound / max(abs(ev["objective"]) - bound, 1e-300),
+            "note": "wall time of one bf16x3 solve that stops itself on the device (its monitor "
+                    "certifies the rounded-kernel problem; the FP64 bound of the same iterate "
+                    "beside it)"}
         out["time_to_rel_obj_err_1e-6"] = conv
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(d, idx, s, args.cpu_seconds)
