@@ -1038,9 +1038,22 @@ def bench_c1(args):
             torch.cuda.synchronize()
             ts.append(time.perf_counter() - t0)
         t = statistics.median(ts)
+        # the same solve replayed from graphs of 16 outer iterations (KDCD_FLAG_GRAPH)
+        tg = []
+        for r in range(reps + 2):
+            a.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            K.kdcd_ksvm_solve(A, y, kern, C, 1, s, H, idx, a, flags=K.FLAG_GRAPH)
+            torch.cuda.synchronize()
+            if r >= 2:                                      # the first calls capture
+                tg.append(time.perf_counter() - t0)
+        t_g = statistics.median(tg)
         n_outer = -(-H // s)
         e = {"s": s, "solve_ms": round(t * 1e3, 3), "us_per_outer_iteration": round(t / n_outer * 1e6, 2),
-             "updates_per_s": round(H / t, 1), "outer_iterations": n_outer}
+             "updates_per_s": round(H / t, 1), "outer_iterations": n_outer,
+             "graph_solve_ms": round(t_g * 1e3, 3),
+             "graph_us_per_outer_iteration": round(t_g / n_outer * 1e6, 2)}
         log(f"c1 {e}")
         runs.append(e)
     out = {"metric": "K-SVM DCD on C1: microseconds per outer iteration", "value": runs[-1]["us_per_outer_iteration"],

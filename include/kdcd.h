@@ -116,6 +116,15 @@ typedef struct {
  * workspace (allocated once with hipMalloc) unless opt->workspace is given,
  * which then must stay valid while the entry lives.  Graph-mode calls are
  * serialised by one lock.  With a profile, only total_ms is reported.
+ * kdcd_ksvm_solve / kdcd_krr_solve without trace, snapshots, profile or a
+ * caller workspace, with at least 18 whole blocks (floor(H/s) >= 18), are
+ * replayed by windows instead: one graph holds 16 outer iterations -- a
+ * kernel that copies the window's index blocks out of idx, the block index
+ * taken from a counter in device memory that the same kernel moves on, then
+ * the window's launches -- and is launched window after window; the set-up,
+ * the first outer iteration and the iterations after the last whole window
+ * run eagerly, in the graph's workspace.  That graph does not depend on H or
+ * on the contents of idx (only on its address), so such calls share it.
  */
 /*
  * KDCD_FLAG_TIME_PRODUCT (with a profile; dense kdcd_ksvm_solve /

@@ -220,6 +220,29 @@ hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t count, hipStream_t st)
     return hipGetLastError();
 }
 
+// Graph window of W outer iterations: copies index blocks k0 - 1 .. k0 + W of
+// idx (blocks of sb) into the window buffer, k0 read from the device counter,
+// and moves the counter on by W.  The caller keeps every window inside idx.
+__global__ __launch_bounds__(1024) void window_advance_kernel(const int32_t *__restrict__ idx,
+                                                              int64_t *counter,
+                                                              int32_t *__restrict__ Swin,
+                                                              int32_t W, int32_t sb)
+{
+    const int64_t k0 = *counter;
+    const int64_t n = (int64_t)(W + 2) * sb;
+    const int32_t *src = idx + (k0 - 1) * (int64_t)sb;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) Swin[i] = src[i];
+    __syncthreads();
+    if (threadIdx.x == 0) *counter = k0 + W;
+}
+
+hipError_t launch_window_advance(const int32_t *idx, int64_t *counter, int32_t *Swin, int32_t W,
+                                 int32_t sb, hipStream_t st)
+{
+    hipLaunchKernelGGL(window_advance_kernel, dim3(1), dim3(1024), 0, st, idx, counter, Swin, W, sb);
+    return hipGetLastError();
+}
+
 hipError_t launch_iota_i32(int32_t *p, int64_t count, hipStream_t st)
 {
     hipLaunchKernelGGL(iota_i32_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, p,

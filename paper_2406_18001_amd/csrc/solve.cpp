@@ -369,7 +369,7 @@ struct SolveArgs {
 };
 
 kdcd_status prepare_lowp(const KBlockArgs &base, const Layout &L, Workspace &ws, hipStream_t st,
-                         KBlockArgs &a)
+                         KBlockArgs &a, bool convert = true)
 {
     a = base;
     if (base.compute == KDCD_F64 || base.A->format != KDCD_DENSE) return KDCD_OK;
@@ -377,8 +377,9 @@ kdcd_status prepare_lowp(const KBlockArgs &base, const Layout &L, Workspace &ws,
     a.Alow2 = ws.at<void>(L.lo);
     a.ldlow = L.ldlow;
     a.normlow = ws.at<float>(L.normlow);
-    KDCD_HIP_TRY(launch_convert_lowp(base.A, base.compute, ws.at<void>(L.hi), ws.at<void>(L.lo),
-                                     L.ldlow, ws.at<float>(L.normlow), st));
+    if (convert)
+        KDCD_HIP_TRY(launch_convert_lowp(base.A, base.compute, ws.at<void>(L.hi), ws.at<void>(L.lo),
+                                         L.ldlow, ws.at<float>(L.normlow), st));
     return KDCD_OK;
 }
 
@@ -496,9 +497,21 @@ struct StopPoller {
     }
 };
 
-// Everything a solve puts on its stream, in the workspace at `base`, without
-// the final status read (the status word is at offset L.status).
-kdcd_status enqueue_solve(const SolveArgs &sa, const Layout &L, char *wsbase, StageTimer &timer)
+// A part of a solve: outer iterations [k_begin, k_end) (k_end < 0: to the
+// end), with or without the set-up launches (validation, norms, conversions,
+// tables).  With S_base the index blocks come from a window buffer instead of
+// idx: block k_begin - 1 at S_base, block k at S_base + (k - k_begin + 1) s b
+// (every block of the range and the one after it full).
+struct SolveRange {
+    int64_t k_begin = 0, k_end = -1;
+    bool setup = true;
+    const int32_t *S_base = nullptr;
+};
+
+// Everything a solve (or a part of it) puts on its stream, in the workspace at
+// `base`, without the final status read (the status word is at offset L.status).
+kdcd_status enqueue_solve(const SolveArgs &sa, const Layout &L, char *wsbase, StageTimer &timer,
+                          const SolveRange &R = SolveRange{})
 {
     const kdcd_matrix *A = sa.A;
     const hipStream_t st = sa.st;
@@ -518,11 +531,13 @@ kdcd_status enqueue_solve(const SolveArgs &sa, const Layout &L, char *wsbase, St
     const double nu = svm ? (sa.opt.loss == 2 ? INFINITY : sa.C) : 0.0;
     const double omega = (svm && sa.opt.loss == 2) ? 1.0 / (2.0 * sa.C) : 0.0;
 
-    KDCD_HIP_TRY(launch_fill_i32(status, 0, 1, st));
-    if (A->format == KDCD_CSR) KDCD_HIP_TRY(launch_validate_csr(A, status, st));
-    KDCD_HIP_TRY(launch_validate(sa.idx, sa.H * sa.b, A->m, sa.y, sa.alpha, A->m, sa.problem, nu,
-                                 status, st));
-    if (sa.kernel->kind == KDCD_KERNEL_RBF) KDCD_HIP_TRY(launch_norms(A, norms, st));
+    if (R.setup) {
+        KDCD_HIP_TRY(launch_fill_i32(status, 0, 1, st));
+        if (A->format == KDCD_CSR) KDCD_HIP_TRY(launch_validate_csr(A, status, st));
+        KDCD_HIP_TRY(launch_validate(sa.idx, sa.H * sa.b, A->m, sa.y, sa.alpha, A->m, sa.problem,
+                                     nu, status, st));
+        if (sa.kernel->kind == KDCD_KERNEL_RBF) KDCD_HIP_TRY(launch_norms(A, norms, st));
+    }
 
     KBlockArgs base{};
     base.A = A;
@@ -537,15 +552,15 @@ kdcd_status enqueue_solve(const SolveArgs &sa, const Layout &L, char *wsbase, St
     if (A->format == KDCD_DENSE && sa.opt.compute == KDCD_F64 &&
         (int64_t)sa.s * sa.b >= kGatherMinSB) {
         base.pos = ws.at<int32_t>(L.pos);
-        KDCD_HIP_TRY(launch_fill_i32(base.pos, -1, A->m, st));
+        if (R.setup) KDCD_HIP_TRY(launch_fill_i32(base.pos, -1, A->m, st));
     }
     if (A->format == KDCD_CSR) {
         base.carry = ws.at<double>(L.carry);
         base.csr_panel = ws.at<void>(L.panel);
-        KDCD_HIP_TRY(launch_csr_panel_init(A, base.csr_panel, st));
+        if (R.setup) KDCD_HIP_TRY(launch_csr_panel_init(A, base.csr_panel, st));
     }
     KBlockArgs kb;
-    rc = prepare_lowp(base, L, ws, st, kb);
+    rc = prepare_lowp(base, L, ws, st, kb, R.setup);
     if (rc != KDCD_OK) return rc;
 
     const bool monitor = sa.opt.monitor_every > 0;
@@ -567,15 +582,21 @@ kdcd_status enqueue_solve(const SolveArgs &sa, const Layout &L, char *wsbase, St
     int64_t snap = 0;
     std::unique_ptr<StopPoller> poll;
     if (monitor) poll.reset(new StopPoller(n_outer / sa.opt.monitor_every + 1));
-    int64_t k = 0;
-    for (; k < n_outer; ++k) {
+    int64_t k = R.k_begin;
+    const int64_t k_end = R.k_end < 0 ? n_outer : R.k_end;
+    const int64_t sb_full = (int64_t)sa.s * sa.b;
+    if (k > 0) {              // the block before the range (full): prevS of its first iteration
+        kb.S = R.S_base ? R.S_base : sa.idx + (k - 1) * sb_full;
+        kb.sb = (int32_t)sb_full;
+    }
+    for (; k < k_end; ++k) {
         if (monitor && k > 0 && k % sa.opt.monitor_every == 0 &&
             poll->stopped(k / sa.opt.monitor_every - 1))
             break;
         const int64_t done = k * sa.s;
         const int32_t sk = (int32_t)std::min<int64_t>(sa.s, sa.H - done);
         const int32_t sb = sk * sa.b;
-        const int32_t *S = sa.idx + done * sa.b;
+        const int32_t *S = R.S_base ? R.S_base + (k - R.k_begin + 1) * sb_full : sa.idx + done * sa.b;
         kb.prevS = kb.S;          // the previous block (null before the first)
         kb.prev_sb = kb.sb;
         kb.S = S;
@@ -701,7 +722,7 @@ kdcd_status enqueue_solve(const SolveArgs &sa, const Layout &L, char *wsbase, St
         }
     }
     // stopped early: the snapshots not yet taken all hold the final iterate
-    if (k < n_outer && sa.opt.snapshot_every > 0 && sa.opt.snapshots) {
+    if (R.k_end < 0 && k < n_outer && sa.opt.snapshot_every > 0 && sa.opt.snapshots) {
         const int64_t rows = (n_outer + sa.opt.snapshot_every - 1) / sa.opt.snapshot_every;
         for (; snap < rows; ++snap)
             KDCD_HIP_TRY(hipMemcpyAsync(sa.opt.snapshots + snap * A->m, sa.alpha,
@@ -768,65 +789,90 @@ struct KeyBuilder {
     }
 };
 
-// prepare(base): synchronous set-up before the capture (host-to-device copies
-// of data the graph reads); enqueue(base, stream): the work to capture.
+// The cache entry of `key` on the current device, captured and instantiated
+// on first use (with c.mu held): prepare(base) is synchronous set-up before
+// the capture (host-to-device copies of data the graph reads); enqueue(base,
+// stream) is the work to capture.
+GraphEntry *graph_entry(GraphCache &c, const std::string &key, size_t bytes,
+                        const kdcd_options &opt,
+                        const std::function<kdcd_status(char *)> &prepare,
+                        const std::function<kdcd_status(char *, hipStream_t)> &enqueue,
+                        kdcd_status &rc)
+{
+    rc = KDCD_OK;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+        rc = KDCD_ERR_HIP;
+        return nullptr;
+    }
+    for (auto &x : c.entries)
+        if (x.device == dev && x.key == key) {
+            x.used = ++c.tick;
+            return &x;
+        }
+    if (!c.capture[dev] &&
+        hipStreamCreateWithFlags(&c.capture[dev], hipStreamNonBlocking) != hipSuccess) {
+        rc = KDCD_ERR_HIP;
+        return nullptr;
+    }
+    GraphEntry ne;
+    ne.key = key;
+    ne.device = dev;
+    if (opt.workspace) {
+        if (opt.workspace_bytes < bytes) rc = KDCD_ERR_WORKSPACE;
+        else if (reinterpret_cast<uintptr_t>(opt.workspace) & 255) rc = KDCD_ERR_INVALID_ARG;
+        else ne.ws = static_cast<char *>(opt.workspace);
+        if (rc != KDCD_OK) return nullptr;
+    } else {
+        void *p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess || !p) {
+            rc = KDCD_ERR_ALLOC;
+            return nullptr;
+        }
+        ne.ws = static_cast<char *>(p);
+        ne.owned = true;
+    }
+    rc = prepare ? prepare(ne.ws) : KDCD_OK;
+    hipGraph_t g = nullptr;
+    if (rc == KDCD_OK) {
+        if (hipStreamBeginCapture(c.capture[dev], hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            rc = KDCD_ERR_HIP;
+        } else {
+            rc = enqueue(ne.ws, c.capture[dev]);
+            const hipError_t ce = hipStreamEndCapture(c.capture[dev], &g);
+            if (rc == KDCD_OK && ce != hipSuccess) rc = KDCD_ERR_HIP;
+        }
+    }
+    if (rc == KDCD_OK && hipGraphInstantiate(&ne.exec, g, nullptr, nullptr, 0) != hipSuccess)
+        rc = KDCD_ERR_HIP;
+    if (g) (void)hipGraphDestroy(g);
+    if (rc != KDCD_OK) {
+        drop_entry(ne);
+        return nullptr;
+    }
+    if (c.entries.size() >= kGraphCacheSize) {   // least recently used goes
+        size_t lru = 0;
+        for (size_t i = 1; i < c.entries.size(); ++i)
+            if (c.entries[i].used < c.entries[lru].used) lru = i;
+        drop_entry(c.entries[lru]);
+        c.entries.erase(c.entries.begin() + (std::ptrdiff_t)lru);
+    }
+    ne.used = ++c.tick;
+    c.entries.push_back(ne);
+    return &c.entries.back();
+}
+
+// A whole call captured as one graph and replayed by calls with identical
+// arguments.
 kdcd_status run_graph(const std::string &key, size_t bytes, const kdcd_options &opt,
                       hipStream_t st, const std::function<kdcd_status(char *)> &prepare,
                       const std::function<kdcd_status(char *, hipStream_t)> &enqueue)
 {
     GraphCache &c = graph_cache();
     std::lock_guard<std::mutex> lk(c.mu);
-    int dev = -1;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return KDCD_ERR_HIP;
-    GraphEntry *e = nullptr;
-    for (auto &x : c.entries)
-        if (x.device == dev && x.key == key) e = &x;
-    if (!e) {
-        if (!c.capture[dev] &&
-            hipStreamCreateWithFlags(&c.capture[dev], hipStreamNonBlocking) != hipSuccess)
-            return KDCD_ERR_HIP;
-        GraphEntry ne;
-        ne.key = key;
-        ne.device = dev;
-        if (opt.workspace) {
-            if (opt.workspace_bytes < bytes) return KDCD_ERR_WORKSPACE;
-            if (reinterpret_cast<uintptr_t>(opt.workspace) & 255) return KDCD_ERR_INVALID_ARG;
-            ne.ws = static_cast<char *>(opt.workspace);
-        } else {
-            void *p = nullptr;
-            if (hipMalloc(&p, bytes) != hipSuccess || !p) return KDCD_ERR_ALLOC;
-            ne.ws = static_cast<char *>(p);
-            ne.owned = true;
-        }
-        kdcd_status rc = prepare ? prepare(ne.ws) : KDCD_OK;
-        hipGraph_t g = nullptr;
-        if (rc == KDCD_OK) {
-            if (hipStreamBeginCapture(c.capture[dev], hipStreamCaptureModeThreadLocal) != hipSuccess) {
-                rc = KDCD_ERR_HIP;
-            } else {
-                rc = enqueue(ne.ws, c.capture[dev]);
-                const hipError_t ce = hipStreamEndCapture(c.capture[dev], &g);
-                if (rc == KDCD_OK && ce != hipSuccess) rc = KDCD_ERR_HIP;
-            }
-        }
-        if (rc == KDCD_OK && hipGraphInstantiate(&ne.exec, g, nullptr, nullptr, 0) != hipSuccess)
-            rc = KDCD_ERR_HIP;
-        if (g) (void)hipGraphDestroy(g);
-        if (rc != KDCD_OK) {
-            drop_entry(ne);
-            return rc;
-        }
-        if (c.entries.size() >= kGraphCacheSize) {   // least recently used goes
-            size_t lru = 0;
-            for (size_t i = 1; i < c.entries.size(); ++i)
-                if (c.entries[i].used < c.entries[lru].used) lru = i;
-            drop_entry(c.entries[lru]);
-            c.entries.erase(c.entries.begin() + (std::ptrdiff_t)lru);
-        }
-        c.entries.push_back(ne);
-        e = &c.entries.back();
-    }
-    e->used = ++c.tick;
+    kdcd_status rc = KDCD_OK;
+    GraphEntry *e = graph_entry(c, key, bytes, opt, prepare, enqueue, rc);
+    if (!e) return rc;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (opt.profile) {
         (void)hipEventCreate(&e0);
@@ -835,7 +881,7 @@ kdcd_status run_graph(const std::string &key, size_t bytes, const kdcd_options &
     }
     if (hipGraphLaunch(e->exec, st) != hipSuccess) return KDCD_ERR_HIP;
     if (opt.profile) (void)hipEventRecord(e1, st);
-    const kdcd_status rc = read_status(reinterpret_cast<int32_t *>(e->ws), st);
+    rc = read_status(reinterpret_cast<int32_t *>(e->ws), st);
     if (opt.profile) {
         float ms = 0.f;
         (void)hipEventElapsedTime(&ms, e0, e1);
@@ -874,6 +920,76 @@ kdcd_status check_monitor(const kdcd_matrix *A, const kdcd_options &o)
     return KDCD_OK;
 }
 
+// Graph replay by windows of kGraphWindow outer iterations: one graph holds a
+// window -- a kernel that copies the window's index blocks from idx into a
+// buffer, the block index taken from a counter in device memory and moved on
+// by the same kernel, then the window's launches reading that buffer -- and
+// is replayed window after window; the set-up, the first outer iteration and
+// the iterations after the last whole window (the ragged one included) run
+// eagerly around the replays, in the graph's own workspace.  The graph does
+// not depend on H or on the index values, so calls that differ only in those
+// share it.  Used for solves without trace or snapshots and with at least
+// kGraphWindow + 2 whole blocks; returns KDCD_ERR_UNSUPPORTED otherwise (the
+// whole call is then captured instead).
+constexpr int32_t kGraphWindow = 16;
+
+kdcd_status run_graph_windowed(const SolveArgs &sa, const Layout &L)
+{
+    const int64_t sbw = (int64_t)sa.s * sa.b;
+    const int64_t n_full = sa.H / sa.s;
+    if (sa.opt.trace || sa.opt.snapshot_every > 0 || sa.opt.workspace || sa.opt.profile ||
+        n_full < kGraphWindow + 2)
+        return KDCD_ERR_UNSUPPORTED;
+    const int64_t nwin = (n_full - 2) / kGraphWindow;
+    const size_t o_cnt = L.total;
+    const size_t o_win = o_cnt + 256;
+    const size_t bytes = o_win + align256(sizeof(int32_t) * (size_t)((kGraphWindow + 2) * sbw));
+    KeyBuilder kb;
+    kb.add('W');
+    kb.add(sa.problem);
+    kb.matrix(sa.A);
+    kb.add(sa.y);
+    kb.kernel(sa.kernel);
+    kb.add(sa.C); kb.add(sa.lambda); kb.add(sa.b); kb.add(sa.s);
+    kb.add(sa.idx); kb.add(sa.alpha);
+    kb.options(sa.opt);
+    GraphCache &c = graph_cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    kdcd_status rc = KDCD_OK;
+    GraphEntry *e = graph_entry(
+        c, kb.k, bytes, sa.opt, nullptr,
+        [&](char *base, hipStream_t cs) {
+            int64_t *cnt = reinterpret_cast<int64_t *>(base + o_cnt);
+            int32_t *win = reinterpret_cast<int32_t *>(base + o_win);
+            KDCD_HIP_TRY(launch_window_advance(sa.idx, cnt, win, kGraphWindow, (int32_t)sbw, cs));
+            SolveArgs g = sa;
+            g.st = cs;
+            StageTimer off;
+            SolveRange R;
+            R.k_begin = 1;
+            R.k_end = 1 + kGraphWindow;
+            R.setup = false;
+            R.S_base = win;
+            return enqueue_solve(g, L, base, off, R);
+        },
+        rc);
+    if (!e) return rc;
+    StageTimer off;
+    SolveRange head;                       // set-up and the first outer iteration
+    head.k_end = 1;
+    if ((rc = enqueue_solve(sa, L, e->ws, off, head)) != KDCD_OK) return rc;
+    int32_t *cnt = reinterpret_cast<int32_t *>(e->ws + o_cnt);   // the counter's two words: 1, 0
+    KDCD_HIP_TRY(launch_fill_i32(cnt, 1, 1, sa.st));
+    KDCD_HIP_TRY(launch_fill_i32(cnt + 1, 0, 1, sa.st));
+    for (int64_t w = 0; w < nwin; ++w)
+        if (hipGraphLaunch(e->exec, sa.st) != hipSuccess) return KDCD_ERR_HIP;
+    SolveRange tail;
+    tail.k_begin = 1 + nwin * kGraphWindow;
+    tail.setup = false;
+    if ((rc = enqueue_solve(sa, L, e->ws, off, tail)) != KDCD_OK) return rc;
+    return read_status(reinterpret_cast<int32_t *>(e->ws + L.status), sa.st);
+}
+
 kdcd_status run_solve(const SolveArgs &sa)
 {
     kdcd_status rc = check_monitor(sa.A, sa.opt);
@@ -881,6 +997,8 @@ kdcd_status run_solve(const SolveArgs &sa)
     Layout L = make_layout(sa.problem, sa.A, sa.kernel, sa.b, sa.s, sa.opt.compute);
     if (sa.opt.monitor_every > 0) add_monitor(L, sa.A->m, (int64_t)sa.s * sa.b);
     if (sa.opt.flags & KDCD_FLAG_GRAPH) {
+        rc = run_graph_windowed(sa, L);
+        if (rc != KDCD_ERR_UNSUPPORTED) return rc;
         KeyBuilder kb;
         kb.add('S');
         kb.add(sa.problem);

@@ -147,3 +147,46 @@ def test_sampled_solve_refuses_graph(K):
     with pytest.raises(K.KdcdError) as e:
         K.kdcd_ksvm_solve_sampled(A, y, (2, 1.0, 0.0, 1), 1.0, 8, 16, a, flags=K.FLAG_GRAPH)
     assert e.value.status == -2
+
+
+def _csr(K, c):
+    return K.CSR(torch.as_tensor(c["row_ptr"]).cuda(), torch.as_tensor(c["col_idx"]).cuda(),
+                 torch.as_tensor(c["val"]).cuda(), c["m"], c["n"])
+
+
+@pytest.mark.parametrize("case", ["krr_f64", "krr_bf16x3", "ksvm_f64", "ksvm_csr"])
+def test_windowed_graph_equals_eager(K, case):
+    """Solves with at least 18 whole blocks replay a graph of 16 outer
+    iterations window after window (the index blocks copied on the device from
+    a counter): every result equals the eager solve bit for bit, also for a
+    later call with another H and other index values in the same buffer (the
+    same graph), with eager work and synchronisations in between."""
+    if case.startswith("krr"):
+        d = inputs.dense_krr_c2(m=2500, n=64, seed=5)
+        A, y, m = dev(d["A"]), dev(d["y"]), 2500
+        b, s, kern, par = 8, 16, (2, 1.0, 0.0, 1), 1e-3
+        comp = "bf16x3" if case.endswith("bf16x3") else "f64"
+        solve = lambda H, idx, a, **kw: K.kdcd_krr_solve(A, y, kern, par, b, s, H, idx, a,
+                                                         compute=comp, **kw)
+        draw = lambda H, seed: inputs.krr_indices(m, b, H, seed=seed)
+    else:
+        if case == "ksvm_csr":
+            c = inputs.csr_ksvm_c3(m=3000, n=2000, nnz_per_row=20, seed=31)
+            A, y, m, kern, s = _csr(K, c), dev(c["y"]), 3000, (1, 0.0, 1.0, 3), 32
+        else:
+            d = inputs.dense_ksvm_c1(m=2000, n=64, seed=5)
+            A, y, m, kern, s = dev(d["A"]), dev(d["y"]), 2000, (2, 1.0, 0.0, 1), 8
+        b, par = 1, 1.0
+        solve = lambda H, idx, a, **kw: K.kdcd_ksvm_solve(A, y, kern, par, b, s, H, idx, a, **kw)
+        draw = lambda H, seed: inputs.ksvm_indices(m, H, seed=seed)
+    Hmax = s * 60
+    buf = idx_dev(draw(Hmax, 1))
+    g = torch.zeros(m, dtype=torch.float64, device="cuda")
+    for H, seed in ((s * 40 + 3, 1), (s * 57, 2), (s * 18, 3), (s * 40 + 3, 1)):
+        buf.copy_(idx_dev(draw(Hmax, seed)))
+        eager = torch.zeros(m, dtype=torch.float64, device="cuda")
+        solve(H, buf, eager)
+        g.zero_()
+        solve(H, buf, g, flags=K.FLAG_GRAPH)
+        torch.cuda.synchronize()
+        assert torch.equal(g, eager), (case, H, seed)
