@@ -167,8 +167,13 @@ typedef struct {
 
 /*
  * Convergence monitor (monitor_every > 0; kdcd_ksvm_solve / kdcd_krr_solve on
- * dense A in FP64, BF16, FP16 or BF16X3, on CSR A in FP64, and
- * kdcd_ksvm_solve_sampled; not with KDCD_FLAG_GRAPH, not in FP32).  With a
+ * dense A in FP64, BF16, FP16 or BF16X3, on CSR A in FP64,
+ * kdcd_ksvm_solve_sampled, and kdcd_batch_solve in FP64; not with
+ * KDCD_FLAG_GRAPH, not in FP32).  A batch keeps every problem's dual vector
+ * (one pass over each sigma group's stored block updates all of the group's
+ * problems), evaluates every problem's bound and stops once the largest is
+ * <= tol; rel_err and the log report that largest bound (objective: the sum
+ * of the problems').  With a
  * low-precision compute the gradient is carried with the kernel values the
  * product computed, so the bound certifies the problem with those values (the
  * exact problem's objective differs by the kernel's rounding).

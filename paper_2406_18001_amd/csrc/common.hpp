@@ -168,6 +168,8 @@ struct KBlockArgs {
     // CSR only: m + s*b doubles of scratch for sampled rows longer than the
     // LDS panel (their dot products are summed over pieces); null refuses them
     double *carry;
+    // batched FP64 with the monitor: U of sigma group g at U + g * u_gstride
+    int64_t u_gstride = 0;
     // CSR only: the dense-head panel (kblock_csr_panel_bytes(n) bytes, prepared
     // once with launch_csr_panel_init); null keeps the broadcast kernels
     void *csr_panel = nullptr;
@@ -286,6 +288,24 @@ hipError_t launch_dual_update(const double *U, int64_t m, int32_t sb, const int3
                               const double *wscale, double diag, double *v, const int32_t *stop,
                               hipStream_t st);
 size_t monitor_partial_bytes();
+// Batched gradient upkeep: one pass over U (sb x m, one sigma group) updates
+// the dual vectors of every problem of the group, each with its own
+// parameters (as launch_dual_update).
+struct DualBatchDesc {
+    int32_t n;
+    const double *theta[kMaxProblems];
+    const double *vscale[kMaxProblems];
+    const double *wscale[kMaxProblems];
+    double uscale[kMaxProblems];
+    double diag[kMaxProblems];
+    double *v[kMaxProblems];
+};
+hipError_t launch_dual_update_batch(const double *U, int64_t m, int32_t sb, const int32_t *S,
+                                    const DualBatchDesc &d, const int32_t *stop, hipStream_t st);
+// Batched monitor: the batch state takes the largest of the problems' last
+// bounds (their states at mons[0 .. n)), stops once it is <= tol, and logs.
+hipError_t launch_monitor_combine(const MonitorState *mons, int32_t n, double tol, int64_t outer,
+                                  MonitorState *batch, hipStream_t st);
 hipError_t launch_monitor(int32_t problem, int64_t m, const double *alpha, const double *y,
                           const double *v, double omega, int32_t loss, double C, double tol,
                           int64_t outer, double *part, MonitorState *mon, hipStream_t st);

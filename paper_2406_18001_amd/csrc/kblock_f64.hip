@@ -59,7 +59,7 @@ void kblock_f64_kernel(
     double *__restrict__ partial, double *__restrict__ W, int32_t n_u_tiles,
     int32_t n_row_groups, int32_t n_w_tiles, int32_t n_tiles_n, int32_t aligned,
     const BatchDesc *__restrict__ bd, double *__restrict__ U, const int32_t *__restrict__ stop,
-    const int32_t *__restrict__ pos)
+    const int32_t *__restrict__ pos, int64_t u_gstride)
 {
     if (stop && *stop) return;   // the solve has converged
     constexpr int NT = 64 * WM * WN;
@@ -328,6 +328,20 @@ void kblock_f64_kernel(
                         }
                     continue;
                 }
+                if (U) {             // the monitor's stored kernel block of group g
+#pragma unroll
+                    for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int64_t grow = row0 + (wm * TM + tm) * 16 + (lane >> 4) + 4 * v;
+#pragma unroll
+                            for (int tn = 0; tn < TN; ++tn) {
+                                const int64_t gcol = col0 + (wn * TN + tn) * 16 + (lane & 15);
+                                if (grow < m && colok[tn])
+                                    U[(int64_t)g * u_gstride + gcol * m + grow] = kv[tm][v][tn];
+                            }
+                        }
+                }
                 for (int p = 0; p < np; ++p) {
                     if (bd->group[p] != g) continue;
                     double bv[TM][4];
@@ -477,8 +491,8 @@ hipError_t launch_cfg(const KBlockArgs &a, hipStream_t st)
     KDCD_TIMED_LAUNCH((kblock_f64_kernel<WM, WN, TM, TN, KIND, BATCH, FULL, OCC>), grid, block, 0, st, \
                        A->values, A->ld, A->m, A->n, a.S, a.sb, a.norms, a.kp, a.beta,          \
                        a.beta_scale, a.partial, a.W, (int32_t)n_u, (int32_t)groups,            \
-                       (int32_t)n_w, (int32_t)n_n, aligned, a.batch, BATCH ? nullptr : a.U,   \
-                       a.stop, BATCH ? nullptr : a.pos)
+                       (int32_t)n_w, (int32_t)n_n, aligned, a.batch, a.U, a.stop,              \
+                       BATCH ? nullptr : a.pos, a.u_gstride)
 #define KDCD_LAUNCH(KIND)                                                                      \
     do {                                                                                        \
         if (full) KDCD_LAUNCH_F(KIND, true);                                                    \

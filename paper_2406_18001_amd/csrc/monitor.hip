@@ -51,6 +51,51 @@ __global__ __launch_bounds__(256) void dual_update_kernel(
     }
 }
 
+// The batched form: one pass over U updates up to DB_MAX problems of a sigma
+// group (their weights w_p = wscale_p * theta_p and updates theta_p staged in
+// LDS); problems [p0, p0 + n) of the descriptor.
+constexpr int DB_MAX = 8;
+__global__ __launch_bounds__(256) void dual_update_batch_kernel(
+    const double *__restrict__ U, int64_t m, int32_t sb, const int32_t *__restrict__ S,
+    const DualBatchDesc d, int32_t p0, int32_t n, const int32_t *__restrict__ stop)
+{
+    extern __shared__ double dsh[];              // w [n][sb], th [n][sb], then S
+    if (stop && *stop) return;
+    double *w = dsh, *th = dsh + (size_t)n * sb;
+    int32_t *Sl = reinterpret_cast<int32_t *>(th + (size_t)n * sb);
+    for (int t = threadIdx.x; t < sb; t += blockDim.x) Sl[t] = S[t];
+    for (int x = threadIdx.x; x < n * sb; x += blockDim.x) {
+        const int q = x / sb, t = x - q * sb;
+        const double tv = d.theta[p0 + q][t];
+        th[x] = tv;
+        w[x] = (d.wscale[p0 + q] ? d.wscale[p0 + q][S[t]] : 1.0) * tv;
+    }
+    __syncthreads();
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double acc[DB_MAX], da[DB_MAX];
+#pragma unroll
+        for (int q = 0; q < DB_MAX; ++q) acc[q] = da[q] = 0.0;
+        for (int t = 0; t < sb; ++t) {
+            const double u = U[(int64_t)t * m + i];
+            const bool hit = Sl[t] == (int32_t)i;
+#pragma unroll
+            for (int q = 0; q < DB_MAX; ++q) {
+                if (q < n) {
+                    acc[q] = fma(u, w[q * sb + t], acc[q]);
+                    if (hit) da[q] += th[q * sb + t];
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < DB_MAX; ++q) {
+            if (q >= n) break;
+            const int p = p0 + q;
+            d.v[p][i] += (d.vscale[p] ? d.vscale[p][i] : 1.0) * d.uscale[p] * acc[q] + d.diag[p] * da[q];
+        }
+    }
+}
+
 // Block tree reduction of NV values per thread into out[blockIdx.x * NV + q].
 template <int NV>
 __device__ __forceinline__ void block_sums(double (&x)[NV], double *out)
@@ -129,6 +174,32 @@ __global__ __launch_bounds__(64) void monitor_final_kernel(int32_t problem, int6
     if (rel <= tol) mon->stop = 1;
 }
 
+__global__ __launch_bounds__(64) void monitor_combine_kernel(const MonitorState *__restrict__ mons,
+                                                             int32_t n, double tol, int64_t outer,
+                                                             MonitorState *__restrict__ mon)
+{
+    if (threadIdx.x != 0 || mon->stop) return;
+    double rel = 0.0, f = 0.0;
+    for (int p = 0; p < n; ++p) {
+        const double r = mons[p].rel;
+        if (!(r <= rel)) rel = r;          // NaN propagates
+        f += mons[p].f;
+    }
+    mon->rel = rel;
+    mon->f = f;
+    mon->outer_done = outer;
+    const int64_t i = mon->nlog;
+    if (mon->log && i < mon->log_len) {
+        double *r = mon->log + 4 * i;
+        r[0] = (double)outer;
+        r[1] = rel;
+        r[2] = f;
+        r[3] = (double)(wall_clock64() - mon->t0) * mon->tick;
+    }
+    mon->nlog = i + 1;
+    if (rel <= tol) mon->stop = 1;
+}
+
 __global__ void monitor_start_kernel(MonitorState *mon, double *log, int64_t log_len, double tick)
 {
     if (threadIdx.x != 0) return;
@@ -170,6 +241,30 @@ hipError_t launch_dual_update(const double *U, int64_t m, int32_t sb, const int3
 }
 
 size_t monitor_partial_bytes() { return sizeof(double) * 4 * MON_BLOCKS; }
+
+hipError_t launch_dual_update_batch(const double *U, int64_t m, int32_t sb, const int32_t *S,
+                                    const DualBatchDesc &d, const int32_t *stop, hipStream_t st)
+{
+    if (d.n < 1 || d.n > kMaxProblems || sb < 1 || sb > kMaxSB) return hipErrorInvalidValue;
+    // problems per launch: at most DB_MAX, and their staged values within 64 KiB
+    const int fit = (int)((65536 - sizeof(int32_t) * (size_t)sb) / (2 * sizeof(double) * (size_t)sb));
+    const int per = std::max(1, std::min(DB_MAX, fit));
+    const int64_t blocks = std::min<int64_t>((m + 255) / 256, 2048);
+    for (int p0 = 0; p0 < d.n; p0 += per) {
+        const int n = std::min(per, d.n - p0);
+        const size_t shm = sizeof(double) * 2 * (size_t)n * sb + sizeof(int32_t) * (size_t)sb;
+        hipLaunchKernelGGL(dual_update_batch_kernel, dim3((unsigned)std::max<int64_t>(blocks, 1)),
+                           dim3(256), shm, st, U, m, sb, S, d, p0, n, stop);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_monitor_combine(const MonitorState *mons, int32_t n, double tol, int64_t outer,
+                                  MonitorState *batch, hipStream_t st)
+{
+    hipLaunchKernelGGL(monitor_combine_kernel, dim3(1), dim3(64), 0, st, mons, n, tol, outer, batch);
+    return hipGetLastError();
+}
 
 hipError_t launch_monitor_start(MonitorState *mon, double *log, int64_t log_len, hipStream_t st)
 {

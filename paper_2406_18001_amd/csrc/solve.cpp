@@ -1119,6 +1119,9 @@ kdcd_status kdcd_batch_solve(const kdcd_matrix *A, const kdcd_kernel *kernel, in
     if ((rc = check_compute(A, o.compute)) != KDCD_OK) return rc;
     if (A->format != KDCD_DENSE) return KDCD_ERR_UNSUPPORTED;
     if (o.snapshot_every != 0 || o.trace) return KDCD_ERR_INVALID_ARG;   // per problem instead
+    if ((rc = check_monitor(A, o)) != KDCD_OK) return rc;
+    const bool monitor = o.monitor_every > 0;
+    if (monitor && o.compute != KDCD_F64) return KDCD_ERR_UNSUPPORTED;   // FP64 stores U
 
     // sigma groups and problem lists
     BatchDesc bd{};
@@ -1142,6 +1145,19 @@ kdcd_status kdcd_batch_solve(const kdcd_matrix *A, const kdcd_kernel *kernel, in
     const size_t o_r = off; off += align256(sizeof(double) * (size_t)(n_problems * sbmax));
     const size_t o_W = off; off += align256(sizeof(double) * (size_t)(bd.ngroups * sbmax * sbmax));
     const size_t o_D = off; off += align256(sizeof(double) * (size_t)(krr.size() * sbmax * b + 1));
+    // monitor: U per sigma group, per problem the dual vector, the updates, a
+    // state and partial sums; the batch's state; an m-vector of scratch
+    size_t o_U = 0, o_v = 0, o_th = 0, o_mons = 0, o_mpart = 0, o_mon = 0, o_tmp = 0;
+    const int64_t m = A->m;
+    if (monitor) {
+        o_U = off; off += align256(sizeof(double) * (size_t)(bd.ngroups * sbmax * m));
+        o_v = off; off += align256(sizeof(double) * (size_t)(n_problems * m));
+        o_th = off; off += align256(sizeof(double) * (size_t)(n_problems * sbmax));
+        o_mons = off; off += align256(sizeof(MonitorState) * (size_t)n_problems);
+        o_mpart = off; off += align256(monitor_partial_bytes() * (size_t)n_problems);
+        o_mon = off; off += 256;
+        o_tmp = off; off += align256(sizeof(double) * (size_t)m);
+    }
     L.total = off;
 
     // the work of the call on stream cs in the workspace at wsbase; in graph
@@ -1184,7 +1200,36 @@ kdcd_status kdcd_batch_solve(const kdcd_matrix *A, const kdcd_kernel *kernel, in
     if ((rc = prepare_lowp(base, L, ws, st, kb)) != KDCD_OK) return rc;
 
     const int64_t n_outer = (H + s - 1) / s;
-    for (int64_t k = 0; k < n_outer; ++k) {
+    MonitorState *mons = monitor ? ws.at<MonitorState>(o_mons) : nullptr;
+    MonitorState *bmon = monitor ? ws.at<MonitorState>(o_mon) : nullptr;
+    double *mon_th = monitor ? ws.at<double>(o_th) : nullptr;
+    std::unique_ptr<StopPoller> poll;
+    if (monitor) {
+        KDCD_HIP_TRY(launch_fill_i32(reinterpret_cast<int32_t *>(mons), 0,
+                                     (int64_t)(sizeof(MonitorState) / 4) * n_problems, st));
+        KDCD_HIP_TRY(launch_fill_i32(reinterpret_cast<int32_t *>(bmon), 0,
+                                     (int64_t)(sizeof(MonitorState) / 4), st));
+        KDCD_HIP_TRY(launch_monitor_start(bmon, o.monitor_log, o.monitor_log_len, st));
+        for (int p = 0; p < n_problems; ++p) {
+            const kdcd_batch_problem &q = problems[p];
+            kdcd_kernel kp = *kernel;
+            kp.sigma = q.sigma;
+            const double om = (q.problem == 0 && q.loss == 2) ? 1.0 / (2.0 * q.param) : 0.0;
+            rc = init_dual_vector(q.problem == 0 ? 0 : 1, A, &kp, q.y, q.alpha, om, q.param,
+                                  ws.at<double>(o_v) + (int64_t)p * m, ws.at<double>(o_tmp),
+                                  &bmon->pad, st);
+            if (rc != KDCD_OK) return rc;
+        }
+        kb.U = ws.at<double>(o_U);
+        kb.u_gstride = sbmax * m;
+        kb.stop = &bmon->stop;
+        poll.reset(new StopPoller(n_outer / o.monitor_every + 1));
+    }
+    const int32_t *stop = monitor ? &bmon->stop : nullptr;
+    int64_t k = 0;
+    for (; k < n_outer; ++k) {
+        if (monitor && k > 0 && k % o.monitor_every == 0 && poll->stopped(k / o.monitor_every - 1))
+            break;
         const int64_t done = k * s;
         const int32_t sk = (int32_t)std::min<int64_t>(s, H - done);
         const int32_t sb = sk * b;
@@ -1201,6 +1246,7 @@ kdcd_status kdcd_batch_solve(const kdcd_matrix *A, const kdcd_kernel *kernel, in
         fd.nprob = n_problems;
         fd.nkrr = (int32_t)krr.size();
         fd.groups = groups;
+        fd.stop = stop;
         for (int p = 0; p < n_problems; ++p) {
             fd.partial[p] = partial + (int64_t)p * groups * sb;
             fd.r[p] = r + (int64_t)p * sb;
@@ -1224,9 +1270,11 @@ kdcd_status kdcd_batch_solve(const kdcd_matrix *A, const kdcd_kernel *kernel, in
                 rd.Dinv[kk] = Dinv + (int64_t)kk * sb * b;
                 rd.y[kk] = problems[p].y;
                 rd.alpha[kk] = problems[p].alpha;
-                rd.trace[kk] = problems[p].trace ? problems[p].trace + done * b : nullptr;
+                rd.trace[kk] = problems[p].trace ? problems[p].trace + done * b
+                                                 : (monitor ? mon_th + (int64_t)p * sbmax : nullptr);
                 rd.lambda[kk] = problems[p].param;
             }
+            rd.stop = stop;
             KDCD_HIP_TRY(launch_krr_recur(rd, (int32_t)krr.size(), S, b, sk, A->m, (double)A->m,
                                           status, st));
         }
@@ -1239,14 +1287,57 @@ kdcd_status kdcd_batch_solve(const kdcd_matrix *A, const kdcd_kernel *kernel, in
                 kd.W[qq] = W + (int64_t)bd.group[p] * sb * sb;
                 kd.y[qq] = q.y;
                 kd.alpha[qq] = q.alpha;
-                kd.trace[qq] = q.trace ? q.trace + done * b : nullptr;
+                kd.trace[qq] = q.trace ? q.trace + done * b
+                                       : (monitor ? mon_th + (int64_t)p * sbmax : nullptr);
                 kd.nu[qq] = q.loss == 2 ? INFINITY : q.param;
                 kd.omega[qq] = q.loss == 2 ? 1.0 / (2.0 * q.param) : 0.0;
             }
+            kd.stop = stop;
             KDCD_HIP_TRY(launch_ksvm_recur(kd, (int32_t)svm.size(), S, sb, A->m, status, st));
         }
         timer.end(2, st);
+        if (monitor) {
+            // every sigma group's problems from one pass over its stored block
+            for (int g = 0; g < bd.ngroups; ++g) {
+                DualBatchDesc dd{};
+                for (int p = 0; p < n_problems; ++p) {
+                    if (bd.group[p] != g) continue;
+                    const kdcd_batch_problem &q = problems[p];
+                    const int i = dd.n++;
+                    dd.theta[i] = q.trace ? q.trace + done * b : mon_th + (int64_t)p * sbmax;
+                    dd.v[i] = ws.at<double>(o_v) + (int64_t)p * m;
+                    if (q.problem == 0) {
+                        dd.vscale[i] = q.y;
+                        dd.wscale[i] = q.y;
+                        dd.uscale[i] = 1.0;
+                        dd.diag[i] = q.loss == 2 ? 1.0 / (2.0 * q.param) : 0.0;
+                    } else {
+                        dd.uscale[i] = -1.0 / q.param;
+                        dd.diag[i] = -(double)m;
+                    }
+                }
+                if (dd.n > 0)
+                    KDCD_HIP_TRY(launch_dual_update_batch(ws.at<double>(o_U) + (int64_t)g * sbmax * m,
+                                                          m, sb, S, dd, stop, st));
+            }
+            if ((k + 1) % o.monitor_every == 0 || k + 1 == n_outer) {
+                for (int p = 0; p < n_problems; ++p) {
+                    const kdcd_batch_problem &q = problems[p];
+                    const double om = (q.problem == 0 && q.loss == 2) ? 1.0 / (2.0 * q.param) : 0.0;
+                    // each problem's bound (never its own stop); the batch stops on the largest
+                    KDCD_HIP_TRY(launch_monitor(q.problem == 0 ? 0 : 1, m, q.alpha, q.y,
+                                                ws.at<double>(o_v) + (int64_t)p * m, om,
+                                                q.loss == 2 ? 2 : 1, q.param, -1.0, k + 1,
+                                                reinterpret_cast<double *>(ws.at<char>(o_mpart) +
+                                                                           monitor_partial_bytes() * p),
+                                                mons + p, st));
+                }
+                KDCD_HIP_TRY(launch_monitor_combine(mons, n_problems, o.tol, k + 1, bmon, st));
+                KDCD_HIP_TRY(poll->post((k + 1) / o.monitor_every - 1, bmon, st));
+            }
+        }
     }
+    if (monitor) rc = report_monitor(o, bmon, n_outer, st);
     return rc;
     };
 

@@ -408,23 +408,27 @@ class BatchProblem(NamedTuple):
 
 
 def kdcd_batch_solve(A, kernel, b, s, H, idx, problems, *, compute="f64", workspace=None,
-                     profile=False, flags=0, stream=None):
+                     profile=False, flags=0, stream=None, monitor_every=0, tol=0.0,
+                     monitor_log=False):
     """Batched s-step solves sharing every kernel-block product: K-RR problem p
     equals kdcd_krr_solve(..., b, s, H, ...) and K-SVM problem q equals
-    kdcd_ksvm_solve(..., 1, s*b, H*b, ...) over the same idx."""
+    kdcd_ksvm_solve(..., 1, s*b, H*b, ...) over the same idx.  With the monitor
+    (FP64) the batch stops once every problem's certified bound is <= tol; the
+    result's rel_err is the largest bound."""
     mat, m, _ = _matrix(A)
     _dev(idx, torch.int32, int(H) * int(b), "idx")
     arr = _batch_array(problems, m, H, b)
-    opt, prof = _options(compute, 1, 0, None, None, workspace, profile, flags, m, 0, 0)
+    n_outer = -(-int(H) // max(int(s), 1))
+    mon = _MonitorOut(n_outer, int(monitor_every), monitor_log) if monitor_every else None
+    opt, prof = _options(compute, 1, 0, None, None, workspace, profile, flags, m, n_outer, 0,
+                         monitor_every, tol, mon)
     kern = _kernel(kernel)
     st = _lib.kdcd_batch_solve(ctypes.byref(mat), ctypes.byref(kern), int(b), int(s), int(H),
                                idx.data_ptr(), arr, len(problems), ctypes.byref(opt),
                                _stream(stream))
     if st != 0:
         raise KdcdError(st, "kdcd_batch_solve")
-    if prof is not None:
-        return {f: getattr(prof, f) for f, _ in _Profile._fields_}
-    return None
+    return _result(prof, mon)
 
 
 def _batch_array(problems, m, H, b):

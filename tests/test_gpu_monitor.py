@@ -220,3 +220,60 @@ def test_lowp_monitor(K, compute, tol):
     K.kdcd_krr_solve(dev(d["A"]), dev(d["y"]), kern, 1e-3, b, s, k * s, idx_dev(idx[:k * s * b]),
                      plain, compute=compute)
     assert torch.equal(a, plain)
+
+
+def test_batch_monitor_value_and_early_stop(K):
+    """Batched solves (two K-RR and two K-SVM problems over two sigma groups,
+    FP64): the batch's bound is the largest of the problems' certified bounds
+    (each against the oracle), the log follows it, and a stop at a logged
+    bound equals a plain batched solve of the reported outer iterations, every
+    problem bit for bit."""
+    d = inputs.dense_ksvm_c1(m=1500, n=32, seed=12)
+    m, b, s = 1500, 4, 8
+    A = dev(d["A"])
+    ys = dev(d["y"])
+    yr = dev(np.random.default_rng(5).standard_normal(m))
+    kern = (2, 1.0 / 32, 0.0, 1)
+    spec = [("krr", 1.0, 1.0 / 32, yr, 1), ("krr", 0.1, 0.5 / 32, yr, 1),
+            ("ksvm", 1.0, 1.0 / 32, ys, 1), ("ksvm", 0.5, 0.5 / 32, ys, 2)]
+    H = 40 * s + 3
+    idx = idx_dev(inputs.krr_indices(m, b, H, seed=4))
+
+    def problems():
+        return [K.BatchProblem(kind, par, sg, y, torch.zeros(m, dtype=torch.float64, device="cuda"),
+                               loss=loss) for kind, par, sg, y, loss in spec]
+
+    ps = problems()
+    info = K.kdcd_batch_solve(A, kern, b, s, H, idx, ps, monitor_every=3, tol=0.0,
+                              monitor_log=True)
+    refs = []
+    for (kind, par, sg, y, loss), q in zip(spec, ps):
+        ok = O.Kernel(O.RBF, sigma=sg)
+        a = q.alpha.cpu().numpy()
+        if kind == "krr":
+            refs.append(krr_rel(O.krr_eval(d["A"], y.cpu().numpy(), ok, par, a), m))
+        else:
+            ev = O.ksvm_eval(d["A"], y.cpu().numpy(), ok, par, a, loss=loss)
+            refs.append(ev["gap"] / abs(ev["dual"]))
+    assert all(0 < r < 1e3 for r in refs), refs      # every bound certifiable here
+    ref = max(refs)
+    assert abs(info["rel_err"] - ref) <= 1e-7 * ref, (info["rel_err"], refs)
+    log = info["log"]
+    n_outer = -(-H // s)
+    assert [int(r[0]) for r in log] == list(range(3, n_outer + 1, 3)) + (
+        [n_outer] if n_outer % 3 else [])
+    assert log[-1][1] == info["rel_err"]
+    fin = [i for i, r in enumerate(log) if np.isfinite(r[1])]   # early bounds may be infinite
+    j = fin[len(fin) // 2]
+    ps = problems()
+    info = K.kdcd_batch_solve(A, kern, b, s, H, idx, ps, monitor_every=3, tol=log[j][1])
+    k = info["outer_done"]
+    assert 0 < k <= int(log[j][0]) and k % 3 == 0 and info["rel_err"] <= log[j][1]
+    plain = problems()
+    K.kdcd_batch_solve(A, kern, b, s, k * s, idx[:k * s * b], plain)
+    for q1, q2 in zip(ps, plain):
+        assert torch.equal(q1.alpha, q2.alpha)
+    with pytest.raises(K.KdcdError) as e:
+        K.kdcd_batch_solve(A, kern, b, s, H, idx, problems(), compute="bf16x3", monitor_every=3,
+                           tol=1e-6)
+    assert e.value.status == -2
