@@ -870,7 +870,7 @@ __global__ __launch_bounds__(HD_BUILD_NT) void csr_panel_build_kernel(
 // (a 16 x 16 MFMA block) of all 16 rows.  Each wave writes only its own rows
 // of X and Pt, so Pt's atomics stay in one wave (fixed order).
 template <int KIND>
-__global__ __launch_bounds__(HD_NT) __attribute__((amdgpu_waves_per_eu(4))) void kblock_csr_head_kernel(
+__global__ __launch_bounds__(HD_NT) __attribute__((amdgpu_waves_per_eu(KIND == KDCD_KERNEL_RBF ? 3 : 4))) void kblock_csr_head_kernel(
     const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx,
     const double *__restrict__ val, int64_t m, int64_t nnz, int64_t n,
     const int32_t *__restrict__ S, int32_t sb, int32_t j0, int32_t nj,
@@ -891,6 +891,8 @@ __global__ __launch_bounds__(HD_NT) __attribute__((amdgpu_waves_per_eu(4))) void
     if (is_w && W == nullptr) return;
     __shared__ double X[HD_RB][HD_XLD];
     __shared__ double Pt[HD_RB][HD_PLD];
+    __shared__ double bsh[HD_RB], nsh[HD_RB];   // the block's rows: beta (scaled), norms
+    __shared__ int64_t rsh[HD_RB];              // and their row indices
 
     auto rp = [&](int64_t r) { return clampi(row_ptr[clampi(r, 0, m)], 0, nnz); };
     const int li = lane & 15, lk = lane >> 4;          // MFMA operand row / k slot
@@ -956,6 +958,20 @@ __global__ __launch_bounds__(HD_NT) __attribute__((amdgpu_waves_per_eu(4))) void
             const int x = lane + 64 * i;
             if (i + 1 < (PW + 63) / 64 || x < PW) (&Pt[8 * wid][0])[x] = 0.0;
         }
+        // wave 0, lanes < 16: row blk * 16 + lane's beta, scale and norm
+        double b0v = 0.0, b0s = 1.0, n0v = 0.0;
+        int64_t r0 = 0;
+        bool rok0 = false;
+        if (wid == 0 && lane < HD_RB) {
+            const int64_t rix = blk * HD_RB + lane;
+            rok0 = is_w ? rix < sb : rix < m;
+            r0 = is_w ? clampi(S[clampi(rix, 0, sb - 1)], 0, m - 1) : clampi(rix, 0, m - 1);
+            if (!is_w) {
+                b0v = beta[r0];
+                if (bscale) b0s = bscale[r0];
+            }
+            if (KIND == KDCD_KERNEL_RBF) n0v = norms[r0];
+        }
         wave_lds_sync();
         const int32_t klast = max(len - 1, 0);
         for (int k0 = 0; __ballot(k0 < len) != 0; k0 += BATCH) {    // uniform
@@ -1013,26 +1029,26 @@ __global__ __launch_bounds__(HD_NT) __attribute__((amdgpu_waves_per_eu(4))) void
                 }
             }
         }
-        // this lane's output rows (t = l/16 + 4 v): beta (zero for rows past
-        // the end) and norms, in flight during the product
+        // the block's rows, staged for the epilogue by wave 0 (loaded before
+        // the entry walk, so their latency hides behind it)
+        if (wid == 0 && lane < HD_RB) {
+            bsh[lane] = rok0 ? b0v * b0s : 0.0;
+            nsh[lane] = n0v;
+            rsh[lane] = r0;
+        }
+        lds_barrier();            // both waves' rows of X / Pt, and the staged rows, are in
         double bvv[4], nav[4];
         int64_t rowv[4];
         bool rokv[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int64_t rix = blk * HD_RB + lk + 4 * v;
+            const int t = lk + 4 * v;
+            const int64_t rix = blk * HD_RB + t;
             rokv[v] = is_w ? rix < sb : rix < m;
-            rowv[v] = is_w ? clampi(S[clampi(rix, 0, sb - 1)], 0, m - 1) : clampi(rix, 0, m - 1);
-            double bv = 0.0;
-            if (!is_w) {
-                bv = beta[rowv[v]];
-                if (bscale) bv *= bscale[rowv[v]];
-                bv = rokv[v] ? bv : 0.0;
-            }
-            bvv[v] = bv;
-            nav[v] = (KIND == KDCD_KERNEL_RBF) ? norms[rowv[v]] : 0.0;
+            rowv[v] = rsh[t];
+            bvv[v] = bsh[t];
+            nav[v] = nsh[t];
         }
-        lds_barrier();            // both waves' rows of X / Pt are in
         // head product on MFMA: this wave's 16 x 16 block of P = X Bh^T (X
         // columns and Bh rows past the head are zero)
         d4 acc = d4{0.0, 0.0, 0.0, 0.0};
