@@ -139,11 +139,28 @@ typedef struct {
  * launches of outer iterations k with k % 8 == 0 are timed (kblock_launches
  * counts them), which keeps the timing's device cost to one launch in eight.
  */
+/*
+ * Lookahead loop (kdcd_krr_solve and kdcd_krr_solve_noalloc; dense A, FP64,
+ * b <= 8, s*b >= 256 and at most twice the threads of the product's
+ * workgroup, n a multiple of 16 with 16-byte aligned rows, at least two outer
+ * iterations, no monitor and no snapshots): the s-step recurrence of index
+ * block k (Algorithm 4's inner loop) runs in one workgroup of the launch that
+ * computes the kernel block of index block k+1.  That product reduces r_{k+1}
+ * against the iterate before block k's updates and also stores the kernel
+ * rows of block k's coordinates; the finish pass of block k+1 then adds those
+ * rows times the updates to r_{k+1} and the updates to alpha, which is
+ * Algorithm 4's r_{k+1} = U_{k+1}^T alpha up to rounding.  Used by default
+ * when 2 m n s b >= 4e9 (the product then outlasts the recurrence it hides);
+ * KDCD_FLAG_LOOKAHEAD asks for it at any size, KDCD_FLAG_SERIAL never.  Calls
+ * that KDCD_FLAG_GRAPH replays by windows run the serial loop.
+ */
 /* Any other bit of flags is refused with KDCD_ERR_INVALID_ARG. */
 enum {
     KDCD_FLAG_GRAPH = 1,
     KDCD_FLAG_TIME_PRODUCT = 4,
-    KDCD_FLAG_TIME_SAMPLE = 8
+    KDCD_FLAG_TIME_SAMPLE = 8,
+    KDCD_FLAG_LOOKAHEAD = 16,
+    KDCD_FLAG_SERIAL = 32
 };
 
 typedef struct {

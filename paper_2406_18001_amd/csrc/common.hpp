@@ -137,6 +137,8 @@ struct BatchDesc {
 };
 
 // Arguments of one kernel-block launch (dense or CSR, any compute type).
+struct LookaheadArgs;
+
 struct KBlockArgs {
     const kdcd_matrix *A;
     const void *Alow;        // low-precision copy of A (F32/BF16/F16), or hi part (BF16X3)
@@ -177,6 +179,45 @@ struct KBlockArgs {
     // the caller together with the row-group count the finish pass sums
     // (-1: looked up in the tuning table at launch)
     int32_t cfg = -1;
+    // dense single-problem FP64 product with a gathered Gram: non-null runs the
+    // K-RR lookahead launch described by *la (the recurrence of the previous
+    // block in workgroup 0, the product storing QX)
+    const LookaheadArgs *la = nullptr;
+};
+
+// K-RR lookahead (one problem, dense FP64, gathered Gram).  The recurrence of
+// index block k needs nothing of the product of block k+1 and the product
+// needs the iterate only through r_{k+1} = U_{k+1}^T alpha, which is linear in
+// alpha.  So one launch runs both: workgroup 0 runs the recurrence of block k
+// (Algorithm 4's inner loop, updates kept apart from alpha), the other
+// workgroups the product of block k+1 against the iterate before those
+// updates, storing as well the kernel rows of S_k's coordinates (QX).  The
+// finish pass of block k+1 then adds QX^T (updates) to r_{k+1} and the updates
+// to alpha.
+constexpr int kLaMaxB = 8;   // largest block size b of the lookahead recurrence
+constexpr int kLaEPT = 2;    // elements of S_k per recurrence thread: s*b <= 2 * threads
+constexpr int kLaLead = 8;   // leading workgroups of a lookahead launch (one per XCD)
+struct LookaheadArgs {
+    const int32_t *S;        // S_k, sb entries
+    int32_t sb, b, sk;
+    const double *r;         // r_k, final
+    const double *W;         // Gram of S_k, [sb][sb], repeated rows copied with lambda m added
+    const double *Dinv;      // inverses of the diagonal blocks, [sk][b][b]
+    const double *y;
+    const double *alpha;     // iterate before block k (read only during the launch)
+    double lambda, mdbl;
+    // row -> position table of S_k: element t of a coordinate is its canonical
+    // element when pos[S_t] == t (the coordinate's last element: the tables
+    // are marked with atomicMax, so the canonical element, and with it the
+    // order of the finish pass's sums, is the same in every run); the product
+    // stores row QX[t] for it
+    const int32_t *pos;
+    double *Dc;              // per element: summed update of its coordinate (canonical), else 0
+    int32_t *Sc;             // per element: its coordinate (canonical), else -1
+    double *trace;           // per-element updates, or null
+    int32_t *status;
+    int64_t m;
+    double *QX;              // [sb][sb of the product]: kernel rows of canonical elements
 };
 
 // Launchers (return hipError_t of the launch).
@@ -235,6 +276,25 @@ struct FinishDesc {
     const int32_t *dup_pos; // row -> position table of S_k
     double *dup_W;          // the Gram, [sb][sb]
     int64_t m;
+    // K-RR lookahead (la_Sc non-null): r also receives sum_t QX[t][j] Dc[t]
+    // over the canonical elements t of the previous block (la_sb of them),
+    // whose summed updates one extra workgroup then adds to alpha; the same
+    // workgroup moves the row -> position table la_pos on (clears the entries
+    // of la_clearS, then marks la_setS), when la_pos is non-null
+    const double *la_QX;
+    const double *la_Dc;
+    const int32_t *la_Sc;
+    int32_t la_sb;
+    double *la_alpha;
+    int32_t *la_pos;
+    const int32_t *la_clearS;
+    int32_t la_clear_sb;
+    const int32_t *la_setS;
+    int32_t la_set_sb;
+    // non-zero: the copied Gram rows (the coordinates that come again later)
+    // also get la_lm = lambda m at the columns of their coordinate's other
+    // elements, the m term of G for the lookahead recurrence
+    double la_lm;
 };
 
 struct KsvmRecurDesc {

@@ -85,10 +85,12 @@ __global__ void iota_i32_kernel(int32_t *p, int64_t count)
 constexpr int FIN_COLS = 8;     // columns per reduction workgroup
 constexpr int FIN_PARTS = 32;   // row-group partitions per column
 
-// Blocks [0, nprob * ceil(sb/16)) reduce r of every problem; the next nkrr * sk
+// Blocks [0, nprob * ceil(sb/8)) reduce r of every problem; the next nkrr * sk
 // invert one diagonal block of one K-RR problem each (Gauss-Jordan without
-// pivoting, valid for SPD matrices); with dup_S the last ceil(sb/4) copy the
-// Gram rows of repeated coordinates (one wave per row).
+// pivoting, valid for SPD matrices); with dup_S the next ceil(sb/4) copy the
+// Gram rows of repeated coordinates (one wave per row); with la_Sc or la_pos
+// the last one applies the previous block's updates to alpha and moves the
+// row -> position table on.
 __global__ __launch_bounds__(256) void finish_kernel(const FinishDesc d, int32_t sb, int32_t b,
                                                      int32_t sk, double mdbl, int32_t *status)
 {
@@ -115,6 +117,14 @@ __global__ __launch_bounds__(256) void finish_kernel(const FinishDesc d, int32_t
 #pragma unroll
                 for (int u = 0; u < 8; ++u) s += v[u];
             }
+        if (d.la_Sc && col < sb) {
+            // the previous block's updates against the kernel rows of their
+            // coordinates (one partition's share of the canonical elements)
+            double f = 0.0;
+            for (int t = part; t < d.la_sb; t += FIN_PARTS)
+                if (d.la_Sc[t] >= 0) f += d.la_QX[(int64_t)t * sb + col] * d.la_Dc[t];
+            s += f;
+        }
         sh[part * FIN_COLS + c] = s;
         __syncthreads();
         if (part == 0 && col < sb) {
@@ -134,6 +144,31 @@ __global__ __launch_bounds__(256) void finish_kernel(const FinishDesc d, int32_t
         const int32_t w = d.dup_pos[p];
         return (w >= 0 && w < sb) ? w : t;
     };
+    const int n_dup = d.dup_S ? (sb + 3) / 4 : 0;
+    if (x >= n_inv + n_dup) {   // the lookahead block
+        if (d.la_Sc)
+            for (int t = tid; t < d.la_sb; t += blockDim.x) {
+                const int32_t p = d.la_Sc[t];
+                if (p < 0 || p >= d.m) continue;
+                const double v = d.la_alpha[p] + d.la_Dc[t];
+                if (!isfinite(v)) set_status(status, KDCD_ERR_NONFINITE);
+                d.la_alpha[p] = v;
+            }
+        if (d.la_pos) {
+            for (int t = tid; t < d.la_clear_sb; t += blockDim.x) {
+                const int32_t p = d.la_clearS[t];
+                if (p >= 0 && p < d.m) d.la_pos[p] = -1;
+            }
+            __syncthreads();
+            // a repeated coordinate keeps its last element, whatever the order
+            // of the stores: the lookahead sums depend on which one it is
+            for (int t = tid; t < d.la_set_sb; t += blockDim.x) {
+                const int32_t p = d.la_setS[t];
+                if (p >= 0 && p < d.m) atomicMax(&d.la_pos[p], t);
+            }
+        }
+        return;
+    }
     if (x >= n_inv) {   // one wave per row
         if (!d.dup_S) return;
         const int lane = tid & 63;
@@ -141,7 +176,14 @@ __global__ __launch_bounds__(256) void finish_kernel(const FinishDesc d, int32_t
         if (t >= sb) return;
         const int64_t w = src_row(t);
         if (w == t) return;
-        for (int64_t c = lane; c < sb; c += 64) d.dup_W[t * sb + c] = d.dup_W[w * sb + c];
+        const int32_t St = d.dup_S[t];
+        for (int64_t c = lane; c < sb; c += 64) {
+            double v = d.dup_W[w * sb + c];
+            // lookahead: lambda m at the other elements of the coordinate, so that
+            // the recurrence reads G = W' / lambda without comparing coordinates
+            if (d.la_lm != 0.0 && c != t && d.dup_S[c] == St) v += d.la_lm;
+            d.dup_W[t * sb + c] = v;
+        }
         return;
     }
     const int k = x / sk, j = x % sk;
@@ -254,7 +296,8 @@ hipError_t launch_finish(const FinishDesc &d, int32_t sb, int32_t b, int32_t sk,
                          int32_t *status, hipStream_t st)
 {
     const int per = (sb + FIN_COLS - 1) / FIN_COLS;
-    const int blocks = per * d.nprob + d.nkrr * sk + (d.dup_S ? (sb + 3) / 4 : 0);
+    const int blocks = per * d.nprob + d.nkrr * sk + (d.dup_S ? (sb + 3) / 4 : 0) +
+                       ((d.la_Sc || d.la_pos) ? 1 : 0);
     KDCD_TIMED_LAUNCH(finish_kernel, dim3(blocks), dim3(256), 0, st, d, sb, b, sk, mdbl, status);
     return hipGetLastError();
 }

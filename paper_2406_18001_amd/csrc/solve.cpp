@@ -141,6 +141,10 @@ size_t lowp_elem_bytes(int32_t compute) { return compute == KDCD_F32 ? 4 : 2; }
 // Workspace regions of one solve.
 struct Layout {
     size_t status, norms, partial, r, W, Dinv, iota, hi, lo, normlow, pos, carry, panel, total;
+    // K-RR lookahead (la_ok): second row table and Gram, the kernel rows of the
+    // previous block's coordinates, its summed updates and their coordinates
+    bool la_ok;
+    size_t pos2, W2, QX, la_dc, la_sc;
     int64_t ldlow;
     // convergence monitor (0 when off): state, partial sums, maintained
     // gradient / residual (m), stored kernel block (s*b x m), updates (s*b),
@@ -174,6 +178,14 @@ Layout make_layout(int32_t problem, const kdcd_matrix *A, const kdcd_kernel *ker
     L.Dinv = off; off += (problem == 1) ? align256(sizeof(double) * (size_t)(sb * b)) : 0;
     L.iota = off; off += (problem == 2) ? align256(sizeof(int32_t) * (size_t)A->m) : 0;
     L.pos = off; off += align256(sizeof(int32_t) * (size_t)A->m);   // row -> position in S
+    L.la_ok = problem == 1 && A->format == KDCD_DENSE && compute == KDCD_F64 &&
+              sb >= kGatherMinSB && b <= kLaMaxB && sb <= kLaEPT * 512;
+    const size_t gram = align256(sizeof(double) * (size_t)(sb * sb));
+    L.pos2 = off; off += L.la_ok ? align256(sizeof(int32_t) * (size_t)A->m) : 0;
+    L.W2 = off; off += L.la_ok ? gram : 0;
+    L.QX = off; off += L.la_ok ? gram : 0;
+    L.la_dc = off; off += L.la_ok ? align256(sizeof(double) * (size_t)sb) : 0;
+    L.la_sc = off; off += L.la_ok ? align256(sizeof(int32_t) * (size_t)sb) : 0;
     L.carry = off;   // CSR: partial dot products of sampled rows longer than the panel
     off += (A->format == KDCD_CSR) ? align256(sizeof(double) * (size_t)(A->m + sb)) : 0;
     L.panel = off;   // CSR: the dense-head panel of a chunk of sampled rows
@@ -508,6 +520,174 @@ struct SolveRange {
     const int32_t *S_base = nullptr;
 };
 
+// Work (2 m n s b flops per product) from which the lookahead loop is the
+// default: the product then takes well over 100 us, several times the
+// recurrence it hides.
+constexpr double kLaMinFlops = 4e9;
+
+// Whether a K-RR solve runs the lookahead loop (see LookaheadArgs): dense FP64
+// with a gathered Gram, b <= 8, whole product tiles along K, every product
+// configuration of the solve wide enough to hold the recurrence's elements,
+// no monitor or snapshots, the whole solve in one call.
+bool lookahead_use(const SolveArgs &sa, const Layout &L, const KBlockArgs &kb,
+                   const SolveRange &R)
+{
+    const kdcd_matrix *A = sa.A;
+    if (!L.la_ok || !kb.pos || sa.problem != 1 || sa.b > kLaMaxB) return false;
+    if (sa.opt.flags & KDCD_FLAG_SERIAL) return false;
+    if (sa.opt.monitor_every > 0 || (sa.opt.snapshot_every > 0 && sa.opt.snapshots)) return false;
+    if (R.k_begin != 0 || R.k_end >= 0 || R.S_base || !R.setup) return false;
+    const int64_t n_outer = (sa.H + sa.s - 1) / sa.s;
+    if (n_outer < 2) return false;
+    const bool aligned = (A->ld % 2 == 0) && ((reinterpret_cast<uintptr_t>(A->values) & 15) == 0);
+    if (!aligned || A->n % 16 != 0) return false;
+    const int64_t sb_full = (int64_t)sa.s * sa.b;
+    const int64_t sb_last = (sa.H - (n_outer - 1) * sa.s) * sa.b;
+    for (const int64_t sbv : {sb_full, sb_last}) {
+        int bm = 0, bn = 0, waves = 0;
+        f64_config_shape(f64_config_id(A->n, (int32_t)sbv), &bm, &bn, &waves);
+        if (sb_full > (int64_t)kLaEPT * 64 * waves) return false;
+    }
+    if (sa.opt.flags & KDCD_FLAG_LOOKAHEAD) return true;
+    return 2.0 * (double)A->m * (double)A->n * (double)sb_full >= kLaMinFlops;
+}
+
+// The lookahead loop of a K-RR solve.  Per outer iteration k: the finish pass
+// of block k (r_k from the partial sums plus the kernel rows of block k-1's
+// coordinates times their updates, D_j^{-1}, repeated Gram rows; block k-1's
+// updates added to alpha; the row table of block k+1), then one launch with
+// the recurrence of block k and the product of block k+1 (the last block's
+// recurrence runs alone and writes alpha itself).  Row tables and Grams
+// alternate between two copies: block k uses copy k % 2, which stays untouched
+// until the finish pass of block k+1 has run.
+kdcd_status enqueue_lookahead(const SolveArgs &sa, const Layout &L, Workspace &ws, KBlockArgs kb,
+                              StageTimer &timer, bool product_only, bool sampled)
+{
+    const kdcd_matrix *A = sa.A;
+    const hipStream_t st = sa.st;
+    int32_t *status = ws.at<int32_t>(L.status);
+    double *r = ws.at<double>(L.r);
+    double *Dinv = ws.at<double>(L.Dinv);
+    int32_t *P[2] = {ws.at<int32_t>(L.pos), ws.at<int32_t>(L.pos2)};
+    double *Wb[2] = {ws.at<double>(L.W), ws.at<double>(L.W2)};
+    double *QX = ws.at<double>(L.QX);
+    double *Dc = ws.at<double>(L.la_dc);
+    int32_t *Sc = ws.at<int32_t>(L.la_sc);
+    const int64_t n_outer = (sa.H + sa.s - 1) / sa.s;
+    auto block = [&](int64_t k, int32_t &sk, int32_t &sb) -> const int32_t * {
+        const int64_t done = k * sa.s;
+        sk = (int32_t)std::min<int64_t>(sa.s, sa.H - done);
+        sb = sk * sa.b;
+        return sa.idx + done * sa.b;
+    };
+    auto trace_of = [&](int64_t k) -> double * {
+        return sa.opt.trace ? sa.opt.trace + k * sa.s * sa.b : nullptr;
+    };
+
+    KDCD_HIP_TRY(launch_fill_i32(P[1], -1, A->m, st));   // copy 0 was cleared by the set-up
+    int32_t sk0 = 0, sb0 = 0;
+    kb.S = block(0, sk0, sb0);
+    kb.sb = sb0;
+    kb.prevS = nullptr;
+    kb.prev_sb = 0;
+    kb.pos = P[0];
+    kb.W = Wb[0];
+    kb.la = nullptr;
+    int64_t groups = bind_config(kb);
+    KDCD_HIP_TRY(launch_kblock_f64_pre(kb, st));   // row table of block 0
+    timer.arm(0);
+    {
+        const hipError_t e = launch_kblock_f64_main(kb, st);
+        timer.disarm();
+        KDCD_HIP_TRY(e);
+    }
+    for (int64_t k = 0; k < n_outer; ++k) {
+        int32_t sk = 0, sb = 0, sk1 = 0, sb1 = 0, skp = 0, sbp = 0;
+        const int32_t *S = block(k, sk, sb);
+        const int32_t *S1 = k + 1 < n_outer ? block(k + 1, sk1, sb1) : nullptr;
+        const int32_t *Sp = k > 0 ? block(k - 1, skp, sbp) : nullptr;
+        FinishDesc fd{};
+        fd.nprob = 1;
+        fd.nkrr = 1;
+        fd.groups = (int32_t)groups;
+        fd.partial[0] = ws.at<double>(L.partial);
+        fd.r[0] = r;
+        fd.W[0] = Wb[k & 1];
+        fd.Dinv[0] = Dinv;
+        fd.inv_lambda[0] = 1.0 / sa.lambda;
+        fd.dup_S = S;
+        fd.dup_pos = P[k & 1];
+        fd.dup_W = Wb[k & 1];
+        fd.m = A->m;
+        if (k > 0) {
+            fd.la_QX = QX;
+            fd.la_Dc = Dc;
+            fd.la_Sc = Sc;
+            fd.la_sb = sbp;
+            fd.la_alpha = sa.alpha;
+        }
+        fd.la_pos = P[(k + 1) & 1];
+        fd.la_clearS = Sp;
+        fd.la_clear_sb = sbp;
+        fd.la_setS = S1;
+        fd.la_set_sb = sb1;
+        // the Gram of block k feeds the lookahead recurrence unless k is the last
+        fd.la_lm = k + 1 < n_outer ? sa.lambda * (double)A->m : 0.0;
+        if (!product_only) timer.arm(1);
+        {
+            const hipError_t e = launch_finish(fd, sb, sa.b, sk, (double)A->m, status, st);
+            timer.disarm();
+            KDCD_HIP_TRY(e);
+        }
+        if (k + 1 < n_outer) {
+            LookaheadArgs la{};
+            la.S = S;
+            la.sb = sb;
+            la.b = sa.b;
+            la.sk = sk;
+            la.r = r;
+            la.W = Wb[k & 1];
+            la.Dinv = Dinv;
+            la.y = sa.y;
+            la.alpha = sa.alpha;
+            la.lambda = sa.lambda;
+            la.mdbl = (double)A->m;
+            la.pos = P[k & 1];
+            la.Dc = Dc;
+            la.Sc = Sc;
+            la.trace = trace_of(k);
+            la.status = status;
+            la.m = A->m;
+            la.QX = QX;
+            kb.S = S1;
+            kb.sb = sb1;
+            kb.pos = P[(k + 1) & 1];
+            kb.W = Wb[(k + 1) & 1];
+            kb.la = &la;
+            groups = bind_config(kb);
+            if (!sampled || (k + 1) % 8 == 0) timer.arm(0);
+            const hipError_t e = launch_kblock_f64_main(kb, st);
+            timer.disarm();
+            KDCD_HIP_TRY(e);
+        } else {
+            KrrRecurDesc rd{};
+            rd.r[0] = r;
+            rd.W[0] = Wb[k & 1];
+            rd.Dinv[0] = Dinv;
+            rd.y[0] = sa.y;
+            rd.alpha[0] = sa.alpha;
+            rd.trace[0] = trace_of(k);
+            rd.lambda[0] = sa.lambda;
+            if (!product_only) timer.arm(2);
+            const hipError_t e =
+                launch_krr_recur(rd, 1, S, sa.b, sk, A->m, (double)A->m, status, st);
+            timer.disarm();
+            KDCD_HIP_TRY(e);
+        }
+    }
+    return KDCD_OK;
+}
+
 // Everything a solve (or a part of it) puts on its stream, in the workspace at
 // `base`, without the final status read (the status word is at offset L.status).
 kdcd_status enqueue_solve(const SolveArgs &sa, const Layout &L, char *wsbase, StageTimer &timer,
@@ -577,6 +757,9 @@ kdcd_status enqueue_solve(const SolveArgs &sa, const Layout &L, char *wsbase, St
         kb.U = ws.at<double>(L.mon_U);
         kb.stop = stop;
     }
+
+    if (lookahead_use(sa, L, kb, R))
+        return enqueue_lookahead(sa, L, ws, kb, timer, product_only, sampled);
 
     const int64_t n_outer = (sa.H + sa.s - 1) / sa.s;
     int64_t snap = 0;
@@ -1046,7 +1229,8 @@ kdcd_status common_checks(const kdcd_matrix *A, const double *y, const kdcd_kern
         if ((rc = check_compute(A, opt->compute)) != KDCD_OK) return rc;
         if (opt->snapshot_every < 0) return KDCD_ERR_INVALID_ARG;
         if (opt->snapshot_every > 0 && !opt->snapshots) return KDCD_ERR_INVALID_ARG;
-        if (opt->flags & ~(KDCD_FLAG_GRAPH | KDCD_FLAG_TIME_PRODUCT | KDCD_FLAG_TIME_SAMPLE))
+        if (opt->flags & ~(KDCD_FLAG_GRAPH | KDCD_FLAG_TIME_PRODUCT | KDCD_FLAG_TIME_SAMPLE |
+                           KDCD_FLAG_LOOKAHEAD | KDCD_FLAG_SERIAL))
             return KDCD_ERR_INVALID_ARG;
     }
     if ((int64_t)s * b > kMaxSB) return KDCD_ERR_UNSUPPORTED;

@@ -32,6 +32,8 @@ COMPUTE = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3, "bf16x3": 4}
 FLAG_GRAPH = 1
 FLAG_TIME_PRODUCT = 4
 FLAG_TIME_SAMPLE = 8
+FLAG_LOOKAHEAD = 16
+FLAG_SERIAL = 32
 
 STATUS = {0: "KDCD_OK", -1: "KDCD_ERR_INVALID_ARG", -2: "KDCD_ERR_UNSUPPORTED",
           -3: "KDCD_ERR_INDEX_RANGE", -4: "KDCD_ERR_INDEX_DUPLICATE", -5: "KDCD_ERR_NOT_SPD",
