@@ -89,7 +89,7 @@ constexpr int FIN_PARTS = 32;   // row-group partitions per column
 // invert one diagonal block of one K-RR problem each (Gauss-Jordan without
 // pivoting, valid for SPD matrices); with dup_S the next ceil(sb/4) copy the
 // Gram rows of repeated coordinates (one wave per row); with la_Sc or la_pos
-// the last one applies the previous block's updates to alpha and moves the
+// the last two apply the previous block's updates to alpha and move the
 // row -> position table on.
 __global__ __launch_bounds__(256) void finish_kernel(const FinishDesc d, int32_t sb, int32_t b,
                                                      int32_t sk, double mdbl, int32_t *status)
@@ -119,10 +119,24 @@ __global__ __launch_bounds__(256) void finish_kernel(const FinishDesc d, int32_t
             }
         if (d.la_Sc && col < sb) {
             // the previous block's updates against the kernel rows of their
-            // coordinates (one partition's share of the canonical elements)
+            // coordinates (one partition's share of the canonical elements),
+            // eight rows in flight, added in row order
             double f = 0.0;
-            for (int t = part; t < d.la_sb; t += FIN_PARTS)
-                if (d.la_Sc[t] >= 0) f += d.la_QX[(int64_t)t * sb + col] * d.la_Dc[t];
+            for (int t0 = part; t0 < d.la_sb; t0 += 8 * FIN_PARTS) {
+                double q[8], dc[8];
+                int32_t sc[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int t = t0 + u * FIN_PARTS;
+                    const int tc = t < d.la_sb ? t : d.la_sb - 1;
+                    sc[u] = t < d.la_sb ? d.la_Sc[tc] : -1;
+                    dc[u] = d.la_Dc[tc];
+                    q[u] = d.la_QX[(int64_t)tc * sb + col];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (sc[u] >= 0) f += q[u] * dc[u];
+            }
             s += f;
         }
         sh[part * FIN_COLS + c] = s;
@@ -145,27 +159,41 @@ __global__ __launch_bounds__(256) void finish_kernel(const FinishDesc d, int32_t
         return (w >= 0 && w < sb) ? w : t;
     };
     const int n_dup = d.dup_S ? (sb + 3) / 4 : 0;
-    if (x >= n_inv + n_dup) {   // the lookahead block
-        if (d.la_Sc)
-            for (int t = tid; t < d.la_sb; t += blockDim.x) {
-                const int32_t p = d.la_Sc[t];
-                if (p < 0 || p >= d.m) continue;
-                const double v = d.la_alpha[p] + d.la_Dc[t];
+    if (x == n_inv + n_dup) {   // lookahead: the previous block's updates into alpha
+        if (!d.la_Sc) return;
+        for (int t0 = tid; t0 < d.la_sb; t0 += 4 * (int)blockDim.x) {
+            int32_t p[4];
+            double dc[4], av[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int t = t0 + u * (int)blockDim.x;
+                p[u] = t < d.la_sb ? d.la_Sc[t] : -1;
+                dc[u] = t < d.la_sb ? d.la_Dc[t] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) av[u] = (p[u] >= 0 && p[u] < d.m) ? d.la_alpha[p[u]] : 0.0;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (p[u] < 0 || p[u] >= d.m) continue;
+                const double v = av[u] + dc[u];
                 if (!isfinite(v)) set_status(status, KDCD_ERR_NONFINITE);
-                d.la_alpha[p] = v;
+                d.la_alpha[p[u]] = v;
             }
-        if (d.la_pos) {
-            for (int t = tid; t < d.la_clear_sb; t += blockDim.x) {
-                const int32_t p = d.la_clearS[t];
-                if (p >= 0 && p < d.m) d.la_pos[p] = -1;
-            }
-            __syncthreads();
-            // a repeated coordinate keeps its last element, whatever the order
-            // of the stores: the lookahead sums depend on which one it is
-            for (int t = tid; t < d.la_set_sb; t += blockDim.x) {
-                const int32_t p = d.la_setS[t];
-                if (p >= 0 && p < d.m) atomicMax(&d.la_pos[p], t);
-            }
+        }
+        return;
+    }
+    if (x > n_inv + n_dup) {    // lookahead: the row -> position table moves on
+        if (!d.la_pos) return;
+        for (int t = tid; t < d.la_clear_sb; t += blockDim.x) {
+            const int32_t p = d.la_clearS[t];
+            if (p >= 0 && p < d.m) d.la_pos[p] = -1;
+        }
+        __syncthreads();
+        // a repeated coordinate keeps its last element, whatever the order
+        // of the stores: the lookahead sums depend on which one it is
+        for (int t = tid; t < d.la_set_sb; t += blockDim.x) {
+            const int32_t p = d.la_setS[t];
+            if (p >= 0 && p < d.m) atomicMax(&d.la_pos[p], t);
         }
         return;
     }
@@ -297,7 +325,7 @@ hipError_t launch_finish(const FinishDesc &d, int32_t sb, int32_t b, int32_t sk,
 {
     const int per = (sb + FIN_COLS - 1) / FIN_COLS;
     const int blocks = per * d.nprob + d.nkrr * sk + (d.dup_S ? (sb + 3) / 4 : 0) +
-                       ((d.la_Sc || d.la_pos) ? 1 : 0);
+                       ((d.la_Sc || d.la_pos) ? 2 : 0);
     KDCD_TIMED_LAUNCH(finish_kernel, dim3(blocks), dim3(256), 0, st, d, sb, b, sk, mdbl, status);
     return hipGetLastError();
 }
