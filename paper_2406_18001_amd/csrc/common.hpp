@@ -383,6 +383,7 @@ hipError_t launch_validate(const int32_t *idx, int64_t count, int64_t m, const d
                            const double *alpha, int64_t mrows, int32_t problem, double nu,
                            int32_t *status, hipStream_t st);
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t count, hipStream_t st);
+hipError_t launch_copy_batch_desc(const BatchDesc &d, BatchDesc *dst, hipStream_t st);
 hipError_t launch_window_advance(const int32_t *idx, int64_t *counter, int32_t *Swin, int32_t W,
                                  int32_t sb, hipStream_t st);
 hipError_t launch_validate_csr(const kdcd_matrix *A, int32_t *status, hipStream_t st);

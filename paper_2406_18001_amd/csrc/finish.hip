@@ -313,6 +313,20 @@ hipError_t launch_window_advance(const int32_t *idx, int64_t *counter, int32_t *
     return hipGetLastError();
 }
 
+// A batch descriptor passed by value (kernel arguments) written to device
+// memory: as a kernel node of a captured graph, every replay rewrites the copy
+// its launches read, whatever another call did to that memory meanwhile.
+__global__ void copy_batch_desc_kernel(const BatchDesc d, BatchDesc *dst)
+{
+    if (threadIdx.x == 0) *dst = d;
+}
+
+hipError_t launch_copy_batch_desc(const BatchDesc &d, BatchDesc *dst, hipStream_t st)
+{
+    hipLaunchKernelGGL(copy_batch_desc_kernel, dim3(1), dim3(64), 0, st, d, dst);
+    return hipGetLastError();
+}
+
 hipError_t launch_iota_i32(int32_t *p, int64_t count, hipStream_t st)
 {
     hipLaunchKernelGGL(iota_i32_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, p,

@@ -150,6 +150,8 @@ struct Layout {
     // gradient / residual (m), stored kernel block (s*b x m), updates (s*b),
     // scratch m-vector
     size_t mon, mon_part, mon_v, mon_U, mon_th, mon_tmp;
+    // second stored kernel block for the lookahead loop with the monitor (0: none)
+    size_t mon_U2;
 };
 
 void add_monitor(Layout &L, int64_t m, int64_t sbmax)
@@ -492,10 +494,11 @@ struct StopPoller {
             if (e) (void)hipEventDestroy(e);
         if (host) (void)hipHostFree(host);
     }
-    // after the monitor launch of period j
+    // after the monitor launch of period j (a final evaluation before the
+    // first whole period comes as j = -1 and is not recorded)
     hipError_t post(int64_t j, const MonitorState *mon, hipStream_t st)
     {
-        if (!ok || j > periods) return hipSuccess;
+        if (!ok || j < 0 || j > periods) return hipSuccess;
         hipError_t e = hipMemcpyAsync(host + j, &mon->stop, sizeof(int32_t), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipEventRecord(ev[j % (LAG + 1)], st);
         return e;
@@ -535,7 +538,8 @@ bool lookahead_use(const SolveArgs &sa, const Layout &L, const KBlockArgs &kb,
     const kdcd_matrix *A = sa.A;
     if (!L.la_ok || !kb.pos || sa.problem != 1 || sa.b > kLaMaxB) return false;
     if (sa.opt.flags & KDCD_FLAG_SERIAL) return false;
-    if (sa.opt.monitor_every > 0 || (sa.opt.snapshot_every > 0 && sa.opt.snapshots)) return false;
+    if (sa.opt.monitor_every > 0 && L.mon_U2 == 0) return false;
+    if (sa.opt.snapshot_every > 0 && sa.opt.snapshots) return false;
     if (R.k_begin != 0 || R.k_end >= 0 || R.S_base || !R.setup) return false;
     const int64_t n_outer = (sa.H + sa.s - 1) / sa.s;
     if (n_outer < 2) return false;
@@ -559,9 +563,14 @@ bool lookahead_use(const SolveArgs &sa, const Layout &L, const KBlockArgs &kb,
 // the recurrence of block k and the product of block k+1 (the last block's
 // recurrence runs alone and writes alpha itself).  Row tables and Grams
 // alternate between two copies: block k uses copy k % 2, which stays untouched
-// until the finish pass of block k+1 has run.
+// until the finish pass of block k+1 has run.  With the monitor the stored
+// kernel blocks alternate too; block k-1's dual update and the evaluation
+// after k outer iterations run between the finish pass of block k (alpha then
+// holds block k-1's updates) and the next launch (which overwrites the
+// updates of block k-1 and the stored kernel block k-1).
 kdcd_status enqueue_lookahead(const SolveArgs &sa, const Layout &L, Workspace &ws, KBlockArgs kb,
-                              StageTimer &timer, bool product_only, bool sampled)
+                              StageTimer &timer, bool product_only, bool sampled,
+                              MonitorState *mon, double *dual, StopPoller *poll)
 {
     const kdcd_matrix *A = sa.A;
     const hipStream_t st = sa.st;
@@ -580,8 +589,29 @@ kdcd_status enqueue_lookahead(const SolveArgs &sa, const Layout &L, Workspace &w
         sb = sk * sa.b;
         return sa.idx + done * sa.b;
     };
+    const bool monitor = mon != nullptr;
+    const int32_t *stop = monitor ? &mon->stop : nullptr;
+    double *Ub[2] = {monitor ? ws.at<double>(L.mon_U) : nullptr,
+                     monitor ? ws.at<double>(L.mon_U2) : nullptr};
     auto trace_of = [&](int64_t k) -> double * {
-        return sa.opt.trace ? sa.opt.trace + k * sa.s * sa.b : nullptr;
+        if (sa.opt.trace) return sa.opt.trace + k * sa.s * sa.b;
+        return monitor ? ws.at<double>(L.mon_th) : nullptr;
+    };
+    const int64_t every = monitor ? sa.opt.monitor_every : 0;
+    // block k's dual update, then the evaluation after k + 1 outer iterations
+    // when one is due
+    auto monitor_after = [&](int64_t k, bool last) -> kdcd_status {
+        int32_t skk = 0, sbk = 0;
+        const int32_t *Sk = block(k, skk, sbk);
+        KDCD_HIP_TRY(launch_dual_update(Ub[k & 1], A->m, sbk, Sk, trace_of(k), nullptr,
+                                        -1.0 / sa.lambda, nullptr, -(double)A->m, dual, stop, st));
+        if ((k + 1) % every == 0 || last) {
+            KDCD_HIP_TRY(launch_monitor(sa.problem, A->m, sa.alpha, sa.y, dual, 0.0, sa.opt.loss,
+                                        sa.C, sa.opt.tol, k + 1, ws.at<double>(L.mon_part), mon,
+                                        st));
+            KDCD_HIP_TRY(poll->post((k + 1) / every - 1, mon, st));
+        }
+        return KDCD_OK;
     };
 
     KDCD_HIP_TRY(launch_fill_i32(P[1], -1, A->m, st));   // copy 0 was cleared by the set-up
@@ -593,6 +623,8 @@ kdcd_status enqueue_lookahead(const SolveArgs &sa, const Layout &L, Workspace &w
     kb.pos = P[0];
     kb.W = Wb[0];
     kb.la = nullptr;
+    kb.U = Ub[0];
+    kb.stop = stop;
     int64_t groups = bind_config(kb);
     KDCD_HIP_TRY(launch_kblock_f64_pre(kb, st));   // row table of block 0
     timer.arm(0);
@@ -602,6 +634,9 @@ kdcd_status enqueue_lookahead(const SolveArgs &sa, const Layout &L, Workspace &w
         KDCD_HIP_TRY(e);
     }
     for (int64_t k = 0; k < n_outer; ++k) {
+        // the evaluation after k - 1 outer iterations is the last one posted
+        if (monitor && k >= 2 && (k - 1) % every == 0 && poll->stopped((k - 1) / every - 1))
+            return KDCD_OK;
         int32_t sk = 0, sb = 0, sk1 = 0, sb1 = 0, skp = 0, sbp = 0;
         const int32_t *S = block(k, sk, sb);
         const int32_t *S1 = k + 1 < n_outer ? block(k + 1, sk1, sb1) : nullptr;
@@ -615,6 +650,7 @@ kdcd_status enqueue_lookahead(const SolveArgs &sa, const Layout &L, Workspace &w
         fd.W[0] = Wb[k & 1];
         fd.Dinv[0] = Dinv;
         fd.inv_lambda[0] = 1.0 / sa.lambda;
+        fd.stop = stop;
         fd.dup_S = S;
         fd.dup_pos = P[k & 1];
         fd.dup_W = Wb[k & 1];
@@ -638,6 +674,10 @@ kdcd_status enqueue_lookahead(const SolveArgs &sa, const Layout &L, Workspace &w
             const hipError_t e = launch_finish(fd, sb, sa.b, sk, (double)A->m, status, st);
             timer.disarm();
             KDCD_HIP_TRY(e);
+        }
+        if (monitor && k > 0) {
+            const kdcd_status mrc = monitor_after(k - 1, false);
+            if (mrc != KDCD_OK) return mrc;
         }
         if (k + 1 < n_outer) {
             LookaheadArgs la{};
@@ -663,6 +703,7 @@ kdcd_status enqueue_lookahead(const SolveArgs &sa, const Layout &L, Workspace &w
             kb.sb = sb1;
             kb.pos = P[(k + 1) & 1];
             kb.W = Wb[(k + 1) & 1];
+            kb.U = Ub[(k + 1) & 1];
             kb.la = &la;
             groups = bind_config(kb);
             if (!sampled || (k + 1) % 8 == 0) timer.arm(0);
@@ -678,11 +719,16 @@ kdcd_status enqueue_lookahead(const SolveArgs &sa, const Layout &L, Workspace &w
             rd.alpha[0] = sa.alpha;
             rd.trace[0] = trace_of(k);
             rd.lambda[0] = sa.lambda;
+            rd.stop = stop;
             if (!product_only) timer.arm(2);
             const hipError_t e =
                 launch_krr_recur(rd, 1, S, sa.b, sk, A->m, (double)A->m, status, st);
             timer.disarm();
             KDCD_HIP_TRY(e);
+            if (monitor) {
+                const kdcd_status mrc = monitor_after(k, true);
+                if (mrc != KDCD_OK) return mrc;
+            }
         }
     }
     return KDCD_OK;
@@ -758,13 +804,14 @@ kdcd_status enqueue_solve(const SolveArgs &sa, const Layout &L, char *wsbase, St
         kb.stop = stop;
     }
 
-    if (lookahead_use(sa, L, kb, R))
-        return enqueue_lookahead(sa, L, ws, kb, timer, product_only, sampled);
-
     const int64_t n_outer = (sa.H + sa.s - 1) / sa.s;
     int64_t snap = 0;
     std::unique_ptr<StopPoller> poll;
     if (monitor) poll.reset(new StopPoller(n_outer / sa.opt.monitor_every + 1));
+    if (lookahead_use(sa, L, kb, R))
+        return enqueue_lookahead(sa, L, ws, kb, timer, product_only, sampled, mon, dual,
+                                 poll.get());
+
     int64_t k = R.k_begin;
     const int64_t k_end = R.k_end < 0 ? n_outer : R.k_end;
     const int64_t sb_full = (int64_t)sa.s * sa.b;
@@ -1178,7 +1225,15 @@ kdcd_status run_solve(const SolveArgs &sa)
     kdcd_status rc = check_monitor(sa.A, sa.opt);
     if (rc != KDCD_OK) return rc;
     Layout L = make_layout(sa.problem, sa.A, sa.kernel, sa.b, sa.s, sa.opt.compute);
-    if (sa.opt.monitor_every > 0) add_monitor(L, sa.A->m, (int64_t)sa.s * sa.b);
+    if (sa.opt.monitor_every > 0) {
+        add_monitor(L, sa.A->m, (int64_t)sa.s * sa.b);
+        // the lookahead loop keeps two stored kernel blocks (not in a caller's
+        // workspace, whose size kdcd_workspace_bytes gives without it)
+        if (L.la_ok && !sa.opt.workspace && !(sa.opt.flags & KDCD_FLAG_SERIAL)) {
+            L.mon_U2 = L.total;
+            L.total += align256(sizeof(double) * (size_t)((int64_t)sa.s * sa.b * sa.A->m));
+        }
+    }
     if (sa.opt.flags & KDCD_FLAG_GRAPH) {
         rc = run_graph_windowed(sa, L);
         if (rc != KDCD_ERR_UNSUPPORTED) return rc;
@@ -1344,8 +1399,9 @@ kdcd_status kdcd_batch_solve(const kdcd_matrix *A, const kdcd_kernel *kernel, in
     }
     L.total = off;
 
-    // the work of the call on stream cs in the workspace at wsbase; in graph
-    // mode the descriptor was copied before the capture
+    // the work of the call on stream cs in the workspace at wsbase (the
+    // descriptor is written by a kernel, so a captured graph rewrites it on
+    // every replay)
     auto enqueue = [&](char *wsbase, hipStream_t cs, bool graph, StageTimer &timer) -> kdcd_status {
     const hipStream_t st = cs;
     Workspace ws;            // a view: not owned
@@ -1359,7 +1415,8 @@ kdcd_status kdcd_batch_solve(const kdcd_matrix *A, const kdcd_kernel *kernel, in
     double *W = ws.at<double>(o_W);
     double *Dinv = ws.at<double>(o_D);
 
-    if (!graph) KDCD_HIP_TRY(hipMemcpyAsync(dbd, &bd, sizeof(BatchDesc), hipMemcpyHostToDevice, st));
+    (void)graph;
+    KDCD_HIP_TRY(launch_copy_batch_desc(bd, dbd, st));
     KDCD_HIP_TRY(launch_fill_i32(status, 0, 1, st));
     KDCD_HIP_TRY(launch_validate(idx, H * b, A->m, nullptr, nullptr, 0, 0, 0.0, status, st));
     for (int p = 0; p < n_problems; ++p) {
@@ -1538,13 +1595,7 @@ kdcd_status kdcd_batch_solve(const kdcd_matrix *A, const kdcd_kernel *kernel, in
         }
         key.options(o);
         return run_graph(
-            key.k, L.total, o, st,
-            [&](char *wsbase) {
-                return hipMemcpy(wsbase + o_bd, &bd, sizeof(BatchDesc), hipMemcpyHostToDevice) ==
-                               hipSuccess
-                           ? KDCD_OK
-                           : KDCD_ERR_HIP;
-            },
+            key.k, L.total, o, st, nullptr,
             [&](char *wsbase, hipStream_t cs) {
                 StageTimer off;
                 return enqueue(wsbase, cs, true, off);

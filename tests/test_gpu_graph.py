@@ -190,3 +190,36 @@ def test_windowed_graph_equals_eager(K, case):
         solve(H, buf, g, flags=K.FLAG_GRAPH)
         torch.cuda.synchronize()
         assert torch.equal(g, eager), (case, H, seed)
+
+
+def test_batch_graph_and_eager_call_share_a_workspace(K):
+    """A graph call and an eager call on one caller workspace: every replay runs
+    with the graph's own problems (its batch descriptor is rewritten by a
+    kernel inside the graph, not left in the workspace from the capture)."""
+    m = 1500
+    d = inputs.dense_c4(m=m, n=64, n_classes=3, seed=6)
+    A, y = dev(d["A"]), dev(d["y"])
+    b, s, H = 4, 8, 40
+    idx = idx_dev(inputs.krr_indices(m, b, H, seed=1))
+    ws = torch.zeros(64 << 20, dtype=torch.uint8, device="cuda")
+    kern = (2, 1.0, 0.0, 1)
+
+    def probs(lam):
+        return [K.BatchProblem("krr", lam, sg, y, torch.zeros(m, dtype=torch.float64, device="cuda"))
+                for sg in (0.5, 1.0)]
+
+    ref = probs(1e-3)
+    K.kdcd_batch_solve(A, kern, b, s, H, idx, ref)
+    g, other = probs(1e-3), probs(1e-2)
+    for rep in range(3):
+        for p in g:
+            p.alpha.zero_()
+        K.kdcd_batch_solve(A, kern, b, s, H, idx, g, flags=K.FLAG_GRAPH, workspace=ws)
+        torch.cuda.synchronize()
+        for pr, pg in zip(ref, g):
+            assert torch.equal(pr.alpha, pg.alpha), f"replay {rep}"
+        for p in other:
+            p.alpha.zero_()
+        K.kdcd_batch_solve(A, kern, b, s, H, idx, other, workspace=ws)   # same workspace
+        torch.cuda.synchronize()
+        assert all(float(p.alpha.abs().max()) > 0 for p in other)

@@ -136,3 +136,48 @@ def test_c2_default_is_lookahead_and_matches_serial(K):
                        K.FLAG_LOOKAHEAD)
     assert_parity(a3, a_ref, TOL, "alpha")
     assert_parity(t3, d_ref, TOL, "delta")
+
+
+def _krr_rel(ev, m):
+    bound = 0.5 * ev["residual_norm"] ** 2 / m
+    return bound / (abs(ev["objective"]) - bound)
+
+
+@pytest.mark.parametrize("H_outer,every", [(13, 4), (12, 16)])
+def test_lookahead_monitor_value(K, H_outer, every):
+    """The monitor inside the lookahead loop: the iterate is the unmonitored
+    lookahead solve's bit for bit, and the reported bound matches the oracle's
+    at the end (also when the only evaluation is the final one)."""
+    m, n, b, s = 2000, 64, 8, 32
+    H = H_outer * s - 3
+    d = inputs.dense_krr_c2(m=m, n=n, seed=12)
+    idx = inputs.krr_indices(m, b, H, seed=2)
+    a = dev(np.zeros(m))
+    info = K.kdcd_krr_solve(dev(d["A"]), dev(d["y"]), RBF1, 1e-3, b, s, H, idx_dev(idx), a,
+                            monitor_every=every, tol=0.0, flags=K.FLAG_LOOKAHEAD)
+    plain, _, _ = _solve(K, d["A"], d["y"], RBF1, 1e-3, b, s, H, idx, K.FLAG_LOOKAHEAD)
+    assert np.array_equal(a.cpu().numpy(), plain)
+    assert info["outer_done"] == H_outer
+    ev = O.krr_eval(d["A"], d["y"], O.Kernel(O.RBF, sigma=1.0), 1e-3, plain)
+    ref = _krr_rel(ev, m)
+    assert ref > 0 and abs(info["rel_err"] - ref) <= 1e-7 * ref
+
+
+def test_lookahead_monitor_early_stop(K):
+    """Stop at 1e-6: the result equals a lookahead solve of exactly the reported
+    outer iterations (to rounding: there the last block's recurrence is a launch
+    of its own), and the oracle's bound at it is within the target."""
+    m, n, b, s = 3000, 64, 8, 32
+    H = 400 * s
+    d = inputs.dense_krr_c2(m=m, n=n, seed=10)
+    idx = inputs.krr_indices(m, b, H, seed=5)
+    a = dev(np.zeros(m))
+    info = K.kdcd_krr_solve(dev(d["A"]), dev(d["y"]), RBF1, 1e-3, b, s, H, idx_dev(idx), a,
+                            monitor_every=8, tol=1e-6, flags=K.FLAG_LOOKAHEAD)
+    k = info["outer_done"]
+    assert 0 < k < H // s and k % 8 == 0 and info["rel_err"] <= 1e-6
+    plain, _, _ = _solve(K, d["A"], d["y"], RBF1, 1e-3, b, s, k * s, idx[:k * s * b],
+                         K.FLAG_LOOKAHEAD)
+    assert max_rel(a.cpu().numpy(), plain) <= 1e-12
+    ev = O.krr_eval(d["A"], d["y"], O.Kernel(O.RBF, sigma=1.0), 1e-3, plain)
+    assert _krr_rel(ev, m) <= 1e-6 * (1 + 1e-6)
