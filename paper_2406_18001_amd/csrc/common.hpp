@@ -175,6 +175,10 @@ struct KBlockArgs {
     // CSR only: the dense-head panel (kblock_csr_panel_bytes(n) bytes, prepared
     // once with launch_csr_panel_init); null keeps the broadcast kernels
     void *csr_panel = nullptr;
+    // CSR: the longest row of A (stored entries) when the caller knows it, else
+    // -1; a chunk of sampled rows that cannot exceed the dense-head panel then
+    // skips the broadcast launch that would only run for an overflowing chunk
+    int64_t csr_max_row = -1;
     // dense single-problem FP64 product: tile configuration, resolved once by
     // the caller together with the row-group count the finish pass sums
     // (-1: looked up in the tuning table at launch)
@@ -387,6 +391,7 @@ hipError_t launch_copy_batch_desc(const BatchDesc &d, BatchDesc *dst, hipStream_
 hipError_t launch_window_advance(const int32_t *idx, int64_t *counter, int32_t *Swin, int32_t W,
                                  int32_t sb, hipStream_t st);
 hipError_t launch_validate_csr(const kdcd_matrix *A, int32_t *status, hipStream_t st);
+hipError_t launch_csr_row_max(const kdcd_matrix *A, unsigned long long *out, hipStream_t st);
 hipError_t launch_iota_i32(int32_t *p, int64_t count, hipStream_t st);
 
 }  // namespace kdcd

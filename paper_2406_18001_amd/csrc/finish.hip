@@ -70,6 +70,25 @@ __global__ __launch_bounds__(256) void validate_csr_kernel(const int64_t *__rest
     }
 }
 
+// Longest row of a CSR matrix (stored entries) into *out (cleared by the caller);
+// a decreasing row_ptr gives a huge unsigned length, i.e. no bound.
+__global__ __launch_bounds__(256) void csr_row_max_kernel(const int64_t *__restrict__ row_ptr,
+                                                          int64_t m, unsigned long long *out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    unsigned long long v = 0;
+    for (int64_t r = i; r < m; r += stride) {
+        const unsigned long long len = (unsigned long long)(row_ptr[r + 1] - row_ptr[r]);
+        v = len > v ? len : v;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(v, off);
+        v = o > v ? o : v;
+    }
+    if ((threadIdx.x & 63) == 0) atomicMax(out, v);
+}
+
 __global__ void fill_i32_kernel(int32_t *p, int32_t v, int64_t count)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -280,6 +299,18 @@ hipError_t launch_validate_csr(const kdcd_matrix *A, int32_t *status, hipStream_
 {
     hipLaunchKernelGGL(validate_csr_kernel, dim3(2048), dim3(256), 0, st, A->row_ptr, A->col_idx,
                        A->m, A->n, A->nnz, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_csr_row_max(const kdcd_matrix *A, unsigned long long *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, st, reinterpret_cast<int32_t *>(out),
+                       0, (int64_t)2);
+    int64_t blocks = (A->m + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(csr_row_max_kernel, dim3((unsigned)blocks), dim3(256), 0, st, A->row_ptr,
+                       A->m, out);
     return hipGetLastError();
 }
 

@@ -1143,7 +1143,8 @@ hipError_t launch_kblock_csr(const KBlockArgs &a, hipStream_t st)
     const CsrPath path = csr_path(A, a.sb);
     if (path == CSR_HEAD && a.csr_panel) {
         // per chunk of HD_NJ sampled rows: panel build, dense-head pass, and the
-        // broadcast kernel gated on the build's fallback flag
+        // broadcast kernel gated on the build's fallback flag (left out when the
+        // longest row of A says that the chunk fits the panel)
         const int64_t groups = kblock_csr_row_groups(A, a.sb);
         const int64_t n_w = a.W ? (a.sb + HD_RB - 1) / HD_RB : 0;
         const PanelPtrs q = panel_ptrs(a.csr_panel, A->n);
@@ -1172,6 +1173,8 @@ hipError_t launch_kblock_csr(const KBlockArgs &a, hipStream_t st)
             }
 #undef KDCD_CSR_HEAD
             if (lastc && armed.stop) (void)hipEventRecord(armed.stop, st);
+            // no chunk of nj rows of at most csr_max_row entries overflows the panel
+            if (a.csr_max_row >= 0 && a.csr_max_row * (int64_t)nj <= HD_CAP) continue;
             dim3 gridb((unsigned)(groups_b + n_w_b)), blockb(CSR_NT);
 #define KDCD_CSR_FB(RPW, KIND)                                                                  \
     hipLaunchKernelGGL((kblock_csr_kernel<RPW, KIND>), gridb, blockb, 0, st, A->row_ptr,          \

@@ -380,6 +380,7 @@ struct SolveArgs {
     double *alpha;
     kdcd_options opt;
     hipStream_t st;
+    int64_t csr_max_row = -1;   // CSR: longest row of A, when measured (-1: unknown)
 };
 
 kdcd_status prepare_lowp(const KBlockArgs &base, const Layout &L, Workspace &ws, hipStream_t st,
@@ -783,6 +784,7 @@ kdcd_status enqueue_solve(const SolveArgs &sa, const Layout &L, char *wsbase, St
     if (A->format == KDCD_CSR) {
         base.carry = ws.at<double>(L.carry);
         base.csr_panel = ws.at<void>(L.panel);
+        base.csr_max_row = sa.csr_max_row;
         if (R.setup) KDCD_HIP_TRY(launch_csr_panel_init(A, base.csr_panel, st));
     }
     KBlockArgs kb;
@@ -1256,9 +1258,21 @@ kdcd_status run_solve(const SolveArgs &sa)
     }
     Workspace ws;
     if ((rc = acquire(ws, L, &sa.opt, sa.st)) != KDCD_OK) return rc;
+    SolveArgs sx = sa;
+    if (sa.A->format == KDCD_CSR && sa.A->m > 0) {
+        // the longest row (one reduction and a wait at the start of the call),
+        // so that chunks which cannot overflow the dense-head panel skip the
+        // gated broadcast launch (kept by graph calls, which cannot wait)
+        unsigned long long *dmax = reinterpret_cast<unsigned long long *>(ws.at<char>(L.status) + 8);
+        unsigned long long hmax = ~0ull;
+        KDCD_HIP_TRY(launch_csr_row_max(sa.A, dmax, sa.st));
+        KDCD_HIP_TRY(hipMemcpyAsync(&hmax, dmax, sizeof(hmax), hipMemcpyDeviceToHost, sa.st));
+        KDCD_HIP_TRY(hipStreamSynchronize(sa.st));
+        if (hmax <= (unsigned long long)sa.A->n) sx.csr_max_row = (int64_t)hmax;
+    }
     StageTimer timer;
     timer.on = sa.opt.profile != nullptr;
-    rc = enqueue_solve(sa, L, ws.base, timer);
+    rc = enqueue_solve(sx, L, ws.base, timer);
     if (rc != KDCD_OK) {
         (void)hipStreamSynchronize(sa.st);
         return rc;
