@@ -181,3 +181,20 @@ def test_lookahead_monitor_early_stop(K):
     assert max_rel(a.cpu().numpy(), plain) <= 1e-12
     ev = O.krr_eval(d["A"], d["y"], O.Kernel(O.RBF, sigma=1.0), 1e-3, plain)
     assert _krr_rel(ev, m) <= 1e-6 * (1 + 1e-6)
+
+
+def test_lookahead_in_a_captured_graph(K):
+    """A whole-call graph of the lookahead loop (fewer than 18 whole blocks, so
+    the call is captured, not windowed): every replay equals the eager solve."""
+    m, n, b, s, H = 2000, 64, 8, 32, 5 * 32 - 3
+    d = inputs.dense_krr_c2(m=m, n=n, seed=13)
+    idx = inputs.krr_indices(m, b, H, seed=4)
+    ref, _, _ = _solve(K, d["A"], d["y"], RBF1, 1e-3, b, s, H, idx, K.FLAG_LOOKAHEAD)
+    A, y, I = dev(d["A"]), dev(d["y"]), idx_dev(idx)
+    a = torch.zeros(m, dtype=torch.float64, device="cuda")
+    for rep in range(3):
+        a.zero_()
+        K.kdcd_krr_solve(A, y, RBF1, 1e-3, b, s, H, I, a,
+                         flags=K.FLAG_GRAPH | K.FLAG_LOOKAHEAD)
+        torch.cuda.synchronize()
+        assert np.array_equal(a.cpu().numpy(), ref), f"replay {rep}"
