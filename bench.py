@@ -93,16 +93,27 @@ PROFILE_LOWP = os.path.join(ROOT, "profiles", "kblock_lowp_krr_c4_bf16.txt")
 KBLOCK_LOWP_SRC = os.path.join(ROOT, "paper_2406_18001_amd", "csrc", "kblock_lowp.hip")
 PROFILE_CSR = os.path.join(ROOT, "profiles", "kblock_csr_head_c3_s32.txt")
 KBLOCK_CSR_SRC = os.path.join(ROOT, "paper_2406_18001_amd", "csrc", "kblock_csr.hip")
-KBLOCK_F64_SRC = os.path.join(ROOT, "paper_2406_18001_amd", "csrc", "kblock_f64.hip")
+# the FP64 product and the lookahead recurrence its workgroup 0 runs
+KBLOCK_F64_SRC = [os.path.join(ROOT, "paper_2406_18001_amd", "csrc", "kblock_f64.hip"),
+                  os.path.join(ROOT, "paper_2406_18001_amd", "csrc", "la_recur.hpp")]
+
+
+def source_digest(source):
+    """sha256 of a kernel source file, or of several concatenated in order."""
+    import hashlib
+    paths = source if isinstance(source, (list, tuple)) else [source]
+    h = hashlib.sha256()
+    for path in paths:
+        h.update(open(path, "rb").read())
+    return h.hexdigest()
 
 
 def profiled_traffic(profile, source):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
     None when the kernel source has changed since the counters were taken."""
-    import hashlib
     try:
         text = open(profile).read()
-        digest = hashlib.sha256(open(source, "rb").read()).hexdigest()
+        digest = source_digest(source)
     except OSError:
         return None
     vals = {}
