@@ -224,12 +224,24 @@ __global__ __launch_bounds__(256) void finish_kernel(const FinishDesc d, int32_t
         const int64_t w = src_row(t);
         if (w == t) return;
         const int32_t St = d.dup_S[t];
-        for (int64_t c = lane; c < sb; c += 64) {
-            double v = d.dup_W[w * sb + c];
-            // lookahead: lambda m at the other elements of the coordinate, so that
-            // the recurrence reads G = W' / lambda without comparing coordinates
-            if (d.la_lm != 0.0 && c != t && d.dup_S[c] == St) v += d.la_lm;
-            d.dup_W[t * sb + c] = v;
+        // the whole row is loaded before any store (a load after a store to the
+        // same array cannot be moved ahead of it, which left one load latency
+        // per 64 columns); lookahead: lambda m at the other elements of the
+        // coordinate, so that the recurrence reads G = W' / lambda without
+        // comparing coordinates
+        constexpr int DUPC = kMaxSB / 64;
+        double v[DUPC];
+        int32_t sc[DUPC];
+#pragma unroll
+        for (int u = 0; u < DUPC; ++u) {
+            const int64_t c = lane + 64 * u;
+            v[u] = c < sb ? d.dup_W[w * sb + c] : 0.0;
+            sc[u] = (c < sb && d.la_lm != 0.0) ? d.dup_S[c] : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < DUPC; ++u) {
+            const int64_t c = lane + 64 * u;
+            if (c < sb) d.dup_W[t * sb + c] = (c != t && sc[u] == St) ? v[u] + d.la_lm : v[u];
         }
         return;
     }
