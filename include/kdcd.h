@@ -141,9 +141,10 @@ typedef struct {
  */
 /*
  * Lookahead loop (kdcd_krr_solve and kdcd_krr_solve_noalloc; dense A, FP64,
- * b <= 8, s*b >= 256 and at most twice the threads of the product's
- * workgroup, n a multiple of 16 with 16-byte aligned rows, at least two outer
- * iterations, no monitor and no snapshots): the s-step recurrence of index
+ * b <= 8, 256 <= s*b <= 512, n a multiple of 16 with 16-byte aligned rows, at
+ * least two outer iterations, no snapshots, and with the monitor only without
+ * a caller workspace, whose size does not include the second stored kernel
+ * block the loop then keeps): the s-step recurrence of index
  * block k (Algorithm 4's inner loop) runs in one workgroup of the launch that
  * computes the kernel block of index block k+1.  That product reduces r_{k+1}
  * against the iterate before block k's updates and also stores the kernel

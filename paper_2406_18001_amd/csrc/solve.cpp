@@ -181,7 +181,7 @@ Layout make_layout(int32_t problem, const kdcd_matrix *A, const kdcd_kernel *ker
     L.iota = off; off += (problem == 2) ? align256(sizeof(int32_t) * (size_t)A->m) : 0;
     L.pos = off; off += align256(sizeof(int32_t) * (size_t)A->m);   // row -> position in S
     L.la_ok = problem == 1 && A->format == KDCD_DENSE && compute == KDCD_F64 &&
-              sb >= kGatherMinSB && b <= kLaMaxB && sb <= kLaEPT * 512;
+              sb >= kGatherMinSB && b <= kLaMaxB && sb <= kLaEPT * 256;
     const size_t gram = align256(sizeof(double) * (size_t)(sb * sb));
     L.pos2 = off; off += L.la_ok ? align256(sizeof(int32_t) * (size_t)A->m) : 0;
     L.W2 = off; off += L.la_ok ? gram : 0;
@@ -530,9 +530,9 @@ struct SolveRange {
 constexpr double kLaMinFlops = 4e9;
 
 // Whether a K-RR solve runs the lookahead loop (see LookaheadArgs): dense FP64
-// with a gathered Gram, b <= 8, whole product tiles along K, every product
-// configuration of the solve wide enough to hold the recurrence's elements,
-// no monitor or snapshots, the whole solve in one call.
+// with a gathered Gram, b <= 8, 256 <= s*b <= 512, whole product tiles along
+// K, no snapshots (the monitor only with the second stored kernel block), the
+// whole solve in one call.
 bool lookahead_use(const SolveArgs &sa, const Layout &L, const KBlockArgs &kb,
                    const SolveRange &R)
 {
@@ -546,13 +546,10 @@ bool lookahead_use(const SolveArgs &sa, const Layout &L, const KBlockArgs &kb,
     if (n_outer < 2) return false;
     const bool aligned = (A->ld % 2 == 0) && ((reinterpret_cast<uintptr_t>(A->values) & 15) == 0);
     if (!aligned || A->n % 16 != 0) return false;
+    // every product configuration has at least 256 threads, so the recurrence
+    // fits whichever configuration a launch resolves
     const int64_t sb_full = (int64_t)sa.s * sa.b;
-    const int64_t sb_last = (sa.H - (n_outer - 1) * sa.s) * sa.b;
-    for (const int64_t sbv : {sb_full, sb_last}) {
-        int bm = 0, bn = 0, waves = 0;
-        f64_config_shape(f64_config_id(A->n, (int32_t)sbv), &bm, &bn, &waves);
-        if (sb_full > (int64_t)kLaEPT * 64 * waves) return false;
-    }
+    if (sb_full > (int64_t)kLaEPT * 256) return false;
     if (sa.opt.flags & KDCD_FLAG_LOOKAHEAD) return true;
     return 2.0 * (double)A->m * (double)A->n * (double)sb_full >= kLaMinFlops;
 }
