@@ -198,3 +198,26 @@ def test_lookahead_in_a_captured_graph(K):
                          flags=K.FLAG_GRAPH | K.FLAG_LOOKAHEAD)
         torch.cuda.synchronize()
         assert np.array_equal(a.cpu().numpy(), ref), f"replay {rep}"
+
+
+@pytest.mark.parametrize("case", range(8))
+def test_lookahead_equals_serial_on_seeded_shapes(K, case):
+    """Seeded shapes across the lookahead's range (b in 1..8, 256 <= s*b <= 512,
+    ragged H, n a multiple of 16, m from below s*b to well above): the
+    lookahead loop and the serial loop agree to the parity bar."""
+    rng = np.random.default_rng(100 + case)
+    b = int(rng.choice([1, 2, 4, 8]))
+    s = int(rng.integers(256 // b, 512 // b + 1))
+    n = 16 * int(rng.integers(1, 9))
+    m = int(rng.integers(200, 6000))
+    H = int(rng.integers(2 * s, 6 * s))
+    d = inputs.dense_krr_c2(m=m, n=n, seed=200 + case)
+    idx = inputs.krr_indices(m, b, H, seed=300 + case)
+    kern = (2, float(rng.choice([0.25, 1.0])), 0.0, 1)
+    lam = float(rng.choice([1e-3, 1e-2]))
+    a_la, t_la, res = _solve(K, d["A"], d["y"], kern, lam, b, s, H, idx, K.FLAG_LOOKAHEAD,
+                             profile=True)
+    assert res["recur_launches"] == 1
+    a_se, t_se, _ = _solve(K, d["A"], d["y"], kern, lam, b, s, H, idx, K.FLAG_SERIAL)
+    assert max_rel(a_la, a_se) <= TOL, (m, n, b, s, H)
+    assert max_rel(t_la, t_se) <= TOL, (m, n, b, s, H)
