@@ -122,3 +122,26 @@ def test_tuning_table_host_side(tmp_path):
     bad.write_text("0 10 10 99\n")
     assert lib.kdcd_tune_load(str(bad).encode()) == -1
     assert lib.kdcd_tune_set(0, 777, 96, -1) == 0
+
+
+def test_flag_constants_match_the_header():
+    from paper_2406_18001_amd import kdcd as K
+    text = open(HEADER).read()
+    for name in ("GRAPH", "TIME_PRODUCT", "TIME_SAMPLE", "LOOKAHEAD", "SERIAL"):
+        m = re.search(r"KDCD_FLAG_%s\s*=\s*(\d+)" % name, text)
+        assert m and int(m.group(1)) == getattr(K, "FLAG_" + name), name
+
+
+def test_unknown_flag_bits_are_refused_on_the_host():
+    """Bits outside KDCD_FLAG_* are refused before any device work."""
+    from paper_2406_18001_amd import kdcd as K
+    mat = K._Matrix()
+    mat.format, mat.m, mat.n, mat.ld = 0, 5000, 4, 4
+    mat.values = 16                        # never dereferenced: the call is refused first
+    good = K._Kernel(2, 1, 1.0, 0.0)
+    for bad in (2, 64, 1 << 20):
+        opt = K._Options()
+        opt.flags = bad
+        rc = K._lib.kdcd_krr_solve(ctypes.byref(mat), 16, ctypes.byref(good), 1e-3, 8, 32, 64,
+                                   16, 16, ctypes.byref(opt), None)
+        assert rc == -1, (bad, rc)
