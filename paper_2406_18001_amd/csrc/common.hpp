@@ -187,6 +187,10 @@ struct KBlockArgs {
     // K-RR lookahead launch described by *la (the recurrence of the previous
     // block in workgroup 0, the product storing QX)
     const LookaheadArgs *la = nullptr;
+    // dense FP64 Gram tiles: their rows are S[w_row0 .. w_row0 + w_rows) (w_rows
+    // <= 0: the sb rows of S), W is then w_rows x sb; the batched launch ignores it
+    int32_t w_row0 = 0;
+    int32_t w_rows = 0;
 };
 
 // K-RR lookahead (one problem, dense FP64, gathered Gram).  The recurrence of

@@ -5,7 +5,10 @@
 //             epilogue, and the column sums partial[g][j] = sum_{p in group g}
 //             K(a_p, a_{S_j}) beta_p -- the right-hand side U^T beta of
 //             Algorithms 2 and 4 -- without ever writing U;
-//   W-tiles:  W = K(A_S, A_S) (sb x sb), the sampled Gram V^T U.
+//   W-tiles:  W = K(A_S, A_S) (sb x sb), the sampled Gram V^T U; with a row
+//             range (w_row0, w_rows) the rows are S[w_row0 .. w_row0 + w_rows)
+//             instead (W then w_rows x sb: index blocks stored back to back
+//             give the Gram of one block against the next in one launch).
 // Both read the sampled rows straight from A through S (no gather pass).
 //
 // Tiling: a workgroup of WM x WN waves owns a BM x BN tile; each wave owns
@@ -63,7 +66,8 @@ void kblock_f64_kernel(
     double *__restrict__ partial, double *__restrict__ W, int32_t n_u_tiles,
     int32_t n_row_groups, int32_t n_w_tiles, int32_t n_tiles_n, int32_t aligned,
     const BatchDesc *__restrict__ bd, double *__restrict__ U, const int32_t *__restrict__ stop,
-    const int32_t *__restrict__ pos, int64_t u_gstride, const LookaheadArgs la)
+    const int32_t *__restrict__ pos, int64_t u_gstride, int32_t w_row0, int32_t w_rows,
+    const LookaheadArgs la)
 {
     if (stop && *stop) return;   // the solve has converged
     constexpr int NT = 64 * WM * WN;
@@ -147,7 +151,7 @@ void kblock_f64_kernel(
             const int r = (seg < BM * 4) ? (seg >> 2) : 0;
             const int c = seg & 3;
             int64_t row;
-            if (is_w) row = clampi(S[clampi(row0 + r, 0, sb - 1)], 0, m - 1);
+            if (is_w) row = clampi(S[w_row0 + clampi(row0 + r, 0, w_rows - 1)], 0, m - 1);
             else row = clampi(row0 + r, 0, m - 1);
             aptr[i] = A + row * lda + 4 * c;
         }
@@ -410,8 +414,8 @@ void kblock_f64_kernel(
                                         la.QX[(int64_t)xrow * sb + gcol] = kv;
                                 }
                         }
-                    } else if (grow < sb) {
-                        const int64_t St = clampi(S[grow], 0, m - 1);
+                    } else if (grow < w_rows) {
+                        const int64_t St = clampi(S[w_row0 + grow], 0, m - 1);
                         const double na = (KIND == KDCD_KERNEL_RBF) ? norms[St] : 0.0;
 #pragma unroll
                         for (int tn = 0; tn < TN; ++tn) {
@@ -505,7 +509,8 @@ hipError_t launch_cfg(const KBlockArgs &a, hipStream_t st)
     const kdcd_matrix *A = a.A;
     const int64_t n_u = a.w_only ? 0 : (A->m + BM - 1) / BM;
     const int64_t groups = n_u < kMaxRowGroups ? n_u : kMaxRowGroups;
-    const int64_t n_w = (a.W && !a.pos) ? (a.sb + BM - 1) / BM : 0;
+    const int32_t w_rows = a.w_rows > 0 ? a.w_rows : a.sb;
+    const int64_t n_w = (a.W && !a.pos) ? (w_rows + BM - 1) / BM : 0;
     if (groups + n_w == 0) return hipSuccess;
     const int64_t n_n = (a.sb + BN - 1) / BN;
     const int aligned = (A->ld % 2 == 0) && ((reinterpret_cast<uintptr_t>(A->values) & 15) == 0);
@@ -521,7 +526,7 @@ hipError_t launch_cfg(const KBlockArgs &a, hipStream_t st)
                        st, A->values, A->ld, A->m, A->n, a.S, a.sb, a.norms, a.kp, a.beta,      \
                        a.beta_scale, a.partial, a.W, (int32_t)n_u, (int32_t)groups,            \
                        (int32_t)n_w, (int32_t)n_n, aligned, a.batch, a.U, a.stop,              \
-                       BATCH ? nullptr : a.pos, a.u_gstride, lav)
+                       BATCH ? nullptr : a.pos, a.u_gstride, a.w_row0, w_rows, lav)
 #define KDCD_LAUNCH(KIND)                                                                      \
     do {                                                                                        \
         if (la) {                                                                               \

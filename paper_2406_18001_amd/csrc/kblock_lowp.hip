@@ -22,6 +22,7 @@
 // in order, hi.hi, hi.lo, lo.hi) whatever the tile, so the batched variant's
 // kernel values are bit for bit those of the single-problem launch.
 #include "common.hpp"
+#include "la_recur.hpp"
 
 namespace kdcd {
 namespace {
@@ -76,14 +77,17 @@ __device__ __forceinline__ float lowp_map(float p, float nab, float s2, float c,
 
 // BK: elements of K per LDS stage (32, or 16 for bf16x3 whose stages hold two
 // layers).  Loads run two stages ahead of the MFMAs (two register stages).
-template <int CMP, int KIND, int BK, int TM, int TN, int OCC, bool STORE_U>
+// LAH: a K-RR lookahead launch: workgroup 0 runs la_recur for the previous
+// block, workgroups 1 .. kLaLead - 1 return, the tiles follow (the kernel rows
+// of the previous block's coordinates come from the FP64 Gram launch).
+template <int CMP, int KIND, int BK, int TM, int TN, int OCC, bool STORE_U, bool LAH>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(OCC)))
 void kblock_lowp_kernel(
     const u4 *__restrict__ Ahi, const u4 *__restrict__ Alo, int64_t ldseg, int64_t m,
     int64_t nchunks, const float *__restrict__ normlow, const int32_t *__restrict__ S, int32_t sb,
     KParams kp, const double *__restrict__ beta, const double *__restrict__ bscale,
     double *__restrict__ partial, int32_t n_u_tiles, int32_t n_row_groups, int32_t n_tiles_n,
-    double *__restrict__ U, const int32_t *__restrict__ stop)
+    double *__restrict__ U, const int32_t *__restrict__ stop, const LookaheadArgs la)
 {
     if (stop && *stop) return;
     constexpr bool X3 = CMP == KDCD_BF16X3;
@@ -106,11 +110,26 @@ void kblock_lowp_kernel(
     __shared__ u4 Bs[2][NL][SB];
     __shared__ double red[2][BN];
 
+    if constexpr (LAH) {
+        static_assert((int)sizeof(As) >= 24 * kThreads + 8 * (2 * kLaMaxB + 256) + kThreads / 4,
+                      "the lookahead recurrence's LDS must fit the A buffers");
+        if (blockIdx.x < kLaLead) {
+            if (blockIdx.x == 0 && la.sb > 0) {
+                char *smem = reinterpret_cast<char *>(&As[0][0][0]);
+                if (la.b == 8) la_recur<kThreads, 8>(la, smem);
+                else la_recur<kThreads, 0>(la, smem);
+            }
+            return;
+        }
+    }
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int wm = wid >> 1, wn = wid & 1;
     const int lslot = (lane >> 5) * HOFF + (lane & 31);   // this lane's slot in a fragment
     const int total = n_tiles_n * n_row_groups;
-    const int L = xcd_remap(blockIdx.x, total);
+    // the leading workgroups of a lookahead launch are a multiple of 8, so
+    // bid % 8 is still the XCD of the workgroup
+    const int bid = LAH ? (int)blockIdx.x - kLaLead : (int)blockIdx.x;
+    const int L = xcd_remap(bid, total);
     const int cn = L % n_tiles_n;
     const int rg = L / n_tiles_n;
     const int col0 = cn * BN;
@@ -337,18 +356,29 @@ hipError_t launch_u(const KBlockArgs &a, hipStream_t st)
     const int64_t ldseg = a.ldlow * 2 / 16;
     if (a.ldlow % BK != 0 || a.ldlow < BK) return hipErrorInvalidValue;   // whole stages only
     const int64_t nchunks = a.ldlow / BK;          // ldlow is a multiple of 64
-    dim3 grid((unsigned)(n_n * groups)), block(kThreads);
+    const bool la = a.la != nullptr;
+    if (la && !(a.la->b <= kLaMaxB && a.la->sb <= kLaEPT * kThreads))
+        return hipErrorInvalidValue;   // the caller checks lookahead_use first
+    const LookaheadArgs lav = la ? *a.la : LookaheadArgs{};
+    dim3 grid((unsigned)(n_n * groups + (la ? kLaLead : 0))), block(kThreads);
+#define KDCD_LAUNCH_L(KIND, LAH)                                                                  \
+    KDCD_TIMED_LAUNCH((kblock_lowp_kernel<CMP, KIND, BK, TM, TN, OCC, STORE_U, LAH>), grid,       \
+                      block, 0, st, static_cast<const u4 *>(a.Alow),                              \
+                      static_cast<const u4 *>(a.Alow2), ldseg, A->m, nchunks, a.normlow, a.S,     \
+                      a.sb, a.kp, a.beta, a.beta_scale, a.partial, (int32_t)n_u, (int32_t)groups, \
+                      (int32_t)n_n, a.U, a.stop, lav)
 #define KDCD_LAUNCH(KIND)                                                                         \
-    KDCD_TIMED_LAUNCH((kblock_lowp_kernel<CMP, KIND, BK, TM, TN, OCC, STORE_U>), grid, block, 0,   \
-                      st, static_cast<const u4 *>(a.Alow), static_cast<const u4 *>(a.Alow2),      \
-                      ldseg, A->m, nchunks, a.normlow, a.S, a.sb, a.kp, a.beta, a.beta_scale,     \
-                      a.partial, (int32_t)n_u, (int32_t)groups, (int32_t)n_n, a.U, a.stop)
+    do {                                                                                          \
+        if (la) KDCD_LAUNCH_L(KIND, true);                                                        \
+        else KDCD_LAUNCH_L(KIND, false);                                                          \
+    } while (0)
     switch (a.kp.kind) {
     case KDCD_KERNEL_LINEAR: KDCD_LAUNCH(KDCD_KERNEL_LINEAR); break;
     case KDCD_KERNEL_POLY: KDCD_LAUNCH(KDCD_KERNEL_POLY); break;
     default: KDCD_LAUNCH(KDCD_KERNEL_RBF); break;
     }
 #undef KDCD_LAUNCH
+#undef KDCD_LAUNCH_L
     return hipGetLastError();
 }
 

@@ -180,12 +180,16 @@ Layout make_layout(int32_t problem, const kdcd_matrix *A, const kdcd_kernel *ker
     L.Dinv = off; off += (problem == 1) ? align256(sizeof(double) * (size_t)(sb * b)) : 0;
     L.iota = off; off += (problem == 2) ? align256(sizeof(int32_t) * (size_t)A->m) : 0;
     L.pos = off; off += align256(sizeof(int32_t) * (size_t)A->m);   // row -> position in S
-    L.la_ok = problem == 1 && A->format == KDCD_DENSE && compute == KDCD_F64 &&
-              sb >= kGatherMinSB && b <= kLaMaxB && sb <= kLaEPT * 256;
+    const bool la_compute = compute == KDCD_F64 || compute == KDCD_BF16 ||
+                            compute == KDCD_F16 || compute == KDCD_BF16X3;
+    L.la_ok = problem == 1 && A->format == KDCD_DENSE && la_compute && sb >= kGatherMinSB &&
+              b <= kLaMaxB && sb <= kLaEPT * 256;
+    // FP64: second Gram and QX; low precision: one buffer of two Grams' rows
+    // (QX of the previous block, then the block's Gram)
     const size_t gram = align256(sizeof(double) * (size_t)(sb * sb));
     L.pos2 = off; off += L.la_ok ? align256(sizeof(int32_t) * (size_t)A->m) : 0;
-    L.W2 = off; off += L.la_ok ? gram : 0;
-    L.QX = off; off += L.la_ok ? gram : 0;
+    L.W2 = off; off += L.la_ok ? (compute == KDCD_F64 ? gram : 2 * gram) : 0;
+    L.QX = off; off += (L.la_ok && compute == KDCD_F64) ? gram : 0;
     L.la_dc = off; off += L.la_ok ? align256(sizeof(double) * (size_t)sb) : 0;
     L.la_sc = off; off += L.la_ok ? align256(sizeof(int32_t) * (size_t)sb) : 0;
     L.carry = off;   // CSR: partial dot products of sampled rows longer than the panel
@@ -537,15 +541,16 @@ bool lookahead_use(const SolveArgs &sa, const Layout &L, const KBlockArgs &kb,
                    const SolveRange &R)
 {
     const kdcd_matrix *A = sa.A;
-    if (!L.la_ok || !kb.pos || sa.problem != 1 || sa.b > kLaMaxB) return false;
+    const bool f64 = sa.opt.compute == KDCD_F64;
+    if (!L.la_ok || sa.problem != 1 || sa.b > kLaMaxB || (f64 && !kb.pos)) return false;
     if (sa.opt.flags & KDCD_FLAG_SERIAL) return false;
-    if (sa.opt.monitor_every > 0 && L.mon_U2 == 0) return false;
+    if (sa.opt.monitor_every > 0 && (!f64 || L.mon_U2 == 0)) return false;
     if (sa.opt.snapshot_every > 0 && sa.opt.snapshots) return false;
     if (R.k_begin != 0 || R.k_end >= 0 || R.S_base || !R.setup) return false;
     const int64_t n_outer = (sa.H + sa.s - 1) / sa.s;
     if (n_outer < 2) return false;
     const bool aligned = (A->ld % 2 == 0) && ((reinterpret_cast<uintptr_t>(A->values) & 15) == 0);
-    if (!aligned || A->n % 16 != 0) return false;
+    if (f64 && (!aligned || A->n % 16 != 0)) return false;
     // every product configuration has at least 256 threads, so the recurrence
     // fits whichever configuration a launch resolves
     const int64_t sb_full = (int64_t)sa.s * sa.b;
@@ -732,6 +737,178 @@ kdcd_status enqueue_lookahead(const SolveArgs &sa, const Layout &L, Workspace &w
     return KDCD_OK;
 }
 
+// The lookahead loop with a low-precision product (bf16, f16, bf16x3).  As the
+// FP64 loop, but the product stores no Gram rows: after each lookahead launch
+// an FP64 Gram launch takes the rows of index blocks k and k+1, which lie back
+// to back in idx, against block k+1's columns, giving in one buffer the kernel
+// rows of block k's coordinates (QX, here in FP64) followed by block k+1's
+// Gram.  The buffer is overwritten only after the launch whose recurrence read
+// block k's Gram and the finish pass that read block k's QX.
+kdcd_status enqueue_lookahead_lowp(const SolveArgs &sa, const Layout &L, Workspace &ws,
+                                   KBlockArgs kb, StageTimer &timer, bool product_only,
+                                   bool sampled)
+{
+    const kdcd_matrix *A = sa.A;
+    const hipStream_t st = sa.st;
+    int32_t *status = ws.at<int32_t>(L.status);
+    double *r = ws.at<double>(L.r);
+    double *Dinv = ws.at<double>(L.Dinv);
+    int32_t *P[2] = {ws.at<int32_t>(L.pos), ws.at<int32_t>(L.pos2)};
+    double *Wx = ws.at<double>(L.W2);
+    double *Dc = ws.at<double>(L.la_dc);
+    int32_t *Sc = ws.at<int32_t>(L.la_sc);
+    const int64_t n_outer = (sa.H + sa.s - 1) / sa.s;
+    auto block = [&](int64_t k, int32_t &sk, int32_t &sb) -> const int32_t * {
+        const int64_t done = k * sa.s;
+        sk = (int32_t)std::min<int64_t>(sa.s, sa.H - done);
+        sb = sk * sa.b;
+        return sa.idx + done * sa.b;
+    };
+    auto trace_of = [&](int64_t k) -> double * {
+        return sa.opt.trace ? sa.opt.trace + k * sa.s * sa.b : nullptr;
+    };
+    // the Gram of block k (after the QX rows of block k - 1, when there is one)
+    auto gram_of = [&](int64_t k) -> double * {
+        int32_t skk = 0, sbk = 0, skp = 0, sbp = 0;
+        block(k, skk, sbk);
+        if (k > 0) block(k - 1, skp, sbp);
+        return Wx + (int64_t)sbp * sbk;
+    };
+    auto gram_launch = [&](int64_t k) -> kdcd_status {
+        int32_t skk = 0, sbk = 0, skp = 0, sbp = 0;
+        const int32_t *Sk = block(k, skk, sbk);
+        if (k > 0) block(k - 1, skp, sbp);
+        KBlockArgs w = kb;
+        w.compute = KDCD_F64;
+        w.w_only = 1;
+        w.cfg = -1;
+        w.U = nullptr;
+        w.pos = nullptr;
+        w.la = nullptr;
+        w.S = Sk;
+        w.sb = sbk;
+        w.W = Wx;
+        w.w_row0 = -sbp;          // block k - 1's indices precede block k's in idx
+        w.w_rows = sbp + sbk;
+        KDCD_HIP_TRY(launch_kblock_f64(w, st));
+        return KDCD_OK;
+    };
+
+    KDCD_HIP_TRY(launch_fill_i32(P[0], -1, A->m, st));
+    KDCD_HIP_TRY(launch_fill_i32(P[1], -1, A->m, st));
+    int32_t sk0 = 0, sb0 = 0;
+    const int32_t *S0 = block(0, sk0, sb0);
+    {   // row table of block 0 (the positions of its coordinates)
+        KBlockArgs t = kb;
+        t.S = S0;
+        t.sb = sb0;
+        t.W = Wx;
+        t.pos = P[0];
+        t.prevS = nullptr;
+        t.prev_sb = 0;
+        t.w_only = 0;
+        KDCD_HIP_TRY(launch_kblock_f64_pre(t, st));
+    }
+    kb.S = S0;
+    kb.sb = sb0;
+    kb.pos = nullptr;
+    kb.la = nullptr;
+    int64_t groups = bind_config(kb);
+    timer.arm(0);
+    {
+        const hipError_t e = launch_kblock_mixed(kb, st);
+        timer.disarm();
+        KDCD_HIP_TRY(e);
+    }
+    kdcd_status rc = gram_launch(0);
+    if (rc != KDCD_OK) return rc;
+    for (int64_t k = 0; k < n_outer; ++k) {
+        int32_t sk = 0, sb = 0, sk1 = 0, sb1 = 0, skp = 0, sbp = 0;
+        const int32_t *S = block(k, sk, sb);
+        const int32_t *S1 = k + 1 < n_outer ? block(k + 1, sk1, sb1) : nullptr;
+        const int32_t *Sp = k > 0 ? block(k - 1, skp, sbp) : nullptr;
+        double *Wk = gram_of(k);
+        FinishDesc fd{};
+        fd.nprob = 1;
+        fd.nkrr = 1;
+        fd.groups = (int32_t)groups;
+        fd.partial[0] = ws.at<double>(L.partial);
+        fd.r[0] = r;
+        fd.W[0] = Wk;
+        fd.Dinv[0] = Dinv;
+        fd.inv_lambda[0] = 1.0 / sa.lambda;
+        fd.dup_S = S;
+        fd.dup_pos = P[k & 1];
+        fd.dup_W = Wk;
+        fd.m = A->m;
+        if (k > 0) {
+            fd.la_QX = Wx;            // block k - 1's rows against block k's columns
+            fd.la_Dc = Dc;
+            fd.la_Sc = Sc;
+            fd.la_sb = sbp;
+            fd.la_alpha = sa.alpha;
+        }
+        fd.la_pos = P[(k + 1) & 1];
+        fd.la_clearS = Sp;
+        fd.la_clear_sb = sbp;
+        fd.la_setS = S1;
+        fd.la_set_sb = sb1;
+        fd.la_lm = k + 1 < n_outer ? sa.lambda * (double)A->m : 0.0;
+        if (!product_only) timer.arm(1);
+        {
+            const hipError_t e = launch_finish(fd, sb, sa.b, sk, (double)A->m, status, st);
+            timer.disarm();
+            KDCD_HIP_TRY(e);
+        }
+        if (k + 1 < n_outer) {
+            LookaheadArgs la{};
+            la.S = S;
+            la.sb = sb;
+            la.b = sa.b;
+            la.sk = sk;
+            la.r = r;
+            la.W = Wk;
+            la.Dinv = Dinv;
+            la.y = sa.y;
+            la.alpha = sa.alpha;
+            la.lambda = sa.lambda;
+            la.mdbl = (double)A->m;
+            la.pos = P[k & 1];
+            la.Dc = Dc;
+            la.Sc = Sc;
+            la.trace = trace_of(k);
+            la.status = status;
+            la.m = A->m;
+            la.QX = nullptr;          // the Gram launch after it stores them
+            kb.S = S1;
+            kb.sb = sb1;
+            kb.la = &la;
+            groups = bind_config(kb);
+            if (!sampled || (k + 1) % 8 == 0) timer.arm(0);
+            const hipError_t e = launch_kblock_mixed(kb, st);
+            timer.disarm();
+            KDCD_HIP_TRY(e);
+            kb.la = nullptr;
+            if ((rc = gram_launch(k + 1)) != KDCD_OK) return rc;
+        } else {
+            KrrRecurDesc rd{};
+            rd.r[0] = r;
+            rd.W[0] = Wk;
+            rd.Dinv[0] = Dinv;
+            rd.y[0] = sa.y;
+            rd.alpha[0] = sa.alpha;
+            rd.trace[0] = trace_of(k);
+            rd.lambda[0] = sa.lambda;
+            if (!product_only) timer.arm(2);
+            const hipError_t e =
+                launch_krr_recur(rd, 1, S, sa.b, sk, A->m, (double)A->m, status, st);
+            timer.disarm();
+            KDCD_HIP_TRY(e);
+        }
+    }
+    return KDCD_OK;
+}
+
 // Everything a solve (or a part of it) puts on its stream, in the workspace at
 // `base`, without the final status read (the status word is at offset L.status).
 kdcd_status enqueue_solve(const SolveArgs &sa, const Layout &L, char *wsbase, StageTimer &timer,
@@ -807,9 +984,12 @@ kdcd_status enqueue_solve(const SolveArgs &sa, const Layout &L, char *wsbase, St
     int64_t snap = 0;
     std::unique_ptr<StopPoller> poll;
     if (monitor) poll.reset(new StopPoller(n_outer / sa.opt.monitor_every + 1));
-    if (lookahead_use(sa, L, kb, R))
+    if (lookahead_use(sa, L, kb, R)) {
+        if (sa.opt.compute != KDCD_F64)
+            return enqueue_lookahead_lowp(sa, L, ws, kb, timer, product_only, sampled);
         return enqueue_lookahead(sa, L, ws, kb, timer, product_only, sampled, mon, dual,
                                  poll.get());
+    }
 
     int64_t k = R.k_begin;
     const int64_t k_end = R.k_end < 0 ? n_outer : R.k_end;

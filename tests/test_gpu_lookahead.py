@@ -221,3 +221,42 @@ def test_lookahead_equals_serial_on_seeded_shapes(K, case):
     a_se, t_se, _ = _solve(K, d["A"], d["y"], kern, lam, b, s, H, idx, K.FLAG_SERIAL)
     assert max_rel(a_la, a_se) <= TOL, (m, n, b, s, H)
     assert max_rel(t_la, t_se) <= TOL, (m, n, b, s, H)
+
+
+@pytest.mark.parametrize("compute", ["bf16x3", "f16", "bf16"])
+def test_lookahead_low_precision(K, compute):
+    """The lookahead loop with a low-precision product (the kernel rows of the
+    previous block's coordinates then come from the FP64 Gram launch): the
+    updates follow the serial low-precision loop's within the precision's own
+    error, and for bf16x3 the objective matches the FP64 solve's to 1e-6 as the
+    serial loop's does."""
+    m, n, b, s = 3000, 512, 8, 32
+    H = 12 * s - 5
+    d = inputs.dense_c4(m=m, n=n, seed=7)
+    idx = inputs.krr_indices(m, b, H, seed=1)
+    kern = RBF1
+    A, y, I = dev(d["A"]), dev(d["y"]), idx_dev(idx)
+
+    def run(flags, comp):
+        a = torch.zeros(m, dtype=torch.float64, device="cuda")
+        t = torch.zeros(H * b, dtype=torch.float64, device="cuda")
+        res = K.kdcd_krr_solve(A, y, kern, 1e-3, b, s, H, I, a, trace=t, compute=comp,
+                               flags=flags, profile=True)
+        return a, t, res
+
+    a_la, t_la, res = run(K.FLAG_LOOKAHEAD, compute)
+    assert res["recur_launches"] == 1
+    a_se, t_se, res = run(K.FLAG_SERIAL, compute)
+    assert res["recur_launches"] == -(-H // s)
+    # the two loops take the product's rounding at different places (the
+    # lookahead adds block k's updates through FP64 kernel rows), so their
+    # updates differ at the level of the precision's kernel-value error
+    bound = {"bf16x3": 5e-6, "f16": 1e-2, "bf16": 5e-2}[compute]
+    assert max_rel(t_la.cpu().numpy(), t_se.cpu().numpy()) <= bound
+    a64, _, _ = run(K.FLAG_SERIAL, "f64")
+    f_la = K.kdcd_krr_eval(A, y, kern, 1e-3, a_la)["objective"]
+    f_se = K.kdcd_krr_eval(A, y, kern, 1e-3, a_se)["objective"]
+    f64 = K.kdcd_krr_eval(A, y, kern, 1e-3, a64)["objective"]
+    assert abs(f_la - f64) <= max(2 * abs(f_se - f64), 1e-6 * abs(f64)), (f_la, f_se, f64)
+    if compute == "bf16x3":
+        assert abs(f_la - f64) <= 1e-6 * abs(f64)
