@@ -58,6 +58,12 @@ int64_t max_row_groups(const kdcd_matrix *A)
 // launches per outer iteration) instead of tiles of their own, which at
 // these widths add a round of workgroups.
 constexpr int64_t kGatherMinSB = 256;
+// Tile configuration of the FP64 Gram-only launches that follow a
+// low-precision product: 128 x 16 (four waves) spreads an s*b-row Gram over
+// the most workgroups; with its long K loop and few tiles that launch is bound
+// by latency, not by the tile's MFMA rate (C2's 1024 x 512 lookahead Gram:
+// 29.8 us against 34.3 for the 64 x 64 tile, 40.3 for 128 x 32).
+constexpr int32_t kGramCfg = 0;
 // Largest rank of a low-rank factor (Nystrom landmarks, columns of Phi).
 constexpr int64_t kMaxRank = 4096;
 
@@ -131,7 +137,7 @@ hipError_t launch_kblock(const KBlockArgs &a, hipStream_t st)
     KBlockArgs w = a;
     w.compute = KDCD_F64;
     w.w_only = 1;
-    w.cfg = -1;          // the FP64 table's choice (a.cfg names a low-precision tile)
+    w.cfg = kGramCfg;    // (a.cfg names a low-precision tile)
     w.U = nullptr;       // the stored kernel block is the low-precision product's
     return launch_kblock_f64(w, st);
 }
@@ -781,7 +787,7 @@ kdcd_status enqueue_lookahead_lowp(const SolveArgs &sa, const Layout &L, Workspa
         KBlockArgs w = kb;
         w.compute = KDCD_F64;
         w.w_only = 1;
-        w.cfg = -1;
+        w.cfg = kGramCfg;
         w.U = nullptr;
         w.pos = nullptr;
         w.la = nullptr;
@@ -1040,7 +1046,7 @@ kdcd_status enqueue_solve(const SolveArgs &sa, const Layout &L, char *wsbase, St
             KBlockArgs w = kb;
             w.compute = KDCD_F64;
             w.w_only = 1;
-            w.cfg = -1;
+            w.cfg = kGramCfg;
             KDCD_HIP_TRY(launch_kblock_f64(w, st));
         } else {
             timer.begin(0, st);
