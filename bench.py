@@ -90,7 +90,8 @@ def copy_probe():
 
 PROFILE_F64 = os.path.join(ROOT, "profiles", "kblock_f64_krr_c2_s64.txt")
 PROFILE_LOWP = os.path.join(ROOT, "profiles", "kblock_lowp_krr_c4_bf16.txt")
-KBLOCK_LOWP_SRC = os.path.join(ROOT, "paper_2406_18001_amd", "csrc", "kblock_lowp.hip")
+KBLOCK_LOWP_SRC = [os.path.join(ROOT, "paper_2406_18001_amd", "csrc", "kblock_lowp.hip"),
+                   os.path.join(ROOT, "paper_2406_18001_amd", "csrc", "la_recur.hpp")]
 PROFILE_CSR = os.path.join(ROOT, "profiles", "kblock_csr_head_c3_s32.txt")
 KBLOCK_CSR_SRC = os.path.join(ROOT, "paper_2406_18001_amd", "csrc", "kblock_csr.hip")
 # the FP64 product and the lookahead recurrence its workgroup 0 runs

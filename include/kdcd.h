@@ -140,17 +140,19 @@ typedef struct {
  * counts them), which keeps the timing's device cost to one launch in eight.
  */
 /*
- * Lookahead loop (kdcd_krr_solve and kdcd_krr_solve_noalloc; dense A, FP64,
- * b <= 8, 256 <= s*b <= 512, n a multiple of 16 with 16-byte aligned rows, at
- * least two outer iterations, no snapshots, and with the monitor only without
- * a caller workspace, whose size does not include the second stored kernel
- * block the loop then keeps): the s-step recurrence of index
+ * Lookahead loop (kdcd_krr_solve and kdcd_krr_solve_noalloc; dense A with
+ * compute FP64, BF16, F16 or BF16X3, b <= 8, 256 <= s*b <= 512, at least two
+ * outer iterations, no snapshots; FP64 also needs n a multiple of 16 with
+ * 16-byte aligned rows; the monitor only in FP64 and without a caller
+ * workspace, whose size does not include the second stored kernel block the
+ * loop then keeps): the s-step recurrence of index
  * block k (Algorithm 4's inner loop) runs in one workgroup of the launch that
  * computes the kernel block of index block k+1.  That product reduces r_{k+1}
- * against the iterate before block k's updates and also stores the kernel
- * rows of block k's coordinates; the finish pass of block k+1 then adds those
- * rows times the updates to r_{k+1} and the updates to alpha, which is
- * Algorithm 4's r_{k+1} = U_{k+1}^T alpha up to rounding.  Used by default
+ * against the iterate before block k's updates; the kernel rows of block k's
+ * coordinates come from the same launch (FP64) or from the FP64 Gram launch
+ * after it (low precision), and the finish pass of block k+1 adds those rows
+ * times the updates to r_{k+1} and the updates to alpha, which is Algorithm
+ * 4's r_{k+1} = U_{k+1}^T alpha up to rounding.  Used by default
  * when 2 m n s b >= 4e9 (the product then outlasts the recurrence it hides);
  * KDCD_FLAG_LOOKAHEAD asks for it at any size, KDCD_FLAG_SERIAL never.  Calls
  * that KDCD_FLAG_GRAPH replays by windows run the serial loop.
