@@ -140,12 +140,12 @@ typedef struct {
  * counts them), which keeps the timing's device cost to one launch in eight.
  */
 /*
- * Lookahead loop (kdcd_krr_solve and kdcd_krr_solve_noalloc; dense A with
- * compute FP64, BF16, F16 or BF16X3, b <= 8, 256 <= s*b <= 512, at least two
- * outer iterations, no snapshots; FP64 also needs n a multiple of 16 with
- * 16-byte aligned rows; the monitor only in FP64 and without a caller
- * workspace, whose size does not include the second stored kernel block the
- * loop then keeps): the s-step recurrence of index
+ * Lookahead loop (kdcd_krr_solve and kdcd_krr_solve_noalloc; dense A, any
+ * compute, b <= 8, 256 <= s*b <= 512, at least two outer iterations, no
+ * snapshots; FP64 also needs n a multiple of 16 with 16-byte aligned rows;
+ * the monitor only in FP64 and without a caller workspace, whose size does
+ * not include the second stored kernel block the loop then keeps): the s-step
+ * recurrence of index
  * block k (Algorithm 4's inner loop) runs in one workgroup of the launch that
  * computes the kernel block of index block k+1.  That product reduces r_{k+1}
  * against the iterate before block k's updates; the kernel rows of block k's

@@ -21,6 +21,7 @@
 // assignment inside a chunk is the same for A and B, which is all the
 // contraction needs.  Output item v of lane l is row 4 (l/16) + v, column l%16.
 #include "common.hpp"
+#include "la_recur.hpp"
 
 namespace kdcd {
 namespace {
@@ -68,14 +69,16 @@ template <int CMP> constexpr int seg_elems() { return CMP == KDCD_F32 ? 4 : 8; }
 // Every variant asks for at least two waves per SIMD (all fit without
 // spilling; the 128 x 64 single-problem tile reaches three): left to itself the
 // compiler runs the batched variants at one.
-template <int CMP, int WM, int WN, int TM, int TN, int KIND, bool BATCH>
+// LAH (single problem): a K-RR lookahead launch: workgroup 0 runs la_recur for
+// the previous block, workgroups 1 .. kLaLead - 1 return, the tiles follow.
+template <int CMP, int WM, int WN, int TM, int TN, int KIND, bool BATCH, bool LAH>
 __global__ __launch_bounds__(64 * WM * WN) __attribute__((amdgpu_waves_per_eu(2)))
 void kblock_mixed_kernel(
     const u4 *__restrict__ Ahi, const u4 *__restrict__ Alo, int64_t ldseg, int64_t m,
     int64_t nseg, const float *__restrict__ normlow, const int32_t *__restrict__ S, int32_t sb,
     KParams kp, const double *__restrict__ beta, const double *__restrict__ bscale,
     double *__restrict__ partial, int32_t n_u_tiles, int32_t n_row_groups, int32_t n_tiles_n,
-    const BatchDesc *__restrict__ bd)
+    const BatchDesc *__restrict__ bd, const LookaheadArgs la)
 {
     constexpr bool X3 = CMP == KDCD_BF16X3;
     constexpr int NT = 64 * WM * WN;
@@ -90,10 +93,25 @@ void kblock_mixed_kernel(
     __shared__ double red[WM][BN];
     __shared__ double redb[BATCH ? kMaxProblems : 1][WM][BN];
 
+    if constexpr (LAH) {
+        static_assert((int)sizeof(As) >= 24 * NT + 8 * (2 * kLaMaxB + 256) + NT / 4,
+                      "the lookahead recurrence's LDS must fit the A buffers");
+        if (blockIdx.x < kLaLead) {
+            if (blockIdx.x == 0 && la.sb > 0) {
+                char *smem = reinterpret_cast<char *>(&As[0][0][0]);
+                if (la.b == 8) la_recur<NT, 8>(la, smem);
+                else la_recur<NT, 0>(la, smem);
+            }
+            return;
+        }
+    }
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int wm = wid / WN, wn = wid % WN;
     const int total = n_tiles_n * n_row_groups;
-    const int L = xcd_remap(blockIdx.x, total);
+    // the leading workgroups of a lookahead launch are a multiple of 8, so
+    // bid % 8 is still the XCD of the workgroup
+    const int bid = LAH ? (int)blockIdx.x - kLaLead : (int)blockIdx.x;
+    const int L = xcd_remap(bid, total);
     const int cn = L % n_tiles_n;
     const int rg = L / n_tiles_n;
     const int col0 = cn * BN;
@@ -421,18 +439,29 @@ hipError_t launch_cfg(const KBlockArgs &a, hipStream_t st)
     const int64_t esz = CMP == KDCD_F32 ? 4 : 2;
     const int64_t ldseg = a.ldlow * esz / 16;
     const int64_t nseg = (A->n * esz + 15) / 16;
-    dim3 grid((unsigned)(n_n * groups)), block(64 * WM * WN);
+    const bool la = !BATCH && a.la != nullptr;
+    if (la && !(a.la->b <= kLaMaxB && a.la->sb <= kLaEPT * 64 * WM * WN))
+        return hipErrorInvalidValue;   // the caller checks lookahead_use first
+    const LookaheadArgs lav = la ? *a.la : LookaheadArgs{};
+    dim3 grid((unsigned)(n_n * groups + (la ? kLaLead : 0))), block(64 * WM * WN);
+#define KDCD_LAUNCH_L(KIND, LAH)                                                                \
+    KDCD_TIMED_LAUNCH((kblock_mixed_kernel<CMP, WM, WN, TM, TN, KIND, BATCH, LAH>), grid, block, \
+                       0, st, static_cast<const u4 *>(a.Alow), static_cast<const u4 *>(a.Alow2), \
+                       ldseg, A->m, nseg, a.normlow, a.S, a.sb, a.kp, a.beta, a.beta_scale,      \
+                       a.partial, (int32_t)n_u, (int32_t)groups, (int32_t)n_n, a.batch, lav)
 #define KDCD_LAUNCH(KIND)                                                                       \
-    KDCD_TIMED_LAUNCH((kblock_mixed_kernel<CMP, WM, WN, TM, TN, KIND, BATCH>), grid, block, 0, st,  \
-                       static_cast<const u4 *>(a.Alow), static_cast<const u4 *>(a.Alow2), ldseg, \
-                       A->m, nseg, a.normlow, a.S, a.sb, a.kp, a.beta, a.beta_scale, a.partial, \
-                       (int32_t)n_u, (int32_t)groups, (int32_t)n_n, a.batch)
+    do {                                                                                        \
+        if (la) {                                                                               \
+            if constexpr (!BATCH) KDCD_LAUNCH_L(KIND, true);                                    \
+        } else KDCD_LAUNCH_L(KIND, false);                                                      \
+    } while (0)
     switch (a.kp.kind) {
     case KDCD_KERNEL_LINEAR: KDCD_LAUNCH(KDCD_KERNEL_LINEAR); break;
     case KDCD_KERNEL_POLY: KDCD_LAUNCH(KDCD_KERNEL_POLY); break;
     default: KDCD_LAUNCH(KDCD_KERNEL_RBF); break;
     }
 #undef KDCD_LAUNCH
+#undef KDCD_LAUNCH_L
     return hipGetLastError();
 }
 

@@ -1,6 +1,6 @@
 // The recurrence of one K-RR index block run inside a lookahead launch (see
-// LookaheadArgs): workgroup 0 of the dense FP64 and of the low-precision
-// kernel-block products calls it.
+// LookaheadArgs): workgroup 0 of the dense FP64, the FP32 and the
+// low-precision kernel-block products calls it.
 #pragma once
 
 #include "common.hpp"

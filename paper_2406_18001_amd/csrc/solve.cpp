@@ -186,8 +186,9 @@ Layout make_layout(int32_t problem, const kdcd_matrix *A, const kdcd_kernel *ker
     L.Dinv = off; off += (problem == 1) ? align256(sizeof(double) * (size_t)(sb * b)) : 0;
     L.iota = off; off += (problem == 2) ? align256(sizeof(int32_t) * (size_t)A->m) : 0;
     L.pos = off; off += align256(sizeof(int32_t) * (size_t)A->m);   // row -> position in S
-    const bool la_compute = compute == KDCD_F64 || compute == KDCD_BF16 ||
-                            compute == KDCD_F16 || compute == KDCD_BF16X3;
+    const bool la_compute = compute == KDCD_F64 || compute == KDCD_F32 ||
+                            compute == KDCD_BF16 || compute == KDCD_F16 ||
+                            compute == KDCD_BF16X3;
     L.la_ok = problem == 1 && A->format == KDCD_DENSE && la_compute && sb >= kGatherMinSB &&
               b <= kLaMaxB && sb <= kLaEPT * 256;
     // FP64: second Gram and QX; low precision: one buffer of two Grams' rows
@@ -743,7 +744,7 @@ kdcd_status enqueue_lookahead(const SolveArgs &sa, const Layout &L, Workspace &w
     return KDCD_OK;
 }
 
-// The lookahead loop with a low-precision product (bf16, f16, bf16x3).  As the
+// The lookahead loop with a low-precision product (f32, bf16, f16, bf16x3).  As the
 // FP64 loop, but the product stores no Gram rows: after each lookahead launch
 // an FP64 Gram launch takes the rows of index blocks k and k+1, which lie back
 // to back in idx, against block k+1's columns, giving in one buffer the kernel

@@ -223,7 +223,7 @@ def test_lookahead_equals_serial_on_seeded_shapes(K, case):
     assert max_rel(t_la, t_se) <= TOL, (m, n, b, s, H)
 
 
-@pytest.mark.parametrize("compute", ["bf16x3", "f16", "bf16"])
+@pytest.mark.parametrize("compute", ["bf16x3", "f16", "bf16", "f32"])
 def test_lookahead_low_precision(K, compute):
     """The lookahead loop with a low-precision product (the kernel rows of the
     previous block's coordinates then come from the FP64 Gram launch): the
@@ -251,12 +251,12 @@ def test_lookahead_low_precision(K, compute):
     # the two loops take the product's rounding at different places (the
     # lookahead adds block k's updates through FP64 kernel rows), so their
     # updates differ at the level of the precision's kernel-value error
-    bound = {"bf16x3": 5e-6, "f16": 1e-2, "bf16": 5e-2}[compute]
+    bound = {"bf16x3": 5e-6, "f32": 5e-6, "f16": 1e-2, "bf16": 5e-2}[compute]
     assert max_rel(t_la.cpu().numpy(), t_se.cpu().numpy()) <= bound
     a64, _, _ = run(K.FLAG_SERIAL, "f64")
     f_la = K.kdcd_krr_eval(A, y, kern, 1e-3, a_la)["objective"]
     f_se = K.kdcd_krr_eval(A, y, kern, 1e-3, a_se)["objective"]
     f64 = K.kdcd_krr_eval(A, y, kern, 1e-3, a64)["objective"]
     assert abs(f_la - f64) <= max(2 * abs(f_se - f64), 1e-6 * abs(f64)), (f_la, f_se, f64)
-    if compute == "bf16x3":
+    if compute in ("bf16x3", "f32"):
         assert abs(f_la - f64) <= 1e-6 * abs(f64)
