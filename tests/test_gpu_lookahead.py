@@ -108,6 +108,20 @@ def test_lookahead_refused_shapes_run_serially(K):
         assert res["recur_launches"] == (H + s - 1) // s
 
 
+def test_lookahead_fp64_needs_whole_k_chunks(K):
+    """The FP64 lookahead product takes n in whole 16-column chunks: n = 40 with
+    the flag runs the serial loop, to the same bar."""
+    d = inputs.dense_krr_c2(m=1500, n=40, seed=9)
+    b, s, H = 8, 32, 200
+    idx = inputs.krr_indices(1500, b, H, seed=3)
+    a_ref, d_ref = _oracle(d["A"], d["y"], RBF1, 1e-3, b, s, H, idx)
+    a, t, res = _solve(K, d["A"], d["y"], RBF1, 1e-3, b, s, H, idx, K.FLAG_LOOKAHEAD,
+                       profile=True)
+    assert_parity(a, a_ref, TOL, "alpha n=40")
+    assert_parity(t, d_ref, TOL, "delta n=40")
+    assert res["recur_launches"] == (H + s - 1) // s
+
+
 def test_lookahead_duplicate_in_block_is_refused(K):
     d = inputs.dense_krr_c2(m=1000, n=32, seed=7)
     idx = inputs.krr_indices(1000, 8, 96, seed=2)
@@ -260,3 +274,29 @@ def test_lookahead_low_precision(K, compute):
     assert abs(f_la - f64) <= max(2 * abs(f_se - f64), 1e-6 * abs(f64)), (f_la, f_se, f64)
     if compute in ("bf16x3", "f32"):
         assert abs(f_la - f64) <= 1e-6 * abs(f64)
+
+
+@pytest.mark.parametrize("compute", ["bf16x3", "f32"])
+def test_lookahead_low_precision_ragged(K, compute):
+    """The low-precision lookahead at n = 40 and m = 1037 (partial K chunks and
+    row tiles; the FP64 Gram launch over two index blocks then has ragged rows
+    too): it runs, and its updates follow the serial loop's within the
+    precision's error."""
+    m, n, b, s = 1037, 40, 8, 40
+    H = 6 * s - 3
+    d = inputs.dense_c4(m=m, n=n, seed=11)
+    idx = inputs.krr_indices(m, b, H, seed=5)
+    A, y, I = dev(d["A"]), dev(d["y"]), idx_dev(idx)
+
+    def run(flags):
+        a = torch.zeros(m, dtype=torch.float64, device="cuda")
+        t = torch.zeros(H * b, dtype=torch.float64, device="cuda")
+        res = K.kdcd_krr_solve(A, y, RBF1, 1e-3, b, s, H, I, a, trace=t, compute=compute,
+                               flags=flags, profile=True)
+        return a.cpu().numpy(), t.cpu().numpy(), res
+
+    a_la, t_la, res = run(K.FLAG_LOOKAHEAD)
+    assert res["recur_launches"] == 1
+    a_se, t_se, _ = run(K.FLAG_SERIAL)
+    assert max_rel(t_la, t_se) <= 5e-6
+    assert max_rel(a_la, a_se) <= 5e-6
