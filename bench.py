@@ -161,11 +161,15 @@ def cpu_baseline(d, idx, s, target_s):
     one outer iteration at s = 8."""
     from oracle import oracle as O
     kern = O.Kernel(O.RBF, sigma=SIGMA)
+    kept = {}
 
     def run(outer, s_run=s):
         t0 = time.perf_counter()
-        O.bdcd_krr(d["A"], d["y"], kern, LAM, B, outer * s, idx, s=s_run)
-        return time.perf_counter() - t0
+        a_o, _ = O.bdcd_krr(d["A"], d["y"], kern, LAM, B, outer * s, idx, s=s_run)
+        dt = time.perf_counter() - t0
+        if s_run == s:
+            kept["alpha"], kept["H"] = a_o, outer * s
+        return dt
 
     outer, dt = 1, run(1)
     if dt < target_s / 2:
@@ -189,7 +193,7 @@ def cpu_baseline(d, idx, s, target_s):
             "one_thread": {"value": block_flops(8, 8, B, M, N) / dt_one / 1e12, "unit": "TFLOP/s",
                            "seconds": round(dt_one, 3),
                            "sample": "one outer iteration at s = 8 (8 block updates), one thread"},
-            "host": host_cpu()}
+            "host": host_cpu()}, kept
 
 
 def krr_outer_to_target(K, A, y, kern, lam, b, s, idx_long, compute, every=8, target=1e-6,
@@ -1378,7 +1382,21 @@ def main():
                     "beside it)"}
         out["time_to_rel_obj_err_1e-6"] = conv
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(d, idx, s, args.cpu_seconds)
+        out["cpu_baseline"], kept = cpu_baseline(d, idx, s, args.cpu_seconds)
+        # the GPU solve of the same block updates (the launch configuration
+        # timed above) against the oracle's iterate
+        import numpy as np
+        hs = kept["H"]
+        alpha.zero_()
+        K.kdcd_krr_solve(A, y, kern, LAM, B, s, hs, I[:hs * B].contiguous(), alpha,
+                         compute=args.compute)
+        a_g = alpha.cpu().numpy()
+        a_o = kept["alpha"]
+        out["oracle_error"] = {
+            "rel_l2": float(np.linalg.norm(a_g - a_o) / np.linalg.norm(a_o)),
+            "max_rel": float(np.max(np.abs(a_g - a_o)) / np.max(np.abs(a_o))),
+            "sample": f"alpha after the first {hs} block updates (the oracle's timed sample), "
+                      f"compute {args.compute}"}
     print(json.dumps(out), flush=True)
 
 
