@@ -1103,6 +1103,32 @@ def bench_c1(args):
            "config": {"workload": f"C1: dense A {m}x{n} N(0,1), y = sign(A w) with 5% flips, "
                                   f"K-SVM-L1 RBF sigma=1, C={C}, b=1, s in (1, 8), H={H}"},
            "runs": runs, "speedup_s8_vs_s1": round(runs[0]["solve_ms"] / runs[1]["solve_ms"], 3)}
+    if not args.no_cpu_baseline:
+        # the oracle runs the whole solve (s = 8, and the classical s = 1);
+        # the GPU iterates of both against it
+        import numpy as np
+
+        from oracle import oracle as O
+        ko = O.Kernel(kern[0], sigma=kern[1], c=kern[2], degree=kern[3])
+        idx_h = idx.cpu().numpy()
+        res, errs = {}, {}
+        for s in (8, 1):
+            t0 = time.perf_counter()
+            a_o, _ = O.dcd_ksvm(d["A"], d["y"], ko, C, H, idx_h, s=s)
+            res[s] = time.perf_counter() - t0
+            a = torch.zeros(m, dtype=torch.float64, device="cuda")
+            K.kdcd_ksvm_solve(A, y, kern, C, 1, s, H, idx, a)
+            a_g = a.cpu().numpy()
+            errs[f"s{s}"] = {"rel_l2": float(np.linalg.norm(a_g - a_o) / np.linalg.norm(a_o)),
+                             "max_abs": float(np.max(np.abs(a_g - a_o)))}
+        out["cpu_baseline"] = {"value": round(res[8] / -(-H // 8) * 1e6, 2),
+                               "unit": "us/outer iteration", "cores": O.threads(), "kind": "oracle",
+                               "sample": f"the whole solve (H = {H}, s = 8), {res[8]:.3f} s, FP64 "
+                                         f"oracle",
+                               "classical_s1": {"seconds": round(res[1], 4),
+                                                "speedup_of_s_step": round(res[1] / res[8], 3)},
+                               "host": host_cpu()}
+        out["oracle_error"] = dict(errs, sample=f"alpha after the whole solve (H = {H})")
     print(json.dumps(out), flush=True)
 
 
@@ -1194,6 +1220,41 @@ def bench_c3_csr(args):
                                 "panel build (csr_panel_build_kernel) and the gated broadcast "
                                 "launch are outside the timed kernel"},
            "runs": runs}
+    if not args.no_cpu_baseline:
+        # the oracle (s-step DCD on the CSR arrays) on the first outer
+        # iterations of the same solve, grown to about --cpu-seconds; then the
+        # GPU solve of those updates against the oracle's iterate
+        from oracle import oracle as O
+        Ao = (c["row_ptr"], c["col_idx"], c["val"], m, n)
+        ko = O.Kernel(kern[0], sigma=kern[1], c=kern[2], degree=kern[3])
+        idx_h = idx.cpu().numpy()
+        s = 32
+
+        def orun(outer):
+            t0 = time.perf_counter()
+            a_o, _ = O.dcd_ksvm(Ao, c["y"], ko, 1.0, outer * s, idx_h, s=s)
+            return time.perf_counter() - t0, a_o
+
+        outer = 1
+        dt, a_o = orun(outer)
+        if dt < args.cpu_seconds / 2:
+            outer = int(min(H // s, max(2, round(args.cpu_seconds / dt))))
+            dt, a_o = orun(outer)
+        hs = outer * s
+        out["cpu_baseline"] = {"value": round(hs / dt, 1), "unit": "updates/s",
+                               "cores": O.threads(), "kind": "oracle",
+                               "sample": f"first {outer} outer iteration(s) = {hs} coordinate "
+                                         f"updates of the same solve (s={s}), {dt:.2f} s, FP64 "
+                                         f"oracle on the CSR arrays",
+                               "seconds": round(dt, 3), "host": host_cpu()}
+        alpha = torch.zeros(m, dtype=torch.float64, device=dev)
+        K.kdcd_ksvm_solve(A, y, kern, 1.0, 1, s, hs, idx[:hs].contiguous(), alpha)
+        a_g = alpha.cpu().numpy()
+        out["oracle_error"] = {
+            "rel_l2": float(np.linalg.norm(a_g - a_o) / max(np.linalg.norm(a_o), 1e-300)),
+            "max_abs": float(np.max(np.abs(a_g - a_o))),
+            "sample": f"alpha after the first {hs} coordinate updates (the oracle's timed "
+                      f"sample), s = {s}"}
     print(json.dumps(out), flush=True)
 
 
