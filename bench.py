@@ -454,6 +454,43 @@ def bench_c4_sweep(args):
     }
     if conv:
         out["time_to_target"] = conv
+    if not args.no_cpu_baseline:
+        # the oracle on one outer iteration of two of the problems (a K-RR
+        # sweep point and the first one-vs-rest K-SVM), each solved alone on
+        # the host, against the batched FP64 solve of all 18
+        import numpy as np
+
+        from oracle import oracle as O
+        # two outer iterations (from alpha = 0 the first one's r is zero, so
+        # only the second exercises the shared product)
+        n_o = 2
+        I1 = I[:n_o * sb].contiguous()
+        ps = problems()
+        K.kdcd_batch_solve(A, kern, b, s, n_o * s, I1, ps)
+        idx1 = I1.cpu().numpy()
+        la, sg = sweep[1]
+        t0 = time.perf_counter()
+        a_r, _ = O.bdcd_krr(d["A"], d["y"], O.Kernel(O.RBF, sigma=sg), la, b, n_o * s, idx1, s=s)
+        dt_r = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        a_k, _ = O.dcd_ksvm(d["A"], d["Y_ovr"][0], O.Kernel(O.RBF, sigma=1.0), 1.0, n_o * sb,
+                            idx1, s=sb)
+        dt_k = time.perf_counter() - t0
+        fl = 2.0 * m * n * sb * n_o
+        out["cpu_baseline"] = {"value": round(2 * fl / (dt_r + dt_k) / 1e12, 6), "unit": "TFLOP/s",
+                               "cores": O.threads(), "kind": "oracle",
+                               "sample": f"{n_o} outer iterations (s*b={sb}) of K-RR "
+                                         f"(lambda={la}, sigma={sg}), {dt_r:.2f} s, and of the "
+                                         f"first K-SVM, {dt_k:.2f} s, each alone, FP64 oracle",
+                               "host": host_cpu()}
+
+        def err(g, o):
+            return {"rel_l2": float(np.linalg.norm(g - o) / np.linalg.norm(o)),
+                    "max_abs": float(np.max(np.abs(g - o)))}
+        out["oracle_error"] = {"krr": err(ps[1].alpha.cpu().numpy(), a_r),
+                               "ksvm": err(ps[len(sweep)].alpha.cpu().numpy(), a_k),
+                               "sample": "alpha after two outer iterations of the batched FP64 "
+                                         "solve of all 18 problems"}
     print(json.dumps(out), flush=True)
 
 
@@ -643,14 +680,32 @@ def bench_c4_mixed(args):
         out["time_to_rel_obj_err_1e-6"] = conv
     if not args.no_cpu_baseline:
         from oracle import oracle as O
-        idx1 = inputs.krr_indices(m, b, s, seed=0)
+        # two outer iterations: the first starts from alpha = 0, where r = U^T
+        # alpha is zero whatever the product's precision, so only the second
+        # shows a precision's rounding
+        n_o = 2
+        idx1 = inputs.krr_indices(m, b, n_o * s, seed=0)
         t0 = time.perf_counter()
-        O.bdcd_krr(d["A"], d["y"], O.Kernel(O.RBF, sigma=sig), lam, b, s, idx1, s=s)
+        a_o, _ = O.bdcd_krr(d["A"], d["y"], O.Kernel(O.RBF, sigma=sig), lam, b, n_o * s, idx1,
+                            s=s)
         dt = time.perf_counter() - t0
-        out["cpu_baseline"] = {"value": round(fl_launch / dt / 1e12, 6), "unit": "TFLOP/s",
+        out["cpu_baseline"] = {"value": round(n_o * fl_launch / dt / 1e12, 6), "unit": "TFLOP/s",
                                "cores": O.threads(), "kind": "oracle",
-                               "sample": f"one outer iteration of the same solve (s*b={sb}), "
-                                         f"{dt:.2f} s, FP64 oracle"}
+                               "sample": f"{n_o} outer iterations of the same solve (s*b={sb}), "
+                                         f"{dt:.2f} s, FP64 oracle", "host": host_cpu()}
+        # every precision's iterate after those outer iterations against the
+        # oracle's (FP64 to the parity bar; the others by their rounding)
+        import numpy as np
+        I1 = torch.tensor(idx1, device="cuda")
+        errs = {}
+        for comp in ["f64"] + [c for c in computes if c != "f64"]:
+            a = torch.zeros(m, dtype=torch.float64, device="cuda")
+            K.kdcd_krr_solve(A, y, kern, lam, b, s, n_o * s, I1, a, compute=comp)
+            a_g = a.cpu().numpy()
+            errs[comp] = {"rel_l2": float(np.linalg.norm(a_g - a_o) / np.linalg.norm(a_o)),
+                          "max_rel": float(np.max(np.abs(a_g - a_o)) / np.max(np.abs(a_o)))}
+        out["oracle_error"] = dict(errs, sample=f"alpha after {n_o} outer iterations ({s} blocks "
+                                                f"of {b} each)")
     print(json.dumps(out), flush=True)
 
 
@@ -675,7 +730,13 @@ def bench_peaks(args):
         res[name] = {"TFLOP/s": round(best, 1), "published": pub, "frac": round(best / pub, 3)}
     res["hbm_read_GB/s"] = round(lib.kdcd_peak_stream(0, 2 << 30), 1)
     res["hbm_copy_GB/s"] = round(lib.kdcd_peak_stream(1, 1 << 30), 1)
-    print(json.dumps({"metric": "measured MFMA / HBM peaks", "peaks": res}), flush=True)
+    print(json.dumps({"metric": "measured MFMA / HBM peaks (bf16 32x32x16 MFMA headline)",
+                      "value": res["bf16_32x32x16"]["TFLOP/s"], "unit": "TFLOP/s", "n_gpus": 1,
+                      "steps": 1, "warmup": 1, "ms_per_step": None, "higher_is_better": True,
+                      "scaling": "weak", "vs_baseline": None, "dtype": "mixed", "data": "synthetic",
+                      "config": {"workload": "MFMA chains without memory traffic at 1, 2 and 4 "
+                                             "waves per SIMD; read and copy streams of 2 / 1 GiB"},
+                      "peaks": res}), flush=True)
 
 
 def _monitored_solve(run, log, label):
@@ -806,6 +867,44 @@ def bench_c5s_sampler(args):
                      "final_rel_gap": info["rel_err"], "outer_done": info["outer_done"],
                      "wall_s": round(info["wall_s"], 3)}
         log(f"c5s-sampler: {name}: {res[name]}")
+    oracle_part = {}
+    if not args.no_cpu_baseline:
+        # the oracle on the first outer iterations of the plain solve (grown
+        # to about --cpu-seconds), and the GPU iterate of the same updates
+        import numpy as np
+
+        from oracle import oracle as O
+        d = inputs.dense_ksvm_c5(m=m, n=n)
+        ko = O.Kernel(kern[0], sigma=kern[1], c=kern[2], degree=kern[3])
+
+        def orun(outer):
+            t0 = time.perf_counter()
+            a_o, _ = O.dcd_ksvm(d["A"], d["y"], ko, C, outer * s, idx[:outer * s].cpu().numpy(),
+                                s=s)
+            return time.perf_counter() - t0, a_o
+
+        outer = 1
+        dt, a_o = orun(outer)
+        if dt < args.cpu_seconds / 2:
+            outer = int(min(64, max(2, round(args.cpu_seconds / dt))))
+            dt, a_o = orun(outer)
+        hs = outer * s
+        del d
+        a = torch.zeros(m, dtype=torch.float64, device="cuda")
+        K.kdcd_ksvm_solve(A, y, kern, C, 1, s, hs, idx[:hs].contiguous(), a)
+        a_g = a.cpu().numpy()
+        fl = 2.0 * m * n * s * outer
+        oracle_part = {
+            "cpu_baseline": {"value": round(fl / dt / 1e12, 6), "unit": "TFLOP/s",
+                             "cores": O.threads(), "kind": "oracle",
+                             "sample": f"first {outer} outer iteration(s) = {hs} coordinate "
+                                       f"updates of the plain solve (s={s}), {dt:.2f} s, FP64 "
+                                       f"oracle (kernel-block flops 2 m n s per outer iteration)",
+                             "seconds": round(dt, 3), "host": host_cpu()},
+            "oracle_error": {"rel_l2": float(np.linalg.norm(a_g - a_o) / np.linalg.norm(a_o)),
+                             "max_abs": float(np.max(np.abs(a_g - a_o))),
+                             "sample": f"alpha after the first {hs} coordinate updates of the "
+                                       f"plain solve"}}
     del idx
     costs = trace_s + train_s
     pu, lp = res["plain_uniform"]["seconds_to_rel_gap"], res["learned_pool256"]["seconds_to_rel_gap"]
@@ -837,6 +936,7 @@ def bench_c5s_sampler(args):
         "gain": gains,
         "draws": res,
     }
+    out.update(oracle_part)
     print(json.dumps(out), flush=True)
 
 
@@ -931,12 +1031,53 @@ def bench_c2_nystrom(args):
             log(f"nystrom {entry}")
             runs.append(entry)
         del Phi
-    out = {"metric": "time to rel obj err 1e-6 of the Nystrom-approximated K-RR; error under the "
-                     "exact problem", "unit": "s", "n_gpus": 1, "higher_is_better": False,
+    # the value: the largest rank (the closest approximation), its faster s
+    top = max(e["rank"] for e in runs)
+    done = [e for e in runs if e.get("outer_iterations") and e["rank"] == top]
+    lead = min(done, key=lambda e: e["factor_plus_solve_s"]) if done else None
+    out = {"metric": "time to rel obj err 1e-6 of the Nystrom-approximated K-RR (factor + solve); "
+                     "error under the exact problem",
+           "value": lead["factor_plus_solve_s"] if lead else None, "unit": "s", "n_gpus": 1,
+           "steps": 1, "warmup": 1,
+           "ms_per_step": round(lead["factor_plus_solve_s"] * 1e3, 3) if lead else None,
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
            "dtype": "f64", "data": "synthetic",
            "config": {"workload": f"C2 K-RR {M}x{N} RBF sigma={SIGMA} lambda={LAM} b={B}, "
-                                  f"Nystrom factor from uniform landmarks, jitter={jitter}"},
+                                  f"Nystrom factor from uniform landmarks, jitter={jitter}",
+                      "value_from": ({"rank": lead["rank"], "s": lead["s"]} if lead else None)},
            "runs": runs}
+    if not args.no_cpu_baseline:
+        # the oracle's factor at rank 256 and its s-step solve on that factor
+        # (linear kernel on the features) over 4 outer iterations at s = 64,
+        # against the GPU factor and the GPU low-rank solve
+        import numpy as np
+
+        from oracle import oracle as O
+        r, s, n_o = 256, 64, 4
+        lm = inputs.landmarks(M, r, seed=1)
+        t0 = time.perf_counter()
+        Phi_o = O.nystrom_features(d["A"], O.Kernel(O.RBF, sigma=SIGMA), lm, jitter)
+        dt_f = time.perf_counter() - t0
+        idx_o = inputs.krr_indices(M, B, n_o * s, seed=0)
+        t0 = time.perf_counter()
+        a_o, _ = O.bdcd_krr(Phi_o, d["y"], O.Kernel(O.LINEAR), LAM, B, n_o * s, idx_o, s=s)
+        dt_s = time.perf_counter() - t0
+        Phi = torch.empty(M, r, dtype=torch.float64, device=dev)
+        K.kdcd_nystrom_features(A, kern, torch.tensor(lm, device=dev), jitter, Phi)
+        Phi_g = Phi.cpu().numpy()
+        alpha = torch.zeros(M, dtype=torch.float64, device=dev)
+        K.kdcd_lowrank_solve("krr", Phi, y, LAM, B, s, n_o * s, torch.tensor(idx_o, device=dev),
+                             alpha)
+        a_g = alpha.cpu().numpy()
+        out["cpu_baseline"] = {"value": round(dt_f + dt_s, 3), "unit": "s", "cores": O.threads(),
+                               "kind": "oracle",
+                               "sample": f"rank-{r} factor ({dt_f:.2f} s) and {n_o} outer "
+                                         f"iterations at s = {s} on it ({dt_s:.2f} s), FP64 oracle",
+                               "host": host_cpu()}
+        out["oracle_error"] = {
+            "factor_rel_fro": float(np.linalg.norm(Phi_g - Phi_o) / np.linalg.norm(Phi_o)),
+            "alpha_rel_l2": float(np.linalg.norm(a_g - a_o) / np.linalg.norm(a_o)),
+            "sample": f"rank-{r} factor; alpha after {n_o} outer iterations at s = {s}"}
     print(json.dumps(out), flush=True)
 
 
@@ -1032,8 +1173,11 @@ def bench_news20_krr(args):
             log(f"news20 {e}")
             runs.append(e)
     best = {b: max(r["speedup_vs_s1"] for r in runs if r["b"] == b) for b in (1, 2, 4)}
+    r1 = max((r for r in runs if r["b"] == 1), key=lambda r: r["speedup_vs_s1"])
     out = {"metric": "s-step BDCD speedup over BDCD, sparse K-RR RBF (Table 4 workload)",
-           "unit": "x", "n_gpus": 1, "higher_is_better": True, "dtype": "f64",
+           "value": best[1], "unit": "x (b = 1, best s against s = 1)", "n_gpus": 1,
+           "steps": 2, "warmup": 1, "ms_per_step": round(r1["solve_s"] * 1e3, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
            "data": "synthetic",
            "config": {"workload": f"news20-shaped CSR {m}x{n}, {nnz} stored entries (lognormal "
                                   f"row lengths, mean {avg:.0f}, longest {int(lens.max())}), RBF "
@@ -1042,6 +1186,27 @@ def bench_news20_krr(args):
            "roofline": {"bound": "hbm", "peak": 8000.0, "unit": "GB/s",
                         "note": "per pass over A: 12 bytes per stored entry + row pointers"},
            "runs": runs}
+    if not args.no_cpu_baseline:
+        # the oracle on the CSR arrays runs the b = 1, s = 64 solve in full;
+        # the GPU iterate of the same solve against it
+        from oracle import oracle as O
+        b, s, H = 1, 64, 512
+        idx_h = inputs.krr_indices(m, b, H, seed=b)
+        Ao = (c["row_ptr"], c["col_idx"], c["val"], m, n)
+        t1 = time.perf_counter()
+        a_o, _ = O.bdcd_krr(Ao, c["y"], O.Kernel(O.RBF, sigma=kern[1]), lam, b, H, idx_h, s=s)
+        dt = time.perf_counter() - t1
+        alpha = torch.zeros(m, dtype=torch.float64, device=dev)
+        K.kdcd_krr_solve(A, y, kern, lam, b, s, H, torch.as_tensor(idx_h, device=dev), alpha)
+        a_g = alpha.cpu().numpy()
+        out["cpu_baseline"] = {"value": round(H / dt, 1), "unit": "block updates/s",
+                               "cores": O.threads(), "kind": "oracle",
+                               "sample": f"the whole b = {b}, s = {s} solve ({H} block updates), "
+                                         f"{dt:.2f} s, FP64 oracle on the CSR arrays",
+                               "seconds": round(dt, 3), "host": host_cpu()}
+        out["oracle_error"] = {"rel_l2": float(np.linalg.norm(a_g - a_o) / np.linalg.norm(a_o)),
+                               "max_abs": float(np.max(np.abs(a_g - a_o))),
+                               "sample": f"alpha after the b = {b}, s = {s} solve"}
     print(json.dumps(out), flush=True)
 
 
