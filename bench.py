@@ -163,19 +163,23 @@ def cpu_baseline(d, idx, s, target_s):
     kern = O.Kernel(O.RBF, sigma=SIGMA)
     kept = {}
 
+    n_outer = -(-H // s)
+
     def run(outer, s_run=s):
+        hb = min(outer * s, H)
         t0 = time.perf_counter()
-        a_o, _ = O.bdcd_krr(d["A"], d["y"], kern, LAM, B, outer * s, idx, s=s_run)
+        a_o, _ = O.bdcd_krr(d["A"], d["y"], kern, LAM, B, hb, idx, s=s_run)
         dt = time.perf_counter() - t0
         if s_run == s:
-            kept["alpha"], kept["H"] = a_o, outer * s
+            kept["alpha"], kept["H"] = a_o, hb
         return dt
 
+    # grown to about target_s, at most the whole solve
     outer, dt = 1, run(1)
     if dt < target_s / 2:
-        outer = int(min(16, max(2, round(target_s / dt))))
+        outer = int(min(n_outer, max(2, round(target_s / dt))))
         dt = run(outer)
-    hb = outer * s
+    hb = min(outer * s, H)
     fl = block_flops(hb, s, B, M, N)
     dt1 = run(outer, 1)
     cores = O.threads()
