@@ -1520,6 +1520,11 @@ def main():
         traffic = profiled_traffic(PROFILE_F64, KBLOCK_F64_SRC)
     fl_timed = block_flops(H, s, B, M, N, every=8 if args.compute == "f64" else 1)
     achieved = fl_timed * args.steps / (kb_ms / 1e3) / 1e12
+    # the product kernel and its MFMA peak for the compute type (bf16x3: the
+    # useful flops 2 m n sb against the bf16 peak; it issues three times as many)
+    kname, peak = {"f64": ("kblock_f64_kernel", PEAK_F64),
+                   "f32": ("kblock_mixed_kernel", PEAK_F32)}.get(
+        args.compute, ("kblock_lowp_kernel", PEAK_LOWP))
     out = {
         "metric": METRIC,
         "value": round(value, 4),
@@ -1537,9 +1542,9 @@ def main():
                                f"lambda={LAM}, b={B}, s={s}, H={H}",
                    "m": M, "n": N, "b": B, "s": s, "H": H, "kernel": "rbf", "sigma": SIGMA,
                    "lambda": LAM, "compute": args.compute},
-        "roofline": {"bound": "mfma", "achieved": round(achieved, 4), "peak": PEAK_F64,
-                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_F64, 4), "traffic": traffic,
-                     "kernel": "kblock_f64_kernel", "launches": kb_launches,
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 4), "peak": peak,
+                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": traffic,
+                     "kernel": kname, "launches": kb_launches,
                      "timed": ("the product launches of outer iterations k % 8 == 0 of every "
                                "timed solve" if args.compute == "f64" else "every product launch"),
                      "avg_launch_us": round(kb_ms / kb_launches * 1e3, 2),
